@@ -1,0 +1,193 @@
+/*
+ * sparsespec -- sparse spectral Galerkin solver for -div(a grad u) = f on the
+ * d-torus, MI355X (gfx950) native.  C ABI.
+ *
+ * Mathematical objects (Gross & Iwen, "Sparse spectral methods for solving
+ * high-dimensional and multiscale elliptic PDEs"):
+ *   - Fourier convention e_k(x) = exp(2 pi i k.x), u_k = <u, e_k> (Sec. 3).
+ *   - Stamping set S^N[a](F): S^0 = F, S^n = S^{n-1} + supp(a), Minkowski sum
+ *     (Sec. 6, Eq. StampSet).  The level of k is the first n with k in S^n.
+ *   - Truncated Galerkin operator (Sec. 9, Eq. FiniteGalerkinOperator):
+ *       (L_N u)_k = sum_{l in S^N} 4 pi^2 (l . k) a_{k-l} u_l,   k in S^N.
+ *   - The solve replaces the dense direct solve of Alg. 1 (step 5) by
+ *     Jacobi-preconditioned conjugate gradients; the Jacobi diagonal
+ *     4 pi^2 |k|^2 a_0 is the denominator of the recurrence in the proof of
+ *     Prop. SolutionSupport.  The solution is the unique mean-zero one
+ *     (u_0 = 0; Prop. ExistenceUniquenessStability needs f_0 = 0).
+ *
+ * Conventions for every call:
+ *   - Every function returns ss_status and never aborts.  ss_last_error()
+ *     returns a thread-local description of the last failure.
+ *   - Frequencies are int16, row-major [count x d].  Complex numbers are
+ *     interleaved (re, im) doubles (complex128) or floats (complex64).
+ *   - "host" pointers are borrowed for the duration of the call only.
+ *     "device" pointers are caller-owned device memory (e.g. a torch
+ *     tensor's data_ptr()) on the current HIP device.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls that return
+ *     host data synchronise that stream; calls that only write device data
+ *     are asynchronous on it.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.
+ *   - Slot order: the keys of one problem are numbered in ascending
+ *     lexicographic order of their signed coordinates, coordinate 0 most
+ *     significant ("canonical order").  A batch numbers problem after
+ *     problem.
+ *   - Limits: 1 <= d <= 1024; |supp a| (after closing under negation) <= 63;
+ *     every key coordinate must fit int16 (else SS_ERANGE); at most 16383
+ *     problems per batch and 4194303 keys per problem.
+ */
+#ifndef SPARSESPEC_H
+#define SPARSESPEC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SS_OK = 0,
+  SS_EINVAL = 1,      /* malformed argument (shape, duplicate, non-conjugate pair, f_0 != 0, ...) */
+  SS_ENOMEM = 2,      /* device or host allocation failed                              */
+  SS_ERANGE = 3,      /* a key coordinate leaves int16, or a size limit is exceeded    */
+  SS_ENOTPD = 4,      /* l1 positivity certificate a_0 > sum_{w != 0} |a_w| failed      */
+  SS_ENOCONV = 5,     /* iteration limit reached; best iterate returned, info filled   */
+  SS_EBREAKDOWN = 6,  /* <p, L p> <= 0 or not finite during CG                        */
+  SS_EDEVICE = 7      /* a HIP runtime call failed                                    */
+} ss_status;
+
+typedef enum { SS_FP64 = 0, SS_FP32_REFINE = 1 } ss_precision;
+
+/* ss_build_op flags */
+#define SS_SKIP_L1_CHECK 1u   /* accept a whose l1 certificate fails (e.g. product coefficients) */
+
+typedef struct ss_stamp ss_stamp;  /* device-resident stamping sets of a batch of problems       */
+typedef struct ss_op ss_op;        /* device-resident operator(s) L_N built on an ss_stamp        */
+
+typedef struct {
+  int32_t iters;          /* CG iterations (summed over refinement steps for FP32_REFINE)     */
+  int32_t outer_steps;    /* refinement steps (FP32_REFINE), else 0                           */
+  double rel_residual;    /* |f - L_N u|_2 / |f|_2 in FP64 at return                           */
+  int64_t n;              /* |S^N|                                                             */
+  int64_t nnz;            /* stored neighbour pairs (k, k - w) with both in S^N                */
+  int32_t n_components;   /* independent classes (Sec. 6, proof of Prop. SolutionSupport)      */
+  int32_t status;         /* ss_status of this problem                                         */
+  double t_build_ms;      /* wall time of stamp + operator build (ss_solve only)               */
+  double t_solve_ms;      /* wall time of the iteration                                        */
+} ss_solve_info;
+
+/* ---------------------------------------------------------------- stamp sets
+ * ss_build_stamp_batch -- build S^{level[p]}[a_p](F_p) for n_prob problems of
+ * the same dimension d (Sec. 6, Eq. StampSet; Alg. 1, step 3).
+ *   n_a[p], a_freqs: supp(a_p) as n_a[p] frequencies, all problems
+ *     concatenated (host).  A half list is completed by negation; 0 must be
+ *     present.  Duplicates -> SS_EINVAL.
+ *   n_f[p], f_freqs: F_p = supp(f_p), concatenated (host).  Duplicates within
+ *     a problem -> SS_EINVAL.
+ *   level[p] >= 0: the stamping level N (host).
+ * On success *out owns the keys (canonical order), their levels, |k|^2 and a
+ * device hash index; free with ss_free_stamp.
+ */
+ss_status ss_build_stamp_batch(int32_t n_prob, int32_t d, const int32_t* n_a,
+                               const int16_t* a_freqs, const int32_t* n_f,
+                               const int16_t* f_freqs, const int32_t* level,
+                               void* stream, ss_stamp** out);
+
+/* single-problem form of ss_build_stamp_batch */
+ss_status ss_build_stamp(int32_t d, int32_t n_a, const int16_t* a_freqs, int32_t n_f,
+                         const int16_t* f_freqs, int32_t level, void* stream,
+                         ss_stamp** out);
+
+/* total keys and number of problems; offsets (host, n_prob+1 entries,
+ * nullable) receive each problem's first canonical slot. */
+ss_status ss_stamp_size(const ss_stamp* st, int64_t* n_total, int32_t* n_prob,
+                        int64_t* offsets);
+
+/* copy keys [n_total x d] int16 (host, canonical order) and levels (host,
+ * nullable) out.  Synchronises. */
+ss_status ss_stamp_keys(const ss_stamp* st, int16_t* keys_out, uint8_t* level_out);
+
+/* hash lookup of nq query keys [nq x d] (host) of problem `prob`: slot_out[i]
+ * (host) = canonical slot within that problem, or -1 if absent.  Synchronises. */
+ss_status ss_stamp_lookup(const ss_stamp* st, int32_t prob, int64_t nq,
+                          const int16_t* q, int64_t* slot_out);
+
+void ss_free_stamp(ss_stamp* st);
+
+/* ---------------------------------------------------------------- operator
+ * ss_build_op -- the truncated Galerkin operator L_N on every problem of st
+ * (Sec. 9, Eq. FiniteGalerkinOperator; replaces the dense assembly of Alg. 1,
+ * step 4 by a matrix-free neighbour map).
+ *   n_a, a_freqs, a_hat: the diffusion coefficients, concatenated per
+ *     problem (host; a_hat interleaved complex128).  After completing -w by
+ *     conjugation the support must equal the one st was built with.  Present
+ *     +-w pairs must be conjugate to 1e-14 max|a| (else SS_EINVAL); a_0 must
+ *     be real and positive; unless SS_SKIP_L1_CHECK, a_0 > sum_{w!=0} |a_w|
+ *     (the positivity check after Cor. SpectralConvergenceNoSFT) else SS_ENOTPD.
+ * The operator copies what it needs; st may be freed afterwards.
+ */
+ss_status ss_build_op(const ss_stamp* st, const int32_t* n_a, const int16_t* a_freqs,
+                      const double* a_hat, uint32_t flags, void* stream, ss_op** out);
+
+/* sizes: n_total keys, n_exec rows of the execution layout (>= n_total), nnz,
+ * number of independent classes summed over problems (all nullable). */
+ss_status ss_op_info(const ss_op* op, int64_t* n_total, int64_t* n_exec, int64_t* nnz,
+                     int64_t* n_components);
+
+/* canonical neighbour map (host outputs, synchronises): row_ptr [n_total+1]
+ * (global offsets), cols [nnz] (canonical slot within the row's problem),
+ * js [nnz] (index into the problem's lexicographically sorted a-table),
+ * component [n_total] (smallest canonical slot of the row's class; nullable). */
+ss_status ss_op_csr(const ss_op* op, int64_t* row_ptr, int32_t* cols, int32_t* js,
+                    int32_t* component);
+
+/* execution order (host output, synchronises): exec_to_canon[e] for
+ * e < n_exec is the global canonical slot held in execution row e, or -1 for a
+ * padding row.  Execution order groups rows by problem, then by class. */
+ss_status ss_op_exec_map(const ss_op* op, int64_t* exec_to_canon);
+
+/* y = L_N x for every problem at once (Sec. 9, Eq. FiniteGalerkinOperator).
+ * x_dev, y_dev: device vectors of n_exec entries in execution order,
+ * complex128 for SS_FP64 and complex64 for SS_FP32_REFINE (which applies the
+ * FP32 operator).  Padding entries of y are written as 0.  Asynchronous. */
+ss_status ss_apply(const ss_op* op, ss_precision prec, const void* x_dev, void* y_dev,
+                   void* stream);
+
+/* Solve L_N u = f for every problem of op (Alg. 1, step 5, by PCG).
+ *   f_dev: device, n_total complex128 in canonical order; f at k = 0 must be 0.
+ *   u_dev: device, n_total complex128 in canonical order; in: initial guess
+ *          (zeros for none); out: solution with u_0 = 0.
+ *   tol:   stop when |f - L_N u|_2 <= tol |f|_2 per problem (FP64 residual).
+ *   prec:  SS_FP64 -- FP64 PCG;  SS_FP32_REFINE -- FP32 PCG inside FP64
+ *          iterative refinement (residual and update in FP64).
+ *   max_iter: CG iteration limit per problem (per refinement step for FP32).
+ *   info:  host, n_prob entries (nullable).
+ * Returns SS_ENOCONV if any problem missed tol (u holds its last iterate).
+ * Synchronises the stream. */
+ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double tol,
+                      ss_precision prec, int32_t max_iter, void* stream,
+                      ss_solve_info* info);
+
+void ss_free_op(ss_op* op);
+
+/* ---------------------------------------------------------------- one shot
+ * ss_solve -- Alg. 1 steps 3-5 for one problem from host data.
+ *   a: n_a frequencies/coefficients (exact zeros dropped, -w completed);
+ *   f: n_f frequencies/coefficients (host);
+ *   u_cap: complex entries available in u_hat_out.  u_hat_out == NULL is a
+ *   size query: *n_out = |S^N| and SS_OK.  u_cap < |S^N| -> SS_EINVAL.
+ *   keys_out (nullable): [|S^N| x d] canonical keys.
+ */
+ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double* a_hat,
+                   int32_t n_f, const int16_t* f_freqs, const double* f_hat, int32_t level,
+                   double tol, ss_precision prec, int32_t max_iter, uint32_t flags,
+                   int64_t u_cap, int64_t* n_out, double* u_hat_out, int16_t* keys_out,
+                   ss_solve_info* info);
+
+const char* ss_last_error(void);
+const char* ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPARSESPEC_H */

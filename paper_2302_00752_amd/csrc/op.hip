@@ -1,0 +1,482 @@
+// Operator construction: the neighbour map of the truncated Galerkin operator
+// (Sec. 9, Eq. FiniteGalerkinOperator) and its execution layout.
+//
+// Row k of L_N has an entry for every w_j in supp(a) with k - w_j in S^N
+// (terms with l outside S^N are dropped by the truncation).  The entry value
+// 4 pi^2 (k . (k - w_j)) a_j is never stored: with
+//     k . (k - w) = (|k|^2 + |k - w|^2 - |w|^2) / 2
+// it is rebuilt in the matvec from three exact integer squared norms, so a
+// stored entry is just (column, j) packed in 32 bits and the operator is
+// independent of d once built.
+//
+// Layout.  The canonical CSR (rows and columns in canonical slot order,
+// entries in a-table order) is kept for export.  The matvec runs on a SELL-64
+// layout in an execution order that groups each problem's rows by connected
+// class (the independent blocks of Sec. 6, proof of Prop. SolutionSupport),
+// then by decreasing row length, so a 64-row slice (one wavefront) holds rows
+// of similar length and gathers stay inside one class.  Each problem's rows
+// are padded to a multiple of 64.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "ss_internal.h"
+
+namespace ss {
+
+namespace {
+
+inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
+
+struct NbrArgs {
+  int64_t total;
+  int32_t d;
+  int32_t smax;
+  const int16_t* keys;
+  const uint64_t* hash;
+  const int32_t* pid;
+  const int16_t* akeys;
+  const uint64_t* ahash;
+  const int32_t* aoff;
+  const uint64_t* table;
+  uint64_t mask;
+  int32_t* nbr;        // [total x smax] global canonical column or -1
+  int64_t* rowlen;     // [total]
+};
+
+__global__ void k_neighbors(NbrArgs a) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.total) return;
+  const int p = a.pid[r];
+  const int j0 = a.aoff[p], j1 = a.aoff[p + 1];
+  const int d = a.d;
+  const int16_t* k = a.keys + r * d;
+  int64_t cnt = 0;
+  for (int j = 0; j < a.smax; ++j) {
+    int32_t col = -1;
+    if (j < j1 - j0) {
+      const int16_t* w = a.akeys + (int64_t)(j0 + j) * d;
+      bool zero = true;
+      for (int t = 0; t < d && zero; ++t) zero = w[t] == 0;
+      if (zero) {
+        col = (int32_t)r;
+      } else {
+        const uint64_t h = a.hash[r] - a.ahash[j0 + j];
+        uint64_t pos = fmix64(h) & a.mask;
+        while (true) {
+          const uint64_t v = a.table[pos];
+          if (v == 0) break;
+          const int64_t m = (int64_t)(v & kIdxMask);
+          if (a.hash[m] == h && a.pid[m] == p) {
+            const int16_t* km = a.keys + m * d;
+            bool eq = true;
+            for (int t = 0; t < d && eq; ++t) eq = (int)km[t] == (int)k[t] - (int)w[t];
+            if (eq) {
+              col = (int32_t)m;
+              break;
+            }
+          }
+          pos = (pos + 1) & a.mask;
+        }
+      }
+    }
+    a.nbr[r * a.smax + j] = col;
+    cnt += col >= 0;
+  }
+  a.rowlen[r] = cnt;
+}
+
+__global__ void k_csr_fill(int64_t total, int32_t smax, const int32_t* __restrict__ nbr,
+                           const int64_t* __restrict__ crow, const int32_t* __restrict__ pid,
+                           const int64_t* __restrict__ rowoff, uint32_t* __restrict__ cent) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const int64_t base = rowoff[pid[r]];
+  int64_t q = crow[r];
+  for (int j = 0; j < smax; ++j) {
+    const int32_t c = nbr[r * smax + j];
+    if (c >= 0) cent[q++] = (uint32_t)(c - base) | ((uint32_t)j << kColBits);
+  }
+}
+
+__global__ void k_iota_i64(int64_t n, int64_t* p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+__global__ void k_cc_prop(int64_t total, int32_t smax, const int32_t* __restrict__ nbr, int64_t* label,
+                          int32_t* changed) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const int64_t own = label[r];
+  int64_t l = own;
+  for (int j = 0; j < smax; ++j) {
+    const int32_t c = nbr[r * smax + j];
+    if (c >= 0) {
+      const int64_t lc = label[c];
+      l = lc < l ? lc : l;
+    }
+  }
+  if (l < own) {
+    label[r] = l;
+    *changed = 1;
+  }
+}
+
+__global__ void k_cc_jump(int64_t total, int64_t* label) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  label[r] = label[label[r]];
+}
+
+__global__ void k_cc_finish(int64_t total, const int64_t* __restrict__ label, const int32_t* __restrict__ pid,
+                            const int64_t* __restrict__ rowoff, int32_t* __restrict__ comp,
+                            int32_t* __restrict__ ncomp) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const int p = pid[r];
+  comp[r] = (int32_t)(label[r] - rowoff[p]);
+  if (label[r] == r) atomicAdd(&ncomp[p], 1);
+}
+
+__global__ void k_exec_keys(int64_t total, const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
+                            const int32_t* __restrict__ comp, const int64_t* __restrict__ rowlen,
+                            uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const int p = pid[r];
+  const uint64_t local = (uint64_t)(r - rowoff[p]);
+  key[r] = ((uint64_t)p << 50) | ((uint64_t)comp[r] << 28) | ((uint64_t)(63 - rowlen[r]) << 22) | local;
+  val[r] = (uint32_t)r;
+}
+
+__global__ void k_fill_i64(int64_t n, int64_t* p, int64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, const int32_t* __restrict__ pid,
+                           const int64_t* __restrict__ rowoff, const int64_t* __restrict__ eoff,
+                           int64_t* __restrict__ canon2exec, int64_t* __restrict__ exec2canon) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  const int64_t r = order[q];
+  const int p = pid[r];
+  const int64_t e = eoff[p] + (q - rowoff[p]);
+  canon2exec[r] = e;
+  exec2canon[e] = r;
+}
+
+__global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec2canon,
+                              const int64_t* __restrict__ rowlen, uint32_t* __restrict__ width) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n_slices) return;
+  int64_t w = 0;
+  for (int l = 0; l < kSlice; ++l) {
+    const int64_t r = exec2canon[sl * kSlice + l];
+    if (r >= 0) w = rowlen[r] > w ? rowlen[r] : w;
+  }
+  width[sl] = (uint32_t)(w * kSlice);
+}
+
+template <typename NormT>
+__global__ void k_sell_fill(int64_t n_exec, const int64_t* __restrict__ exec2canon,
+                            const int64_t* __restrict__ canon2exec, const int64_t* __restrict__ rowlen,
+                            const int64_t* __restrict__ crow, const uint32_t* __restrict__ cent,
+                            const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
+                            const int64_t* __restrict__ eoff, const int64_t* __restrict__ norm,
+                            const uint32_t* __restrict__ sptr, uint32_t* __restrict__ sent,
+                            NormT* __restrict__ norm_exec) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_exec) return;
+  const int64_t sl = e / kSlice;
+  const int lane = (int)(e % kSlice);
+  const uint32_t base = sptr[sl];
+  const uint32_t w = (sptr[sl + 1] - base) / kSlice;
+  const int64_t r = exec2canon[e];
+  const uint32_t null_ent = (uint32_t)kNullJ << kColBits;
+  if (r < 0) {
+    for (uint32_t q = 0; q < w; ++q) sent[base + q * kSlice + lane] = null_ent;
+    norm_exec[e] = 0;
+    return;
+  }
+  const int p = pid[r];
+  const int64_t len = rowlen[r];
+  const int64_t c0 = crow[r];
+  for (uint32_t q = 0; q < w; ++q) {
+    uint32_t out = null_ent;
+    if ((int64_t)q < len) {
+      const uint32_t ent = cent[c0 + q];
+      const int64_t cg = rowoff[p] + (ent & kColMask);
+      out = (uint32_t)(canon2exec[cg] - eoff[p]) | (ent & ~kColMask);
+    }
+    sent[base + q * kSlice + lane] = out;
+  }
+  norm_exec[e] = (NormT)norm[r];
+}
+
+}  // namespace
+
+OpDev OpImpl::dev() const {
+  OpDev o;
+  o.sent = d_sent;
+  o.sptr = d_sptr;
+  o.norm = d_norm;
+  o.eoff = d_eoff;
+  o.work = d_work;
+  o.wrange = d_wrange;
+  o.A64 = d_A64;
+  o.A32 = d_A32;
+  o.nu = d_nu;
+  o.a0 = d_a0;
+  o.n_work = (int32_t)work.size();
+  o.n_prob = n_prob;
+  return o;
+}
+
+ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* a_freqs,
+                        const double* a_hat, uint32_t flags, hipStream_t stream, OpImpl** out) {
+  *out = nullptr;
+  if (!st || !n_a || !a_freqs || !a_hat) return fail(SS_EINVAL, "null argument");
+  const int32_t n_prob = st->n_prob, d = st->d;
+  OpImpl* op = new OpImpl();
+  std::unique_ptr<OpImpl, void (*)(OpImpl*)> guard(op, free_op_impl);
+  op->n_prob = n_prob;
+  op->d = d;
+  op->total = st->total;
+  op->row_off = st->row_off;
+  op->wide_norm = st->max_norm >= (int64_t(1) << 30);
+
+  // ---- coefficient tables (host), matched to the stamp's a-tables
+  const double two_pi2 = 2.0 * M_PI * M_PI;
+  std::vector<double2> A64((size_t)n_prob * 64, make_double2(0, 0));
+  std::vector<float2> A32((size_t)n_prob * 64, make_float2(0, 0));
+  std::vector<int64_t> nu((size_t)n_prob * 64, 0);
+  std::vector<double> a0(n_prob);
+  int smax = 1;
+  int64_t pos = 0;
+  for (int p = 0; p < n_prob; ++p) {
+    ATable at;
+    SS_TRY(canonical_a(d, n_a[p], a_freqs + pos * d, a_hat + 2 * pos, false, &at));
+    pos += n_a[p];
+    const int s = st->a_off[p + 1] - st->a_off[p];
+    bool same = (int)at.keys.size() == s;
+    for (int j = 0; same && j < s; ++j)
+      same = std::equal(at.keys[j].begin(), at.keys[j].end(), st->a_keys.begin() + (int64_t)(st->a_off[p] + j) * d);
+    if (!same) return fail(SS_EINVAL, "supp(a) differs from the one the stamping set was built with");
+    smax = std::max(smax, s);
+    double l1 = 0;
+    for (int j = 0; j < s; ++j) {
+      const double2 c = at.coef[j];
+      A64[(size_t)p * 64 + j] = make_double2(two_pi2 * c.x, two_pi2 * c.y);
+      A32[(size_t)p * 64 + j] = make_float2((float)(two_pi2 * c.x), (float)(two_pi2 * c.y));
+      int64_t nn = 0;
+      for (int t = 0; t < d; ++t) nn += (int64_t)at.keys[j][t] * at.keys[j][t];
+      nu[(size_t)p * 64 + j] = nn;
+      if (j != at.zero) l1 += std::hypot(c.x, c.y);
+    }
+    a0[p] = at.coef[at.zero].x;
+    if (!(flags & SS_SKIP_L1_CHECK) && !(l1 < a0[p]))
+      return fail(SS_ENOTPD, "l1 positivity certificate failed: a_0 <= sum |a_w| (pass SS_SKIP_L1_CHECK "
+                             "if a is known to be positive)");
+  }
+
+  const int64_t total = st->total;
+  SS_HIP(hipGetDevice(&op->device));
+  struct Tmp {
+    std::vector<void*> p;
+    ~Tmp() {
+      for (void* q : p)
+        if (q) (void)hipFree(q);
+    }
+  } tmpmem;
+  auto track = [&](void* q) { tmpmem.p.push_back(q); };
+
+  // ---- neighbour map
+  int32_t* nbr = nullptr;
+  int64_t* rowlen = nullptr;
+  SS_TRY(dalloc(&nbr, (size_t)total * smax));
+  track(nbr);
+  SS_TRY(dalloc(&rowlen, total + 1));
+  track(rowlen);
+  NbrArgs na{total, d, smax, st->d_keys, st->d_hash, st->d_pid, st->d_akeys, st->d_ahash, st->d_aoff,
+             st->d_table, st->table_mask, nbr, rowlen};
+  k_neighbors<<<grid_for(total), kBlock, 0, stream>>>(na);
+  SS_TRY(dalloc(&op->d_crow, total + 1));
+  {
+    size_t tb = 0;
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, rowlen, op->d_crow, total + 1, stream));
+    void* t = nullptr;
+    SS_HIP(hipMalloc(&t, tb));
+    track(t);
+    SS_HIP(hipMemsetAsync(rowlen + total, 0, 8, stream));
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, rowlen, op->d_crow, total + 1, stream));
+  }
+  SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  SS_TRY(dalloc(&op->d_cent, op->nnz));
+  k_csr_fill<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, st->d_pid, st->d_rowoff,
+                                                     op->d_cent);
+  // per-problem nnz
+  {
+    std::vector<int64_t> crow_at(n_prob + 1);
+    for (int p = 0; p <= n_prob; ++p)
+      SS_HIP(hipMemcpyAsync(&crow_at[p], op->d_crow + st->row_off[p], 8, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+    op->nnz_p.resize(n_prob);
+    for (int p = 0; p < n_prob; ++p) op->nnz_p[p] = crow_at[p + 1] - crow_at[p];
+  }
+
+  // ---- connected classes: min-label propagation with pointer jumping
+  int64_t* label = nullptr;
+  int32_t* changed = nullptr;
+  int32_t* ncomp = nullptr;
+  SS_TRY(dalloc(&label, total));
+  track(label);
+  SS_TRY(dalloc(&changed, 1));
+  track(changed);
+  SS_TRY(dalloc(&ncomp, n_prob));
+  track(ncomp);
+  k_iota_i64<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+  for (int it = 0; it < 100000; ++it) {
+    int32_t h = 0;
+    SS_HIP(hipMemsetAsync(changed, 0, 4, stream));
+    k_cc_prop<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, label, changed);
+    k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+    k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+    SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+    if (!h) break;
+  }
+  SS_TRY(dalloc(&op->d_comp, total));
+  SS_HIP(hipMemsetAsync(ncomp, 0, n_prob * 4, stream));
+  k_cc_finish<<<grid_for(total), kBlock, 0, stream>>>(total, label, st->d_pid, st->d_rowoff, op->d_comp, ncomp);
+  op->comps.assign(n_prob, 0);
+  SS_HIP(hipMemcpyAsync(op->comps.data(), ncomp, n_prob * 4, hipMemcpyDeviceToHost, stream));
+
+  // ---- execution order: (problem, class, -row length, canonical slot)
+  op->eoff.assign(n_prob + 1, 0);
+  for (int p = 0; p < n_prob; ++p)
+    op->eoff[p + 1] = op->eoff[p] + ceil_div(st->row_off[p + 1] - st->row_off[p], kSlice) * kSlice;
+  op->n_exec = op->eoff[n_prob];
+  op->n_slices = op->n_exec / kSlice;
+  if (op->n_slices * (int64_t)kMaxA * kSlice >= (int64_t(1) << 32))
+    return fail(SS_ERANGE, "batch too large for 32-bit SELL offsets (split it)");
+  SS_TRY(dalloc(&op->d_eoff, n_prob + 1));
+  SS_HIP(hipMemcpyAsync(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, hipMemcpyHostToDevice, stream));
+  uint64_t *ek = nullptr, *ek2 = nullptr;
+  uint32_t *ev = nullptr, *ev2 = nullptr;
+  SS_TRY(dalloc(&ek, total));
+  track(ek);
+  SS_TRY(dalloc(&ek2, total));
+  track(ek2);
+  SS_TRY(dalloc(&ev, total));
+  track(ev);
+  SS_TRY(dalloc(&ev2, total));
+  track(ev2);
+  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff, op->d_comp, rowlen, ek, ev);
+  {
+    size_t tb = 0;
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, 64, stream));
+    void* t = nullptr;
+    SS_HIP(hipMalloc(&t, tb));
+    track(t);
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, ek, ek2, ev, ev2, total, 0, 64, stream));
+  }
+  SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
+  SS_TRY(dalloc(&op->d_canon2exec, total));
+  k_fill_i64<<<grid_for(op->n_exec), kBlock, 0, stream>>>(op->n_exec, op->d_exec2canon, -1);
+  k_exec_map<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, st->d_pid, st->d_rowoff, op->d_eoff,
+                                                      op->d_canon2exec, op->d_exec2canon);
+
+  // ---- SELL-64 slices
+  uint32_t* width = nullptr;
+  SS_TRY(dalloc(&width, op->n_slices + 1));
+  track(width);
+  SS_TRY(dalloc(&op->d_sptr, op->n_slices + 1));
+  k_slice_width<<<grid_for(op->n_slices), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen, width);
+  SS_HIP(hipMemsetAsync(width + op->n_slices, 0, 4, stream));
+  {
+    size_t tb = 0;
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, width, op->d_sptr, op->n_slices + 1, stream));
+    void* t = nullptr;
+    SS_HIP(hipMalloc(&t, tb));
+    track(t);
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, width, op->d_sptr, op->n_slices + 1, stream));
+  }
+  uint32_t n_sell = 0;
+  SS_HIP(hipMemcpyAsync(&n_sell, op->d_sptr + op->n_slices, 4, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  op->n_sell = n_sell;
+  int64_t ncomp_total = 0;
+  for (int p = 0; p < n_prob; ++p) ncomp_total += op->comps[p];
+  op->n_components = ncomp_total;
+  SS_TRY(dalloc(&op->d_sent, std::max<int64_t>(n_sell, 1)));
+  if (op->wide_norm) {
+    int64_t* ne = nullptr;
+    SS_TRY(dalloc(&ne, op->n_exec));
+    op->d_norm = ne;
+    k_sell_fill<int64_t><<<grid_for(op->n_exec), kBlock, 0, stream>>>(
+        op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
+        op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
+  } else {
+    int32_t* ne = nullptr;
+    SS_TRY(dalloc(&ne, op->n_exec));
+    op->d_norm = ne;
+    k_sell_fill<int32_t><<<grid_for(op->n_exec), kBlock, 0, stream>>>(
+        op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
+        op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
+  }
+
+  // ---- work items: up to 4 slices (256 rows) of one problem per block
+  op->wrange.resize(n_prob);
+  for (int p = 0; p < n_prob; ++p) {
+    const int s0 = (int)(op->eoff[p] / kSlice), s1 = (int)(op->eoff[p + 1] / kSlice);
+    op->wrange[p].x = (int)op->work.size();
+    for (int s = s0; s < s1; s += kSlicesPerBlock)
+      op->work.push_back(make_int4(p, s, std::min(kSlicesPerBlock, s1 - s), 0));
+    op->wrange[p].y = (int)op->work.size();
+  }
+  SS_TRY(dalloc(&op->d_work, op->work.size()));
+  SS_TRY(dalloc(&op->d_wrange, n_prob));
+  SS_TRY(dalloc(&op->d_A64, A64.size()));
+  SS_TRY(dalloc(&op->d_A32, A32.size()));
+  SS_TRY(dalloc(&op->d_nu, nu.size()));
+  SS_TRY(dalloc(&op->d_a0, n_prob));
+  SS_HIP(hipMemcpyAsync(op->d_work, op->work.data(), op->work.size() * sizeof(int4), hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(op->d_wrange, op->wrange.data(), n_prob * sizeof(int2), hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(op->d_A64, A64.data(), A64.size() * sizeof(double2), hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(op->d_A32, A32.data(), A32.size() * sizeof(float2), hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(op->d_nu, nu.data(), nu.size() * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(op->d_a0, a0.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  *out = guard.release();
+  return SS_OK;
+}
+
+void free_op_impl(OpImpl* op) {
+  if (!op) return;
+  dfree(op->d_crow);
+  dfree(op->d_cent);
+  dfree(op->d_comp);
+  dfree(op->d_exec2canon);
+  dfree(op->d_canon2exec);
+  dfree(op->d_sent);
+  dfree(op->d_sptr);
+  if (op->d_norm) (void)hipFree(op->d_norm);
+  op->d_norm = nullptr;
+  dfree(op->d_eoff);
+  dfree(op->d_work);
+  dfree(op->d_wrange);
+  dfree(op->d_A64);
+  dfree(op->d_A32);
+  dfree(op->d_nu);
+  dfree(op->d_a0);
+  if (op->ws.base) (void)hipFree(op->ws.base);
+  if (op->h_pinned) (void)hipHostFree(op->h_pinned);
+  delete op;
+}
+
+}  // namespace ss

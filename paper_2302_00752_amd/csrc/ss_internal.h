@@ -1,0 +1,221 @@
+// Internal declarations shared by the sparsespec translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sparsespec.h"
+
+namespace ss {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+ss_status fail(ss_status st, const std::string& msg);
+
+#define SS_HIP(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::ss::fail(e_ == hipErrorOutOfMemory ? SS_ENOMEM : SS_EDEVICE,        \
+                        std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define SS_TRY(expr)                 \
+  do {                               \
+    ss_status s_ = (expr);           \
+    if (s_ != SS_OK) return s_;      \
+  } while (0)
+
+// ------------------------------------------------------------------ limits
+constexpr int kMaxA = 63;             // a-table entries per problem (index 63 = null entry)
+constexpr int kNullJ = 63;
+constexpr int kColBits = 26;          // execution-layout column bits in a packed entry
+constexpr uint32_t kColMask = (1u << kColBits) - 1;
+constexpr int kSlice = 64;            // SELL slice height = wavefront size
+constexpr int kBlock = 256;           // threads per block (4 wavefronts)
+constexpr int kSlicesPerBlock = kBlock / kSlice;
+constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;
+constexpr int kMaxProblems = (1 << 14) - 1;
+
+// hash-slot encoding
+constexpr uint64_t kTagMain = 1ull << 62;
+constexpr uint64_t kTagCand = 2ull << 62;
+constexpr uint64_t kTagMask = 3ull << 62;
+constexpr uint64_t kIdxMask = ~kTagMask;
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+__host__ __device__ inline uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  return x ^ (x >> 31);
+}
+
+// ------------------------------------------------------------------ objects
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// A batch of stamping sets, keys in canonical order.
+struct StampImpl {
+  int device = 0;
+  int32_t d = 0;
+  int32_t n_prob = 0;
+  std::vector<int32_t> level;
+  // canonical a-tables (host): per problem s entries, lexicographic
+  std::vector<int32_t> a_off;          // [n_prob+1] offsets into a_keys (entries)
+  std::vector<int16_t> a_keys;         // [sum s x d]
+  std::vector<int32_t> a_zero;         // index of w = 0 in each problem's table
+  // device: a-tables
+  int16_t* d_akeys = nullptr;          // [sum s x d]
+  uint64_t* d_ahash = nullptr;         // [sum s] linear hash (no problem term)
+  int64_t* d_anorm = nullptr;          // [sum s] |w|^2
+  int32_t* d_aoff = nullptr;           // [n_prob+1]
+  // keys, canonical order, grouped by problem
+  int64_t total = 0;
+  std::vector<int64_t> row_off;        // [n_prob+1]
+  int16_t* d_keys = nullptr;           // [total x d]
+  uint8_t* d_lev = nullptr;            // [total]
+  int64_t* d_norm = nullptr;           // [total] |k|^2
+  uint64_t* d_hash = nullptr;          // [total] linear hash incl. problem term
+  int32_t* d_pid = nullptr;            // [total]
+  int64_t* d_rowoff = nullptr;         // [n_prob+1]
+  uint64_t* d_coef = nullptr;          // [d] hash multipliers
+  uint64_t* d_table = nullptr;         // hash table: MAIN | canonical index
+  uint64_t table_mask = 0;
+  int64_t max_norm = 0;
+};
+
+// Per-problem solver scalars (device).
+struct PState {
+  double rho[2];      // <r, z> at the current / next iteration (parity-indexed)
+  double ff;          // |f|^2 of the current right-hand side
+  double rr;          // |r|^2 of the current residual
+  double scale;       // refinement: |r64| used to normalise the FP32 right-hand side
+  double rr0;         // |r|^2 at the start of the current CG run
+  int32_t iters;
+  int32_t done;
+  int32_t status;
+  int32_t total_iters;
+};
+
+// Plain-old-data view of an operator passed to kernels by value.
+struct OpDev {
+  const uint32_t* sent;      // SELL entries: local exec column | j << 26
+  const uint32_t* sptr;      // [n_slices+1] entry offset of each slice
+  const void* norm;          // [n_exec] |k|^2 per exec row (int32 or int64)
+  const int64_t* eoff;       // [n_prob+1] first exec row of each problem
+  const int4* work;          // [n_work] {problem, first slice, slices, 0}
+  const int2* wrange;        // [n_prob] {first work item, end work item}
+  const double2* A64;        // [n_prob x 64] 2 pi^2 a_j (index 63 = 0)
+  const float2* A32;         // [n_prob x 64]
+  const int64_t* nu;         // [n_prob x 64] |w_j|^2
+  const double* a0;          // [n_prob] a_0 (real)
+  int32_t n_work;
+  int32_t n_prob;
+};
+
+struct OpImpl {
+  int device = 0;
+  int32_t n_prob = 0;
+  int32_t d = 0;
+  int64_t total = 0;                   // canonical rows
+  int64_t n_exec = 0;                  // padded execution rows
+  int64_t nnz = 0;
+  int64_t n_components = 0;
+  int64_t n_slices = 0;
+  int64_t n_sell = 0;                  // stored SELL entries (incl. padding)
+  bool wide_norm = false;              // |k|^2 needs int64
+  std::vector<int64_t> row_off;        // canonical offsets [n_prob+1]
+  std::vector<int64_t> eoff;           // exec offsets [n_prob+1]
+  std::vector<int32_t> comps;          // classes per problem
+  std::vector<int64_t> nnz_p;          // per problem
+  std::vector<int4> work;
+  std::vector<int2> wrange;
+  // canonical CSR (kept for export and tests)
+  int64_t* d_crow = nullptr;           // [total+1]
+  uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << 26
+  int32_t* d_comp = nullptr;           // [total] local label
+  // execution layout
+  int64_t* d_exec2canon = nullptr;     // [n_exec] global canonical or -1
+  int64_t* d_canon2exec = nullptr;     // [total]
+  uint32_t* d_sent = nullptr;
+  uint32_t* d_sptr = nullptr;
+  void* d_norm = nullptr;
+  int64_t* d_eoff = nullptr;
+  int4* d_work = nullptr;
+  int2* d_wrange = nullptr;
+  double2* d_A64 = nullptr;
+  float2* d_A32 = nullptr;
+  int64_t* d_nu = nullptr;
+  double* d_a0 = nullptr;
+  // solver workspace (lazily allocated, reused)
+  struct Work {
+    size_t bytes = 0;
+    void* base = nullptr;
+  } ws;
+  int* h_pinned = nullptr;             // pinned host word for convergence polling
+  OpDev dev() const;
+};
+
+// ------------------------------------------------------------------ entry points (internal)
+ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
+                           const int32_t* n_f, const int16_t* f_freqs, const int32_t* level,
+                           hipStream_t stream, StampImpl** out);
+void free_stamp_impl(StampImpl* st);
+ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const int16_t* q,
+                            int64_t* slot_out, hipStream_t stream);
+
+ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* a_freqs,
+                        const double* a_hat, uint32_t flags, hipStream_t stream, OpImpl** out);
+void free_op_impl(OpImpl* op);
+
+ss_status apply_impl(const OpImpl* op, ss_precision prec, const void* x, void* y,
+                     hipStream_t stream);
+ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
+                        int32_t max_iter, hipStream_t stream, ss_solve_info* info);
+
+// host-side canonicalisation of a-support (shared by stamp and op builders)
+struct ATable {
+  std::vector<std::vector<int16_t>> keys;   // lexicographic
+  std::vector<double2> coef;                // may be empty (support only)
+  int zero = -1;
+};
+ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
+                      bool drop_zero_coef, ATable* out);
+
+// device memory helpers
+template <typename T>
+ss_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EDEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return SS_OK;
+}
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace ss

@@ -1,0 +1,721 @@
+// Stamping-set construction on the GPU (Sec. 6, Eq. StampSet; Alg. 1, step 3).
+//
+// S^0 = F and S^n = S^{n-1} + supp(a).  Because 0 is in supp(a), S^{n-1} is
+// contained in S^n, and every key of S^n \ S^{n-1} is k + w for a key k of
+// level n-1 (the frontier) and a nonzero w.  So each level only expands the
+// frontier: every (frontier key, w) pair is a candidate, candidates are
+// deduplicated through an open-addressing hash table, and the survivors are
+// appended as the next frontier.  Among equal candidates the one with the
+// smallest (frontier index, w index) wins, so the append order -- and with it
+// everything downstream -- is deterministic.
+//
+// The hash of a key is linear in its coordinates, h(k) = sum_t k_t Z_t
+// (mod 2^64), so h(k + w) = h(k) + h(w): a candidate's hash costs one add and
+// a neighbour lookup h(k - w) one subtract.  Keys are always verified
+// coordinate by coordinate after a hash match.
+//
+// After the last level, keys are put in canonical order (per problem,
+// ascending lexicographic, coordinate 0 most significant) by an LSD radix
+// sort that packs four biased int16 coordinates per 64-bit pass and skips
+// coordinates that are constant over the whole batch, then a final pass on
+// the problem id.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <set>
+
+#include "ss_internal.h"
+
+namespace ss {
+
+namespace {
+
+std::vector<uint64_t> hash_coefs(int d) {
+  std::vector<uint64_t> z(d + 1);
+  for (int t = 0; t <= d; ++t) z[t] = splitmix64(0x5eed0000ULL + (uint64_t)t * 7919u) | 1ull;
+  return z;   // z[d] multiplies the problem id
+}
+
+__device__ inline uint64_t atomic_load_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline bool eq_shift(const int16_t* a, const int16_t* b, const int16_t* w, int d) {
+  for (int t = 0; t < d; ++t)
+    if ((int)a[t] != (int)b[t] + (int)w[t]) return false;
+  return true;
+}
+
+__device__ inline bool eq_shift2(const int16_t* b1, const int16_t* w1, const int16_t* b2,
+                                 const int16_t* w2, int d) {
+  for (int t = 0; t < d; ++t)
+    if ((int)b1[t] + (int)w1[t] != (int)b2[t] + (int)w2[t]) return false;
+  return true;
+}
+
+__global__ void k_hash_keys(int64_t n, int d, const int16_t* __restrict__ keys,
+                            const int32_t* __restrict__ pid, const uint64_t* __restrict__ z,
+                            uint64_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t h = (uint64_t)(int64_t)pid[i] * z[d];
+  const int16_t* k = keys + i * d;
+  for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
+  out[i] = h;
+}
+
+__global__ void k_insert_main(int64_t n0, int64_t n, const uint64_t* __restrict__ hash,
+                              uint64_t* table, uint64_t mask) {
+  int64_t i = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t pos = fmix64(hash[i]) & mask;
+  while (true) {
+    unsigned long long old =
+        atomicCAS((unsigned long long*)&table[pos], 0ull, (unsigned long long)(kTagMain | (uint64_t)i));
+    if (old == 0ull) return;
+    pos = (pos + 1) & mask;
+  }
+}
+
+struct ExpandArgs {
+  int64_t n_cand;         // frontier size * smax1
+  int64_t f0;             // first frontier key
+  int32_t smax1;          // max nonzero w per problem
+  int32_t d;
+  const int16_t* keys;    // unsorted keys
+  const uint64_t* hash;
+  const int32_t* pid;
+  const int16_t* wkeys;   // nonzero a-support, concatenated per problem
+  const uint64_t* whash;
+  const int32_t* woff;    // [n_prob+1]
+  const int32_t* plevel;  // [n_prob] stamping level of each problem
+  int32_t level;          // level being built
+  uint64_t* table;
+  uint64_t mask;
+  uint32_t* cpos;         // [n_cand] slot of the candidate's key, or kNoSlot
+  int32_t* err;
+};
+
+__global__ void k_expand(ExpandArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_cand) return;
+  const int64_t i = a.f0 + t / a.smax1;
+  const int j = (int)(t % a.smax1);
+  const int p = a.pid[i];
+  const int wo = a.woff[p];
+  if (j >= a.woff[p + 1] - wo || a.plevel[p] < a.level) {
+    a.cpos[t] = kNoSlot;
+    return;
+  }
+  const int d = a.d;
+  const int16_t* k = a.keys + i * d;
+  const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
+  for (int c = 0; c < d; ++c) {
+    int v = (int)k[c] + (int)w[c];
+    if (v < -32768 || v > 32767) {
+      atomicOr(a.err, 1);
+      a.cpos[t] = kNoSlot;
+      return;
+    }
+  }
+  const uint64_t h = a.hash[i] + a.whash[wo + j];
+  const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)j;
+  uint64_t pos = fmix64(h) & a.mask;
+  while (true) {
+    uint64_t v = atomic_load_u64(&a.table[pos]);
+    if (v == 0) {
+      unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos], 0ull,
+                                         (unsigned long long)my);
+      if (old == 0ull) {
+        a.cpos[t] = (uint32_t)pos;
+        return;
+      }
+      v = old;
+    }
+    if ((v & kTagMask) == kTagMain) {
+      const int64_t m = (int64_t)(v & kIdxMask);
+      if (a.hash[m] == h && a.pid[m] == p && eq_shift(a.keys + m * d, k, w, d)) {
+        a.cpos[t] = kNoSlot;   // already in an earlier level
+        return;
+      }
+    } else {
+      const int64_t i2 = (int64_t)((v & kIdxMask) >> 6);
+      const int j2 = (int)(v & 63);
+      const int p2 = a.pid[i2];
+      const int wo2 = a.woff[p2];
+      const uint64_t h2 = a.hash[i2] + a.whash[wo2 + j2];
+      if (h2 == h && p2 == p &&
+          eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo2 + j2) * d, k, w, d)) {
+        // equal key found among this level's candidates: the smallest candidate keeps the slot
+        while (my < v) {
+          unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos],
+                                             (unsigned long long)v, (unsigned long long)my);
+          if (old == (unsigned long long)v) break;
+          v = old;
+        }
+        a.cpos[t] = (uint32_t)pos;
+        return;
+      }
+    }
+    pos = (pos + 1) & a.mask;
+  }
+}
+
+__global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint32_t* __restrict__ cpos,
+                          const uint64_t* __restrict__ table, uint32_t* __restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cand) return;
+  uint32_t f = 0;
+  if (cpos[t] != kNoSlot) {
+    const int64_t i = f0 + t / smax1;
+    const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)(t % smax1);
+    f = table[cpos[t]] == my ? 1u : 0u;
+  }
+  flag[t] = f;
+}
+
+__global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag,
+                         const uint32_t* __restrict__ idx, int64_t base, int level,
+                         int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_cand || !flag[t]) return;
+  const int64_t i = a.f0 + t / a.smax1;
+  const int j = (int)(t % a.smax1);
+  const int p = a.pid[i];
+  const int wo = a.woff[p];
+  const int d = a.d;
+  const int64_t m = base + idx[t];
+  const int16_t* k = a.keys + i * d;
+  const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
+  int16_t* o = keys_out + m * d;
+  for (int c = 0; c < d; ++c) o[c] = (int16_t)((int)k[c] + (int)w[c]);
+  hash_out[m] = a.hash[i] + a.whash[wo + j];
+  pid_out[m] = p;
+  lev_out[m] = (uint8_t)level;
+  a.table[a.cpos[t]] = kTagMain | (uint64_t)m;
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t* p, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_minmax(int64_t n, int d, const int16_t* __restrict__ keys, int32_t* mn, int32_t* mx) {
+  // thread g scans coordinate g % d of a chunk of 1024 keys, then one atomic pair
+  constexpr int64_t kChunk = 1024;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)(g % d);
+  const int64_t k0 = (g / d) * kChunk;
+  if (k0 >= n) return;
+  const int64_t k1 = k0 + kChunk < n ? k0 + kChunk : n;
+  int lo = 32767, hi = -32768;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int v = keys[k * d + c];
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  atomicMin(&mn[c], lo);
+  atomicMax(&mx[c], hi);
+}
+
+struct Dims4 {
+  int t[4];
+  int n;
+};
+
+__global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys,
+                         const uint32_t* __restrict__ perm, Dims4 dims, uint64_t* __restrict__ out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int16_t* k = keys + (int64_t)perm[r] * d;
+  uint64_t v = 0;
+  for (int q = 0; q < dims.n; ++q) v = (v << 16) | (uint64_t)((uint16_t)k[dims.t[q]] ^ 0x8000u);
+  out[r] = v;
+}
+
+__global__ void k_pid_digits(int64_t n, const int32_t* __restrict__ pid, const uint32_t* __restrict__ perm,
+                             uint32_t* __restrict__ out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = (uint32_t)pid[perm[r]];
+}
+
+__global__ void k_iota_u32(int64_t n, uint32_t* p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+__global__ void k_permute_out(int64_t n, int d, const uint32_t* __restrict__ perm,
+                              const int16_t* __restrict__ ukeys, const uint64_t* __restrict__ uhash,
+                              const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
+                              int16_t* keys, uint64_t* hash, int32_t* pid, uint8_t* lev, int64_t* norm,
+                              uint32_t* inv) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t s = perm[r];
+  const int16_t* k = ukeys + s * d;
+  int16_t* o = keys + r * d;
+  int64_t nn = 0;
+  for (int c = 0; c < d; ++c) {
+    const int v = k[c];
+    o[c] = (int16_t)v;
+    nn += (int64_t)v * v;
+  }
+  hash[r] = uhash[s];
+  pid[r] = upid[s];
+  lev[r] = ulev[s];
+  norm[r] = nn;
+  inv[s] = (uint32_t)r;
+}
+
+__global__ void k_remap_table(uint64_t cap, uint64_t* table, const uint32_t* __restrict__ inv) {
+  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cap) return;
+  const uint64_t v = table[s];
+  if ((v & kTagMask) == kTagMain) table[s] = kTagMain | (uint64_t)inv[v & kIdxMask];
+}
+
+__global__ void k_rowoff(int64_t n, const int32_t* __restrict__ pid, int64_t* rowoff) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  if (r == 0 || pid[r] != pid[r - 1]) rowoff[pid[r]] = r;
+}
+
+__global__ void k_max_norm(int64_t n, const int64_t* __restrict__ norm, unsigned long long* out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) atomicMax(out, (unsigned long long)norm[r]);
+}
+
+__global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32_t prob,
+                         const uint64_t* __restrict__ z, const int16_t* __restrict__ keys,
+                         const uint64_t* __restrict__ hash, const int32_t* __restrict__ pid,
+                         const uint64_t* __restrict__ table, uint64_t mask, const int64_t* rowoff,
+                         int64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int16_t* k = q + i * d;
+  uint64_t h = (uint64_t)(int64_t)prob * z[d];
+  for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
+  uint64_t pos = fmix64(h) & mask;
+  int64_t res = -1;
+  while (true) {
+    const uint64_t v = table[pos];
+    if (v == 0) break;
+    const int64_t m = (int64_t)(v & kIdxMask);
+    if (hash[m] == h && pid[m] == prob) {
+      bool eq = true;
+      for (int t = 0; t < d && eq; ++t) eq = keys[m * d + t] == k[t];
+      if (eq) {
+        res = m - rowoff[prob];
+        break;
+      }
+    }
+    pos = (pos + 1) & mask;
+  }
+  out[i] = res;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
+
+template <typename T>
+ss_status grow(T** p, int64_t* cap, int64_t need, int64_t keep, int mult, hipStream_t stream) {
+  if (need <= *cap) return SS_OK;
+  int64_t ncap = std::max<int64_t>(need, *cap * 2);
+  T* q = nullptr;
+  SS_TRY(dalloc(&q, (size_t)ncap * mult));
+  if (keep > 0 && *p) SS_HIP(hipMemcpyAsync(q, *p, (size_t)keep * mult * sizeof(T), hipMemcpyDeviceToDevice, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  dfree(*p);
+  *p = q;
+  *cap = ncap;
+  return SS_OK;
+}
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- canonical a
+ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
+                      bool drop_zero_coef, ATable* out) {
+  if (n_a <= 0 || !freqs) return fail(SS_EINVAL, "supp(a) must be a non-empty list");
+  std::map<std::vector<int16_t>, double2> table;
+  double scale = 0;
+  for (int32_t i = 0; i < n_a; ++i) {
+    std::vector<int16_t> w(freqs + (int64_t)i * d, freqs + (int64_t)(i + 1) * d);
+    double2 c = coef ? make_double2(coef[2 * i], coef[2 * i + 1]) : make_double2(1.0, 0.0);
+    if (!std::isfinite(c.x) || !std::isfinite(c.y)) return fail(SS_EINVAL, "a_hat is not finite");
+    if (!table.emplace(w, c).second) return fail(SS_EINVAL, "duplicate frequency in supp(a)");
+    scale = std::max(scale, std::hypot(c.x, c.y));
+  }
+  std::vector<std::pair<std::vector<int16_t>, double2>> add;
+  for (auto& kv : table) {
+    std::vector<int16_t> nw(d);
+    for (int t = 0; t < d; ++t) {
+      if (kv.first[t] == -32768) return fail(SS_ERANGE, "a frequency coordinate -32768 has no int16 negation");
+      nw[t] = (int16_t)(-kv.first[t]);
+    }
+    auto it = table.find(nw);
+    double2 cj = make_double2(kv.second.x, -kv.second.y);
+    if (it == table.end()) {
+      add.emplace_back(nw, cj);
+    } else if (coef && std::hypot(it->second.x - cj.x, it->second.y - cj.y) > 1e-14 * scale) {
+      return fail(SS_EINVAL, "coefficients at w and -w are not complex conjugates (a must be real)");
+    }
+  }
+  for (auto& kv : add) table.emplace(kv.first, kv.second);
+  std::vector<int16_t> zero(d, 0);
+  auto z = table.find(zero);
+  if (z == table.end()) return fail(SS_EINVAL, "0 must be in supp(a) (a_0 > 0 for a positive coefficient)");
+  if (coef) {
+    if (std::fabs(z->second.y) > 1e-14 * scale || z->second.x <= 0)
+      return fail(SS_EINVAL, "a_0 must be real and positive");
+    z->second.y = 0;
+  }
+  out->keys.clear();
+  out->coef.clear();
+  out->zero = -1;
+  for (auto& kv : table) {
+    const bool is_zero = kv.first == zero;
+    if (coef && drop_zero_coef && !is_zero && kv.second.x == 0 && kv.second.y == 0) continue;
+    if (is_zero) out->zero = (int)out->keys.size();
+    out->keys.push_back(kv.first);
+    out->coef.push_back(kv.second);
+  }
+  if ((int)out->keys.size() > kMaxA)
+    return fail(SS_ERANGE, "|supp(a)| after closing under negation exceeds 63");
+  return SS_OK;
+}
+
+// ---------------------------------------------------------------- build
+namespace {
+
+// Owns scratch device allocations of one build; frees them on every exit path.
+struct Scratch {
+  std::vector<void**> slots;
+  template <typename T>
+  T*& hold(T*& p) {
+    slots.push_back((void**)&p);
+    return p;
+  }
+  ~Scratch() {
+    for (void** s : slots)
+      if (*s) {
+        (void)hipFree(*s);
+        *s = nullptr;
+      }
+  }
+};
+
+}  // namespace
+
+ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
+                           const int32_t* n_f, const int16_t* f_freqs, const int32_t* level,
+                           hipStream_t stream, StampImpl** out) {
+  *out = nullptr;
+  if (n_prob < 1 || n_prob > kMaxProblems) return fail(SS_EINVAL, "n_prob must be in [1, 16383]");
+  if (d < 1 || d > 1024) return fail(SS_EINVAL, "d must be in [1, 1024]");
+  if (!n_a || !a_freqs || !n_f || !f_freqs || !level) return fail(SS_EINVAL, "null argument");
+  StampImpl* st = new StampImpl();
+  std::unique_ptr<StampImpl, void (*)(StampImpl*)> guard(st, free_stamp_impl);
+  st->d = d;
+  st->n_prob = n_prob;
+  st->level.assign(level, level + n_prob);
+  st->a_off.assign(n_prob + 1, 0);
+
+  // ---- host: canonical a-tables, validation
+  const std::vector<uint64_t> z = hash_coefs(d);
+  std::vector<int16_t> wkeys;
+  std::vector<uint64_t> ahash, whash;
+  std::vector<int64_t> anorm;
+  std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0);
+  int max_level = 0, smax1 = 1;
+  int64_t a_pos = 0;
+  for (int p = 0; p < n_prob; ++p) {
+    if (level[p] < 0 || level[p] > 255) return fail(SS_EINVAL, "level must be in [0, 255]");
+    if (n_a[p] < 1) return fail(SS_EINVAL, "every problem needs a non-empty supp(a)");
+    if (n_f[p] < 1) return fail(SS_EINVAL, "every problem needs at least one forcing frequency");
+    max_level = std::max(max_level, level[p]);
+    ATable at;
+    SS_TRY(canonical_a(d, n_a[p], a_freqs + a_pos * d, nullptr, false, &at));
+    a_pos += n_a[p];
+    st->a_zero.push_back(at.zero);
+    for (size_t j = 0; j < at.keys.size(); ++j) {
+      st->a_keys.insert(st->a_keys.end(), at.keys[j].begin(), at.keys[j].end());
+      uint64_t h = 0;
+      int64_t nn = 0;
+      for (int t = 0; t < d; ++t) {
+        h += (uint64_t)(int64_t)at.keys[j][t] * z[t];
+        nn += (int64_t)at.keys[j][t] * at.keys[j][t];
+      }
+      ahash.push_back(h);
+      anorm.push_back(nn);
+      if ((int)j != at.zero) {
+        wkeys.insert(wkeys.end(), at.keys[j].begin(), at.keys[j].end());
+        whash.push_back(h);
+      }
+    }
+    st->a_off[p + 1] = st->a_off[p] + (int32_t)at.keys.size();
+    woff[p + 1] = woff[p] + (int32_t)at.keys.size() - 1;
+    smax1 = std::max<int>(smax1, (int)at.keys.size() - 1);
+    f_off[p + 1] = f_off[p] + n_f[p];
+    std::set<std::vector<int16_t>> fs;
+    for (int i = f_off[p]; i < f_off[p + 1]; ++i)
+      if (!fs.emplace(f_freqs + (int64_t)i * d, f_freqs + (int64_t)(i + 1) * d).second)
+        return fail(SS_EINVAL, "duplicate forcing frequency within a problem");
+  }
+  const int64_t nF = f_off[n_prob];
+  SS_HIP(hipGetDevice(&st->device));
+
+  // ---- device a-tables (kept by the stamp)
+  SS_TRY(dalloc(&st->d_akeys, st->a_keys.size()));
+  SS_TRY(dalloc(&st->d_ahash, ahash.size()));
+  SS_TRY(dalloc(&st->d_anorm, anorm.size()));
+  SS_TRY(dalloc(&st->d_aoff, n_prob + 1));
+  SS_TRY(dalloc(&st->d_coef, d + 1));
+  SS_HIP(hipMemcpyAsync(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_ahash, ahash.data(), ahash.size() * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_anorm, anorm.data(), anorm.size() * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_aoff, st->a_off.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_coef, z.data(), (d + 1) * 8, hipMemcpyHostToDevice, stream));
+
+  // ---- build scratch
+  Scratch sc;
+  int16_t* wk = nullptr;
+  uint64_t* wh = nullptr;
+  int32_t *wo = nullptr, *plev = nullptr, *err = nullptr, *fpid_d = nullptr;
+  int16_t* ukeys = nullptr;
+  uint64_t* uhash = nullptr;
+  int32_t* upid = nullptr;
+  uint8_t* ulev = nullptr;
+  uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
+  void* tmp = nullptr;
+  sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev); sc.hold(err); sc.hold(fpid_d);
+  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev);
+  sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
+  SS_TRY(dalloc(&wk, wkeys.size()));
+  SS_TRY(dalloc(&wh, whash.size()));
+  SS_TRY(dalloc(&wo, n_prob + 1));
+  SS_TRY(dalloc(&plev, n_prob));
+  SS_TRY(dalloc(&err, 1));
+  if (!wkeys.empty()) SS_HIP(hipMemcpyAsync(wk, wkeys.data(), wkeys.size() * 2, hipMemcpyHostToDevice, stream));
+  if (!whash.empty()) SS_HIP(hipMemcpyAsync(wh, whash.data(), whash.size() * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(wo, woff.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(plev, level, n_prob * 4, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemsetAsync(err, 0, 4, stream));
+
+  // ---- level 0: F
+  int64_t kcap = std::max<int64_t>(nF * 4, 1024);
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap;
+  SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
+  SS_TRY(dalloc(&uhash, kcap));
+  SS_TRY(dalloc(&upid, kcap));
+  SS_TRY(dalloc(&ulev, kcap));
+  {
+    std::vector<int32_t> fpid(nF);
+    for (int p = 0; p < n_prob; ++p)
+      for (int i = f_off[p]; i < f_off[p + 1]; ++i) fpid[i] = p;
+    SS_HIP(hipMemcpyAsync(ukeys, f_freqs, (size_t)nF * d * 2, hipMemcpyHostToDevice, stream));
+    SS_HIP(hipMemcpyAsync(upid, fpid.data(), nF * 4, hipMemcpyHostToDevice, stream));
+    SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
+    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, upid, st->d_coef, uhash);
+    SS_HIP(hipStreamSynchronize(stream));   // fpid is a host temporary
+  }
+  uint64_t tcap = next_pow2((uint64_t)std::max<int64_t>(2 * nF, 1024));
+  SS_TRY(dalloc(&st->d_table, tcap));
+  SS_HIP(hipMemsetAsync(st->d_table, 0, tcap * 8, stream));
+  k_insert_main<<<grid_for(nF), kBlock, 0, stream>>>(0, nF, uhash, st->d_table, tcap - 1);
+
+  // ---- levels 1..N: expand the frontier
+  int64_t total = nF, f0 = 0, f1 = nF, ccap = 0;
+  size_t tmp_bytes = 0;
+  for (int n = 1; n <= max_level; ++n) {
+    const int64_t n_front = f1 - f0;
+    if (n_front == 0) break;
+    const int64_t n_cand = n_front * smax1;
+    const int64_t need = total + n_cand;       // worst case: every candidate is new
+    if (need > (int64_t(1) << 31)) return fail(SS_ERANGE, "stamping sets exceed 2^31 keys in one batch");
+    SS_TRY(grow(&ukeys, &kcap, need, total, d, stream));
+    SS_TRY(grow(&uhash, &kcap_h, need, total, 1, stream));
+    SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
+    SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
+    if ((uint64_t)need * 2 > tcap) {
+      tcap = next_pow2((uint64_t)need * 2);
+      dfree(st->d_table);
+      SS_TRY(dalloc(&st->d_table, tcap));
+      SS_HIP(hipMemsetAsync(st->d_table, 0, tcap * 8, stream));
+      k_insert_main<<<grid_for(total), kBlock, 0, stream>>>(0, total, uhash, st->d_table, tcap - 1);
+    }
+    if (n_cand > ccap) {
+      dfree(cpos);
+      dfree(flag);
+      dfree(idx);
+      ccap = n_cand;
+      SS_TRY(dalloc(&cpos, ccap));
+      SS_TRY(dalloc(&flag, ccap));
+      SS_TRY(dalloc(&idx, ccap));
+    }
+    ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_table, tcap - 1, cpos, err};
+    k_expand<<<grid_for(n_cand), kBlock, 0, stream>>>(ea);
+    k_winners<<<grid_for(n_cand), kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, st->d_table, flag);
+    size_t need_tmp = 0;
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
+    if (need_tmp > tmp_bytes) {
+      dfree(tmp);
+      SS_HIP(hipMalloc(&tmp, need_tmp));
+      tmp_bytes = need_tmp;
+    }
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
+    k_append<<<grid_for(n_cand), kBlock, 0, stream>>>(ea, flag, idx, total, n, ukeys, uhash, upid, ulev);
+    uint32_t last[2] = {0, 0};
+    int32_t herr = 0;
+    SS_HIP(hipMemcpyAsync(&last[0], idx + n_cand - 1, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipMemcpyAsync(&last[1], flag + n_cand - 1, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+    if (herr) return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
+    f0 = total;
+    total += (int64_t)last[0] + last[1];
+    f1 = total;
+  }
+  dfree(cpos);
+  dfree(flag);
+  dfree(idx);
+  dfree(tmp);
+  tmp_bytes = 0;
+
+  // ---- canonical order: LSD radix sort over coordinates, then problem id
+  st->total = total;
+  std::vector<int32_t> mn(d, 32767), mx(d, -32768);
+  int32_t *d_mn = nullptr, *d_mx = nullptr;
+  sc.hold(d_mn); sc.hold(d_mx);
+  SS_TRY(dalloc(&d_mn, d));
+  SS_TRY(dalloc(&d_mx, d));
+  SS_HIP(hipMemcpyAsync(d_mn, mn.data(), d * 4, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(d_mx, mx.data(), d * 4, hipMemcpyHostToDevice, stream));
+  k_minmax<<<grid_for(ceil_div(total, 1024) * d), kBlock, 0, stream>>>(total, d, ukeys, d_mn, d_mx);
+  SS_HIP(hipMemcpyAsync(mn.data(), d_mn, d * 4, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipMemcpyAsync(mx.data(), d_mx, d * 4, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  std::vector<int> active;
+  for (int t = 0; t < d; ++t)
+    if (mn[t] != mx[t]) active.push_back(t);
+
+  uint32_t *perm = nullptr, *perm2 = nullptr;
+  uint64_t *k64 = nullptr, *k64b = nullptr;
+  sc.hold(perm); sc.hold(perm2); sc.hold(k64); sc.hold(k64b);
+  SS_TRY(dalloc(&perm, total));
+  SS_TRY(dalloc(&perm2, total));
+  SS_TRY(dalloc(&k64, total));
+  SS_TRY(dalloc(&k64b, total));
+  k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
+  {
+    size_t t64 = 0, t32 = 0;
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, t64, k64, k64b, perm, perm2, total, 0, 64, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, t32, (uint32_t*)k64, (uint32_t*)k64b, perm, perm2,
+                                              total, 0, 32, stream));
+    tmp_bytes = std::max(t64, t32);
+    SS_HIP(hipMalloc(&tmp, tmp_bytes));
+  }
+  for (int end = (int)active.size(); end > 0; end -= 4) {
+    const int beg = std::max(0, end - 4);
+    Dims4 dm{};
+    dm.n = end - beg;
+    for (int q = 0; q < dm.n; ++q) dm.t[q] = active[beg + q];
+    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, perm, dm, k64);
+    size_t tb = tmp_bytes;
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, 16 * dm.n, stream));
+    std::swap(perm, perm2);
+  }
+  if (n_prob > 1) {
+    int bits = 1;
+    while ((1 << bits) < n_prob) ++bits;
+    k_pid_digits<<<grid_for(total), kBlock, 0, stream>>>(total, upid, perm, (uint32_t*)k64);
+    size_t tb = tmp_bytes;
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, (uint32_t*)k64, (uint32_t*)k64b, perm, perm2, total, 0,
+                                              bits, stream));
+    std::swap(perm, perm2);
+  }
+
+  // ---- final arrays in canonical order; re-point the hash table at them
+  SS_TRY(dalloc(&st->d_keys, (size_t)total * d));
+  SS_TRY(dalloc(&st->d_hash, total));
+  SS_TRY(dalloc(&st->d_pid, total));
+  SS_TRY(dalloc(&st->d_lev, total));
+  SS_TRY(dalloc(&st->d_norm, total));
+  SS_TRY(dalloc(&st->d_rowoff, n_prob + 1));
+  uint32_t* inv = perm2;
+  k_permute_out<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, uhash, upid, ulev, st->d_keys,
+                                                        st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv);
+  k_remap_table<<<(unsigned)ceil_div((int64_t)tcap, kBlock), kBlock, 0, stream>>>(tcap, st->d_table, inv);
+  st->table_mask = tcap - 1;
+  k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff);
+  unsigned long long* d_maxn = (unsigned long long*)k64;
+  SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
+  k_max_norm<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_norm, d_maxn);
+  unsigned long long maxn = 0;
+  st->row_off.assign(n_prob + 1, 0);
+  SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, n_prob * 8, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  st->row_off[n_prob] = total;
+  SS_HIP(hipMemcpyAsync(st->d_rowoff + n_prob, &st->row_off[n_prob], 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipStreamSynchronize(stream));
+  st->max_norm = (int64_t)maxn;
+  for (int p = 0; p < n_prob; ++p)
+    if (st->row_off[p + 1] - st->row_off[p] > kMaxRowsPerProblem)
+      return fail(SS_ERANGE, "a stamping set exceeds 4194303 keys");
+  *out = guard.release();
+  return SS_OK;
+}
+
+void free_stamp_impl(StampImpl* st) {
+  if (!st) return;
+  dfree(st->d_akeys);
+  dfree(st->d_ahash);
+  dfree(st->d_anorm);
+  dfree(st->d_aoff);
+  dfree(st->d_keys);
+  dfree(st->d_lev);
+  dfree(st->d_norm);
+  dfree(st->d_hash);
+  dfree(st->d_pid);
+  dfree(st->d_rowoff);
+  dfree(st->d_coef);
+  dfree(st->d_table);
+  delete st;
+}
+
+ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const int16_t* q,
+                            int64_t* slot_out, hipStream_t stream) {
+  if (prob < 0 || prob >= st->n_prob) return fail(SS_EINVAL, "problem index out of range");
+  if (nq < 0 || (nq > 0 && (!q || !slot_out))) return fail(SS_EINVAL, "bad query arrays");
+  if (nq == 0) return SS_OK;
+  int16_t* dq = nullptr;
+  int64_t* dout = nullptr;
+  SS_TRY(dalloc(&dq, (size_t)nq * st->d));
+  ss_status s = dalloc(&dout, nq);
+  if (s != SS_OK) {
+    dfree(dq);
+    return s;
+  }
+  hipError_t e = hipMemcpyAsync(dq, q, (size_t)nq * st->d * 2, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) {
+    k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, st->d_coef, st->d_keys, st->d_hash,
+                                                   st->d_pid, st->d_table, st->table_mask, st->d_rowoff, dout);
+    e = hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  dfree(dq);
+  dfree(dout);
+  if (e != hipSuccess) return fail(SS_EDEVICE, std::string("lookup: ") + hipGetErrorString(e));
+  return SS_OK;
+}
+
+}  // namespace ss

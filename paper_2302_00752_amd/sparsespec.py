@@ -1,0 +1,256 @@
+"""Python binding of ``libsparsespec`` (ctypes; argument marshalling only).
+
+Every computation happens in the HIP library.  PyTorch provides device
+memory (tensors' ``data_ptr()``) and the current HIP stream.  If the built
+library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsparsespec.so")
+
+SS_OK, SS_EINVAL, SS_ENOMEM, SS_ERANGE, SS_ENOTPD, SS_ENOCONV, SS_EBREAKDOWN, SS_EDEVICE = range(8)
+SS_FP64, SS_FP32_REFINE = 0, 1
+SS_SKIP_L1_CHECK = 1
+STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_ERANGE", 4: "SS_ENOTPD",
+                5: "SS_ENOCONV", 6: "SS_EBREAKDOWN", 7: "SS_EDEVICE"}
+PRECISION = {"fp64": SS_FP64, "fp32_refine": SS_FP32_REFINE, SS_FP64: SS_FP64, SS_FP32_REFINE: SS_FP32_REFINE}
+
+EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp_keys", "ss_stamp_lookup",
+            "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
+            "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version"]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_steps", C.c_int32), ("rel_residual", C.c_double),
+                ("n", C.c_int64), ("nnz", C.c_int64), ("n_components", C.c_int32), ("status", C.c_int32),
+                ("t_build_ms", C.c_double), ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SparseSpecError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2302_00752_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    i32, i64, u32, dbl = C.c_int32, C.c_int64, C.c_uint32, C.c_double
+    pi32, pi64, pi16, pu8, pd = (C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_int16),
+                                 C.POINTER(C.c_uint8), C.POINTER(dbl))
+    sig = {
+        "ss_build_stamp_batch": [i32, i32, pi32, pi16, pi32, pi16, pi32, P, C.POINTER(P)],
+        "ss_build_stamp": [i32, i32, pi16, i32, pi16, i32, P, C.POINTER(P)],
+        "ss_stamp_size": [P, pi64, pi32, pi64],
+        "ss_stamp_keys": [P, pi16, pu8],
+        "ss_stamp_lookup": [P, i32, i64, pi16, pi64],
+        "ss_build_op": [P, pi32, pi16, pd, u32, P, C.POINTER(P)],
+        "ss_op_info": [P, pi64, pi64, pi64, pi64],
+        "ss_op_csr": [P, pi64, pi32, pi32, pi32],
+        "ss_op_exec_map": [P, pi64],
+        "ss_apply": [P, i32, P, P, P],
+        "ss_solve_op": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
+        "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, i64, pi64, pd, pi16,
+                     C.POINTER(SolveInfo)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.ss_free_stamp.argtypes = [P]
+    lib.ss_free_stamp.restype = None
+    lib.ss_free_op.argtypes = [P]
+    lib.ss_free_op.restype = None
+    lib.ss_last_error.restype = C.c_char_p
+    lib.ss_version.restype = C.c_char_p
+    return lib
+
+
+_lib = load()
+
+
+def _check(status: int):
+    if status != SS_OK:
+        raise SparseSpecError(status, _lib.ss_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _i16(a) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    if a.dtype != np.int16:
+        if a.size and (a.min() < -32768 or a.max() > 32767):
+            raise SparseSpecError(SS_ERANGE, "frequency coordinate outside int16")
+        a = a.astype(np.int16)
+    return a
+
+
+def _c128(a) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return a.view(np.float64)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+class Stamp:
+    """Stamping sets S^N of a batch of problems of one dimension (device-resident)."""
+
+    def __init__(self, handle, d: int):
+        self._h = handle
+        self.d = d
+        n = C.c_int64()
+        npb = C.c_int32()
+        _check(_lib.ss_stamp_size(self._h, C.byref(n), C.byref(npb), None))
+        self.n_total = n.value
+        self.n_prob = npb.value
+        off = np.zeros(self.n_prob + 1, dtype=np.int64)
+        _check(_lib.ss_stamp_size(self._h, None, None, _ptr(off, C.c_int64)))
+        self.offsets = off
+
+    @classmethod
+    def build(cls, problems: Sequence, stream=None) -> "Stamp":
+        """Build from objects with ``d, a_freqs, f_freqs, level`` (one dimension)."""
+        d = int(problems[0].d)
+        if any(int(p.d) != d for p in problems):
+            raise SparseSpecError(SS_EINVAL, "a batch must share the dimension d")
+        n_a = np.array([len(p.a_freqs) for p in problems], dtype=np.int32)
+        n_f = np.array([len(p.f_freqs) for p in problems], dtype=np.int32)
+        lev = np.array([int(p.level) for p in problems], dtype=np.int32)
+        af = _i16(np.concatenate([np.asarray(p.a_freqs).reshape(-1, d) for p in problems]))
+        ff = _i16(np.concatenate([np.asarray(p.f_freqs).reshape(-1, d) for p in problems]))
+        h = C.c_void_p()
+        _check(_lib.ss_build_stamp_batch(len(problems), d, _ptr(n_a, C.c_int32), _ptr(af, C.c_int16),
+                                         _ptr(n_f, C.c_int32), _ptr(ff, C.c_int16), _ptr(lev, C.c_int32),
+                                         C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h, d)
+
+    def keys(self):
+        k = np.zeros((self.n_total, self.d), dtype=np.int16)
+        lev = np.zeros(self.n_total, dtype=np.uint8)
+        _check(_lib.ss_stamp_keys(self._h, _ptr(k, C.c_int16), _ptr(lev, C.c_uint8)))
+        return k, lev
+
+    def lookup(self, prob: int, q) -> np.ndarray:
+        q = _i16(np.asarray(q).reshape(-1, self.d))
+        out = np.zeros(len(q), dtype=np.int64)
+        _check(_lib.ss_stamp_lookup(self._h, int(prob), len(q), _ptr(q, C.c_int16), _ptr(out, C.c_int64)))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.ss_free_stamp(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """Truncated Galerkin operators L_N of a stamped batch (device-resident)."""
+
+    def __init__(self, handle, stamp: Stamp):
+        self._h = handle
+        self.n_prob = stamp.n_prob
+        self.offsets = stamp.offsets.copy()
+        vals = [C.c_int64() for _ in range(4)]
+        _check(_lib.ss_op_info(self._h, *[C.byref(v) for v in vals]))
+        self.n_total, self.n_exec, self.nnz, self.n_components = [v.value for v in vals]
+
+    @classmethod
+    def build(cls, stamp: Stamp, problems: Sequence, flags: int = 0, stream=None) -> "Operator":
+        d = stamp.d
+        n_a = np.array([len(p.a_freqs) for p in problems], dtype=np.int32)
+        af = _i16(np.concatenate([np.asarray(p.a_freqs).reshape(-1, d) for p in problems]))
+        ah = _c128(np.concatenate([np.asarray(p.a_hat) for p in problems]))
+        h = C.c_void_p()
+        _check(_lib.ss_build_op(stamp._h, _ptr(n_a, C.c_int32), _ptr(af, C.c_int16), _ptr(ah, C.c_double),
+                                int(flags), C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h, stamp)
+
+    def csr(self):
+        rp = np.zeros(self.n_total + 1, dtype=np.int64)
+        cols = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        js = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        comp = np.zeros(self.n_total, dtype=np.int32)
+        _check(_lib.ss_op_csr(self._h, _ptr(rp, C.c_int64), _ptr(cols, C.c_int32), _ptr(js, C.c_int32),
+                              _ptr(comp, C.c_int32)))
+        return rp, cols[:self.nnz], js[:self.nnz], comp
+
+    def exec_map(self) -> np.ndarray:
+        m = np.zeros(self.n_exec, dtype=np.int64)
+        _check(_lib.ss_op_exec_map(self._h, _ptr(m, C.c_int64)))
+        return m
+
+    def apply(self, x, y, precision="fp64", stream=None):
+        """y = L_N x on device tensors in execution order (complex128 / complex64)."""
+        _check(_lib.ss_apply(self._h, PRECISION[precision], C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                             C.c_void_p(_stream(stream))))
+
+    def solve(self, f, u, tol: float, precision="fp64", max_iter: int = 1000, stream=None,
+              raise_on_error: bool = True) -> List[dict]:
+        """Solve L_N u = f in place (device complex128 tensors, canonical order)."""
+        info = (SolveInfo * self.n_prob)()
+        st = _lib.ss_solve_op(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), float(tol),
+                              PRECISION[precision], int(max_iter), C.c_void_p(_stream(stream)), info)
+        if raise_on_error:
+            _check(st)
+        return [i.as_dict() for i in info]
+
+    def close(self):
+        if self._h:
+            _lib.ss_free_op(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64", max_iter=2000, flags=0,
+          want_keys=True):
+    """One-shot solve from host data; returns ``(u_hat, keys, info)`` in canonical order."""
+    af = _i16(np.asarray(a_freqs).reshape(-1, d))
+    ff = _i16(np.asarray(f_freqs).reshape(-1, d))
+    ah = _c128(a_hat)
+    fh = _c128(f_hat)
+    n = C.c_int64()
+    info = SolveInfo()
+    _check(_lib.ss_solve(d, len(af), _ptr(af, C.c_int16), _ptr(ah, C.c_double), len(ff), _ptr(ff, C.c_int16),
+                         _ptr(fh, C.c_double), int(level), float(tol), PRECISION[precision], int(max_iter),
+                         int(flags), 0, C.byref(n), None, None, C.byref(info)))
+    u = np.zeros(n.value, dtype=np.complex128)
+    keys = np.zeros((n.value, d), dtype=np.int16) if want_keys else None
+    _check(_lib.ss_solve(d, len(af), _ptr(af, C.c_int16), _ptr(ah, C.c_double), len(ff), _ptr(ff, C.c_int16),
+                         _ptr(fh, C.c_double), int(level), float(tol), PRECISION[precision], int(max_iter),
+                         int(flags), n.value, C.byref(n), _ptr(u.view(np.float64), C.c_double),
+                         _ptr(keys, C.c_int16) if want_keys else None, C.byref(info)))
+    return u, keys, info.as_dict()
+
+
+def version() -> str:
+    return _lib.ss_version().decode()

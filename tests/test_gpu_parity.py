@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: stamp keys, levels, slot lookups, the canonical neighbour map and
+class labels bit-exact; the matvec within a rounding bound derived from the
+absolute row sums (FP64: 64 eps64 |L| |x|; FP32: 1e-5 |L| |x| for x rounded
+to complex64); solves within the spec errors |u - u*| / |u*| <= 1e-10
+(FP64) and <= 1e-9 (FP32 + FP64 refinement), the paper's configurations at
+literal size; a batch gives each problem bitwise the result it gets alone.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import galerkin as og
+from oracle import stamp as ost
+from paper_2302_00752_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_00752_amd import sparsespec
+    return sparsespec
+
+
+FLAGS = {3: 1}          # the multiscale product coefficient fails the l1 certificate but is positive
+TOL64, TOL32 = 1e-11, 1e-10
+ERR64, ERR32 = 1e-10, 1e-9
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(config, instance=0, level=None):
+    p = workloads.make(config, instance) if level is None else workloads.make(config, instance, level=level)
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, lev = ost.stamp(p.f_freqs, af, p.level)
+    nbr = og.neighbours(keys, af)
+    label = og.classes(nbr[0], nbr[1])
+    M = og.matrix(keys, af, ah, nbr)
+    pos = og.slot_index(keys)
+    f = np.zeros(len(keys), dtype=np.complex128)
+    for k, v in zip(p.f_freqs, p.f_hat):
+        f[pos[tuple(int(x) for x in k)]] = v
+    u = og.solve(keys, af, ah, f, M=M)
+    return dict(p=p, af=af, ah=ah, keys=keys, lev=lev, nbr=nbr, label=label, M=M, f=f, u=u)
+
+
+def build(ss, problems, flags=0):
+    st = ss.Stamp.build(problems)
+    op = ss.Operator.build(st, problems, flags)
+    return st, op
+
+
+def f_vector(ss, st, problems):
+    f = np.zeros(st.n_total, dtype=np.complex128)
+    for i, p in enumerate(problems):
+        slots = st.lookup(i, p.f_freqs)
+        assert np.all(slots >= 0)
+        f[st.offsets[i] + slots] = p.f_hat
+    return f
+
+
+def gpu_solve(ss, op, f, tol, precision, max_iter=2000, u0=None):
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd) if u0 is None else torch.from_numpy(u0).cuda()
+    info = op.solve(fd, ud, tol, precision, max_iter)
+    torch.cuda.synchronize()
+    return ud.cpu().numpy(), info
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
+def test_stamp_and_lookup_bit_exact(ss, config):
+    oc = oracle_case(config)
+    st = ss.Stamp.build([oc["p"]])
+    keys, lev = st.keys()
+    assert np.array_equal(keys.astype(np.int64), oc["keys"])
+    assert np.array_equal(lev.astype(np.int64), oc["lev"])
+    slots = st.lookup(0, keys)
+    assert np.array_equal(slots, np.arange(len(keys)))
+    absent = keys.astype(np.int64).copy()
+    absent[:, 0] += 20000
+    absent = np.clip(absent, -32768, 32767)
+    member = {tuple(k) for k in oc["keys"].tolist()}
+    expect = np.array([-1 if tuple(k) not in member else -2 for k in absent.tolist()])
+    got = st.lookup(0, absent)
+    assert np.all(got[expect == -1] == -1)
+
+
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
+def test_neighbour_map_and_classes_bit_exact(ss, config):
+    oc = oracle_case(config)
+    st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+    rp, cols, js, comp = op.csr()
+    orp, ocols, ojs = oc["nbr"]
+    assert np.array_equal(rp, orp) and np.array_equal(cols, ocols) and np.array_equal(js, ojs)
+    assert np.array_equal(comp.astype(np.int64), oc["label"])
+    assert op.n_components == len(np.unique(oc["label"]))
+    em = op.exec_map()
+    valid = em[em >= 0]
+    assert np.array_equal(np.sort(valid), np.arange(op.n_total))
+
+
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
+def test_apply_matches_oracle(ss, config):
+    oc = oracle_case(config)
+    st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+    em = op.exec_map()
+    rng = np.random.default_rng(config)
+    x = rng.standard_normal(op.n_total) + 1j * rng.standard_normal(op.n_total)
+    xe = np.zeros(op.n_exec, dtype=np.complex128)
+    xe[em >= 0] = x[em[em >= 0]]
+    y_ref = oc["M"] @ x
+    bound = abs(oc["M"]) @ np.abs(x)
+    # FP64
+    xd = torch.from_numpy(xe).cuda()
+    yd = torch.full_like(xd, np.nan)
+    op.apply(xd, yd, "fp64")
+    torch.cuda.synchronize()
+    ye = yd.cpu().numpy()
+    assert np.all(ye[em < 0] == 0)
+    y = np.zeros(op.n_total, dtype=np.complex128)
+    y[em[em >= 0]] = ye[em >= 0]
+    assert np.all(np.abs(y - y_ref) <= 64 * np.finfo(np.float64).eps * bound + 1e-300)
+    # FP32 operator on x rounded to complex64
+    xd32 = torch.from_numpy(xe.astype(np.complex64)).cuda()
+    yd32 = torch.zeros_like(xd32)
+    op.apply(xd32, yd32, "fp32_refine")
+    torch.cuda.synchronize()
+    y32 = np.zeros(op.n_total, dtype=np.complex128)
+    y32[em[em >= 0]] = yd32.cpu().numpy()[em >= 0]
+    assert np.all(np.abs(y32 - y_ref) <= 1e-5 * bound)
+
+
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_solve_matches_oracle(ss, config, precision):
+    oc = oracle_case(config)
+    st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+    f = f_vector(ss, st, [oc["p"]])
+    assert np.array_equal(f, oc["f"])
+    tol, err = (TOL64, ERR64) if precision == "fp64" else (TOL32, ERR32)
+    u, info = gpu_solve(ss, op, f, tol, precision)
+    assert info[0]["status"] == ss.SS_OK and info[0]["rel_residual"] <= tol
+    assert rel(u, oc["u"]) <= err, (rel(u, oc["u"]), info)
+    assert np.all(u[~np.any(oc["keys"] != 0, axis=1)] == 0)       # u_0 = 0
+
+
+@pytest.mark.parametrize("config", [2, 4])
+def test_manufactured_solution(ss, config):
+    oc = oracle_case(config)
+    st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+    u_star = workloads.manufactured_solution(op.n_total, 77 + config, density=0.2)
+    u_star[~np.any(oc["keys"] != 0, axis=1)] = 0
+    f = oc["M"] @ u_star                    # L_N u* by the (pinned) oracle operator
+    for precision, tol, err in (("fp64", TOL64, ERR64), ("fp32_refine", TOL32, ERR32)):
+        u, info = gpu_solve(ss, op, f, tol, precision)
+        assert rel(u, u_star) <= err, (precision, rel(u, u_star))
+
+
+def test_batch_equals_alone_bitwise(ss):
+    probs = [workloads.make(2, i) for i in range(3)] + [workloads.make(2, 3, level=2)]
+    st, op = build(ss, probs)
+    f = f_vector(ss, st, probs)
+    for precision in ("fp64", "fp32_refine"):
+        ub, infob = gpu_solve(ss, op, f, TOL64 if precision == "fp64" else TOL32, precision)
+        for i, p in enumerate(probs):
+            st1, op1 = build(ss, [p])
+            k1, _ = st1.keys()
+            kb, _ = st.keys()
+            assert np.array_equal(k1, kb[st.offsets[i]:st.offsets[i + 1]])
+            f1 = f_vector(ss, st1, [p])
+            u1, info1 = gpu_solve(ss, op1, f1, TOL64 if precision == "fp64" else TOL32, precision)
+            assert np.array_equal(u1, ub[st.offsets[i]:st.offsets[i + 1]]), (precision, i)
+            assert info1[0]["iters"] == infob[i]["iters"]
+
+
+def test_mixed_levels_batch_matches_oracle(ss):
+    probs = [workloads.make(2, 0, level=1), workloads.make(2, 1, level=3), workloads.make(2, 2, level=0)]
+    st, op = build(ss, probs)
+    keys, lev = st.keys()
+    for i, p in enumerate(probs):
+        af, _ = ost.canonical_a(p.a_freqs, p.a_hat)
+        ok, olev = ost.stamp(p.f_freqs, af, p.level)
+        sl = slice(st.offsets[i], st.offsets[i + 1])
+        assert np.array_equal(keys[sl].astype(np.int64), ok) and np.array_equal(lev[sl].astype(np.int64), olev)
+
+
+def test_deterministic_rebuild_and_solve(ss):
+    p = workloads.make(4)
+    st1, op1 = build(ss, [p])
+    st2, op2 = build(ss, [p])
+    assert np.array_equal(st1.keys()[0], st2.keys()[0])
+    assert np.array_equal(op1.exec_map(), op2.exec_map())
+    f = f_vector(ss, st1, [p])
+    a, _ = gpu_solve(ss, op1, f, TOL32, "fp32_refine")
+    b, _ = gpu_solve(ss, op2, f, TOL32, "fp32_refine")
+    assert np.array_equal(a, b)
+
+
+def test_one_shot_solve(ss):
+    oc = oracle_case(1)
+    p = oc["p"]
+    u, keys, info = ss.solve(p.d, p.a_freqs, p.a_hat, p.f_freqs, p.f_hat, p.level, tol=TOL64)
+    assert np.array_equal(keys.astype(np.int64), oc["keys"])
+    assert rel(u, oc["u"]) <= ERR64 and info["status"] == 0 and info["n"] == len(keys)
+
+
+# ---------------------------------------------------------------- edge cases
+class P:
+    def __init__(self, d, af, ah, ff, fh, level):
+        self.d, self.level = d, level
+        self.a_freqs, self.a_hat = np.array(af, dtype=np.int16).reshape(-1, d), np.array(ah, dtype=np.complex128)
+        self.f_freqs, self.f_hat = np.array(ff, dtype=np.int16).reshape(-1, d), np.array(fh, dtype=np.complex128)
+
+
+def _check_against_oracle(ss, p, flags=0, precision="fp64"):
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, lev = ost.stamp(p.f_freqs, af, p.level)
+    st, op = build(ss, [p], flags)
+    gk, gl = st.keys()
+    assert np.array_equal(gk.astype(np.int64), keys) and np.array_equal(gl.astype(np.int64), lev)
+    f = f_vector(ss, st, [p])
+    u_ref = og.solve(keys, af, ah, f)
+    u, info = gpu_solve(ss, op, f, TOL64 if precision == "fp64" else TOL32, precision)
+    if np.linalg.norm(u_ref) == 0:
+        assert np.all(u == 0)
+    else:
+        assert rel(u, u_ref) <= (ERR64 if precision == "fp64" else ERR32)
+    return keys, u
+
+
+def test_level_zero_is_diagonal(ss):
+    p = workloads.make(2, 5, level=0)
+    keys, u = _check_against_oracle(ss, p)
+    assert len(keys) == len(p.f_freqs)
+
+
+def test_constant_coefficient_is_poisson(ss):
+    # supp(a) = {0}: S^N = F and u_k = f_k / (4 pi^2 |k|^2 a_0)
+    p = P(3, [[0, 0, 0]], [2.0], [[1, 2, 3], [-1, -2, -3], [4, 0, 0]], [1 + 1j, 1 - 1j, 0.5], 2)
+    keys, u = _check_against_oracle(ss, p)
+    st = ss.Stamp.build([p])
+    f = f_vector(ss, st, [p])
+    closed = f / (4 * np.pi ** 2 * 2.0 * (keys ** 2).sum(1))
+    assert len(keys) == 3 and np.allclose(u, closed, rtol=1e-12, atol=0)
+
+
+def test_zero_frequency_in_the_set(ss):
+    # F = {+-(1,0)} and w = (1,0): k = 0 enters S^1; its row and column vanish and u_0 = 0
+    p = P(2, [[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], [1.0, 0.2, 0.2, 0.1j, -0.1j],
+          [[1, 0], [-1, 0]], [1.0, 1.0], 2)
+    keys, u = _check_against_oracle(ss, p)
+    z = np.nonzero(~np.any(keys != 0, axis=1))[0]
+    assert len(z) == 1 and u[z[0]] == 0
+    _check_against_oracle(ss, p, precision="fp32_refine")
+
+
+def test_single_key_and_one_dimension(ss):
+    _check_against_oracle(ss, P(1, [[0]], [1.5], [[7]], [2.0], 3))
+    _check_against_oracle(ss, P(1, [[0], [3], [-3]], [2.0, 0.4 + 0.3j, 0.4 - 0.3j], [[5], [-5]], [1j, -1j], 6))
+
+
+def test_overflow_is_reported(ss):
+    with pytest.raises(ss.SparseSpecError) as e:
+        ss.Stamp.build([P(2, [[0, 0], [1, 0], [-1, 0]], [1, .1, .1], [[32767, 0]], [1.0], 1)])
+    assert e.value.status == ss.SS_ERANGE
+
+
+def test_no_convergence_and_l1_certificate(ss):
+    oc = oracle_case(3)
+    st = ss.Stamp.build([oc["p"]])
+    with pytest.raises(ss.SparseSpecError) as e:
+        ss.Operator.build(st, [oc["p"]])
+    assert e.value.status == ss.SS_ENOTPD
+    op = ss.Operator.build(st, [oc["p"]], 1)
+    f = f_vector(ss, st, [oc["p"]])
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd)
+    with pytest.raises(ss.SparseSpecError) as e:
+        op.solve(fd, ud, 1e-14, "fp64", max_iter=2)
+    assert e.value.status == ss.SS_ENOCONV
+    info = op.solve(fd, ud, 1e-14, "fp64", max_iter=2, raise_on_error=False)
+    assert info[0]["status"] == ss.SS_ENOCONV and info[0]["iters"] == 2
+
+
+def test_warm_start_from_solution(ss):
+    oc = oracle_case(4)
+    st, op = build(ss, [oc["p"]])
+    f = f_vector(ss, st, [oc["p"]])
+    u, info = gpu_solve(ss, op, f, TOL64, "fp64", u0=oc["u"].copy())
+    assert info[0]["iters"] <= 1 and rel(u, oc["u"]) <= ERR64
