@@ -112,6 +112,11 @@ ss_status ss_stamp_keys(const ss_stamp* st, int16_t* keys_out, uint8_t* level_ou
 ss_status ss_stamp_lookup(const ss_stamp* st, int32_t prob, int64_t nq,
                           const int16_t* q, int64_t* slot_out);
 
+/* batched form: query i belongs to problem prob[i] (host); slot_out[i] (host)
+ * = global canonical slot (problem offset included), or -1.  Synchronises. */
+ss_status ss_stamp_lookup_batch(const ss_stamp* st, int64_t nq, const int32_t* prob,
+                                const int16_t* q, int64_t* slot_out);
+
 void ss_free_stamp(ss_stamp* st);
 
 /* ---------------------------------------------------------------- operator

@@ -113,6 +113,15 @@ ss_status ss_stamp_lookup(const ss_stamp* st, int32_t prob, int64_t nq, const in
   });
 }
 
+ss_status ss_stamp_lookup_batch(const ss_stamp* st, int64_t nq, const int32_t* prob, const int16_t* q,
+                                int64_t* slot_out) {
+  return guarded([&]() -> ss_status {
+    if (!st || !st->impl) return fail(SS_EINVAL, "null stamp");
+    if (nq > 0 && !prob) return fail(SS_EINVAL, "null problem ids");
+    return stamp_lookup_impl(st->impl, -1, nq, q, slot_out, nullptr, prob);
+  });
+}
+
 void ss_free_stamp(ss_stamp* st) {
   if (!st) return;
   free_stamp_impl(st->impl);

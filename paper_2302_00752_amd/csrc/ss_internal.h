@@ -176,8 +176,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
                            const int32_t* n_f, const int16_t* f_freqs, const int32_t* level,
                            hipStream_t stream, StampImpl** out);
 void free_stamp_impl(StampImpl* st);
+// prob >= 0: all queries of that problem, local slots out; prob < 0: per-query
+// problem ids in probs (host), global slots out.
 ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const int16_t* q,
-                            int64_t* slot_out, hipStream_t stream);
+                            int64_t* slot_out, hipStream_t stream, const int32_t* probs = nullptr);
 
 ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* a_freqs,
                         const double* a_hat, uint32_t flags, hipStream_t stream, OpImpl** out);

@@ -289,14 +289,15 @@ __global__ void k_max_norm(int64_t n, const int64_t* __restrict__ norm, unsigned
 }
 
 __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32_t prob,
-                         const uint64_t* __restrict__ z, const int16_t* __restrict__ keys,
-                         const uint64_t* __restrict__ hash, const int32_t* __restrict__ pid,
-                         const uint64_t* __restrict__ table, uint64_t mask, const int64_t* rowoff,
-                         int64_t* out) {
+                         const int32_t* __restrict__ probs, const uint64_t* __restrict__ z,
+                         const int16_t* __restrict__ keys, const uint64_t* __restrict__ hash,
+                         const int32_t* __restrict__ pid, const uint64_t* __restrict__ table, uint64_t mask,
+                         const int64_t* rowoff, int64_t* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
+  const int pq = probs ? probs[i] : prob;
   const int16_t* k = q + i * d;
-  uint64_t h = (uint64_t)(int64_t)prob * z[d];
+  uint64_t h = (uint64_t)(int64_t)pq * z[d];
   for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
   uint64_t pos = fmix64(h) & mask;
   int64_t res = -1;
@@ -304,11 +305,11 @@ __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32
     const uint64_t v = table[pos];
     if (v == 0) break;
     const int64_t m = (int64_t)(v & kIdxMask);
-    if (hash[m] == h && pid[m] == prob) {
+    if (hash[m] == h && pid[m] == pq) {
       bool eq = true;
       for (int t = 0; t < d && eq; ++t) eq = keys[m * d + t] == k[t];
       if (eq) {
-        res = m - rowoff[prob];
+        res = probs ? m : m - rowoff[pq];
         break;
       }
     }
@@ -693,28 +694,37 @@ void free_stamp_impl(StampImpl* st) {
 }
 
 ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const int16_t* q,
-                            int64_t* slot_out, hipStream_t stream) {
-  if (prob < 0 || prob >= st->n_prob) return fail(SS_EINVAL, "problem index out of range");
+                            int64_t* slot_out, hipStream_t stream, const int32_t* probs) {
+  if (!probs && (prob < 0 || prob >= st->n_prob)) return fail(SS_EINVAL, "problem index out of range");
   if (nq < 0 || (nq > 0 && (!q || !slot_out))) return fail(SS_EINVAL, "bad query arrays");
+  if (probs)
+    for (int64_t i = 0; i < nq; ++i)
+      if (probs[i] < 0 || probs[i] >= st->n_prob) return fail(SS_EINVAL, "problem index out of range");
   if (nq == 0) return SS_OK;
   int16_t* dq = nullptr;
   int64_t* dout = nullptr;
+  int32_t* dp = nullptr;
+  struct Free {
+    int16_t*& a;
+    int64_t*& b;
+    int32_t*& c;
+    ~Free() {
+      dfree(a);
+      dfree(b);
+      dfree(c);
+    }
+  } fr{dq, dout, dp};
   SS_TRY(dalloc(&dq, (size_t)nq * st->d));
-  ss_status s = dalloc(&dout, nq);
-  if (s != SS_OK) {
-    dfree(dq);
-    return s;
+  SS_TRY(dalloc(&dout, nq));
+  if (probs) {
+    SS_TRY(dalloc(&dp, nq));
+    SS_HIP(hipMemcpyAsync(dp, probs, nq * 4, hipMemcpyHostToDevice, stream));
   }
-  hipError_t e = hipMemcpyAsync(dq, q, (size_t)nq * st->d * 2, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) {
-    k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, st->d_coef, st->d_keys, st->d_hash,
-                                                   st->d_pid, st->d_table, st->table_mask, st->d_rowoff, dout);
-    e = hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  dfree(dq);
-  dfree(dout);
-  if (e != hipSuccess) return fail(SS_EDEVICE, std::string("lookup: ") + hipGetErrorString(e));
+  SS_HIP(hipMemcpyAsync(dq, q, (size_t)nq * st->d * 2, hipMemcpyHostToDevice, stream));
+  k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_hash,
+                                                 st->d_pid, st->d_table, st->table_mask, st->d_rowoff, dout);
+  SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
+  SS_HIP(hipStreamSynchronize(stream));
   return SS_OK;
 }
 

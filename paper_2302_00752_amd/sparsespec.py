@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_ERANGE", 4: "
 PRECISION = {"fp64": SS_FP64, "fp32_refine": SS_FP32_REFINE, SS_FP64: SS_FP64, SS_FP32_REFINE: SS_FP32_REFINE}
 
 EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp_keys", "ss_stamp_lookup",
+            "ss_stamp_lookup_batch",
             "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version"]
 
@@ -57,6 +58,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_stamp_size": [P, pi64, pi32, pi64],
         "ss_stamp_keys": [P, pi16, pu8],
         "ss_stamp_lookup": [P, i32, i64, pi16, pi64],
+        "ss_stamp_lookup_batch": [P, i64, pi32, pi16, pi64],
         "ss_build_op": [P, pi32, pi16, pd, u32, P, C.POINTER(P)],
         "ss_op_info": [P, pi64, pi64, pi64, pi64],
         "ss_op_csr": [P, pi64, pi32, pi32, pi32],
@@ -155,6 +157,28 @@ class Stamp:
         out = np.zeros(len(q), dtype=np.int64)
         _check(_lib.ss_stamp_lookup(self._h, int(prob), len(q), _ptr(q, C.c_int16), _ptr(out, C.c_int64)))
         return out
+
+    def lookup_batch(self, prob, q) -> np.ndarray:
+        """Global canonical slots of keys ``q`` of problems ``prob`` (-1 if absent)."""
+        q = _i16(np.asarray(q).reshape(-1, self.d))
+        prob = np.ascontiguousarray(prob, dtype=np.int32)
+        out = np.zeros(len(q), dtype=np.int64)
+        _check(_lib.ss_stamp_lookup_batch(self._h, len(q), _ptr(prob, C.c_int32), _ptr(q, C.c_int16),
+                                          _ptr(out, C.c_int64)))
+        return out
+
+    def forcing_vector(self, problems, device=None):
+        """f in canonical slot order (complex128 tensor on ``device``) from each problem's F."""
+        import torch
+        prob = np.concatenate([np.full(len(p.f_freqs), i, dtype=np.int32) for i, p in enumerate(problems)])
+        q = np.concatenate([np.asarray(p.f_freqs).reshape(-1, self.d) for p in problems])
+        slots = self.lookup_batch(prob, q)
+        if np.any(slots < 0):
+            raise SparseSpecError(SS_EINVAL, "a forcing frequency is missing from its stamping set")
+        vals = np.concatenate([np.asarray(p.f_hat, dtype=np.complex128) for p in problems])
+        f = torch.zeros(self.n_total, dtype=torch.complex128, device=device or "cuda")
+        f[torch.from_numpy(slots).to(f.device)] = torch.from_numpy(vals).to(f.device)
+        return f
 
     def close(self):
         if self._h:
