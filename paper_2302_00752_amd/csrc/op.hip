@@ -34,90 +34,100 @@ struct NbrArgs {
   int64_t total;
   int32_t d;
   int32_t smax;
+  int32_t rows_per_wave;          // floor(64 / smax)
   const int16_t* keys;
   const uint64_t* hash;
   const int32_t* pid;
+  const int64_t* rowoff;
   const int16_t* akeys;
   const uint64_t* ahash;
   const int32_t* aoff;
+  const int32_t* azero;
+  const int64_t* toff;
+  const uint64_t* tmask;
   const uint64_t* table;
-  uint64_t mask;
-  int32_t* nbr;        // [total x smax] global canonical column or -1
+  uint32_t* buf;       // [total x smax] compact row entries: local canonical column | j << 26
   int64_t* rowlen;     // [total]
 };
 
-__global__ void k_neighbors(NbrArgs a) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.total) return;
-  const int p = a.pid[r];
-  const int j0 = a.aoff[p], j1 = a.aoff[p + 1];
-  const int d = a.d;
-  const int16_t* k = a.keys + r * d;
-  int64_t cnt = 0;
-  for (int j = 0; j < a.smax; ++j) {
-    int32_t col = -1;
-    if (j < j1 - j0) {
-      const int16_t* w = a.akeys + (int64_t)(j0 + j) * d;
-      bool zero = true;
-      for (int t = 0; t < d && zero; ++t) zero = w[t] == 0;
-      if (zero) {
-        col = (int32_t)r;
+// One lane per (row, a-table index): look up k - w_j; a ballot over the row's
+// lanes compacts the hits to the front of the row's buffer in j order.
+__global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int rl = lane / a.smax, j = lane % a.smax;
+  const int64_t r = wave * a.rows_per_wave + rl;
+  const bool live = rl < a.rows_per_wave && r < a.total;
+  int64_t col = -1;
+  int p = 0;
+  if (live) {
+    p = a.pid[r];
+    const int j0 = a.aoff[p];
+    if (j < a.aoff[p + 1] - j0) {
+      if (j == a.azero[p]) {
+        col = r;
       } else {
+        const int d = a.d;
+        const int16_t* k = a.keys + r * d;
+        const int16_t* w = a.akeys + (int64_t)(j0 + j) * d;
         const uint64_t h = a.hash[r] - a.ahash[j0 + j];
-        uint64_t pos = fmix64(h) & a.mask;
+        const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
+        uint64_t pos = slot_first(h, base, mask);
         while (true) {
-          const uint64_t v = a.table[pos];
+          const uint64_t v = a.table[2 * pos];
           if (v == 0) break;
-          const int64_t m = (int64_t)(v & kIdxMask);
-          if (a.hash[m] == h && a.pid[m] == p) {
+          if (a.table[2 * pos + 1] == h) {
+            const int64_t m = (int64_t)(v & kIdxMask);
             const int16_t* km = a.keys + m * d;
             bool eq = true;
             for (int t = 0; t < d && eq; ++t) eq = (int)km[t] == (int)k[t] - (int)w[t];
             if (eq) {
-              col = (int32_t)m;
+              col = m;
               break;
             }
           }
-          pos = (pos + 1) & a.mask;
+          pos = slot_next(pos, base, mask);
         }
       }
     }
-    a.nbr[r * a.smax + j] = col;
-    cnt += col >= 0;
   }
-  a.rowlen[r] = cnt;
+  const uint64_t hits = __ballot(col >= 0);
+  const int sh = rl * a.smax;
+  const uint64_t seg = a.smax >= 64 ? hits : (hits >> sh) & ((1ull << a.smax) - 1);
+  if (live) {
+    if (col >= 0) {
+      const int q = __popcll(seg & ((1ull << j) - 1));
+      a.buf[r * a.smax + q] = (uint32_t)(col - a.rowoff[p]) | ((uint32_t)j << kColBits);
+    }
+    if (j == 0) a.rowlen[r] = __popcll(seg);
+  }
 }
 
-__global__ void k_csr_fill(int64_t total, int32_t smax, const int32_t* __restrict__ nbr,
-                           const int64_t* __restrict__ crow, const int32_t* __restrict__ pid,
-                           const int64_t* __restrict__ rowoff, uint32_t* __restrict__ cent) {
+__global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
+                           const int64_t* __restrict__ crow, uint32_t* __restrict__ cent) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
-  const int64_t base = rowoff[pid[r]];
-  int64_t q = crow[r];
-  for (int j = 0; j < smax; ++j) {
-    const int32_t c = nbr[r * smax + j];
-    if (c >= 0) cent[q++] = (uint32_t)(c - base) | ((uint32_t)j << kColBits);
-  }
+  const int64_t c0 = crow[r], n = crow[r + 1] - c0;
+  for (int64_t q = 0; q < n; ++q) cent[c0 + q] = buf[r * smax + q];
 }
 
-__global__ void k_iota_i64(int64_t n, int64_t* p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = i;
+__global__ void k_nnz_per_problem(int n_prob, const int64_t* __restrict__ rowoff, const int64_t* __restrict__ crow,
+                                  int64_t* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_prob) out[p] = crow[rowoff[p + 1]] - crow[rowoff[p]];
 }
 
-__global__ void k_cc_prop(int64_t total, int32_t smax, const int32_t* __restrict__ nbr, int64_t* label,
+__global__ void k_cc_prop(int64_t total, const int64_t* __restrict__ crow, const uint32_t* __restrict__ cent,
+                          const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff, int64_t* label,
                           int32_t* changed) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
+  const int64_t base = rowoff[pid[r]];
   const int64_t own = label[r];
   int64_t l = own;
-  for (int j = 0; j < smax; ++j) {
-    const int32_t c = nbr[r * smax + j];
-    if (c >= 0) {
-      const int64_t lc = label[c];
-      l = lc < l ? lc : l;
-    }
+  for (int64_t e = crow[r]; e < crow[r + 1]; ++e) {
+    const int64_t lc = label[base + (cent[e] & kColMask)];
+    l = lc < l ? lc : l;
   }
   if (l < own) {
     label[r] = l;
@@ -131,24 +141,39 @@ __global__ void k_cc_jump(int64_t total, int64_t* label) {
   label[r] = label[label[r]];
 }
 
-__global__ void k_cc_finish(int64_t total, const int64_t* __restrict__ label, const int32_t* __restrict__ pid,
+__global__ void k_fill_u64(int64_t n, unsigned long long* p, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// class label -> smallest canonical slot of the class
+__global__ void k_cc_min(int64_t total, const int64_t* __restrict__ label, unsigned long long* cmin) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < total) atomicMin(&cmin[label[r]], (unsigned long long)r);
+}
+
+__global__ void k_cc_finish(int64_t total, const int64_t* __restrict__ label,
+                            const unsigned long long* __restrict__ cmin, const int32_t* __restrict__ pid,
                             const int64_t* __restrict__ rowoff, int32_t* __restrict__ comp,
                             int32_t* __restrict__ ncomp) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r];
-  comp[r] = (int32_t)(label[r] - rowoff[p]);
-  if (label[r] == r) atomicAdd(&ncomp[p], 1);
+  const int64_t m = (int64_t)cmin[label[r]];
+  comp[r] = (int32_t)(m - rowoff[p]);
+  if (m == r) atomicAdd(&ncomp[p], 1);
 }
 
-__global__ void k_exec_keys(int64_t total, const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
-                            const int32_t* __restrict__ comp, const int64_t* __restrict__ rowlen,
-                            uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+// sort key (problem, class, 63 - row length, canonical slot) packed with `lb` bits per local index
+__global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ pid,
+                            const int64_t* __restrict__ rowoff, const int32_t* __restrict__ comp,
+                            const int64_t* __restrict__ rowlen, uint64_t* __restrict__ key,
+                            uint32_t* __restrict__ val) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r];
   const uint64_t local = (uint64_t)(r - rowoff[p]);
-  key[r] = ((uint64_t)p << 50) | ((uint64_t)comp[r] << 28) | ((uint64_t)(63 - rowlen[r]) << 22) | local;
+  key[r] = ((((((uint64_t)p << lb) | (uint64_t)comp[r]) << 6) | (uint64_t)(63 - rowlen[r])) << lb) | local;
   val[r] = (uint32_t)r;
 }
 
@@ -294,16 +319,18 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   } tmpmem;
   auto track = [&](void* q) { tmpmem.p.push_back(q); };
 
-  // ---- neighbour map
-  int32_t* nbr = nullptr;
+  // ---- neighbour map (one lane per (row, j); rows compacted in j order)
+  uint32_t* nbr = nullptr;
   int64_t* rowlen = nullptr;
   SS_TRY(dalloc(&nbr, (size_t)total * smax));
   track(nbr);
   SS_TRY(dalloc(&rowlen, total + 1));
   track(rowlen);
-  NbrArgs na{total, d, smax, st->d_keys, st->d_hash, st->d_pid, st->d_akeys, st->d_ahash, st->d_aoff,
-             st->d_table, st->table_mask, nbr, rowlen};
-  k_neighbors<<<grid_for(total), kBlock, 0, stream>>>(na);
+  const int rpw = 64 / smax;
+  NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
+             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_table, nbr, rowlen};
+  const int64_t n_waves = ceil_div(total, rpw);
+  k_neighbors<<<(unsigned)ceil_div(n_waves, kBlock / 64), kBlock, 0, stream>>>(na);
   SS_TRY(dalloc(&op->d_crow, total + 1));
   {
     size_t tb = 0;
@@ -314,45 +341,49 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     SS_HIP(hipMemsetAsync(rowlen + total, 0, 8, stream));
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, rowlen, op->d_crow, total + 1, stream));
   }
+  int64_t* d_nnzp = nullptr;
+  SS_TRY(dalloc(&d_nnzp, n_prob));
+  track(d_nnzp);
+  k_nnz_per_problem<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, st->d_rowoff, op->d_crow, d_nnzp);
+  op->nnz_p.resize(n_prob);
+  SS_HIP(hipMemcpyAsync(op->nnz_p.data(), d_nnzp, n_prob * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   SS_TRY(dalloc(&op->d_cent, op->nnz));
-  k_csr_fill<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, st->d_pid, st->d_rowoff,
-                                                     op->d_cent);
-  // per-problem nnz
-  {
-    std::vector<int64_t> crow_at(n_prob + 1);
-    for (int p = 0; p <= n_prob; ++p)
-      SS_HIP(hipMemcpyAsync(&crow_at[p], op->d_crow + st->row_off[p], 8, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
-    op->nnz_p.resize(n_prob);
-    for (int p = 0; p < n_prob; ++p) op->nnz_p[p] = crow_at[p + 1] - crow_at[p];
-  }
+  k_csr_copy<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
 
-  // ---- connected classes: min-label propagation with pointer jumping
+  // ---- connected classes: labels start at each key's root forcing key (so classes that no
+  // coincidence merged are final at once), min-propagation with pointer jumping settles merges,
+  // then the label becomes the smallest canonical slot of the class
   int64_t* label = nullptr;
   int32_t* changed = nullptr;
   int32_t* ncomp = nullptr;
+  unsigned long long* cmin = nullptr;
   SS_TRY(dalloc(&label, total));
   track(label);
   SS_TRY(dalloc(&changed, 1));
   track(changed);
   SS_TRY(dalloc(&ncomp, n_prob));
   track(ncomp);
-  k_iota_i64<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+  SS_TRY(dalloc(&cmin, total));
+  track(cmin);
+  SS_HIP(hipMemcpyAsync(label, st->d_root, total * 8, hipMemcpyDeviceToDevice, stream));
   for (int it = 0; it < 100000; ++it) {
     int32_t h = 0;
     SS_HIP(hipMemsetAsync(changed, 0, 4, stream));
-    k_cc_prop<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, label, changed);
-    k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+    k_cc_prop<<<grid_for(total), kBlock, 0, stream>>>(total, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
+                                                       label, changed);
     k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
     SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipStreamSynchronize(stream));
     if (!h) break;
   }
+  k_fill_u64<<<grid_for(total), kBlock, 0, stream>>>(total, cmin, ~0ull);
+  k_cc_min<<<grid_for(total), kBlock, 0, stream>>>(total, label, cmin);
   SS_TRY(dalloc(&op->d_comp, total));
   SS_HIP(hipMemsetAsync(ncomp, 0, n_prob * 4, stream));
-  k_cc_finish<<<grid_for(total), kBlock, 0, stream>>>(total, label, st->d_pid, st->d_rowoff, op->d_comp, ncomp);
+  k_cc_finish<<<grid_for(total), kBlock, 0, stream>>>(total, label, cmin, st->d_pid, st->d_rowoff, op->d_comp,
+                                                      ncomp);
   op->comps.assign(n_prob, 0);
   SS_HIP(hipMemcpyAsync(op->comps.data(), ncomp, n_prob * 4, hipMemcpyDeviceToHost, stream));
 
@@ -376,14 +407,22 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(ev);
   SS_TRY(dalloc(&ev2, total));
   track(ev2);
-  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff, op->d_comp, rowlen, ek, ev);
+  int64_t max_rows = 1;
+  for (int p = 0; p < n_prob; ++p) max_rows = std::max(max_rows, st->row_off[p + 1] - st->row_off[p]);
+  int lb = 1;
+  while ((int64_t(1) << lb) < max_rows) ++lb;
+  int pb = 0;
+  while ((1 << pb) < n_prob) ++pb;
+  const int key_bits = pb + 2 * lb + 6;   // <= 14 + 44 + 6
+  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, op->d_comp, rowlen, ek,
+                                                      ev);
   {
     size_t tb = 0;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, 64, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
     void* t = nullptr;
     SS_HIP(hipMalloc(&t, tb));
     track(t);
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, ek, ek2, ev, ev2, total, 0, 64, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
   }
   SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
   SS_TRY(dalloc(&op->d_canon2exec, total));

@@ -56,6 +56,14 @@ __host__ __device__ inline uint64_t fmix64(uint64_t k) {
   return k;
 }
 
+// linear probing inside one problem's power-of-two table region [base, base + mask + 1)
+__host__ __device__ inline uint64_t slot_first(uint64_t h, uint64_t base, uint64_t mask) {
+  return base + (fmix64(h) & mask);
+}
+__host__ __device__ inline uint64_t slot_next(uint64_t pos, uint64_t base, uint64_t mask) {
+  return base + ((pos - base + 1) & mask);
+}
+
 inline uint64_t splitmix64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ULL;
   x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -79,6 +87,7 @@ struct StampImpl {
   std::vector<int32_t> a_off;          // [n_prob+1] offsets into a_keys (entries)
   std::vector<int16_t> a_keys;         // [sum s x d]
   std::vector<int32_t> a_zero;         // index of w = 0 in each problem's table
+  int32_t* d_azero = nullptr;          // [n_prob]
   // device: a-tables
   int16_t* d_akeys = nullptr;          // [sum s x d]
   uint64_t* d_ahash = nullptr;         // [sum s] linear hash (no problem term)
@@ -90,12 +99,16 @@ struct StampImpl {
   int16_t* d_keys = nullptr;           // [total x d]
   uint8_t* d_lev = nullptr;            // [total]
   int64_t* d_norm = nullptr;           // [total] |k|^2
-  uint64_t* d_hash = nullptr;          // [total] linear hash incl. problem term
+  uint64_t* d_hash = nullptr;          // [total] linear hash of the key
   int32_t* d_pid = nullptr;            // [total]
+  int64_t* d_root = nullptr;           // [total] canonical slot of the forcing key the first path started at
   int64_t* d_rowoff = nullptr;         // [n_prob+1]
   uint64_t* d_coef = nullptr;          // [d] hash multipliers
-  uint64_t* d_table = nullptr;         // hash table: MAIN | canonical index
-  uint64_t table_mask = 0;
+  uint64_t* d_table = nullptr;         // 2 words per slot: {MAIN | canonical index, hash}
+  int64_t* d_toff = nullptr;           // [n_prob] first slot of each problem's region
+  uint64_t* d_tmask = nullptr;         // [n_prob] region size - 1
+  uint64_t n_slots = 0;
+  std::vector<uint64_t> tcap;
   int64_t max_norm = 0;
 };
 

@@ -7,18 +7,23 @@
 // deduplicated through an open-addressing hash table, and the survivors are
 // appended as the next frontier.  Among equal candidates the one with the
 // smallest (frontier index, w index) wins, so the append order -- and with it
-// everything downstream -- is deterministic.
+// everything downstream -- is deterministic.  Every key also records the
+// forcing frequency its first (winning) path started from; connected classes
+// are seeded from that root later.
 //
-// The hash of a key is linear in its coordinates, h(k) = sum_t k_t Z_t
-// (mod 2^64), so h(k + w) = h(k) + h(w): a candidate's hash costs one add and
-// a neighbour lookup h(k - w) one subtract.  Keys are always verified
-// coordinate by coordinate after a hash match.
+// Hash: h(k) = sum_t k_t Z_t (mod 2^64) is linear, so h(k + w) = h(k) + h(w)
+// and a neighbour lookup h(k - w) costs one subtraction.  Each problem owns a
+// power-of-two region of the table, sized from the App. A count (exact when no
+// sums coincide) and grown per level if needed, so a problem's probes stay in
+// one small region (L2-resident while its keys are processed) and a slot
+// never has to record its problem.  A slot is 16 bytes: {tag|index, hash};
+// keys are verified coordinate by coordinate after a hash match.
 //
-// After the last level, keys are put in canonical order (per problem,
-// ascending lexicographic, coordinate 0 most significant) by an LSD radix
-// sort that packs four biased int16 coordinates per 64-bit pass and skips
-// coordinates that are constant over the whole batch, then a final pass on
-// the problem id.
+// Canonical order (per problem, ascending lexicographic, coordinate 0 most
+// significant): LSD radix sort over the coordinates, each biased by its
+// minimum over the batch and packed into 64-bit words with only the bits its
+// range needs (constant coordinates drop out); the problem id is the most
+// significant field.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -34,9 +39,9 @@ namespace ss {
 namespace {
 
 std::vector<uint64_t> hash_coefs(int d) {
-  std::vector<uint64_t> z(d + 1);
-  for (int t = 0; t <= d; ++t) z[t] = splitmix64(0x5eed0000ULL + (uint64_t)t * 7919u) | 1ull;
-  return z;   // z[d] multiplies the problem id
+  std::vector<uint64_t> z(d);
+  for (int t = 0; t < d; ++t) z[t] = splitmix64(0x5eed0000ULL + (uint64_t)t * 7919u) | 1ull;
+  return z;
 }
 
 __device__ inline uint64_t atomic_load_u64(const uint64_t* p) {
@@ -56,27 +61,32 @@ __device__ inline bool eq_shift2(const int16_t* b1, const int16_t* w1, const int
   return true;
 }
 
-__global__ void k_hash_keys(int64_t n, int d, const int16_t* __restrict__ keys,
-                            const int32_t* __restrict__ pid, const uint64_t* __restrict__ z,
+__global__ void k_hash_keys(int64_t n, int d, const int16_t* __restrict__ keys, const uint64_t* __restrict__ z,
                             uint64_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint64_t h = (uint64_t)(int64_t)pid[i] * z[d];
+  uint64_t h = 0;
   const int16_t* k = keys + i * d;
   for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
   out[i] = h;
 }
 
-__global__ void k_insert_main(int64_t n0, int64_t n, const uint64_t* __restrict__ hash,
-                              uint64_t* table, uint64_t mask) {
-  int64_t i = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, const int32_t* __restrict__ pid,
+                              const int64_t* __restrict__ toff, const uint64_t* __restrict__ tmask,
+                              uint64_t* table) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint64_t pos = fmix64(hash[i]) & mask;
+  const int p = pid[i];
+  const uint64_t h = hash[i], base = (uint64_t)toff[p], mask = tmask[p];
+  uint64_t pos = slot_first(h, base, mask);
   while (true) {
-    unsigned long long old =
-        atomicCAS((unsigned long long*)&table[pos], 0ull, (unsigned long long)(kTagMain | (uint64_t)i));
-    if (old == 0ull) return;
-    pos = (pos + 1) & mask;
+    unsigned long long old = atomicCAS((unsigned long long*)&table[2 * pos], 0ull,
+                                       (unsigned long long)(kTagMain | (uint64_t)i));
+    if (old == 0ull) {
+      table[2 * pos + 1] = h;
+      return;
+    }
+    pos = slot_next(pos, base, mask);
   }
 }
 
@@ -93,9 +103,10 @@ struct ExpandArgs {
   const int32_t* woff;    // [n_prob+1]
   const int32_t* plevel;  // [n_prob] stamping level of each problem
   int32_t level;          // level being built
-  uint64_t* table;
-  uint64_t mask;
-  uint32_t* cpos;         // [n_cand] slot of the candidate's key, or kNoSlot
+  const int64_t* toff;    // [n_prob] first slot of each problem's region
+  const uint64_t* tmask;  // [n_prob] region size - 1
+  uint64_t* table;        // 2 words per slot
+  uint32_t* cpos;         // [n_cand] slot of the candidate's key (region-relative), or kNoSlot
   int32_t* err;
 };
 
@@ -123,48 +134,46 @@ __global__ void k_expand(ExpandArgs a) {
   }
   const uint64_t h = a.hash[i] + a.whash[wo + j];
   const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)j;
-  uint64_t pos = fmix64(h) & a.mask;
+  const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
+  uint64_t pos = slot_first(h, base, mask);
   while (true) {
-    uint64_t v = atomic_load_u64(&a.table[pos]);
+    uint64_t v = atomic_load_u64(&a.table[2 * pos]);
     if (v == 0) {
-      unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos], 0ull,
-                                         (unsigned long long)my);
+      unsigned long long old = atomicCAS((unsigned long long*)&a.table[2 * pos], 0ull, (unsigned long long)my);
       if (old == 0ull) {
-        a.cpos[t] = (uint32_t)pos;
+        a.cpos[t] = (uint32_t)(pos - base);
         return;
       }
       v = old;
     }
     if ((v & kTagMask) == kTagMain) {
       const int64_t m = (int64_t)(v & kIdxMask);
-      if (a.hash[m] == h && a.pid[m] == p && eq_shift(a.keys + m * d, k, w, d)) {
+      if (a.table[2 * pos + 1] == h && eq_shift(a.keys + m * d, k, w, d)) {
         a.cpos[t] = kNoSlot;   // already in an earlier level
         return;
       }
     } else {
       const int64_t i2 = (int64_t)((v & kIdxMask) >> 6);
       const int j2 = (int)(v & 63);
-      const int p2 = a.pid[i2];
-      const int wo2 = a.woff[p2];
-      const uint64_t h2 = a.hash[i2] + a.whash[wo2 + j2];
-      if (h2 == h && p2 == p &&
-          eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo2 + j2) * d, k, w, d)) {
-        // equal key found among this level's candidates: the smallest candidate keeps the slot
+      const uint64_t h2 = a.hash[i2] + a.whash[wo + j2];     // same problem: same region
+      if (h2 == h && eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo + j2) * d, k, w, d)) {
+        // equal key among this level's candidates: the smallest candidate keeps the slot
         while (my < v) {
-          unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos],
-                                             (unsigned long long)v, (unsigned long long)my);
+          unsigned long long old = atomicCAS((unsigned long long*)&a.table[2 * pos], (unsigned long long)v,
+                                             (unsigned long long)my);
           if (old == (unsigned long long)v) break;
           v = old;
         }
-        a.cpos[t] = (uint32_t)pos;
+        a.cpos[t] = (uint32_t)(pos - base);
         return;
       }
     }
-    pos = (pos + 1) & a.mask;
+    pos = slot_next(pos, base, mask);
   }
 }
 
 __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint32_t* __restrict__ cpos,
+                          const int32_t* __restrict__ pid, const int64_t* __restrict__ toff,
                           const uint64_t* __restrict__ table, uint32_t* __restrict__ flag) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_cand) return;
@@ -172,14 +181,14 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
   if (cpos[t] != kNoSlot) {
     const int64_t i = f0 + t / smax1;
     const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)(t % smax1);
-    f = table[cpos[t]] == my ? 1u : 0u;
+    f = table[2 * ((uint64_t)toff[pid[i]] + cpos[t])] == my ? 1u : 0u;
   }
   flag[t] = f;
 }
 
-__global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag,
-                         const uint32_t* __restrict__ idx, int64_t base, int level,
-                         int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out) {
+__global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                         int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out,
+                         int64_t* root) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand || !flag[t]) return;
   const int64_t i = a.f0 + t / a.smax1;
@@ -192,15 +201,28 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag,
   const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
   int16_t* o = keys_out + m * d;
   for (int c = 0; c < d; ++c) o[c] = (int16_t)((int)k[c] + (int)w[c]);
-  hash_out[m] = a.hash[i] + a.whash[wo + j];
+  const uint64_t h = a.hash[i] + a.whash[wo + j];
+  hash_out[m] = h;
   pid_out[m] = p;
-  lev_out[m] = (uint8_t)level;
-  a.table[a.cpos[t]] = kTagMain | (uint64_t)m;
+  lev_out[m] = (uint8_t)a.level;
+  root[m] = root[i];
+  const uint64_t s = (uint64_t)a.toff[p] + a.cpos[t];
+  a.table[2 * s] = kTagMain | (uint64_t)m;
+  a.table[2 * s + 1] = h;
 }
 
-__global__ void k_fill_i32(int64_t n, int32_t* p, int32_t v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+// new keys per problem of the level just built (candidates are grouped by problem)
+__global__ void k_level_counts(int n_prob, int64_t f0, int32_t smax1, const int64_t* __restrict__ fstart,
+                               const int64_t* __restrict__ fcount, const uint32_t* __restrict__ idx,
+                               const uint32_t* __restrict__ flag, int64_t* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_prob) return;
+  if (fcount[p] == 0) {
+    out[p] = 0;
+    return;
+  }
+  const int64_t c0 = (fstart[p] - f0) * smax1, c1 = c0 + fcount[p] * smax1;
+  out[p] = (int64_t)idx[c1 - 1] + flag[c1 - 1] - (int64_t)idx[c0];
 }
 
 __global__ void k_minmax(int64_t n, int d, const int16_t* __restrict__ keys, int32_t* mn, int32_t* mx) {
@@ -221,25 +243,28 @@ __global__ void k_minmax(int64_t n, int d, const int16_t* __restrict__ keys, int
   atomicMax(&mx[c], hi);
 }
 
-struct Dims4 {
-  int t[4];
-  int n;
+// one packed field of a radix pass: coordinate t (or -1 = problem id), minus `lo`, at bit `shift`
+struct Field {
+  int32_t t;
+  int32_t lo;
+  int32_t shift;
+  int32_t pad;
 };
 
-__global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys,
-                         const uint32_t* __restrict__ perm, Dims4 dims, uint64_t* __restrict__ out) {
+__global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys, const int32_t* __restrict__ pid,
+                         const uint32_t* __restrict__ perm, const Field* __restrict__ fields, int f0, int f1,
+                         uint64_t* __restrict__ out) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const int16_t* k = keys + (int64_t)perm[r] * d;
+  const int64_t s = perm[r];
+  const int16_t* k = keys + s * d;
   uint64_t v = 0;
-  for (int q = 0; q < dims.n; ++q) v = (v << 16) | (uint64_t)((uint16_t)k[dims.t[q]] ^ 0x8000u);
+  for (int q = f0; q < f1; ++q) {
+    const Field f = fields[q];
+    const int val = f.t >= 0 ? (int)k[f.t] : pid[s];
+    v |= (uint64_t)(uint32_t)(val - f.lo) << f.shift;
+  }
   out[r] = v;
-}
-
-__global__ void k_pid_digits(int64_t n, const int32_t* __restrict__ pid, const uint32_t* __restrict__ perm,
-                             uint32_t* __restrict__ out) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) out[r] = (uint32_t)pid[perm[r]];
 }
 
 __global__ void k_iota_u32(int64_t n, uint32_t* p) {
@@ -251,30 +276,50 @@ __global__ void k_permute_out(int64_t n, int d, const uint32_t* __restrict__ per
                               const int16_t* __restrict__ ukeys, const uint64_t* __restrict__ uhash,
                               const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
                               int16_t* keys, uint64_t* hash, int32_t* pid, uint8_t* lev, int64_t* norm,
-                              uint32_t* inv) {
+                              uint32_t* inv, unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int64_t s = perm[r];
-  const int16_t* k = ukeys + s * d;
-  int16_t* o = keys + r * d;
   int64_t nn = 0;
-  for (int c = 0; c < d; ++c) {
-    const int v = k[c];
-    o[c] = (int16_t)v;
-    nn += (int64_t)v * v;
+  if (r < n) {
+    const int64_t s = perm[r];
+    const int16_t* k = ukeys + s * d;
+    int16_t* o = keys + r * d;
+    for (int c = 0; c < d; ++c) {
+      const int v = k[c];
+      o[c] = (int16_t)v;
+      nn += (int64_t)v * v;
+    }
+    hash[r] = uhash[s];
+    pid[r] = upid[s];
+    lev[r] = ulev[s];
+    norm[r] = nn;
+    inv[s] = (uint32_t)r;
   }
-  hash[r] = uhash[s];
-  pid[r] = upid[s];
-  lev[r] = ulev[s];
-  norm[r] = nn;
-  inv[s] = (uint32_t)r;
+  // block maximum of |k|^2, one atomic per block
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(nn, off, 64);
+    nn = o > nn ? o : nn;
+  }
+  __shared__ int64_t wmax[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = nn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t m = wmax[0];
+    for (int q = 1; q < kBlock / 64; ++q) m = wmax[q] > m ? wmax[q] : m;
+    atomicMax(max_norm, (unsigned long long)m);
+  }
 }
 
-__global__ void k_remap_table(uint64_t cap, uint64_t* table, const uint32_t* __restrict__ inv) {
+__global__ void k_root_out(int64_t n, const uint32_t* __restrict__ perm, const int64_t* __restrict__ uroot,
+                           const uint32_t* __restrict__ inv, int64_t* __restrict__ root) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) root[r] = inv[uroot[perm[r]]];
+}
+
+__global__ void k_remap_table(uint64_t n_slots, uint64_t* table, const uint32_t* __restrict__ inv) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cap) return;
-  const uint64_t v = table[s];
-  if ((v & kTagMask) == kTagMain) table[s] = kTagMain | (uint64_t)inv[v & kIdxMask];
+  if (s >= n_slots) return;
+  const uint64_t v = table[2 * s];
+  if ((v & kTagMask) == kTagMain) table[2 * s] = kTagMain | (uint64_t)inv[v & kIdxMask];
 }
 
 __global__ void k_rowoff(int64_t n, const int32_t* __restrict__ pid, int64_t* rowoff) {
@@ -283,29 +328,30 @@ __global__ void k_rowoff(int64_t n, const int32_t* __restrict__ pid, int64_t* ro
   if (r == 0 || pid[r] != pid[r - 1]) rowoff[pid[r]] = r;
 }
 
-__global__ void k_max_norm(int64_t n, const int64_t* __restrict__ norm, unsigned long long* out) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) atomicMax(out, (unsigned long long)norm[r]);
+__global__ void k_iota_i64(int64_t n, int64_t* p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
 }
 
 __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32_t prob,
                          const int32_t* __restrict__ probs, const uint64_t* __restrict__ z,
-                         const int16_t* __restrict__ keys, const uint64_t* __restrict__ hash,
-                         const int32_t* __restrict__ pid, const uint64_t* __restrict__ table, uint64_t mask,
+                         const int16_t* __restrict__ keys, const int64_t* __restrict__ toff,
+                         const uint64_t* __restrict__ tmask, const uint64_t* __restrict__ table,
                          const int64_t* rowoff, int64_t* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   const int pq = probs ? probs[i] : prob;
   const int16_t* k = q + i * d;
-  uint64_t h = (uint64_t)(int64_t)pq * z[d];
+  uint64_t h = 0;
   for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
-  uint64_t pos = fmix64(h) & mask;
+  const uint64_t base = (uint64_t)toff[pq], mask = tmask[pq];
+  uint64_t pos = slot_first(h, base, mask);
   int64_t res = -1;
   while (true) {
-    const uint64_t v = table[pos];
+    const uint64_t v = table[2 * pos];
     if (v == 0) break;
     const int64_t m = (int64_t)(v & kIdxMask);
-    if (hash[m] == h && pid[m] == pq) {
+    if (table[2 * pos + 1] == h) {
       bool eq = true;
       for (int t = 0; t < d && eq; ++t) eq = keys[m * d + t] == k[t];
       if (eq) {
@@ -313,7 +359,7 @@ __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32
         break;
       }
     }
-    pos = (pos + 1) & mask;
+    pos = slot_next(pos, base, mask);
   }
   out[i] = res;
 }
@@ -338,6 +384,71 @@ uint64_t next_pow2(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
   return p;
+}
+
+int bits_for(uint64_t range) {   // bits to hold 0..range
+  int b = 0;
+  while (b < 64 && (range >> b) != 0) ++b;
+  return b;
+}
+
+// App. A count for |F| forcing frequencies, s support points, level N (capped)
+double app_a_count(int64_t n_f, int s, int N) {
+  const int half = (s - 1) / 2;
+  auto comb = [](int n, int k) -> double {
+    if (n == -1 && k == -1) return 1;
+    if (n < 0 || k < 0 || k > n) return 0;
+    double c = 1;
+    for (int q = 1; q <= k; ++q) c = c * (n - k + q) / q;
+    return c;
+  };
+  double tot = 0;
+  for (int n = 0; n <= N; ++n)
+    for (int t = 0; t <= std::min(n, half); ++t) tot += std::ldexp(1.0, t) * comb(half, t) * comb(n - 1, t - 1);
+  return tot * (double)n_f;
+}
+
+// Owns scratch device allocations of one build; frees them on every exit path.
+struct Scratch {
+  std::vector<void**> slots;
+  template <typename T>
+  void hold(T*& p) {
+    slots.push_back((void**)&p);
+  }
+  ~Scratch() {
+    for (void** s : slots)
+      if (*s) {
+        (void)hipFree(*s);
+        *s = nullptr;
+      }
+  }
+};
+
+// Lay out per-problem table regions of the given capacities and insert keys [0, n).
+ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t n, const uint64_t* hash,
+                       const int32_t* pid, hipStream_t stream) {
+  const int np = st->n_prob;
+  std::vector<int64_t> off(np);
+  std::vector<uint64_t> mask(np);
+  uint64_t total = 0;
+  for (int p = 0; p < np; ++p) {
+    off[p] = (int64_t)total;
+    mask[p] = cap[p] - 1;
+    total += cap[p];
+  }
+  if (total >= (uint64_t(1) << 40)) return fail(SS_ERANGE, "hash table too large");
+  dfree(st->d_table);
+  SS_TRY(dalloc(&st->d_table, 2 * total));
+  if (!st->d_toff) SS_TRY(dalloc(&st->d_toff, np));
+  if (!st->d_tmask) SS_TRY(dalloc(&st->d_tmask, np));
+  SS_HIP(hipMemsetAsync(st->d_table, 0, 2 * total * 8, stream));
+  SS_HIP(hipMemcpyAsync(st->d_toff, off.data(), np * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_tmask, mask.data(), np * 8, hipMemcpyHostToDevice, stream));
+  st->n_slots = total;
+  st->tcap = cap;
+  if (n > 0) k_insert_main<<<grid_for(n), kBlock, 0, stream>>>(n, hash, pid, st->d_toff, st->d_tmask, st->d_table);
+  SS_HIP(hipStreamSynchronize(stream));   // host vectors above are temporaries
+  return SS_OK;
 }
 
 }  // namespace
@@ -395,27 +506,6 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
 }
 
 // ---------------------------------------------------------------- build
-namespace {
-
-// Owns scratch device allocations of one build; frees them on every exit path.
-struct Scratch {
-  std::vector<void**> slots;
-  template <typename T>
-  T*& hold(T*& p) {
-    slots.push_back((void**)&p);
-    return p;
-  }
-  ~Scratch() {
-    for (void** s : slots)
-      if (*s) {
-        (void)hipFree(*s);
-        *s = nullptr;
-      }
-  }
-};
-
-}  // namespace
-
 ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
                            const int32_t* n_f, const int16_t* f_freqs, const int32_t* level,
                            hipStream_t stream, StampImpl** out) {
@@ -435,7 +525,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   std::vector<int16_t> wkeys;
   std::vector<uint64_t> ahash, whash;
   std::vector<int64_t> anorm;
-  std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0);
+  std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0), s_of(n_prob);
   int max_level = 0, smax1 = 1;
   int64_t a_pos = 0;
   for (int p = 0; p < n_prob; ++p) {
@@ -447,6 +537,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(canonical_a(d, n_a[p], a_freqs + a_pos * d, nullptr, false, &at));
     a_pos += n_a[p];
     st->a_zero.push_back(at.zero);
+    s_of[p] = (int32_t)at.keys.size();
     for (size_t j = 0; j < at.keys.size(); ++j) {
       st->a_keys.insert(st->a_keys.end(), at.keys[j].begin(), at.keys[j].end());
       uint64_t h = 0;
@@ -479,32 +570,40 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&st->d_ahash, ahash.size()));
   SS_TRY(dalloc(&st->d_anorm, anorm.size()));
   SS_TRY(dalloc(&st->d_aoff, n_prob + 1));
-  SS_TRY(dalloc(&st->d_coef, d + 1));
+  SS_TRY(dalloc(&st->d_azero, n_prob));
+  SS_TRY(dalloc(&st->d_coef, d));
   SS_HIP(hipMemcpyAsync(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, hipMemcpyHostToDevice, stream));
   SS_HIP(hipMemcpyAsync(st->d_ahash, ahash.data(), ahash.size() * 8, hipMemcpyHostToDevice, stream));
   SS_HIP(hipMemcpyAsync(st->d_anorm, anorm.data(), anorm.size() * 8, hipMemcpyHostToDevice, stream));
   SS_HIP(hipMemcpyAsync(st->d_aoff, st->a_off.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_coef, z.data(), (d + 1) * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_azero, st->a_zero.data(), n_prob * 4, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->d_coef, z.data(), d * 8, hipMemcpyHostToDevice, stream));
 
   // ---- build scratch
   Scratch sc;
   int16_t* wk = nullptr;
   uint64_t* wh = nullptr;
-  int32_t *wo = nullptr, *plev = nullptr, *err = nullptr, *fpid_d = nullptr;
+  int32_t *wo = nullptr, *plev = nullptr, *err = nullptr;
   int16_t* ukeys = nullptr;
   uint64_t* uhash = nullptr;
   int32_t* upid = nullptr;
   uint8_t* ulev = nullptr;
+  int64_t* uroot = nullptr;
   uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
+  int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
-  sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev); sc.hold(err); sc.hold(fpid_d);
-  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev);
+  sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev); sc.hold(err);
+  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev); sc.hold(uroot);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
+  sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
   SS_TRY(dalloc(&wk, wkeys.size()));
   SS_TRY(dalloc(&wh, whash.size()));
   SS_TRY(dalloc(&wo, n_prob + 1));
   SS_TRY(dalloc(&plev, n_prob));
   SS_TRY(dalloc(&err, 1));
+  SS_TRY(dalloc(&d_fstart, n_prob));
+  SS_TRY(dalloc(&d_fcount, n_prob));
+  SS_TRY(dalloc(&d_cnt, n_prob));
   if (!wkeys.empty()) SS_HIP(hipMemcpyAsync(wk, wkeys.data(), wkeys.size() * 2, hipMemcpyHostToDevice, stream));
   if (!whash.empty()) SS_HIP(hipMemcpyAsync(wh, whash.data(), whash.size() * 8, hipMemcpyHostToDevice, stream));
   SS_HIP(hipMemcpyAsync(wo, woff.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
@@ -513,11 +612,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- level 0: F
   int64_t kcap = std::max<int64_t>(nF * 4, 1024);
-  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap;
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
   SS_TRY(dalloc(&upid, kcap));
   SS_TRY(dalloc(&ulev, kcap));
+  SS_TRY(dalloc(&uroot, kcap));
   {
     std::vector<int32_t> fpid(nF);
     for (int p = 0; p < n_prob; ++p)
@@ -525,15 +625,26 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipMemcpyAsync(ukeys, f_freqs, (size_t)nF * d * 2, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemcpyAsync(upid, fpid.data(), nF * 4, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
-    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, upid, st->d_coef, uhash);
+    k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
+    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash);
     SS_HIP(hipStreamSynchronize(stream));   // fpid is a host temporary
   }
-  uint64_t tcap = next_pow2((uint64_t)std::max<int64_t>(2 * nF, 1024));
-  SS_TRY(dalloc(&st->d_table, tcap));
-  SS_HIP(hipMemsetAsync(st->d_table, 0, tcap * 8, stream));
-  k_insert_main<<<grid_for(nF), kBlock, 0, stream>>>(0, nF, uhash, st->d_table, tcap - 1);
+  // per-problem regions sized from the App. A count (grown below if coincidences are rarer than it assumes)
+  std::vector<uint64_t> cap(n_prob);
+  for (int p = 0; p < n_prob; ++p) {
+    const double bound = app_a_count(n_f[p], s_of[p], level[p]);
+    const double first = (double)n_f[p] * s_of[p];
+    const double want = bound <= (double)(1 << 22) ? bound : first;
+    cap[p] = next_pow2((uint64_t)std::max(64.0, 2.0 * want));
+  }
+  SS_TRY(layout_table(st, cap, nF, uhash, upid, stream));
 
-  // ---- levels 1..N: expand the frontier
+  std::vector<int64_t> cnt(n_prob), fstart(n_prob), fcount(n_prob);
+  for (int p = 0; p < n_prob; ++p) {
+    cnt[p] = n_f[p];
+    fstart[p] = f_off[p];
+    fcount[p] = n_f[p];
+  }
   int64_t total = nF, f0 = 0, f1 = nF, ccap = 0;
   size_t tmp_bytes = 0;
   for (int n = 1; n <= max_level; ++n) {
@@ -546,13 +657,16 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&uhash, &kcap_h, need, total, 1, stream));
     SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
     SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
-    if ((uint64_t)need * 2 > tcap) {
-      tcap = next_pow2((uint64_t)need * 2);
-      dfree(st->d_table);
-      SS_TRY(dalloc(&st->d_table, tcap));
-      SS_HIP(hipMemsetAsync(st->d_table, 0, tcap * 8, stream));
-      k_insert_main<<<grid_for(total), kBlock, 0, stream>>>(0, total, uhash, st->d_table, tcap - 1);
+    SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
+    bool relayout = false;
+    for (int p = 0; p < n_prob; ++p) {
+      const int64_t need_p = cnt[p] + (level[p] >= n ? fcount[p] * (s_of[p] - 1) : 0);
+      if ((uint64_t)need_p * 2 > cap[p]) {
+        cap[p] = next_pow2((uint64_t)need_p * 2);
+        relayout = true;
+      }
     }
+    if (relayout) SS_TRY(layout_table(st, cap, total, uhash, upid, stream));
     if (n_cand > ccap) {
       dfree(cpos);
       dfree(flag);
@@ -562,9 +676,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       SS_TRY(dalloc(&flag, ccap));
       SS_TRY(dalloc(&idx, ccap));
     }
-    ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_table, tcap - 1, cpos, err};
+    ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_toff, st->d_tmask,
+                  st->d_table, cpos, err};
     k_expand<<<grid_for(n_cand), kBlock, 0, stream>>>(ea);
-    k_winners<<<grid_for(n_cand), kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, st->d_table, flag);
+    k_winners<<<grid_for(n_cand), kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
     size_t need_tmp = 0;
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
     if (need_tmp > tmp_bytes) {
@@ -573,16 +688,23 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       tmp_bytes = need_tmp;
     }
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
-    k_append<<<grid_for(n_cand), kBlock, 0, stream>>>(ea, flag, idx, total, n, ukeys, uhash, upid, ulev);
-    uint32_t last[2] = {0, 0};
+    k_append<<<grid_for(n_cand), kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot);
+    SS_HIP(hipMemcpyAsync(d_fstart, fstart.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
+    SS_HIP(hipMemcpyAsync(d_fcount, fcount.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
+    k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, smax1, d_fstart, d_fcount, idx, flag, d_cnt);
+    std::vector<int64_t> added(n_prob);
     int32_t herr = 0;
-    SS_HIP(hipMemcpyAsync(&last[0], idx + n_cand - 1, 4, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipMemcpyAsync(&last[1], flag + n_cand - 1, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipStreamSynchronize(stream));
     if (herr) return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
     f0 = total;
-    total += (int64_t)last[0] + last[1];
+    for (int p = 0; p < n_prob; ++p) {
+      fstart[p] = total;
+      fcount[p] = added[p];
+      cnt[p] += added[p];
+      total += added[p];
+    }
     f1 = total;
   }
   dfree(cpos);
@@ -591,7 +713,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   dfree(tmp);
   tmp_bytes = 0;
 
-  // ---- canonical order: LSD radix sort over coordinates, then problem id
+  // ---- canonical order: LSD radix sort over packed, range-biased coordinates, then problem id
   st->total = total;
   std::vector<int32_t> mn(d, 32767), mx(d, -32768);
   int32_t *d_mn = nullptr, *d_mx = nullptr;
@@ -604,9 +726,35 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_HIP(hipMemcpyAsync(mn.data(), d_mn, d * 4, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipMemcpyAsync(mx.data(), d_mx, d * 4, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
-  std::vector<int> active;
-  for (int t = 0; t < d; ++t)
-    if (mn[t] != mx[t]) active.push_back(t);
+  // words of <= 64 bits, filled from the least significant coordinate up; the problem id on top
+  std::vector<Field> fields;
+  std::vector<std::pair<int, int>> passes;   // [first field, end field), bits
+  std::vector<int> pass_bits;
+  {
+    int used = 0, first = 0;
+    auto add = [&](int t, int lo, int bits) {
+      if (bits == 0) return;
+      if (used + bits > 64) {
+        passes.emplace_back(first, (int)fields.size());
+        pass_bits.push_back(used);
+        first = (int)fields.size();
+        used = 0;
+      }
+      fields.push_back(Field{t, lo, used, 0});
+      used += bits;
+    };
+    for (int t = d - 1; t >= 0; --t) add(t, mn[t], bits_for((uint64_t)(mx[t] - mn[t])));
+    add(-1, 0, bits_for((uint64_t)(n_prob - 1)));
+    if (used > 0) {
+      passes.emplace_back(first, (int)fields.size());
+      pass_bits.push_back(used);
+    }
+  }
+  Field* d_fields = nullptr;
+  sc.hold(d_fields);
+  SS_TRY(dalloc(&d_fields, std::max<size_t>(fields.size(), 1)));
+  if (!fields.empty())
+    SS_HIP(hipMemcpyAsync(d_fields, fields.data(), fields.size() * sizeof(Field), hipMemcpyHostToDevice, stream));
 
   uint32_t *perm = nullptr, *perm2 = nullptr;
   uint64_t *k64 = nullptr, *k64b = nullptr;
@@ -616,31 +764,15 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&k64, total));
   SS_TRY(dalloc(&k64b, total));
   k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
-  {
-    size_t t64 = 0, t32 = 0;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, t64, k64, k64b, perm, perm2, total, 0, 64, stream));
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, t32, (uint32_t*)k64, (uint32_t*)k64b, perm, perm2,
-                                              total, 0, 32, stream));
-    tmp_bytes = std::max(t64, t32);
+  if (!passes.empty()) {
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k64, k64b, perm, perm2, total, 0, 64, stream));
     SS_HIP(hipMalloc(&tmp, tmp_bytes));
   }
-  for (int end = (int)active.size(); end > 0; end -= 4) {
-    const int beg = std::max(0, end - 4);
-    Dims4 dm{};
-    dm.n = end - beg;
-    for (int q = 0; q < dm.n; ++q) dm.t[q] = active[beg + q];
-    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, perm, dm, k64);
+  for (size_t q = 0; q < passes.size(); ++q) {
+    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, perm, d_fields, passes[q].first,
+                                                     passes[q].second, k64);
     size_t tb = tmp_bytes;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, 16 * dm.n, stream));
-    std::swap(perm, perm2);
-  }
-  if (n_prob > 1) {
-    int bits = 1;
-    while ((1 << bits) < n_prob) ++bits;
-    k_pid_digits<<<grid_for(total), kBlock, 0, stream>>>(total, upid, perm, (uint32_t*)k64);
-    size_t tb = tmp_bytes;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, (uint32_t*)k64, (uint32_t*)k64b, perm, perm2, total, 0,
-                                              bits, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, pass_bits[q], stream));
     std::swap(perm, perm2);
   }
 
@@ -650,16 +782,17 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&st->d_pid, total));
   SS_TRY(dalloc(&st->d_lev, total));
   SS_TRY(dalloc(&st->d_norm, total));
+  SS_TRY(dalloc(&st->d_root, total));
   SS_TRY(dalloc(&st->d_rowoff, n_prob + 1));
   uint32_t* inv = perm2;
-  k_permute_out<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, uhash, upid, ulev, st->d_keys,
-                                                        st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv);
-  k_remap_table<<<(unsigned)ceil_div((int64_t)tcap, kBlock), kBlock, 0, stream>>>(tcap, st->d_table, inv);
-  st->table_mask = tcap - 1;
-  k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff);
   unsigned long long* d_maxn = (unsigned long long*)k64;
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
-  k_max_norm<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_norm, d_maxn);
+  k_permute_out<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, uhash, upid, ulev, st->d_keys,
+                                                        st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
+  k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots, st->d_table,
+                                                                                          inv);
+  k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff);
   unsigned long long maxn = 0;
   st->row_off.assign(n_prob + 1, 0);
   SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
@@ -682,14 +815,18 @@ void free_stamp_impl(StampImpl* st) {
   dfree(st->d_ahash);
   dfree(st->d_anorm);
   dfree(st->d_aoff);
+  dfree(st->d_azero);
   dfree(st->d_keys);
   dfree(st->d_lev);
   dfree(st->d_norm);
   dfree(st->d_hash);
   dfree(st->d_pid);
+  dfree(st->d_root);
   dfree(st->d_rowoff);
   dfree(st->d_coef);
   dfree(st->d_table);
+  dfree(st->d_toff);
+  dfree(st->d_tmask);
   delete st;
 }
 
@@ -704,16 +841,8 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   int16_t* dq = nullptr;
   int64_t* dout = nullptr;
   int32_t* dp = nullptr;
-  struct Free {
-    int16_t*& a;
-    int64_t*& b;
-    int32_t*& c;
-    ~Free() {
-      dfree(a);
-      dfree(b);
-      dfree(c);
-    }
-  } fr{dq, dout, dp};
+  Scratch sc;
+  sc.hold(dq); sc.hold(dout); sc.hold(dp);
   SS_TRY(dalloc(&dq, (size_t)nq * st->d));
   SS_TRY(dalloc(&dout, nq));
   if (probs) {
@@ -721,8 +850,8 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
     SS_HIP(hipMemcpyAsync(dp, probs, nq * 4, hipMemcpyHostToDevice, stream));
   }
   SS_HIP(hipMemcpyAsync(dq, q, (size_t)nq * st->d * 2, hipMemcpyHostToDevice, stream));
-  k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_hash,
-                                                 st->d_pid, st->d_table, st->table_mask, st->d_rowoff, dout);
+  k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_toff,
+                                                 st->d_tmask, st->d_table, st->d_rowoff, dout);
   SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   return SS_OK;
