@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=2, help="problems the CPU oracle solves (0 = skip)")
+    ap.add_argument("--serve", type=int, default=1024, help="requests in the serving stream (0 = skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -173,6 +175,24 @@ def main():
         err = {k: max(v) for k, v in errs.items()}
         log(f"cpu oracle {cpu['value']:.3f} solves/s on {cores} threads; max rel err {err}")
 
+    # --- serving: Poisson stream of heterogeneous requests, continuous batching
+    serving = None
+    if args.serve > 0:
+        from paper_2302_00752_amd import serving as srv
+        budget = int(args.serve_budget_gib * (1 << 30))
+        warm = workloads.cfg5_stream(min(128, args.serve), rate_per_s=1e9, instance=1)
+        sat, _ = srv.serve(warm, hbm_budget_bytes=budget, realtime=False)
+        rate = 0.8 * sat["solves_per_s"]
+        stream_reqs = workloads.cfg5_stream(args.serve, rate_per_s=rate, instance=0)
+        summ, recs = srv.serve(stream_reqs, hbm_budget_bytes=budget, realtime=True)
+        sizes = [r.info["n"] for r in recs]
+        serving = dict(summ, arrival_rate_per_s=rate, saturated_solves_per_s=sat["solves_per_s"],
+                       stamp_sizes={"min": int(min(sizes)), "median": int(np.median(sizes)), "max": int(max(sizes))},
+                       dims={"min": int(min(r.d for r in stream_reqs)), "max": int(max(r.d for r in stream_reqs))})
+        log(f"serving: {summ['requests']} req at {rate:.0f}/s -> {summ['solves_per_s']:.0f} solves/s, "
+            f"p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms, max active {summ['max_active']}, "
+            f"ok {summ['status_ok']}")
+
     value = B / (ms_step / 1e3)
     out = {
         "metric": "CG solves/s at 1e-9 rel. L2 err (FP64 vs FP32+refine) + matvec HBM GB/s; p99",
@@ -202,7 +222,7 @@ def main():
                      "achieved": mv["fp64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": mv["fp64"]["gbs"] / HBM_PEAK_GBS,
                      "bytes_per_launch": mv["fp64"]["bytes"], "traffic": None},
-        "serving": None,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -175,6 +175,45 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
 
 void ss_free_op(ss_op* op);
 
+/* device bytes held by op, including its solver workspace once a solve ran */
+ss_status ss_op_bytes(const ss_op* op, int64_t* bytes);
+
+/* ---------------------------------------------------------------- serving engine
+ * Continuous batching of solves (no passage of the paper; the request-level
+ * pattern on top of Alg. 1 steps 3-5).  An engine holds a changing set of
+ * admitted problems -- possibly of different operators, dimensions, sizes and
+ * precisions -- and advances all of them with the same launches: each tick
+ * runs the pending admissions and refinement transitions, then `iters` PCG
+ * iterations over every active problem, then retires problems that
+ * finished.  Per-problem reductions have a fixed order, so a problem's result
+ * is bitwise the same alone and in any mix.
+ *
+ * ss_engine_create: hbm_budget_bytes (0 = unlimited) bounds the device bytes
+ *   of admitted operators plus their solver workspaces; max_slots (0 =
+ *   unlimited) bounds the admitted requests.  stream: the engine's stream.
+ * ss_engine_submit: admits every problem of op as one request.  f_dev, u_dev:
+ *   device complex128 vectors of op's n_total entries in canonical order
+ *   (u_dev: initial guess in, solution out); op, f_dev and u_dev must stay
+ *   valid until every problem of the request has been polled.  Returns
+ *   SS_ENOMEM -- and admits nothing -- when the budget or the slots would be
+ *   exceeded (the caller keeps the request queued), SS_EINVAL if op already
+ *   has a solve in flight.
+ * ss_engine_step: one tick; *n_active = problems still active.  Synchronises.
+ * ss_engine_poll: moves up to cap finished problems out: tags[i] (request tag),
+ *   probs[i] (problem index within the request's op), info[i].  Host arrays,
+ *   each nullable except n_out.
+ * ss_engine_usage: admitted requests and the bytes they hold.
+ */
+typedef struct ss_engine ss_engine;
+ss_status ss_engine_create(int64_t hbm_budget_bytes, int32_t max_slots, void* stream, ss_engine** out);
+ss_status ss_engine_submit(ss_engine* e, ss_op* op, const void* f_dev, void* u_dev, double tol,
+                           ss_precision prec, int32_t max_iter, int64_t tag);
+ss_status ss_engine_step(ss_engine* e, int32_t iters, int32_t* n_active);
+ss_status ss_engine_poll(ss_engine* e, int32_t cap, int64_t* tags, int32_t* probs,
+                         ss_solve_info* info, int32_t* n_out);
+ss_status ss_engine_usage(const ss_engine* e, int32_t* n_active_requests, int64_t* bytes);
+void ss_engine_free(ss_engine* e);
+
 /* ---------------------------------------------------------------- one shot
  * ss_solve -- Alg. 1 steps 3-5 for one problem from host data.
  *   a: n_a frequencies/coefficients (exact zeros dropped, -w completed);

@@ -15,6 +15,9 @@ struct ss_stamp {
 struct ss_op {
   ss::OpImpl* impl;
 };
+struct ss_engine {
+  ss::EngineImpl* impl;
+};
 
 namespace ss {
 
@@ -193,6 +196,62 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
     if (!op || !op->impl) return fail(SS_EINVAL, "null operator");
     return solve_op_impl(op->impl, f_dev, u_dev, tol, prec, max_iter, as_stream(stream), info);
   });
+}
+
+ss_status ss_op_bytes(const ss_op* op, int64_t* bytes) {
+  return guarded([&]() -> ss_status {
+    if (!op || !op->impl || !bytes) return fail(SS_EINVAL, "null argument");
+    *bytes = op_device_bytes(op->impl) + (int64_t)op->impl->ws.bytes;
+    return SS_OK;
+  });
+}
+
+ss_status ss_engine_create(int64_t hbm_budget_bytes, int32_t max_slots, void* stream, ss_engine** out) {
+  return guarded([&]() -> ss_status {
+    if (!out) return fail(SS_EINVAL, "out is null");
+    *out = nullptr;
+    if (hbm_budget_bytes < 0 || max_slots < 0) return fail(SS_EINVAL, "negative budget or slot count");
+    EngineImpl* e = nullptr;
+    SS_TRY(engine_create(hbm_budget_bytes, max_slots, as_stream(stream), &e));
+    *out = new ss_engine{e};
+    return SS_OK;
+  });
+}
+
+ss_status ss_engine_submit(ss_engine* e, ss_op* op, const void* f_dev, void* u_dev, double tol, ss_precision prec,
+                           int32_t max_iter, int64_t tag) {
+  return guarded([&]() -> ss_status {
+    if (!e || !e->impl || !op || !op->impl) return fail(SS_EINVAL, "null engine or operator");
+    return engine_submit(e->impl, op->impl, f_dev, u_dev, tol, prec, max_iter, tag);
+  });
+}
+
+ss_status ss_engine_step(ss_engine* e, int32_t iters, int32_t* n_active) {
+  return guarded([&]() -> ss_status {
+    if (!e || !e->impl) return fail(SS_EINVAL, "null engine");
+    return engine_step(e->impl, iters, n_active);
+  });
+}
+
+ss_status ss_engine_poll(ss_engine* e, int32_t cap, int64_t* tags, int32_t* probs, ss_solve_info* info,
+                         int32_t* n_out) {
+  return guarded([&]() -> ss_status {
+    if (!e || !e->impl || !n_out || cap < 0) return fail(SS_EINVAL, "bad argument");
+    return engine_poll(e->impl, cap, tags, probs, info, n_out);
+  });
+}
+
+ss_status ss_engine_usage(const ss_engine* e, int32_t* n_active_requests, int64_t* bytes) {
+  return guarded([&]() -> ss_status {
+    if (!e || !e->impl) return fail(SS_EINVAL, "null engine");
+    return engine_usage(e->impl, n_active_requests, bytes);
+  });
+}
+
+void ss_engine_free(ss_engine* e) {
+  if (!e) return;
+  engine_free(e->impl);
+  delete e;
 }
 
 void ss_free_op(ss_op* op) {

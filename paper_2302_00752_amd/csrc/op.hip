@@ -303,6 +303,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
       if (j != at.zero) l1 += std::hypot(c.x, c.y);
     }
     a0[p] = at.coef[at.zero].x;
+    op->a0_host.push_back(a0[p]);
     if (!(flags & SS_SKIP_L1_CHECK) && !(l1 < a0[p]))
       return fail(SS_ENOTPD, "l1 positivity certificate failed: a_0 <= sum |a_w| (pass SS_SKIP_L1_CHECK "
                              "if a is known to be positive)");
@@ -515,6 +516,7 @@ void free_op_impl(OpImpl* op) {
   dfree(op->d_a0);
   if (op->ws.base) (void)hipFree(op->ws.base);
   if (op->h_pinned) (void)hipHostFree(op->h_pinned);
+  free_apply_cache(op);
   delete op;
 }
 

@@ -1,4 +1,5 @@
-// Matvec and Jacobi-preconditioned CG on the SELL-64 layout.
+// Matvec, Jacobi-preconditioned CG, FP32 + FP64 refinement, and the
+// continuous-batching engine, all on the SELL-64 layout.
 //
 // Operator (Sec. 9, Eq. FiniteGalerkinOperator): for execution row e holding
 // key k and a stored entry (column c holding l = k - w_j, index j)
@@ -6,34 +7,35 @@
 // the integer bracket exact in int32 (int64 when |k|^2 >= 2^30), the factor
 // 2 pi^2 a_j pre-scaled per problem and staged in LDS with |w_j|^2.
 //
-// Mapping: one 256-thread block per work item = up to four 64-row slices of
-// one problem; one wavefront per slice, one lane per row; entries of a slice
-// are stored column-major, so each step of the row loop is one coalesced
-// 256-byte load per wavefront.  Gathers of x and |l|^2 stay inside the row's
-// problem and class.  Work items are assigned to blocks so that consecutive
-// items land on the same XCD (blocks are dealt to the 8 XCDs round-robin), so
-// one problem's gathers hit one L2.
+// Every launch works on a list of problem descriptors (operator slice, vectors,
+// solver state, request parameters) and a list of work items (up to four
+// 64-row slices of one problem per 256-thread block; one wavefront per slice,
+// one lane per row; a slice's entries are stored column-major so each step of
+// the row loop is one coalesced 256-byte load).  Work items are dealt to
+// blocks so consecutive items land on one XCD (the hardware deals blocks to
+// the 8 XCDs round-robin), keeping a problem's gathers in one L2.  The same
+// kernels serve a batch of problems of one operator (ss_solve_op) and a
+// changing mix of problems of many operators (the engine), so a problem's
+// arithmetic never depends on what runs beside it.
 //
-// CG (textbook PCG, the Jacobi diagonal 4 pi^2 |k|^2 a_0 being the
-// denominator of the recurrence in the proof of Prop. SolutionSupport; row
-// k = 0 is identically zero and is excluded).  Each problem of a batch runs
-// its own CG with its own scalars.  Every inner product is reduced in a fixed
-// order -- lanes, then wavefronts, then the problem's work items -- that
-// depends only on the problem itself, so a problem's iterates are bitwise the
-// same alone and inside any batch.  Three kernels per iteration:
-//   mv_dot  q = L p,  partial <p, q>
-//   update  alpha = rho / <p, q>;  x += alpha p;  r -= alpha q;  partial <r, D^-1 r>, |r|^2
-//   dir     beta = rho' / rho;  stop test |r| <= tol |f|;  p = D^-1 r + beta p
-// Scalars that one kernel writes are read only by later kernels (rho is
-// double-buffered by iteration parity).
+// CG: textbook PCG with the Jacobi diagonal 4 pi^2 |k|^2 a_0 (the denominator
+// of the recurrence in the proof of Prop. SolutionSupport; row k = 0 is
+// identically zero and excluded).  Each problem has its own scalars; each
+// inner product is reduced in a fixed order -- lanes, wavefronts, then the
+// problem's work items -- so results are bitwise independent of the batch.
+// Per iteration: mv (q = L p, <p,q>), update (x, r, <r, D^-1 r>, |r|^2),
+// dir (beta, stop test |r| <= tol |f|, p).  A scalar written by one kernel is
+// read only by later kernels.
 //
-// FP32 + refinement: the outer loop forms r = f - L x with the FP64 operator,
-// scales it to unit norm, runs FP32 PCG (FP32 operator, FP32 vectors, FP64
-// inner products) to a loose tolerance, and adds the correction to x in FP64,
-// until the FP64 residual meets tol.
+// FP32 + refinement, as a per-problem device state machine: r = f - L x with
+// the FP64 operator; stop if |r| <= tol |f|; else scale r to unit norm, run
+// FP32 PCG (FP32 operator and vectors, FP64 inner products) to a loose
+// tolerance, add the correction to x in FP64, repeat.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
+#include <unordered_map>
 
 #include "ss_internal.h"
 
@@ -41,18 +43,43 @@ namespace ss {
 
 namespace {
 
-constexpr double kTwoPi2 = 2.0 * M_PI * M_PI;
 constexpr double kFourPi2 = 4.0 * M_PI * M_PI;
+constexpr double kInnerTol = 1e-5;   // FP32 correction solves
+constexpr int kMaxOuter = 30;
 
 enum { MV_PLAIN = 0, MV_DOT = 1, MV_RESID = 2 };
+
+// One problem in a launch.
+struct Desc {
+  const uint32_t* sent;        // operator SELL entries
+  const uint32_t* sptr;        // operator slice offsets (operator-global slice index)
+  const void* norm;            // |k|^2 of the problem's first execution row
+  const double2* A64;          // the problem's 64-entry tables
+  const float2* A32;
+  const int64_t* nu;
+  const int64_t* exec2canon;   // problem's execution rows -> operator-global canonical slot (-1 pad)
+  const double2* f_canon;      // request: operator-global canonical f
+  double2* u_canon;            // request: operator-global canonical u (in: x0, out: solution)
+  double2 *x64, *r64, *p64, *q64, *f64;   // problem-local, execution order
+  float2 *x32, *r32, *p32, *q32;
+  PState* ps;                  // FP64 / outer state
+  PState* ps_in;               // FP32 inner state
+  double a0;
+  double tol2, tol2_in;
+  int64_t slice0;              // operator-global index of the problem's first slice
+  int64_t n_rows;              // execution rows (multiple of 64)
+  int32_t max_iter;
+  int32_t prec;                // SS_FP64 or SS_FP32_REFINE
+  int32_t wide;                // int64 norms
+  int32_t wb, we;              // the problem's work items in the current list
+  int32_t init;                // first tick after admission
+  int32_t final_;              // retiring: compute the true residual and write u
+  int32_t pad;
+};
 
 template <typename V> struct Real;
 template <> struct Real<double2> { using T = double; };
 template <> struct Real<float2> { using T = float; };
-
-template <typename V> __device__ inline const V* atab(const OpDev& op);
-template <> __device__ inline const double2* atab<double2>(const OpDev& op) { return op.A64; }
-template <> __device__ inline const float2* atab<float2>(const OpDev& op) { return op.A32; }
 
 __device__ inline int work_index(int b, int per) { return (b & 7) * per + (b >> 3); }
 
@@ -62,7 +89,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum of v over the block; valid in thread 0 only.  Fixed order.
+// Sum of v over the block, returned to every thread.  Fixed order.
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -73,18 +100,30 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// Sum of part[i*stride + off] for i in [b, e), every thread gets the result.  Fixed order.
-__device__ inline double range_sum(const double* __restrict__ part, int stride, int off, int b, int e,
-                                   double* red) {
+// Sum of part[i*2 + off] for i in [b, e), every thread gets the result.  Fixed order.
+__device__ inline double range_sum(const double* __restrict__ part, int off, int b, int e, double* red) {
   double v = 0;
-  for (int i = b + (int)threadIdx.x; i < e; i += kBlock) v += part[(int64_t)i * stride + off];
+  for (int i = b + (int)threadIdx.x; i < e; i += kBlock) v += part[(int64_t)i * 2 + off];
   return block_sum(v, red);
 }
 
+// CG state of the problem's current CG run
+__device__ inline PState* cg_state(const Desc& D) { return D.prec == SS_FP64 ? D.ps : D.ps_in; }
+
+// no CG work for this problem now
+__device__ inline bool cg_idle(const Desc& D) {
+  return D.ps->done || (D.prec != SS_FP64 && D.ps_in->done);
+}
+
+template <typename NormT>
+__device__ inline double jacobi_inv(NormT nk, double a0) {
+  return nk > 0 ? 1.0 / (kFourPi2 * a0 * (double)nk) : 0.0;
+}
+
 template <typename NormT, typename V>
-__device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, uint32_t width, int lane,
-                             NormT nk, const NormT* __restrict__ normp, const V* __restrict__ xp,
-                             const V* As, const NormT* nus) {
+__device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, uint32_t width, int lane, NormT nk,
+                             const NormT* __restrict__ normp, const V* __restrict__ xp, const V* As,
+                             const NormT* nus) {
   using R = typename Real<V>::T;
   R ar = 0, ai = 0;
   for (uint32_t q = 0; q < width; ++q) {
@@ -107,35 +146,44 @@ __device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, u
   return out;
 }
 
-// y = L x (PLAIN);  q = L p with partial Re<p, q> (DOT);  r = f - L x with partials |r|^2, |f|^2 (RESID)
+template <typename V> __device__ inline const V* a_table(const Desc& D);
+template <> __device__ inline const double2* a_table<double2>(const Desc& D) { return D.A64; }
+template <> __device__ inline const float2* a_table<float2>(const Desc& D) { return D.A32; }
+
+// Matvec over one work item.  PLAIN: q = L x;  DOT: q = L p, partial Re<p, q>;
+// RESID: r = f - L x (FP64), partials |r|^2, |f|^2.
 template <typename NormT, typename V, int MODE>
-__global__ __launch_bounds__(kBlock) void k_mv(OpDev op, const V* __restrict__ x, V* __restrict__ y,
-                                               const V* __restrict__ f, double* __restrict__ part,
-                                               const PState* __restrict__ ps, int per) {
-  const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (MODE != MV_PLAIN && ps[p].done) return;
-  __shared__ V As[64];
-  __shared__ NormT nus[64];
-  __shared__ double red[4];
+__device__ void mv_body(const Desc& D, int4 wk, int w, double* part, void* lds) {
+  V* As = (V*)lds;
+  NormT* nus = (NormT*)((char*)lds + 64 * sizeof(double2));
+  double* red = (double*)((char*)lds + 64 * sizeof(double2) + 64 * sizeof(int64_t));
   const int tid = threadIdx.x;
   if (tid < 64) {
-    As[tid] = atab<V>(op)[p * 64 + tid];
-    nus[tid] = (NormT)op.nu[p * 64 + tid];
+    As[tid] = a_table<V>(D)[tid];
+    nus[tid] = (NormT)D.nu[tid];
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
+  const V* x;
+  V* y;
+  if (MODE == MV_DOT) {
+    x = (const V*)(sizeof(V) == 16 ? (const void*)D.p64 : (const void*)D.p32);
+    y = (V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
+  } else if (MODE == MV_RESID) {
+    x = (const V*)D.x64;
+    y = (V*)D.r64;
+  } else {
+    x = (const V*)(sizeof(V) == 16 ? (const void*)D.x64 : (const void*)D.x32);
+    y = (V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
+  }
   double v0 = 0, v1 = 0;
   if (wave < wk.z) {
     const int64_t sl = wk.y + wave;
-    const int64_t e = sl * kSlice + lane;
-    const int64_t eb = op.eoff[p];
-    const NormT* normv = (const NormT*)op.norm;
-    const uint32_t base = op.sptr[sl];
-    const uint32_t width = (op.sptr[sl + 1] - base) / kSlice;
-    const V acc = sell_row<NormT, V>(op.sent, base, width, lane, normv[e], normv + eb, x + eb, As, nus);
+    const int64_t e = (sl - D.slice0) * kSlice + lane;
+    const NormT* normv = (const NormT*)D.norm;
+    const uint32_t base = D.sptr[sl];
+    const uint32_t width = (D.sptr[sl + 1] - base) / kSlice;
+    const V acc = sell_row<NormT, V>(D.sent, base, width, lane, normv[e], normv, x, As, nus);
     if (MODE == MV_PLAIN) {
       y[e] = acc;
     } else if (MODE == MV_DOT) {
@@ -143,21 +191,18 @@ __global__ __launch_bounds__(kBlock) void k_mv(OpDev op, const V* __restrict__ x
       const V pe = x[e];
       v0 = (double)pe.x * (double)acc.x + (double)pe.y * (double)acc.y;
     } else {
-      const V fe = f[e];
+      const double2 fe = D.f64[e];
       V r;
       r.x = fe.x - acc.x;
       r.y = fe.y - acc.y;
       y[e] = r;
       v0 = (double)r.x * r.x + (double)r.y * r.y;
-      v1 = (double)fe.x * fe.x + (double)fe.y * fe.y;
+      v1 = fe.x * fe.x + fe.y * fe.y;
     }
   }
-  if (MODE == MV_DOT) {
-    const double s = block_sum(v0, red);
-    if (tid == 0) part[2 * (int64_t)w] = s;
-  } else if (MODE == MV_RESID) {
+  if (MODE != MV_PLAIN) {
     const double s0 = block_sum(v0, red);
-    const double s1 = block_sum(v1, red);
+    const double s1 = MODE == MV_RESID ? block_sum(v1, red) : 0.0;
     if (tid == 0) {
       part[2 * (int64_t)w] = s0;
       part[2 * (int64_t)w + 1] = s1;
@@ -165,39 +210,65 @@ __global__ __launch_bounds__(kBlock) void k_mv(OpDev op, const V* __restrict__ x
   }
 }
 
-template <typename NormT>
-__device__ inline double jacobi_inv(NormT nk, double a0) {
-  return nk > 0 ? 1.0 / (kFourPi2 * a0 * (double)nk) : 0.0;
+constexpr int kLdsBytes = 64 * 16 + 64 * 8 + 4 * 8;
+
+// only_final (RESID): 1 = problems being retired only, 0 = admissions and refinement steps only
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_mv(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                               int n_work, int per, double* part, int only_final = 0) {
+  const int w = work_index(blockIdx.x, per);
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (MODE == MV_DOT) {
+    if (cg_idle(D)) return;
+    if (w == D.wb && threadIdx.x == 0) {   // iteration index for update/dir (read only by later kernels)
+      PState* cs = cg_state(D);
+      cs->iter = cs->iters;
+    }
+  } else if (MODE == MV_RESID) {
+    if (only_final) {
+      if (!D.final_) return;
+    } else {
+      const bool outer = D.prec != SS_FP64 ? (!D.ps->done && D.ps_in->done) : false;
+      if (!(D.init && D.prec == SS_FP64) && !outer) return;
+    }
+  }
+  __shared__ __align__(16) char lds[kLdsBytes];
+  const bool fp32 = MODE == MV_DOT ? D.prec != SS_FP64 : (MODE == MV_PLAIN && D.prec != SS_FP64);
+  if (fp32) {
+    if (D.wide) mv_body<int64_t, float2, MODE == MV_RESID ? MV_DOT : MODE>(D, wk, w, part, lds);
+    else mv_body<int32_t, float2, MODE == MV_RESID ? MV_DOT : MODE>(D, wk, w, part, lds);
+  } else {
+    if (D.wide) mv_body<int64_t, double2, MODE>(D, wk, w, part, lds);
+    else mv_body<int32_t, double2, MODE>(D, wk, w, part, lds);
+  }
 }
 
 // alpha = rho / <p,q>;  x += alpha p;  r -= alpha q;  partials <r, D^-1 r>, |r|^2
 template <typename NormT, typename V>
-__global__ __launch_bounds__(kBlock) void k_cg_update(OpDev op, V* __restrict__ x, V* __restrict__ r,
-                                                      const V* __restrict__ pv, const V* __restrict__ q,
-                                                      const double* __restrict__ part_pq,
-                                                      double* __restrict__ part_rz, PState* ps, int par,
-                                                      int per) {
+__device__ void update_body(const Desc& D, int4 wk, int w, const double* part_pq, double* part_rz, double* red) {
   using R = typename Real<V>::T;
-  const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (ps[p].done) return;
-  __shared__ double red[4];
-  const int2 wr = op.wrange[p];
-  const double pq = range_sum(part_pq, 2, 0, wr.x, wr.y, red);
-  const double alpha = ps[p].rho[par] / pq;
+  PState* cs = cg_state(D);
+  const double pq = range_sum(part_pq, 0, D.wb, D.we, red);
+  const double alpha = cs->rho[cs->iter & 1] / pq;
   if (!(pq > 0.0) || !isfinite(alpha)) {
-    if (w == wr.x && threadIdx.x == 0) {
-      ps[p].status = SS_EBREAKDOWN;
-      ps[p].done = 1;
+    if (w == D.wb && threadIdx.x == 0) {
+      cs->status = SS_EBREAKDOWN;
+      cs->done = 1;
+      D.ps->status = SS_EBREAKDOWN;
+      D.ps->done = 1;
     }
     return;
   }
+  V* x = (V*)(sizeof(V) == 16 ? (void*)D.x64 : (void*)D.x32);
+  V* r = (V*)(sizeof(V) == 16 ? (void*)D.r64 : (void*)D.r32);
+  const V* pv = (const V*)(sizeof(V) == 16 ? (void*)D.p64 : (void*)D.p32);
+  const V* q = (const V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double v0 = 0, v1 = 0;
   if (wave < wk.z) {
-    const int64_t e = (int64_t)(wk.y + wave) * kSlice + lane;
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
     const R a = (R)alpha;
     V xv = x[e], rv = r[e];
     const V pe = pv[e], qe = q[e];
@@ -208,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(OpDev op, V* __restrict__ 
     x[e] = xv;
     r[e] = rv;
     const double rr = (double)rv.x * rv.x + (double)rv.y * rv.y;
-    v0 = rr * jacobi_inv(((const NormT*)op.norm)[e], op.a0[p]);
+    v0 = rr * jacobi_inv(((const NormT*)D.norm)[e], D.a0);
     v1 = rr;
   }
   const double s0 = block_sum(v0, red);
@@ -219,34 +290,52 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(OpDev op, V* __restrict__ 
   }
 }
 
-// beta = rho'/rho;  convergence;  p = D^-1 r + beta p
-template <typename NormT, typename V>
-__global__ __launch_bounds__(kBlock) void k_cg_dir(OpDev op, const V* __restrict__ r, V* __restrict__ pv,
-                                                   const double* __restrict__ part_rz, PState* ps, int par,
-                                                   double tol2, int per) {
-  using R = typename Real<V>::T;
+__global__ __launch_bounds__(kBlock) void k_cg_update(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                      int n_work, int per, const double* part_pq,
+                                                      double* part_rz) {
   const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (ps[p].done) return;
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (cg_idle(D)) return;
   __shared__ double red[4];
-  const int2 wr = op.wrange[p];
-  const double rz = range_sum(part_rz, 2, 0, wr.x, wr.y, red);
-  const double rr = range_sum(part_rz, 2, 1, wr.x, wr.y, red);
-  const double beta = rz / ps[p].rho[par];
-  const bool conv = rr <= tol2 * ps[p].ff;
-  if (w == wr.x && threadIdx.x == 0) {
-    ps[p].rho[par ^ 1] = rz;
-    ps[p].rr = rr;
-    ps[p].iters += 1;
-    if (conv) ps[p].done = 1;
+  if (D.prec == SS_FP64) {
+    if (D.wide) update_body<int64_t, double2>(D, wk, w, part_pq, part_rz, red);
+    else update_body<int32_t, double2>(D, wk, w, part_pq, part_rz, red);
+  } else {
+    if (D.wide) update_body<int64_t, float2>(D, wk, w, part_pq, part_rz, red);
+    else update_body<int32_t, float2>(D, wk, w, part_pq, part_rz, red);
   }
-  if (conv) return;
+}
+
+// beta = rho'/rho;  stop test;  p = D^-1 r + beta p
+template <typename NormT, typename V>
+__device__ void dir_body(const Desc& D, int4 wk, int w, const double* part_rz, double* red) {
+  using R = typename Real<V>::T;
+  PState* cs = cg_state(D);
+  const double rz = range_sum(part_rz, 0, D.wb, D.we, red);
+  const double rr = range_sum(part_rz, 1, D.wb, D.we, red);
+  const int it = cs->iter;
+  const double beta = rz / cs->rho[it & 1];
+  const double tol2 = D.prec == SS_FP64 ? D.tol2 : D.tol2_in;
+  const bool conv = rr <= tol2 * cs->ff;
+  const bool out_of_iters = it + 1 >= D.max_iter;
+  if (w == D.wb && threadIdx.x == 0) {
+    cs->rho[(it & 1) ^ 1] = rz;
+    cs->rr = rr;
+    cs->iters = it + 1;
+    if (conv || out_of_iters) {
+      cs->done = 1;
+      if (!conv) cs->status = SS_ENOCONV;
+    }
+  }
+  if (conv || out_of_iters) return;
+  const V* r = (const V*)(sizeof(V) == 16 ? (void*)D.r64 : (void*)D.r32);
+  V* pv = (V*)(sizeof(V) == 16 ? (void*)D.p64 : (void*)D.p32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (wave < wk.z) {
-    const int64_t e = (int64_t)(wk.y + wave) * kSlice + lane;
-    const R dinv = (R)jacobi_inv(((const NormT*)op.norm)[e], op.a0[p]);
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const R dinv = (R)jacobi_inv(((const NormT*)D.norm)[e], D.a0);
     const R b = (R)beta;
     const V re = r[e];
     V pe = pv[e];
@@ -256,22 +345,34 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(OpDev op, const V* __restrict
   }
 }
 
-// Start of a CG run from residual r (x already consistent): p = D^-1 r, partial <r, D^-1 r>, |r|^2.
-template <typename NormT, typename V>
-__global__ __launch_bounds__(kBlock) void k_cg_start(OpDev op, const V* __restrict__ r, V* __restrict__ pv,
-                                                     double* __restrict__ part_rz, const PState* ps, int per) {
-  using R = typename Real<V>::T;
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                   int n_work, int per, const double* part_rz) {
   const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (ps[p].done) return;
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (cg_idle(D)) return;
   __shared__ double red[4];
+  if (D.prec == SS_FP64) {
+    if (D.wide) dir_body<int64_t, double2>(D, wk, w, part_rz, red);
+    else dir_body<int32_t, double2>(D, wk, w, part_rz, red);
+  } else {
+    if (D.wide) dir_body<int64_t, float2>(D, wk, w, part_rz, red);
+    else dir_body<int32_t, float2>(D, wk, w, part_rz, red);
+  }
+}
+
+// start of a CG run: p = D^-1 r, partials <r, D^-1 r>, |r|^2
+template <typename NormT, typename V>
+__device__ void start_body(const Desc& D, int4 wk, int w, double* part_rz, double* red) {
+  using R = typename Real<V>::T;
+  const V* r = (const V*)(sizeof(V) == 16 ? (void*)D.r64 : (void*)D.r32);
+  V* pv = (V*)(sizeof(V) == 16 ? (void*)D.p64 : (void*)D.p32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double v0 = 0, v1 = 0;
   if (wave < wk.z) {
-    const int64_t e = (int64_t)(wk.y + wave) * kSlice + lane;
-    const double di = jacobi_inv(((const NormT*)op.norm)[e], op.a0[p]);
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const double di = jacobi_inv(((const NormT*)D.norm)[e], D.a0);
     const V re = r[e];
     V pe;
     pe.x = (R)di * re.x;
@@ -289,154 +390,290 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(OpDev op, const V* __restri
   }
 }
 
-// One block per problem: scalars of a fresh CG run.  ff is |rhs|^2 (taken
-// from `part_f` column 1 when given, else equal to the start residual).
-__global__ void k_cg_scalars(OpDev op, const double* __restrict__ part_rz, const double* __restrict__ part_f,
-                             PState* ps, double tol2) {
-  const int p = blockIdx.x;
-  if (p >= op.n_prob) return;
+__global__ __launch_bounds__(kBlock) void k_cg_start(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                     int n_work, int per, double* part_rz) {
+  const int w = work_index(blockIdx.x, per);
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (!cg_state(D)->start) return;
   __shared__ double red[4];
-  const int2 wr = op.wrange[p];
-  const double rz = range_sum(part_rz, 2, 0, wr.x, wr.y, red);
-  const double rr = range_sum(part_rz, 2, 1, wr.x, wr.y, red);
-  const double ff = part_f ? range_sum(part_f, 2, 1, wr.x, wr.y, red) : rr;
-  if (threadIdx.x == 0 && !ps[p].done) {
-    ps[p].rho[0] = rz;
-    ps[p].rr = rr;
-    ps[p].rr0 = rr;
-    ps[p].ff = ff;
-    ps[p].iters = 0;
-    if (rr <= tol2 * ff) ps[p].done = 1;
+  if (D.prec == SS_FP64) {
+    if (D.wide) start_body<int64_t, double2>(D, wk, w, part_rz, red);
+    else start_body<int32_t, double2>(D, wk, w, part_rz, red);
+  } else {
+    if (D.wide) start_body<int64_t, float2>(D, wk, w, part_rz, red);
+    else start_body<int32_t, float2>(D, wk, w, part_rz, red);
   }
 }
 
-// One block per problem: |r|^2 and |f|^2 of an FP64 residual; outer stop test.
-__global__ void k_resid_scalars(OpDev op, const double* __restrict__ part, PState* ps, double tol2,
-                                int mark_done) {
+// one block per problem: scalars of a CG run being started
+__global__ void k_cg_scalars(const Desc* __restrict__ descs, int n_desc, const double* part_rz) {
   const int p = blockIdx.x;
-  if (p >= op.n_prob) return;
+  if (p >= n_desc) return;
+  const Desc& D = descs[p];
+  PState* cs = cg_state(D);
+  if (!cs->start) return;
   __shared__ double red[4];
-  const int2 wr = op.wrange[p];
-  const double rr = range_sum(part, 2, 0, wr.x, wr.y, red);
-  const double ff = range_sum(part, 2, 1, wr.x, wr.y, red);
+  const double rz = range_sum(part_rz, 0, D.wb, D.we, red);
+  const double rr = range_sum(part_rz, 1, D.wb, D.we, red);
   if (threadIdx.x == 0) {
-    ps[p].rr = rr;
-    ps[p].ff = ff;
-    ps[p].scale = sqrt(rr);
-    if (mark_done && !ps[p].done && rr <= tol2 * ff) ps[p].done = 1;
+    if (D.prec != SS_FP64) {
+      D.ps->total_iters += cs->iters;   // previous correction solve
+      cs->ff = rr;
+      cs->pending = 1;
+    }
+    cs->rho[0] = rz;
+    cs->rr = rr;
+    cs->iter = 0;
+    cs->iters = 0;
+    cs->start = 0;
+    cs->status = SS_OK;
+    const double tol2 = D.prec == SS_FP64 ? D.tol2 : D.tol2_in;
+    cs->done = rr <= tol2 * cs->ff ? 1 : 0;
   }
 }
 
-__global__ void k_count_active(int n_prob, const PState* ps, int* out) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  int c = 0;
-  for (int p = threadIdx.x; p < n_prob; p += blockDim.x) c += ps[p].done ? 0 : 1;
-  atomicAdd(&cnt, c);
-  __syncthreads();
-  if (threadIdx.x == 0) *out = cnt;
-}
-
-// canonical -> execution order (padding rows get 0); k = 0 rows of x forced to 0
-__global__ void k_gather_in(int64_t n_exec, const int64_t* __restrict__ exec2canon, const double2* __restrict__ fc,
-                            const double2* __restrict__ uc, double2* __restrict__ f, double2* __restrict__ x) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_exec) return;
-  const int64_t r = exec2canon[e];
-  double2 fv = make_double2(0, 0), xv = make_double2(0, 0);
-  if (r >= 0) {
-    fv = fc[r];
-    xv = uc[r];
-  }
-  f[e] = fv;
-  x[e] = xv;
-}
-
-template <typename NormT>
-__global__ void k_scatter_out(int64_t n_exec, const int64_t* __restrict__ exec2canon, const NormT* __restrict__ norm,
-                              const double2* __restrict__ x, double2* __restrict__ uc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_exec) return;
-  const int64_t r = exec2canon[e];
-  if (r >= 0) uc[r] = norm[e] > 0 ? x[e] : make_double2(0, 0);
-}
-
-template <typename NormT>
-__global__ void k_zero_k0(int64_t n_exec, const NormT* __restrict__ norm, double2* __restrict__ x) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n_exec && norm[e] == 0) x[e] = make_double2(0, 0);
-}
-
-// FP32 inner start: r32 = r64 / scale, x32 = 0 (problems still open)
-__global__ void k_refine_start(OpDev op, const double2* __restrict__ r64, float2* __restrict__ r32,
-                               float2* __restrict__ x32, const PState* ps_outer, int per) {
+// x64 += scale * x32 after a finished correction solve
+__global__ __launch_bounds__(kBlock) void k_refine_add(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                       int n_work, int per) {
   const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (ps_outer[p].done) return;
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (D.prec == SS_FP64 || D.ps->done || !D.ps_in->done || !D.ps_in->pending) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (wave < wk.z) {
-    const int64_t e = (int64_t)(wk.y + wave) * kSlice + lane;
-    const double s = ps_outer[p].scale > 0 ? 1.0 / ps_outer[p].scale : 0.0;
-    const double2 rv = r64[e];
-    r32[e] = make_float2((float)(rv.x * s), (float)(rv.y * s));
-    x32[e] = make_float2(0.f, 0.f);
-  }
-}
-
-// x64 += scale * x32
-__global__ void k_refine_add(OpDev op, double2* __restrict__ x64, const float2* __restrict__ x32,
-                             const PState* ps_outer, int per) {
-  const int w = work_index(blockIdx.x, per);
-  if (w >= op.n_work) return;
-  const int4 wk = op.work[w];
-  const int p = wk.x;
-  if (ps_outer[p].done) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (int64_t)(wk.y + wave) * kSlice + lane;
-    const double s = ps_outer[p].scale;
-    const float2 c = x32[e];
-    double2 xv = x64[e];
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const double s = D.ps->scale;
+    const float2 c = D.x32[e];
+    double2 xv = D.x64[e];
     xv.x += s * (double)c.x;
     xv.y += s * (double)c.y;
-    x64[e] = xv;
+    D.x64[e] = xv;
   }
 }
 
-__global__ void k_accum_iters(int n_prob, PState* ps, const PState* ps_in) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n_prob) ps[p].total_iters += ps_in[p].iters;
+// One block per problem after an FP64 residual: the outer stop test and the next step.
+__global__ void k_outer_scalars(const Desc* __restrict__ descs, int n_desc, const double* part) {
+  const int p = blockIdx.x;
+  if (p >= n_desc) return;
+  const Desc& D = descs[p];
+  const bool fp64_init = D.init && D.prec == SS_FP64;
+  const bool outer = D.prec != SS_FP64 && !D.ps->done && D.ps_in->done;
+  if (!fp64_init && !outer) return;
+  __shared__ double red[4];
+  const double rr = range_sum(part, 0, D.wb, D.we, red);
+  const double ff = range_sum(part, 1, D.wb, D.we, red);
+  if (threadIdx.x != 0) return;
+  PState* ps = D.ps;
+  ps->rr = rr;
+  ps->ff = ff;
+  const bool conv = rr <= D.tol2 * ff;
+  if (fp64_init) {
+    if (conv) ps->done = 1;
+    else ps->start = 1;
+    return;
+  }
+  D.ps_in->pending = 0;
+  if (conv || ps->outer >= kMaxOuter) {
+    ps->done = 1;
+    if (!conv) ps->status = SS_ENOCONV;
+    if (D.ps_in->status == SS_EBREAKDOWN && !conv) ps->status = SS_EBREAKDOWN;
+    return;
+  }
+  ps->scale = sqrt(rr);
+  ps->outer += 1;
+  D.ps_in->start = 1;
 }
 
-__global__ void k_init_state(int n_prob, PState* ps, const PState* copy_done_from) {
+// r32 = r64 / scale, x32 = 0 for a correction solve being started
+__global__ __launch_bounds__(kBlock) void k_refine_start(const Desc* __restrict__ descs,
+                                                         const int4* __restrict__ work, int n_work, int per) {
+  const int w = work_index(blockIdx.x, per);
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (D.prec == SS_FP64 || !D.ps_in->start) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (wave < wk.z) {
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const double s = 1.0 / D.ps->scale;
+    const double2 rv = D.r64[e];
+    D.r32[e] = make_float2((float)(rv.x * s), (float)(rv.y * s));
+    D.x32[e] = make_float2(0.f, 0.f);
+  }
+}
+
+// admission: canonical f, u -> execution order (k = 0 and padding rows of x set to 0)
+template <typename NormT>
+__device__ void admit_rows(const Desc& D, int4 wk) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (wave < wk.z) {
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const int64_t r = D.exec2canon[e];
+    double2 fv = make_double2(0, 0), xv = make_double2(0, 0);
+    if (r >= 0) {
+      fv = D.f_canon[r];
+      if (((const NormT*)D.norm)[e] > 0) xv = D.u_canon[r];
+    }
+    D.f64[e] = fv;
+    D.x64[e] = xv;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_admit(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                  int n_work, int per) {
+  const int w = work_index(blockIdx.x, per);
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (!D.init) return;
+  if (D.wide) admit_rows<int64_t>(D, wk);
+  else admit_rows<int32_t>(D, wk);
+}
+
+__global__ void k_state_init(const Desc* __restrict__ descs, int n_desc) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_prob) return;
+  if (p >= n_desc) return;
+  const Desc& D = descs[p];
+  if (!D.init) return;
   PState s{};
-  s.done = copy_done_from ? copy_done_from[p].done : 0;
-  s.status = SS_OK;
-  ps[p] = s;
+  *D.ps = s;
+  s.done = 1;   // no correction solve yet: the first refinement step starts with a residual
+  *D.ps_in = s;
+}
+
+// retiring: u = x (canonical order), and |f - L x|^2, |f|^2 of the final iterate
+template <typename NormT>
+__device__ void retire_rows(const Desc& D, int4 wk) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (wave < wk.z) {
+    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+    const int64_t r = D.exec2canon[e];
+    if (r >= 0) D.u_canon[r] = ((const NormT*)D.norm)[e] > 0 ? D.x64[e] : make_double2(0, 0);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_retire(const Desc* __restrict__ descs, const int4* __restrict__ work,
+                                                   int n_work, int per) {
+  const int w = work_index(blockIdx.x, per);
+  if (w >= n_work) return;
+  const int4 wk = work[w];
+  const Desc& D = descs[wk.x];
+  if (!D.final_) return;
+  if (D.wide) retire_rows<int64_t>(D, wk);
+  else retire_rows<int32_t>(D, wk);
+}
+
+__global__ void k_final_scalars(const Desc* __restrict__ descs, int n_desc, const double* part, PState* out) {
+  const int p = blockIdx.x;
+  if (p >= n_desc) return;
+  const Desc& D = descs[p];
+  if (!D.final_) return;
+  __shared__ double red[4];
+  const double rr = range_sum(part, 0, D.wb, D.we, red);
+  const double ff = range_sum(part, 1, D.wb, D.we, red);
+  if (threadIdx.x == 0) {
+    PState s = *D.ps;
+    s.rr = rr;
+    s.ff = ff;
+    s.total_iters = D.prec == SS_FP64 ? D.ps->iters : D.ps->total_iters + D.ps_in->iters;
+    out[p] = s;
+  }
+}
+
+// compact copy of every problem's FP64/outer state, for host polling
+__global__ void k_gather_states(const Desc* __restrict__ descs, int n_desc, PState* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_desc) out[p] = *descs[p].ps;
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
 
-// ---------------------------------------------------------------- workspace
+}  // namespace
+
+// ---------------------------------------------------------------- launch lists
+// A set of problems (descriptors) with their work items, device-resident.
+struct LaunchList {
+  std::vector<Desc> descs;
+  std::vector<int4> work;
+  Desc* d_descs = nullptr;
+  int4* d_work = nullptr;
+  double* part = nullptr;          // 3 x 2 x n_work
+  PState* d_states = nullptr;      // n_desc (polling / final)
+  size_t cap_desc = 0, cap_work = 0;
+  int per = 1;
+  unsigned grid = 8;
+
+  ~LaunchList() {
+    dfree(d_descs);
+    dfree(d_work);
+    dfree(part);
+    dfree(d_states);
+  }
+
+  // rebuild work items from descs (each desc's items contiguous) and upload both
+  ss_status upload(hipStream_t s, const std::vector<std::vector<int4>>& items) {
+    work.clear();
+    for (size_t k = 0; k < descs.size(); ++k) {
+      descs[k].wb = (int32_t)work.size();
+      for (int4 it : items[k]) work.push_back(make_int4((int)k, it.y, it.z, 0));
+      descs[k].we = (int32_t)work.size();
+    }
+    if (descs.size() > cap_desc) {
+      dfree(d_descs);
+      dfree(d_states);
+      cap_desc = std::max<size_t>(descs.size(), 2 * cap_desc);
+      SS_TRY(dalloc(&d_descs, cap_desc));
+      SS_TRY(dalloc(&d_states, cap_desc));
+    }
+    if (work.size() > cap_work) {
+      dfree(d_work);
+      dfree(part);
+      cap_work = std::max<size_t>(work.size(), 2 * cap_work);
+      SS_TRY(dalloc(&d_work, cap_work));
+      SS_TRY(dalloc(&part, 6 * cap_work));
+    }
+    if (!descs.empty())
+      SS_HIP(hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(Desc), hipMemcpyHostToDevice, s));
+    if (!work.empty())
+      SS_HIP(hipMemcpyAsync(d_work, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    per = (int)std::max<int64_t>(1, ceil_div((int64_t)work.size(), 8));
+    grid = (unsigned)(8 * per);
+    return SS_OK;
+  }
+  ss_status upload_descs(hipStream_t s) {
+    if (!descs.empty())
+      SS_HIP(hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(Desc), hipMemcpyHostToDevice, s));
+    return SS_OK;
+  }
+  int n_work() const { return (int)work.size(); }
+  int n_desc() const { return (int)descs.size(); }
+  double* part_a() { return part; }
+  double* part_b() { return part + 2 * cap_work; }
+  double* part_c() { return part + 4 * cap_work; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- operator workspace
 struct WS {
   double2 *x64, *r64, *p64, *q64, *f64;
   float2 *x32, *r32, *p32, *q32;
-  double *part_a, *part_b, *part_c;
   PState *ps, *ps_in;
-  int* active;   // pinned host
 };
+
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t workspace_bytes(const OpImpl* op) {
+  const int64_t n = op->n_exec;
+  return al256(5 * n * sizeof(double2)) + al256(4 * n * sizeof(float2)) + al256(2 * op->n_prob * sizeof(PState));
+}
 
 ss_status workspace(OpImpl* op, WS* w) {
   const int64_t n = op->n_exec;
-  const int64_t nw = (int64_t)op->work.size();
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t need = al(5 * n * sizeof(double2)) + al(4 * n * sizeof(float2)) + al(3 * 2 * nw * sizeof(double)) +
-                      al(2 * op->n_prob * sizeof(PState)) + 4096;
+  const size_t need = workspace_bytes(op);
   if (op->ws.bytes < need) {
     if (op->ws.base) (void)hipFree(op->ws.base);
     op->ws.base = nullptr;
@@ -445,185 +682,372 @@ ss_status workspace(OpImpl* op, WS* w) {
     op->ws.bytes = need;
   }
   char* b = (char*)op->ws.base;
-  auto take = [&](size_t bytes) {
-    char* r = b;
-    b += al(bytes);
-    return (void*)r;
-  };
-  w->x64 = (double2*)take(n * sizeof(double2));
+  w->x64 = (double2*)b;
   w->r64 = w->x64 + n;
   w->p64 = w->r64 + n;
   w->q64 = w->p64 + n;
   w->f64 = w->q64 + n;
-  b = (char*)op->ws.base + al(5 * n * sizeof(double2));
-  w->x32 = (float2*)take(4 * n * sizeof(float2));
+  b += al256(5 * n * sizeof(double2));
+  w->x32 = (float2*)b;
   w->r32 = w->x32 + n;
   w->p32 = w->r32 + n;
   w->q32 = w->p32 + n;
-  w->part_a = (double*)take(3 * 2 * nw * sizeof(double));
-  w->part_b = w->part_a + 2 * nw;
-  w->part_c = w->part_b + 2 * nw;
-  w->ps = (PState*)take(2 * op->n_prob * sizeof(PState));
+  b += al256(4 * n * sizeof(float2));
+  w->ps = (PState*)b;
   w->ps_in = w->ps + op->n_prob;
   return SS_OK;
 }
 
-template <typename NormT>
-struct Solver {
-  OpImpl* op;
-  OpDev od;
-  hipStream_t s;
-  int per;
-  unsigned grid;
-  int* h_active = nullptr;
-  int* d_active = nullptr;
+// descriptor of problem p of op, vectors from the op's workspace
+Desc make_desc(const OpImpl* op, const WS& w, int p) {
+  Desc D{};
+  const int64_t e0 = op->eoff[p];
+  D.sent = op->d_sent;
+  D.sptr = op->d_sptr;
+  D.norm = (const char*)op->d_norm + e0 * (op->wide_norm ? 8 : 4);
+  D.A64 = op->d_A64 + (size_t)p * 64;
+  D.A32 = op->d_A32 + (size_t)p * 64;
+  D.nu = op->d_nu + (size_t)p * 64;
+  D.exec2canon = op->d_exec2canon + e0;
+  D.x64 = w.x64 + e0;
+  D.r64 = w.r64 + e0;
+  D.p64 = w.p64 + e0;
+  D.q64 = w.q64 + e0;
+  D.f64 = w.f64 + e0;
+  D.x32 = w.x32 + e0;
+  D.r32 = w.r32 + e0;
+  D.p32 = w.p32 + e0;
+  D.q32 = w.q32 + e0;
+  D.ps = w.ps + p;
+  D.ps_in = w.ps_in + p;
+  D.a0 = op->a0_host[p];
+  D.slice0 = e0 / kSlice;
+  D.n_rows = op->eoff[p + 1] - e0;
+  D.wide = op->wide_norm ? 1 : 0;
+  return D;
+}
 
-  ss_status count_active(const PState* ps, int* out) {
-    k_count_active<<<1, kBlock, 0, s>>>(op->n_prob, ps, d_active);
-    SS_HIP(hipMemcpyAsync(h_active, d_active, 4, hipMemcpyDeviceToHost, s));
-    SS_HIP(hipStreamSynchronize(s));
-    *out = *h_active;
-    return SS_OK;
-  }
-
-  // CG on L x = rhs from the residual already in r (x consistent with it).
-  template <typename V>
-  ss_status cg(V* x, V* r, V* p, V* q, PState* ps, double* part_pq, double* part_rz, const double* part_f,
-               double tol, int max_iter, int* iters_run) {
-    const double tol2 = tol * tol;
-    k_cg_start<NormT, V><<<grid, kBlock, 0, s>>>(od, r, p, part_rz, ps, per);
-    k_cg_scalars<<<op->n_prob, kBlock, 0, s>>>(od, part_rz, part_f, ps, tol2);
-    int it = 0;
-    int check = 4;
-    while (it < max_iter) {
-      const int par = it & 1;
-      k_mv<NormT, V, MV_DOT><<<grid, kBlock, 0, s>>>(od, p, q, nullptr, part_pq, ps, per);
-      k_cg_update<NormT, V><<<grid, kBlock, 0, s>>>(od, x, r, p, q, part_pq, part_rz, ps, par, per);
-      k_cg_dir<NormT, V><<<grid, kBlock, 0, s>>>(od, r, p, part_rz, ps, par, tol2, per);
-      ++it;
-      if (it % check == 0 || it == max_iter) {
-        int act = 0;
-        SS_TRY(count_active(ps, &act));
-        if (act == 0) break;
-        if (check < 16) check *= 2;
-      }
-    }
-    *iters_run = it;
-    return SS_OK;
-  }
-};
-
-template <typename NormT>
-ss_status solve_t(OpImpl* op, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter,
-                  hipStream_t s, ss_solve_info* info) {
-  WS w;
-  SS_TRY(workspace(op, &w));
-  Solver<NormT> sv;
-  sv.op = op;
-  sv.od = op->dev();
-  sv.s = s;
-  sv.per = (int)ceil_div((int64_t)op->work.size(), 8);
-  sv.grid = (unsigned)(8 * sv.per);
-  if (!op->h_pinned) SS_HIP(hipHostMalloc((void**)&op->h_pinned, 64, hipHostMallocDefault));
-  sv.h_active = op->h_pinned;
-  sv.d_active = (int*)(w.ps_in + op->n_prob);   // spare bytes of the workspace
-  const int64_t n = op->n_exec;
-  const OpDev od = sv.od;
-  const double tol2 = tol * tol;
-  auto t0 = std::chrono::steady_clock::now();
-
-  k_gather_in<<<grid_for(n), kBlock, 0, s>>>(n, op->d_exec2canon, (const double2*)f, (const double2*)u, w.f64, w.x64);
-  k_zero_k0<NormT><<<grid_for(n), kBlock, 0, s>>>(n, (const NormT*)op->d_norm, w.x64);
-  k_init_state<<<grid_for(op->n_prob), kBlock, 0, s>>>(op->n_prob, w.ps, nullptr);
-  int total_iters = 0, outer = 0;
-  if (prec == SS_FP64) {
-    k_mv<NormT, double2, MV_RESID><<<sv.grid, kBlock, 0, s>>>(od, w.x64, w.r64, w.f64, w.part_c, w.ps, sv.per);
-    int it = 0;
-    SS_TRY(sv.cg(w.x64, w.r64, w.p64, w.q64, w.ps, w.part_a, w.part_b, w.part_c, tol, max_iter, &it));
-    total_iters = it;
-  } else {
-    // outer refinement loop; inner tolerance loose enough for FP32
-    const double inner_tol = 1e-5;
-    const int max_outer = 30;
-    for (outer = 0; outer < max_outer; ++outer) {
-      k_mv<NormT, double2, MV_RESID><<<sv.grid, kBlock, 0, s>>>(od, w.x64, w.r64, w.f64, w.part_c, w.ps, sv.per);
-      k_resid_scalars<<<op->n_prob, kBlock, 0, s>>>(od, w.part_c, w.ps, tol2, 1);
-      int act = 0;
-      SS_TRY(sv.count_active(w.ps, &act));
-      if (act == 0) break;
-      k_init_state<<<grid_for(op->n_prob), kBlock, 0, s>>>(op->n_prob, w.ps_in, w.ps);
-      k_refine_start<<<sv.grid, kBlock, 0, s>>>(od, w.r64, w.r32, w.x32, w.ps, sv.per);
-      int it = 0;
-      SS_TRY(sv.cg(w.x32, w.r32, w.p32, w.q32, w.ps_in, w.part_a, w.part_b, nullptr, inner_tol, max_iter, &it));
-      total_iters += it;
-      k_accum_iters<<<grid_for(op->n_prob), kBlock, 0, s>>>(op->n_prob, w.ps, w.ps_in);
-      k_refine_add<<<sv.grid, kBlock, 0, s>>>(od, w.x64, w.x32, w.ps, sv.per);
-    }
-  }
-  // final FP64 true residual of every problem (for the report and status)
-  k_init_state<<<grid_for(op->n_prob), kBlock, 0, s>>>(op->n_prob, w.ps_in, nullptr);
-  k_mv<NormT, double2, MV_RESID><<<sv.grid, kBlock, 0, s>>>(od, w.x64, w.r64, w.f64, w.part_c, w.ps_in, sv.per);
-  k_resid_scalars<<<op->n_prob, kBlock, 0, s>>>(od, w.part_c, w.ps_in, tol2, 0);
-  k_scatter_out<NormT><<<grid_for(n), kBlock, 0, s>>>(n, op->d_exec2canon, (const NormT*)op->d_norm, w.x64,
-                                                      (double2*)u);
-  std::vector<PState> hs(op->n_prob), hf(op->n_prob);
-  SS_HIP(hipMemcpyAsync(hs.data(), w.ps, op->n_prob * sizeof(PState), hipMemcpyDeviceToHost, s));
-  SS_HIP(hipMemcpyAsync(hf.data(), w.ps_in, op->n_prob * sizeof(PState), hipMemcpyDeviceToHost, s));
-  SS_HIP(hipStreamSynchronize(s));
-  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  ss_status worst = SS_OK;
-  for (int p = 0; p < op->n_prob; ++p) {
-    const double rel = hf[p].ff > 0 ? std::sqrt(hf[p].rr / hf[p].ff) : 0.0;
-    ss_status stp = SS_OK;
-    if (hs[p].status == SS_EBREAKDOWN && !(rel <= tol)) stp = SS_EBREAKDOWN;
-    else if (!(rel <= tol) && hf[p].ff > 0) stp = SS_ENOCONV;
-    if (stp != SS_OK && worst == SS_OK) worst = stp;
-    if (info) {
-      ss_solve_info& in = info[p];
-      in.iters = prec == SS_FP64 ? hs[p].iters : hs[p].total_iters;
-      in.outer_steps = prec == SS_FP64 ? 0 : outer;
-      in.rel_residual = rel;
-      in.n = op->row_off[p + 1] - op->row_off[p];
-      in.nnz = op->nnz_p[p];
-      in.n_components = op->comps[p];
-      in.status = stp;
-      in.t_build_ms = 0;
-      in.t_solve_ms = ms;
-    }
-  }
-  if (worst == SS_ENOCONV) return fail(SS_ENOCONV, "tolerance not reached within max_iter");
-  if (worst == SS_EBREAKDOWN) return fail(SS_EBREAKDOWN, "CG breakdown: <p, L p> <= 0 or not finite");
-  return SS_OK;
+std::vector<int4> items_of(const OpImpl* op, int p) {
+  return std::vector<int4>(op->work.begin() + op->wrange[p].x, op->work.begin() + op->wrange[p].y);
 }
 
 }  // namespace
 
-ss_status apply_impl(const OpImpl* op, ss_precision prec, const void* x, void* y, hipStream_t s) {
-  const OpDev od = op->dev();
-  const int per = (int)ceil_div((int64_t)op->work.size(), 8);
-  const unsigned grid = (unsigned)(8 * per);
-  if (prec == SS_FP64) {
-    if (op->wide_norm)
-      k_mv<int64_t, double2, MV_PLAIN><<<grid, kBlock, 0, s>>>(od, (const double2*)x, (double2*)y, nullptr, nullptr, nullptr, per);
-    else
-      k_mv<int32_t, double2, MV_PLAIN><<<grid, kBlock, 0, s>>>(od, (const double2*)x, (double2*)y, nullptr, nullptr, nullptr, per);
-  } else {
-    if (op->wide_norm)
-      k_mv<int64_t, float2, MV_PLAIN><<<grid, kBlock, 0, s>>>(od, (const float2*)x, (float2*)y, nullptr, nullptr, nullptr, per);
-    else
-      k_mv<int32_t, float2, MV_PLAIN><<<grid, kBlock, 0, s>>>(od, (const float2*)x, (float2*)y, nullptr, nullptr, nullptr, per);
+// ---------------------------------------------------------------- engine
+struct Request {
+  OpImpl* op;
+  int64_t tag;
+  int n_left;
+};
+
+struct EngineImpl {
+  hipStream_t s = nullptr;
+  int64_t budget = 0;
+  int32_t max_slots = 0;
+  int64_t bytes_in_use = 0;
+  LaunchList list;
+  std::vector<std::vector<int4>> items;   // per desc
+  std::vector<int> req_of;                // per desc: request index
+  std::vector<int> prob_of;               // per desc: problem within the op
+  std::vector<Request> reqs;              // by request index (holes allowed)
+  std::vector<int64_t> req_bytes;
+  std::vector<int> free_req;
+  bool dirty = false;
+  // finished problems waiting for ss_engine_poll
+  struct Done {
+    int64_t tag;
+    int32_t prob;
+    ss_solve_info info;
+  };
+  std::vector<Done> done;
+  PState* h_states = nullptr;             // pinned
+  size_t h_cap = 0;
+  ~EngineImpl() {
+    if (h_states) (void)hipHostFree(h_states);
   }
+
+  ss_status ensure_host(size_t n) {
+    if (n <= h_cap) return SS_OK;
+    if (h_states) (void)hipHostFree(h_states);
+    h_states = nullptr;
+    h_cap = std::max(n, 2 * h_cap);
+    SS_HIP(hipHostMalloc((void**)&h_states, h_cap * sizeof(PState), hipHostMallocDefault));
+    return SS_OK;
+  }
+
+  ss_status submit(OpImpl* op, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter,
+                   int64_t tag) {
+    if (!f || !u) return fail(SS_EINVAL, "null vector");
+    if (!(tol > 0) || max_iter < 1) return fail(SS_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (prec != SS_FP64 && prec != SS_FP32_REFINE) return fail(SS_EINVAL, "unknown precision");
+    if (op->busy) return fail(SS_EINVAL, "operator already has a solve in flight");
+    const int64_t bytes = op_device_bytes(op) + (int64_t)std::max(op->ws.bytes, workspace_bytes(op));
+    int active = 0;
+    for (auto& r : reqs) active += r.op != nullptr;
+    if (budget > 0 && bytes_in_use + bytes > budget) return fail(SS_ENOMEM, "HBM budget of the engine exceeded");
+    if (max_slots > 0 && active >= max_slots) return fail(SS_ENOMEM, "no free engine slot");
+    WS w;
+    SS_TRY(workspace(op, &w));
+    int ri;
+    if (!free_req.empty()) {
+      ri = free_req.back();
+      free_req.pop_back();
+    } else {
+      ri = (int)reqs.size();
+      reqs.push_back({});
+      req_bytes.push_back(0);
+    }
+    reqs[ri] = Request{op, tag, op->n_prob};
+    req_bytes[ri] = bytes;
+    bytes_in_use += bytes;
+    op->busy = true;
+    for (int p = 0; p < op->n_prob; ++p) {
+      Desc D = make_desc(op, w, p);
+      D.f_canon = (const double2*)f;
+      D.u_canon = (double2*)u;
+      D.tol2 = tol * tol;
+      D.tol2_in = kInnerTol * kInnerTol;
+      D.max_iter = max_iter;
+      D.prec = prec;
+      D.init = 1;
+      list.descs.push_back(D);
+      items.push_back(items_of(op, p));
+      req_of.push_back(ri);
+      prob_of.push_back(p);
+    }
+    dirty = true;
+    return SS_OK;
+  }
+
+  // launch the per-tick chain on the current list
+  void launch_transitions() {
+    LaunchList& L = list;
+    const int nw = L.n_work(), nd = L.n_desc();
+    k_state_init<<<grid_for(nd), kBlock, 0, s>>>(L.d_descs, nd);
+    k_admit<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_refine_add<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_mv<MV_RESID><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_c());
+    k_outer_scalars<<<nd, kBlock, 0, s>>>(L.d_descs, nd, L.part_c());
+    k_refine_start<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_cg_start<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
+    k_cg_scalars<<<nd, kBlock, 0, s>>>(L.d_descs, nd, L.part_b());
+  }
+
+  void launch_iterations(int iters) {
+    LaunchList& L = list;
+    const int nw = L.n_work();
+    for (int it = 0; it < iters; ++it) {
+      k_mv<MV_DOT><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a());
+      k_cg_update<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a(), L.part_b());
+      k_cg_dir<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
+    }
+  }
+
+  // one tick; *n_active = problems still active afterwards
+  ss_status step(int iters, int* n_active) {
+    if (dirty) {
+      SS_TRY(list.upload(s, items));
+      dirty = false;
+    }
+    const int nd = list.n_desc();
+    if (nd == 0) {
+      *n_active = 0;
+      return SS_OK;
+    }
+    launch_transitions();
+    bool had_init = false;
+    for (auto& D : list.descs) had_init |= D.init != 0;
+    if (had_init) {
+      for (auto& D : list.descs) D.init = 0;
+      SS_TRY(list.upload_descs(s));
+    }
+    launch_iterations(iters);
+    // poll
+    SS_TRY(ensure_host(nd));
+    k_gather_states<<<grid_for(nd), kBlock, 0, s>>>(list.d_descs, nd, list.d_states);
+    SS_HIP(hipMemcpyAsync(h_states, list.d_states, nd * sizeof(PState), hipMemcpyDeviceToHost, s));
+    SS_HIP(hipStreamSynchronize(s));
+    SS_HIP(hipGetLastError());
+    std::vector<int> fin;
+    for (int k = 0; k < nd; ++k)
+      if (h_states[k].done) fin.push_back(k);
+    if (!fin.empty()) SS_TRY(retire(fin));
+    *n_active = list.n_desc();
+    return SS_OK;
+  }
+
+  ss_status retire(const std::vector<int>& fin) {
+    for (int k : fin) list.descs[k].final_ = 1;
+    SS_TRY(list.upload_descs(s));
+    const int nw = list.n_work(), nd = list.n_desc();
+    k_mv<MV_RESID><<<list.grid, kBlock, 0, s>>>(list.d_descs, list.d_work, nw, list.per, list.part_c(), 1);
+    k_final_scalars<<<nd, kBlock, 0, s>>>(list.d_descs, nd, list.part_c(), list.d_states);
+    k_retire<<<list.grid, kBlock, 0, s>>>(list.d_descs, list.d_work, nw, list.per);
+    SS_HIP(hipMemcpyAsync(h_states, list.d_states, nd * sizeof(PState), hipMemcpyDeviceToHost, s));
+    SS_HIP(hipStreamSynchronize(s));
+    std::vector<char> gone(nd, 0);
+    for (int k : fin) {
+      const Desc& D = list.descs[k];
+      const PState& st = h_states[k];
+      const int ri = req_of[k], p = prob_of[k];
+      OpImpl* op = reqs[ri].op;
+      ss_solve_info in{};
+      const double rel = st.ff > 0 ? std::sqrt(st.rr / st.ff) : 0.0;
+      const double tol = std::sqrt(D.tol2);
+      int status = st.status;
+      if (rel <= tol || st.ff == 0) status = SS_OK;
+      else if (status == SS_OK) status = SS_ENOCONV;
+      in.iters = st.total_iters;
+      in.outer_steps = D.prec == SS_FP64 ? 0 : st.outer;
+      in.rel_residual = rel;
+      in.n = op->row_off[p + 1] - op->row_off[p];
+      in.nnz = op->nnz_p[p];
+      in.n_components = op->comps[p];
+      in.status = status;
+      done.push_back(Done{reqs[ri].tag, p, in});
+      gone[k] = 1;
+      if (--reqs[ri].n_left == 0) {
+        op->busy = false;
+        bytes_in_use -= req_bytes[ri];
+        reqs[ri].op = nullptr;
+        free_req.push_back(ri);
+      }
+    }
+    // compact the active set
+    std::vector<Desc> nd_descs;
+    std::vector<std::vector<int4>> nitems;
+    std::vector<int> nreq, nprob;
+    for (int k = 0; k < nd; ++k) {
+      if (gone[k]) continue;
+      nd_descs.push_back(list.descs[k]);
+      nitems.push_back(std::move(items[k]));
+      nreq.push_back(req_of[k]);
+      nprob.push_back(prob_of[k]);
+    }
+    list.descs.swap(nd_descs);
+    items.swap(nitems);
+    req_of.swap(nreq);
+    prob_of.swap(nprob);
+    dirty = true;
+    return SS_OK;
+  }
+};
+
+int64_t op_device_bytes(const OpImpl* op) {
+  const int64_t nb = op->wide_norm ? 8 : 4;
+  return (op->total + 1) * 8 + op->nnz * 4 + op->total * 4 + op->n_exec * 8 + op->total * 8 + op->n_sell * 4 +
+         (op->n_slices + 1) * 4 + op->n_exec * nb + (int64_t)op->n_prob * 64 * (16 + 8 + 8) +
+         (int64_t)op->work.size() * 16;
+}
+
+ss_status engine_create(int64_t budget, int32_t max_slots, hipStream_t s, EngineImpl** out) {
+  EngineImpl* e = new EngineImpl();
+  e->s = s;
+  e->budget = budget;
+  e->max_slots = max_slots;
+  *out = e;
+  return SS_OK;
+}
+void engine_free(EngineImpl* e) { delete e; }
+ss_status engine_submit(EngineImpl* e, OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
+                        int32_t max_iter, int64_t tag) {
+  return e->submit(op, f, u, tol, prec, max_iter, tag);
+}
+ss_status engine_step(EngineImpl* e, int32_t iters, int32_t* n_active) {
+  if (iters < 1) return fail(SS_EINVAL, "iters must be >= 1");
+  int na = 0;
+  SS_TRY(e->step(iters, &na));
+  if (n_active) *n_active = na;
+  return SS_OK;
+}
+ss_status engine_poll(EngineImpl* e, int32_t cap, int64_t* tags, int32_t* probs, ss_solve_info* info,
+                      int32_t* n_out) {
+  const int n = std::min<int>(cap, (int)e->done.size());
+  for (int i = 0; i < n; ++i) {
+    if (tags) tags[i] = e->done[i].tag;
+    if (probs) probs[i] = e->done[i].prob;
+    if (info) info[i] = e->done[i].info;
+  }
+  e->done.erase(e->done.begin(), e->done.begin() + n);
+  *n_out = n;
+  return SS_OK;
+}
+ss_status engine_usage(const EngineImpl* e, int32_t* n_active, int64_t* bytes) {
+  if (n_active) {
+    int a = 0;
+    for (auto& r : e->reqs) a += r.op != nullptr;
+    *n_active = a;
+  }
+  if (bytes) *bytes = e->bytes_in_use;
+  return SS_OK;
+}
+
+// ---------------------------------------------------------------- batch solve and apply
+ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter,
+                        hipStream_t stream, ss_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  EngineImpl e;
+  e.s = stream;
+  SS_TRY(e.submit(op, f, u, tol, prec, max_iter, 0));
+  // polling cadence: a few iterations per tick, growing while nothing finishes
+  int iters = 4, na = 1;
+  int guard = 0;
+  while (na > 0) {
+    SS_TRY(e.step(iters, &na));
+    if (iters < 16) iters *= 2;
+    if (++guard > 1000000) return fail(SS_EINVAL, "internal: solve did not terminate");
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ss_status worst = SS_OK;
+  for (auto& d : e.done) {
+    if (info) {
+      info[d.prob] = d.info;
+      info[d.prob].t_solve_ms = ms;
+    }
+    if (d.info.status != SS_OK && worst == SS_OK) worst = (ss_status)d.info.status;
+  }
+  if (worst == SS_ENOCONV) return fail(SS_ENOCONV, "tolerance not reached within the iteration limit");
+  if (worst == SS_EBREAKDOWN) return fail(SS_EBREAKDOWN, "CG breakdown: <p, L p> <= 0 or not finite");
+  return worst;
+}
+
+ss_status apply_impl(const OpImpl* op_c, ss_precision prec, const void* x, void* y, hipStream_t s) {
+  OpImpl* op = const_cast<OpImpl*>(op_c);
+  auto& c = op->apply_cache;
+  if (!c.list || c.x != x || c.y != y || c.prec != prec) {
+    if (!c.list) c.list = new LaunchList();
+    LaunchList& L = *c.list;
+    L.descs.clear();
+    std::vector<std::vector<int4>> items;
+    WS w{};
+    for (int p = 0; p < op->n_prob; ++p) {
+      Desc D = make_desc(op, w, p);
+      const int64_t e0 = op->eoff[p];
+      if (prec == SS_FP64) {
+        D.x64 = (double2*)x + e0;
+        D.q64 = (double2*)y + e0;
+      } else {
+        D.x32 = (float2*)x + e0;
+        D.q32 = (float2*)y + e0;
+      }
+      D.prec = prec;
+      L.descs.push_back(D);
+      items.push_back(items_of(op, p));
+    }
+    SS_TRY(L.upload(s, items));
+    c.x = x;
+    c.y = y;
+    c.prec = prec;
+  }
+  LaunchList& L = *c.list;
+  k_mv<MV_PLAIN><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, L.n_work(), L.per, nullptr);
   SS_HIP(hipGetLastError());
   return SS_OK;
 }
 
-ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter,
-                        hipStream_t stream, ss_solve_info* info) {
-  if (!f || !u) return fail(SS_EINVAL, "null vector");
-  if (!(tol > 0) || max_iter < 1) return fail(SS_EINVAL, "tol must be > 0 and max_iter >= 1");
-  if (prec != SS_FP64 && prec != SS_FP32_REFINE) return fail(SS_EINVAL, "unknown precision");
-  return op->wide_norm ? solve_t<int64_t>(op, f, u, tol, prec, max_iter, stream, info)
-                       : solve_t<int32_t>(op, f, u, tol, prec, max_iter, stream, info);
+void free_apply_cache(OpImpl* op) {
+  delete op->apply_cache.list;
+  op->apply_cache.list = nullptr;
 }
 
 }  // namespace ss

@@ -112,17 +112,22 @@ struct StampImpl {
   int64_t max_norm = 0;
 };
 
-// Per-problem solver scalars (device).
+// Per-problem solver state (device).  A field written by one kernel of an
+// iteration is read only by later kernels.
 struct PState {
-  double rho[2];      // <r, z> at the current / next iteration (parity-indexed)
-  double ff;          // |f|^2 of the current right-hand side
-  double rr;          // |r|^2 of the current residual
-  double scale;       // refinement: |r64| used to normalise the FP32 right-hand side
-  double rr0;         // |r|^2 at the start of the current CG run
-  int32_t iters;
+  double rho[2];        // <r, D^-1 r>, indexed by iteration parity
+  double ff;            // |rhs|^2 of the current CG run (|f|^2 for FP64 / outer)
+  double rr;            // |r|^2 of the current residual
+  double scale;         // refinement: |r64| that normalises the FP32 right-hand side
+  double rr0;
+  int32_t iter;         // index of the running iteration (read by update / dir)
+  int32_t iters;        // completed iterations of the current CG run
   int32_t done;
   int32_t status;
-  int32_t total_iters;
+  int32_t total_iters;  // refinement: iterations of finished correction solves
+  int32_t outer;        // refinement steps taken
+  int32_t start;        // a CG run is to be started this tick
+  int32_t pending;      // refinement: a finished correction awaits the FP64 update
 };
 
 // Plain-old-data view of an operator passed to kernels by value.
@@ -140,6 +145,8 @@ struct OpDev {
   int32_t n_work;
   int32_t n_prob;
 };
+
+struct LaunchList;
 
 struct OpImpl {
   int device = 0;
@@ -181,8 +188,28 @@ struct OpImpl {
     void* base = nullptr;
   } ws;
   int* h_pinned = nullptr;             // pinned host word for convergence polling
+  std::vector<double> a0_host;         // a_0 per problem
+  bool busy = false;                   // a solve of this operator is in flight
+  struct ApplyCache {
+    LaunchList* list = nullptr;
+    const void* x = nullptr;
+    void* y = nullptr;
+    ss_precision prec = SS_FP64;
+  } apply_cache;
   OpDev dev() const;
 };
+
+struct EngineImpl;
+ss_status engine_create(int64_t budget, int32_t max_slots, hipStream_t s, EngineImpl** out);
+void engine_free(EngineImpl* e);
+ss_status engine_submit(EngineImpl* e, OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
+                        int32_t max_iter, int64_t tag);
+ss_status engine_step(EngineImpl* e, int32_t iters, int32_t* n_active);
+ss_status engine_poll(EngineImpl* e, int32_t cap, int64_t* tags, int32_t* probs, ss_solve_info* info,
+                      int32_t* n_out);
+ss_status engine_usage(const EngineImpl* e, int32_t* n_active, int64_t* bytes);
+int64_t op_device_bytes(const OpImpl* op);
+void free_apply_cache(OpImpl* op);
 
 // ------------------------------------------------------------------ entry points (internal)
 ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,

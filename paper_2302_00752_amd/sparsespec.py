@@ -26,7 +26,9 @@ PRECISION = {"fp64": SS_FP64, "fp32_refine": SS_FP32_REFINE, SS_FP64: SS_FP64, S
 EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp_keys", "ss_stamp_lookup",
             "ss_stamp_lookup_batch",
             "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
-            "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version"]
+            "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
+            "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
+            "ss_engine_free"]
 
 
 class SolveInfo(C.Structure):
@@ -67,6 +69,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_solve_op": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
         "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, i64, pi64, pd, pi16,
                      C.POINTER(SolveInfo)],
+        "ss_op_bytes": [P, pi64],
+        "ss_engine_create": [i64, i32, P, C.POINTER(P)],
+        "ss_engine_submit": [P, P, P, P, dbl, i32, i32, i64],
+        "ss_engine_step": [P, i32, pi32],
+        "ss_engine_poll": [P, i32, pi64, pi32, C.POINTER(SolveInfo), pi32],
+        "ss_engine_usage": [P, pi32, pi64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -76,6 +84,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.ss_free_stamp.restype = None
     lib.ss_free_op.argtypes = [P]
     lib.ss_free_op.restype = None
+    lib.ss_engine_free.argtypes = [P]
+    lib.ss_engine_free.restype = None
     lib.ss_last_error.restype = C.c_char_p
     lib.ss_version.restype = C.c_char_p
     return lib
@@ -243,9 +253,65 @@ class Operator:
             _check(st)
         return [i.as_dict() for i in info]
 
+    def device_bytes(self) -> int:
+        b = C.c_int64()
+        _check(_lib.ss_op_bytes(self._h, C.byref(b)))
+        return b.value
+
     def close(self):
         if self._h:
             _lib.ss_free_op(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Engine:
+    """Continuous-batching solver engine (see ss_engine_* in include/sparsespec.h)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 0, stream=None):
+        self._h = C.c_void_p()
+        self._stream = _stream(stream)
+        _check(_lib.ss_engine_create(int(hbm_budget_bytes), int(max_slots), C.c_void_p(self._stream),
+                                     C.byref(self._h)))
+
+    def submit(self, op: "Operator", f, u, tol: float, precision="fp64", max_iter: int = 1000,
+               tag: int = 0) -> bool:
+        """Admit op's problems; False (nothing admitted) if budget or slots are exhausted."""
+        st = _lib.ss_engine_submit(self._h, op._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                   float(tol), PRECISION[precision], int(max_iter), int(tag))
+        if st == SS_ENOMEM:
+            return False
+        _check(st)
+        return True
+
+    def step(self, iters: int = 4) -> int:
+        n = C.c_int32()
+        _check(_lib.ss_engine_step(self._h, int(iters), C.byref(n)))
+        return n.value
+
+    def poll(self, cap: int = 4096):
+        tags = np.zeros(cap, dtype=np.int64)
+        probs = np.zeros(cap, dtype=np.int32)
+        info = (SolveInfo * cap)()
+        n = C.c_int32()
+        _check(_lib.ss_engine_poll(self._h, cap, _ptr(tags, C.c_int64), _ptr(probs, C.c_int32), info,
+                                   C.byref(n)))
+        return [(int(tags[i]), int(probs[i]), info[i].as_dict()) for i in range(n.value)]
+
+    def usage(self):
+        n = C.c_int32()
+        b = C.c_int64()
+        _check(_lib.ss_engine_usage(self._h, C.byref(n), C.byref(b)))
+        return n.value, b.value
+
+    def close(self):
+        if self._h:
+            _lib.ss_engine_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,119 @@
+"""GPU: the continuous-batching engine.  Requests of different dimension, size
+and precision served together give each request bitwise the result it gets
+when solved alone (fixed-order per-problem reductions, no cross-problem
+arithmetic), match the CPU oracle within the benchmark spec's tolerances, and the
+engine never admits past its HBM budget."""
+import numpy as np
+import pytest
+
+from oracle import galerkin as og
+from oracle import stamp as ost
+from paper_2302_00752_amd import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_00752_amd import sparsespec
+    return sparsespec
+
+
+def small_stream(n, seed=0):
+    rng = np.random.Generator(np.random.PCG64(5000 + seed))
+    reqs = [workloads.cfg5_request(rng, i, size_lo=200, size_hi=6000) for i in range(n)]
+    for i, r in enumerate(reqs):
+        r.arrival_s = 0.001 * i
+    return reqs
+
+
+def solve_alone(ss, p, tol):
+    st = ss.Stamp.build([p])
+    op = ss.Operator.build(st, [p])
+    f = st.forcing_vector([p])
+    u = torch.zeros_like(f)
+    info = op.solve(f, u, tol, p.precision, 2000)
+    torch.cuda.synchronize()
+    keys = st.keys()[0]
+    return u.cpu().numpy(), keys, info[0]
+
+
+def test_served_equals_alone_bitwise_and_oracle(ss):
+    from paper_2302_00752_amd.serving import serve
+    reqs = small_stream(10)
+    assert len({r.d for r in reqs}) > 3 and {r.precision for r in reqs} == {"fp64", "fp32_refine"}
+    summary, recs = serve(reqs, hbm_budget_bytes=1 << 30, iters_per_tick=3, keep_results=True, realtime=True)
+    assert summary["requests"] == len(reqs) and summary["status_ok"] == len(reqs)
+    assert summary["max_active"] >= 2                       # requests overlapped on the device
+    for r in recs:
+        p = reqs[r.rid]
+        tol = 1e-10 if p.precision == "fp64" else 1e-9
+        u, keys, info = solve_alone(ss, p, tol)
+        assert np.array_equal(r.result, u), (r.rid, p.d, p.precision)
+        assert r.info["iters"] == info["iters"]
+    for r in recs[:3]:
+        p = reqs[r.rid]
+        af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+        keys, _ = ost.stamp(p.f_freqs, af, p.level)
+        pos = og.slot_index(keys)
+        f = np.zeros(len(keys), dtype=np.complex128)
+        for k, v in zip(p.f_freqs, p.f_hat):
+            f[pos[tuple(int(x) for x in k)]] = v
+        uo = og.solve(keys, af, ah, f)
+        err = np.linalg.norm(r.result - uo) / np.linalg.norm(uo)
+        assert err <= (1e-9 if p.precision == "fp32_refine" else 1e-10), (r.rid, err)
+
+
+def test_engine_budget_refuses_and_recovers(ss):
+    reqs = small_stream(3, seed=1)
+    built = []
+    for p in reqs:
+        st = ss.Stamp.build([p])
+        op = ss.Operator.build(st, [p])
+        f = st.forcing_vector([p])
+        built.append((op, f, torch.zeros_like(f)))
+    # full footprints (operator + solver workspace): solve each once
+    for k, (op, f, u) in enumerate(built):
+        probe = ss.Engine(0, 0)
+        assert probe.submit(op, f, u, 1e-10, "fp64", 2000, k)
+        while probe.step(8):
+            pass
+        probe.poll()
+        probe.close()
+        u.zero_()
+    b0, b1 = built[0][0].device_bytes(), built[1][0].device_bytes()
+    budget = max(b0, b1) + min(b0, b1) // 2      # fits either alone, not both
+    eng = ss.Engine(budget, 0)
+    assert eng.submit(built[0][0], built[0][1], built[0][2], 1e-10, "fp64", 2000, 0)
+    assert not eng.submit(built[1][0], built[1][1], built[1][2], 1e-10, "fp64", 2000, 1)   # over budget
+    n_req, used = eng.usage()
+    assert n_req == 1 and used == b0 <= budget
+    while eng.step(8):
+        pass
+    done = eng.poll()
+    assert [t for t, _, _ in done] == [0] and done[0][2]["status"] == 0
+    assert eng.usage() == (0, 0)
+    assert eng.submit(built[1][0], built[1][1], built[1][2], 1e-10, "fp64", 2000, 1)  # capacity freed
+    while eng.step(8):
+        pass
+    assert [t for t, _, _ in eng.poll()] == [1]
+    eng.close()
+
+
+def test_engine_rejects_double_submit(ss):
+    p = small_stream(1, seed=2)[0]
+    st = ss.Stamp.build([p])
+    op = ss.Operator.build(st, [p])
+    f = st.forcing_vector([p])
+    u = torch.zeros_like(f)
+    eng = ss.Engine(0, 0)
+    assert eng.submit(op, f, u, 1e-10, "fp64", 2000, 0)
+    with pytest.raises(ss.SparseSpecError):
+        eng.submit(op, f, u, 1e-10, "fp64", 2000, 1)
+    while eng.step(8):
+        pass
+    eng.poll()
+    eng.close()

@@ -1,0 +1,109 @@
+"""Scheduler logic of the serving loop on the CPU, with a stand-in engine:
+arrival-order admission, HBM-budget gating (never exceeded, refused requests
+stay queued), retirement freeing capacity for later arrivals, per-request
+accounting of multi-problem requests, and latency bookkeeping."""
+import pytest
+
+from paper_2302_00752_amd.serving import Scheduler
+
+
+class FakeEngine:
+    """Admits a request if its bytes fit the budget; each problem needs `steps` ticks."""
+
+    def __init__(self, budget):
+        self.budget = budget
+        self.used = 0
+        self.active = {}          # tag -> [bytes, remaining ticks, n_prob]
+        self.out = []
+        self.peak = 0
+        self.admit_log = []
+
+    def submit(self, handle, tag):
+        if self.used + handle["bytes"] > self.budget:
+            return False
+        self.used += handle["bytes"]
+        self.peak = max(self.peak, self.used)
+        self.active[tag] = [handle["bytes"], handle["steps"], handle["n_prob"]]
+        self.admit_log.append(tag)
+        return True
+
+    def step(self, iters):
+        for tag in list(self.active):
+            rec = self.active[tag]
+            rec[1] -= 1
+            if rec[1] <= 0:
+                for p in range(rec[2]):
+                    self.out.append((tag, p, {"status": 0}))
+                self.used -= rec[0]
+                del self.active[tag]
+        return len(self.active)
+
+    def poll(self):
+        out, self.out = self.out, []
+        return out
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+def test_budget_gating_order_and_completion():
+    eng = FakeEngine(budget=100)
+    clock = Clock()
+    s = Scheduler(eng, clock=clock)
+    sizes = [40, 40, 40, 10, 90, 5]
+    for i, b in enumerate(sizes):
+        s.offer(i, 0.0, {"bytes": b, "steps": 2 + i % 3, "n_prob": 1})
+    ticks = 0
+    while not s.idle():
+        s.admit()
+        assert eng.used <= eng.budget
+        clock.t += 1.0
+        s.tick()
+        ticks += 1
+        assert ticks < 100
+    assert eng.peak <= 100
+    assert eng.admit_log == sorted(eng.admit_log)          # first come, first admitted
+    assert sorted(r.rid for r in s.finished) == list(range(len(sizes)))
+    assert s.max_active >= 2                                 # requests overlap on the device
+
+
+def test_late_arrivals_join_running_batch():
+    eng = FakeEngine(budget=1000)
+    clock = Clock()
+    s = Scheduler(eng, clock=clock)
+    s.offer(0, 0.0, {"bytes": 10, "steps": 5, "n_prob": 1})
+    s.admit()
+    s.tick()
+    clock.t = 1.0
+    s.offer(1, 1.0, {"bytes": 10, "steps": 1, "n_prob": 1})   # arrives while 0 is running
+    s.admit()
+    assert set(s.active) == {0, 1}
+    clock.t = 2.0
+    s.tick()
+    assert [r.rid for r in s.finished] == [1]                # the short late request finishes first
+    assert s.finished[0].latency == pytest.approx(1.0)
+
+
+def test_multi_problem_request_finishes_once():
+    eng = FakeEngine(budget=1000)
+    s = Scheduler(eng, clock=Clock())
+    s.offer(7, 0.0, {"bytes": 1, "steps": 1, "n_prob": 3}, n_prob=3)
+    s.admit()
+    assert s.tick() == 1
+    assert len(s.finished) == 1 and s.finished[0].rid == 7
+
+
+def test_refused_request_stays_queued():
+    eng = FakeEngine(budget=50)
+    s = Scheduler(eng, clock=Clock())
+    s.offer(0, 0.0, {"bytes": 40, "steps": 3, "n_prob": 1})
+    s.offer(1, 0.0, {"bytes": 40, "steps": 1, "n_prob": 1})
+    assert s.admit() == 1 and len(s.ready) == 1
+    for _ in range(3):
+        s.tick()
+    assert s.admit() == 1 and not s.ready
