@@ -37,6 +37,8 @@ constexpr uint32_t kColMask = (1u << kColBits) - 1;
 constexpr int kSlice = 64;            // SELL slice height = wavefront size
 constexpr int kBlock = 256;           // threads per block (4 wavefronts)
 constexpr int kSlicesPerBlock = kBlock / kSlice;
+constexpr int kWinRows = 2048;        // rows of x / |k|^2 a block stages in LDS
+constexpr int kMaxItemSlices = 64;    // slices per work item (window items)
 constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;
 constexpr int kMaxProblems = (1 << 14) - 1;
 
@@ -163,8 +165,9 @@ struct OpImpl {
   std::vector<int64_t> eoff;           // exec offsets [n_prob+1]
   std::vector<int32_t> comps;          // classes per problem
   std::vector<int64_t> nnz_p;          // per problem
-  std::vector<int4> work;
+  std::vector<int4> work;               // {problem, first slice, slices | window rows << 16, window start row}
   std::vector<int2> wrange;
+  int64_t max_window = 0;
   // canonical CSR (kept for export and tests)
   int64_t* d_crow = nullptr;           // [total+1]
   uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << 26
@@ -239,22 +242,25 @@ struct ATable {
 ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
                       bool drop_zero_coef, ATable* out);
 
-// device memory helpers
+// device memory: a caching allocator (see alloc.hip)
+hipError_t pool_alloc(void** out, size_t bytes);
+void pool_free(void* p);
+
 template <typename T>
 ss_status dalloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  hipError_t e = pool_alloc((void**)p, count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
     return fail(e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EDEVICE,
-                std::string("hipMalloc: ") + hipGetErrorString(e));
+                std::string("device allocation: ") + hipGetErrorString(e));
   }
   return SS_OK;
 }
 template <typename T>
 void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  pool_free((void*)p);
   p = nullptr;
 }
 
