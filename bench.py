@@ -138,8 +138,20 @@ def main():
         ms = e0.elapsed_time(e1) / args.matvec_reps
         byt = matvec_bytes(op.nnz, op.n_total, cb)
         mv[prec] = dict(ms=ms, bytes=byt, gbs=byt / ms / 1e6)
+    # a plain device copy of known size: calibrates the HBM byte counters (FETCH_SIZE / WRITE_SIZE)
+    # of a profiled run against a kernel whose traffic is exactly 2 x 1 GiB
+    cal_src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    cal_dst = torch.empty_like(cal_src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    cal_dst.copy_(cal_src)
+    e1.record(stream)
+    e1.synchronize()
+    copy_gbs = 2 * cal_src.numel() * 8 / (e0.elapsed_time(e1) * 1e6)
+    del cal_src, cal_dst
     log(f"matvec fp64 {mv['fp64']['ms']*1e3:.1f} us {mv['fp64']['gbs']:.0f} GB/s; "
-        f"fp32 {mv['fp32_refine']['ms']*1e3:.1f} us {mv['fp32_refine']['gbs']:.0f} GB/s")
+        f"fp32 {mv['fp32_refine']['ms']*1e3:.1f} us {mv['fp32_refine']['gbs']:.0f} GB/s; copy {copy_gbs:.0f} GB/s")
 
     # --- CPU oracle on a bounded sample; its solutions check the GPU error
     cpu = None
@@ -221,7 +233,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_mv<int,double2,MV_PLAIN> (ss_apply, FP64)",
                      "achieved": mv["fp64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": mv["fp64"]["gbs"] / HBM_PEAK_GBS,
-                     "bytes_per_launch": mv["fp64"]["bytes"], "traffic": None},
+                     "bytes_per_launch": mv["fp64"]["bytes"], "traffic": None,
+                     "measured_copy_GB/s": copy_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
         "cpu_baseline": cpu,
     }

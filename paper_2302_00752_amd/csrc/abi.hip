@@ -59,7 +59,7 @@ ss_status guarded(F&& f) {
 struct DevMem {
   void* p = nullptr;
   ~DevMem() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p);
   }
 };
 
@@ -316,8 +316,8 @@ ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double*
     }
     if (keys_out) SS_HIP(hipMemcpy(keys_out, st->impl->d_keys, (size_t)n * d * 2, hipMemcpyDeviceToHost));
     DevMem fd, ud;
-    SS_HIP(hipMalloc(&fd.p, n * 16));
-    SS_HIP(hipMalloc(&ud.p, n * 16));
+    SS_HIP(pool_alloc((void**)&fd.p, n * 16));
+    SS_HIP(pool_alloc((void**)&ud.p, n * 16));
     SS_HIP(hipMemcpy(fd.p, fdense.data(), n * 16, hipMemcpyHostToDevice));
     SS_HIP(hipMemset(ud.p, 0, n * 16));
     const double t_build = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

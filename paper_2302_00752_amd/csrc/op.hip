@@ -182,14 +182,16 @@ __global__ void k_fill_i64(int64_t n, int64_t* p, int64_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, const int32_t* __restrict__ pid,
-                           const int64_t* __restrict__ rowoff, const int64_t* __restrict__ eoff,
-                           int64_t* __restrict__ canon2exec, int64_t* __restrict__ exec2canon) {
+// sorted position q -> execution row: start of its class in the execution layout + offset in the class
+__global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, const uint32_t* __restrict__ cflag,
+                           const uint32_t* __restrict__ cidx, const int64_t* __restrict__ cq0,
+                           const int64_t* __restrict__ ce0, int64_t* __restrict__ canon2exec,
+                           int64_t* __restrict__ exec2canon) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= total) return;
   const int64_t r = order[q];
-  const int p = pid[r];
-  const int64_t e = eoff[p] + (q - rowoff[p]);
+  const int64_t k = (int64_t)cidx[q] + cflag[q] - 1;
+  const int64_t e = ce0[k] + (q - cq0[k]);
   canon2exec[r] = e;
   exec2canon[e] = r;
 }
@@ -204,6 +206,27 @@ __global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec
     if (r >= 0) w = rowlen[r] > w ? rowlen[r] : w;
   }
   width[sl] = (uint32_t)(w * kSlice);
+}
+
+// 1 where a position of `order` (sorted rows; -1 = none) starts a new class: first row of a
+// problem, or a class change
+__global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ order, const int32_t* __restrict__ comp,
+                                    const int32_t* __restrict__ pid, uint32_t* __restrict__ flag) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int64_t r = order[q];
+  uint32_t f = 1;
+  if (q > 0) {
+    const int64_t rp = order[q - 1];
+    f = (pid[rp] != pid[r] || comp[rp] != comp[r]) ? 1u : 0u;
+  }
+  flag[q] = f;
+}
+
+__global__ void k_compact_starts(int64_t n_exec, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                 int64_t* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_exec && flag[e]) out[idx[e]] = e;
 }
 
 template <typename NormT>
@@ -312,12 +335,14 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   const int64_t total = st->total;
   SS_HIP(hipGetDevice(&op->device));
   struct Tmp {
+    hipStream_t s;
     std::vector<void*> p;
     ~Tmp() {
+      (void)hipStreamSynchronize(s);   // queued work may still use the blocks (error paths)
       for (void* q : p)
-        if (q) (void)hipFree(q);
+        if (q) pool_free(q);
     }
-  } tmpmem;
+  } tmpmem{stream, {}};
   auto track = [&](void* q) { tmpmem.p.push_back(q); };
 
   // ---- neighbour map (one lane per (row, j); rows compacted in j order)
@@ -337,7 +362,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     size_t tb = 0;
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, rowlen, op->d_crow, total + 1, stream));
     void* t = nullptr;
-    SS_HIP(hipMalloc(&t, tb));
+    SS_HIP(pool_alloc((void**)&t, tb));
     track(t);
     SS_HIP(hipMemsetAsync(rowlen + total, 0, 8, stream));
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, rowlen, op->d_crow, total + 1, stream));
@@ -388,16 +413,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   op->comps.assign(n_prob, 0);
   SS_HIP(hipMemcpyAsync(op->comps.data(), ncomp, n_prob * 4, hipMemcpyDeviceToHost, stream));
 
-  // ---- execution order: (problem, class, -row length, canonical slot)
-  op->eoff.assign(n_prob + 1, 0);
-  for (int p = 0; p < n_prob; ++p)
-    op->eoff[p + 1] = op->eoff[p] + ceil_div(st->row_off[p + 1] - st->row_off[p], kSlice) * kSlice;
-  op->n_exec = op->eoff[n_prob];
-  op->n_slices = op->n_exec / kSlice;
-  if (op->n_slices * (int64_t)kMaxA * kSlice >= (int64_t(1) << 32))
-    return fail(SS_ERANGE, "batch too large for 32-bit SELL offsets (split it)");
-  SS_TRY(dalloc(&op->d_eoff, n_prob + 1));
-  SS_HIP(hipMemcpyAsync(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, hipMemcpyHostToDevice, stream));
+  // ---- execution order: (problem, class, -row length, canonical slot); a class whose
+  // padding to a slice boundary costs at most 1/8 of its rows is padded, so the slices of
+  // large classes never straddle two classes (their matvec windows stay one class wide)
   uint64_t *ek = nullptr, *ek2 = nullptr;
   uint32_t *ev = nullptr, *ev2 = nullptr;
   SS_TRY(dalloc(&ek, total));
@@ -421,15 +439,81 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     size_t tb = 0;
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
     void* t = nullptr;
-    SS_HIP(hipMalloc(&t, tb));
+    SS_HIP(pool_alloc((void**)&t, tb));
     track(t);
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
+  }
+  // class starts in sorted order
+  uint32_t *cflag = nullptr, *cidx = nullptr;
+  SS_TRY(dalloc(&cflag, total + 1));
+  track(cflag);
+  SS_TRY(dalloc(&cidx, total + 1));
+  track(cidx);
+  k_class_start_flags<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, op->d_comp, st->d_pid, cflag);
+  SS_HIP(hipMemsetAsync(cflag + total, 0, 4, stream));
+  std::vector<int64_t> cq;   // sorted position of every class start
+  {
+    size_t tb = 0;
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cflag, cidx, total + 1, stream));
+    void* t = nullptr;
+    SS_HIP(pool_alloc((void**)&t, tb));
+    track(t);
+    SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, cflag, cidx, total + 1, stream));
+    uint32_t n_cls = 0;
+    SS_HIP(hipMemcpyAsync(&n_cls, cidx + total, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+    int64_t* d_cq = nullptr;
+    SS_TRY(dalloc(&d_cq, std::max<uint32_t>(n_cls, 1)));
+    track(d_cq);
+    k_compact_starts<<<grid_for(total), kBlock, 0, stream>>>(total, cflag, cidx, d_cq);
+    cq.resize(n_cls);
+    if (n_cls) SS_HIP(hipMemcpyAsync(cq.data(), d_cq, n_cls * 8, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+  }
+  // exec layout of every class (host), per problem
+  const int64_t n_cls = (int64_t)cq.size();
+  std::vector<int64_t> ce0(n_cls);                       // global exec row of each class start
+  std::vector<std::vector<int64_t>> cbounds(n_prob);     // local class starts + problem end
+  op->eoff.assign(n_prob + 1, 0);
+  {
+    size_t k = 0;
+    for (int p = 0; p < n_prob; ++p) {
+      const int64_t q1 = st->row_off[p + 1];
+      int64_t cur = 0;
+      while (k < cq.size() && cq[k] < q1) {
+        const int64_t size = (k + 1 < cq.size() ? std::min(cq[k + 1], q1) : q1) - cq[k];
+        const int64_t pad = (kSlice - size % kSlice) % kSlice;
+        ce0[k] = op->eoff[p] + cur;
+        cbounds[p].push_back(cur);
+        cur += size + (pad * 8 <= size ? pad : 0);
+        ++k;
+      }
+      const int64_t rows = ceil_div(cur, kSlice) * kSlice;
+      cbounds[p].push_back(rows);
+      op->eoff[p + 1] = op->eoff[p] + rows;
+    }
+  }
+  op->n_exec = op->eoff[n_prob];
+  op->n_slices = op->n_exec / kSlice;
+  if (op->n_slices * (int64_t)kMaxA * kSlice >= (int64_t(1) << 32))
+    return fail(SS_ERANGE, "batch too large for 32-bit SELL offsets (split it)");
+  SS_TRY(dalloc(&op->d_eoff, n_prob + 1));
+  SS_HIP(hipMemcpyAsync(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, hipMemcpyHostToDevice, stream));
+  int64_t *d_cq0 = nullptr, *d_ce0 = nullptr;
+  SS_TRY(dalloc(&d_cq0, std::max<int64_t>(n_cls, 1)));
+  track(d_cq0);
+  SS_TRY(dalloc(&d_ce0, std::max<int64_t>(n_cls, 1)));
+  track(d_ce0);
+  if (n_cls) {
+    SS_HIP(hipMemcpyAsync(d_cq0, cq.data(), n_cls * 8, hipMemcpyHostToDevice, stream));
+    SS_HIP(hipMemcpyAsync(d_ce0, ce0.data(), n_cls * 8, hipMemcpyHostToDevice, stream));
   }
   SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
   SS_TRY(dalloc(&op->d_canon2exec, total));
   k_fill_i64<<<grid_for(op->n_exec), kBlock, 0, stream>>>(op->n_exec, op->d_exec2canon, -1);
-  k_exec_map<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, st->d_pid, st->d_rowoff, op->d_eoff,
-                                                      op->d_canon2exec, op->d_exec2canon);
+  k_exec_map<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, cflag, cidx, d_cq0, d_ce0, op->d_canon2exec,
+                                                      op->d_exec2canon);
+  SS_HIP(hipStreamSynchronize(stream));   // host class tables above are temporaries
 
   // ---- SELL-64 slices
   uint32_t* width = nullptr;
@@ -442,7 +526,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     size_t tb = 0;
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, width, op->d_sptr, op->n_slices + 1, stream));
     void* t = nullptr;
-    SS_HIP(hipMalloc(&t, tb));
+    SS_HIP(pool_alloc((void**)&t, tb));
     track(t);
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, width, op->d_sptr, op->n_slices + 1, stream));
   }
@@ -470,13 +554,41 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
         op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
   }
 
-  // ---- work items: up to 4 slices (256 rows) of one problem per block
+  // ---- work items: runs of slices of one problem whose rows' classes fit an LDS window
+  // (the matvec stages x and |k|^2 of the window once per block); a class larger than the
+  // window gets items of four slices that gather from global memory
   op->wrange.resize(n_prob);
+  op->max_window = 0;
   for (int p = 0; p < n_prob; ++p) {
-    const int s0 = (int)(op->eoff[p] / kSlice), s1 = (int)(op->eoff[p + 1] / kSlice);
+    const int64_t e0 = op->eoff[p], e1 = op->eoff[p + 1];
+    // class boundaries of this problem, local rows (a class owns the padding rows after it)
+    const std::vector<int64_t>& cb = cbounds[p];
+    auto class_of = [&](int64_t row) {   // index k with cb[k] <= row < cb[k+1]
+      return (int64_t)(std::upper_bound(cb.begin(), cb.end(), row) - cb.begin()) - 1;
+    };
+    const int ns = (int)((e1 - e0) / kSlice);
     op->wrange[p].x = (int)op->work.size();
-    for (int s = s0; s < s1; s += kSlicesPerBlock)
-      op->work.push_back(make_int4(p, s, std::min(kSlicesPerBlock, s1 - s), 0));
+    int sl = 0;
+    while (sl < ns) {
+      const int64_t w0 = cb[class_of((int64_t)sl * kSlice)];
+      int64_t w1 = cb[class_of((int64_t)(sl + 1) * kSlice - 1) + 1];
+      if (w1 - w0 > kWinRows) {   // too large for LDS: global gathers
+        const int n = std::min(kSolveWaves, ns - sl);
+        op->work.push_back(make_int4(p, (int)(e0 / kSlice) + sl, n, 0));
+        sl += n;
+        continue;
+      }
+      int n = 1;
+      while (sl + n < ns && n < kMaxItemSlices) {
+        const int64_t nw1 = cb[class_of((int64_t)(sl + n + 1) * kSlice - 1) + 1];
+        if (nw1 - w0 > kWinRows) break;
+        w1 = nw1;
+        ++n;
+      }
+      op->work.push_back(make_int4(p, (int)(e0 / kSlice) + sl, n | (int)((w1 - w0) << 16), (int)w0));
+      op->max_window = std::max<int64_t>(op->max_window, w1 - w0);
+      sl += n;
+    }
     op->wrange[p].y = (int)op->work.size();
   }
   SS_TRY(dalloc(&op->d_work, op->work.size()));
@@ -505,7 +617,7 @@ void free_op_impl(OpImpl* op) {
   dfree(op->d_canon2exec);
   dfree(op->d_sent);
   dfree(op->d_sptr);
-  if (op->d_norm) (void)hipFree(op->d_norm);
+  if (op->d_norm) pool_free(op->d_norm);
   op->d_norm = nullptr;
   dfree(op->d_eoff);
   dfree(op->d_work);
@@ -514,7 +626,7 @@ void free_op_impl(OpImpl* op) {
   dfree(op->d_A32);
   dfree(op->d_nu);
   dfree(op->d_a0);
-  if (op->ws.base) (void)hipFree(op->ws.base);
+  if (op->ws.base) pool_free(op->ws.base);
   if (op->h_pinned) (void)hipHostFree(op->h_pinned);
   free_apply_cache(op);
   delete op;

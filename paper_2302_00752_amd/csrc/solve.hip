@@ -49,6 +49,14 @@ constexpr int kMaxOuter = 30;
 
 enum { MV_PLAIN = 0, MV_DOT = 1, MV_RESID = 2 };
 
+// LDS of the matvec: a-table (64 x 16 B), |w_j|^2 (64 x 8 B), 4 partials, then the window
+constexpr int kLdsFixed = 64 * 16 + 64 * 8 + kSolveWaves * 8;
+
+// dynamic LDS bytes of a matvec over windows of up to `win` rows
+inline size_t mv_lds_bytes(int64_t win, bool fp64, bool wide) {
+  return kLdsFixed + (size_t)win * ((fp64 ? 16 : 8) + (wide ? 8 : 4));
+}
+
 // One problem in a launch.
 struct Desc {
   const uint32_t* sent;        // operator SELL entries
@@ -91,11 +99,12 @@ __device__ inline double wave_sum(double v) {
 
 // Sum of v over the block, returned to every thread.  Fixed order.
 __device__ inline double block_sum(double v, double* red) {
+  static_assert(kSolveWaves == 8, "reduction tree below is written for 8 wavefronts");
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  const double s = ((red[0] + red[1]) + (red[2] + red[3])) + ((red[4] + red[5]) + (red[6] + red[7]));
   __syncthreads();
   return s;
 }
@@ -103,7 +112,7 @@ __device__ inline double block_sum(double v, double* red) {
 // Sum of part[i*2 + off] for i in [b, e), every thread gets the result.  Fixed order.
 __device__ inline double range_sum(const double* __restrict__ part, int off, int b, int e, double* red) {
   double v = 0;
-  for (int i = b + (int)threadIdx.x; i < e; i += kBlock) v += part[(int64_t)i * 2 + off];
+  for (int i = b + (int)threadIdx.x; i < e; i += kSolveBlock) v += part[(int64_t)i * 2 + off];
   return block_sum(v, red);
 }
 
@@ -120,24 +129,34 @@ __device__ inline double jacobi_inv(NormT nk, double a0) {
   return nk > 0 ? 1.0 / (kFourPi2 * a0 * (double)nk) : 0.0;
 }
 
-template <typename NormT, typename V>
+// Row of the SELL slice at `base`: sum over its entries of (nk + |l|^2 - nu_j) A_j x_l.
+// WIN: x and |l|^2 come from the LDS window starting at execution row w0.
+template <bool WIN, typename NormT, typename V>
 __device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, uint32_t width, int lane, NormT nk,
-                             const NormT* __restrict__ normp, const V* __restrict__ xp, const V* As,
+                             const NormT* __restrict__ normp, const V* __restrict__ xp, int w0, const V* As,
                              const NormT* nus) {
   using R = typename Real<V>::T;
   R ar = 0, ai = 0;
-  for (uint32_t q = 0; q < width; ++q) {
-    const uint32_t ent = sent[base + q * kSlice + lane];
-    const uint32_t j = ent >> kColBits;
-    if (j != (uint32_t)kNullJ) {
-      const uint32_t c = ent & kColMask;
-      const NormT I = nk + normp[c] - nus[j];
-      const V a = As[j];
-      const V x = xp[c];
-      const R fi = (R)I;
-      const R cr = fi * a.x, ci = fi * a.y;
-      ar += cr * x.x - ci * x.y;
-      ai += cr * x.y + ci * x.x;
+  constexpr int kChunk = 8;   // entry loads in flight per lane
+  for (uint32_t q0 = 0; q0 < width; q0 += kChunk) {
+    uint32_t ent[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k)
+      ent[k] = q0 + k < width ? __builtin_nontemporal_load(sent + base + (q0 + k) * kSlice + lane)
+                              : (uint32_t)kNullJ << kColBits;
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const uint32_t j = ent[k] >> kColBits;
+      if (j != (uint32_t)kNullJ) {
+        const int c = (int)(ent[k] & kColMask) - (WIN ? w0 : 0);
+        const NormT I = nk + normp[c] - nus[j];
+        const V a = As[j];
+        const V x = xp[c];
+        const R fi = (R)I;
+        const R cr = fi * a.x, ci = fi * a.y;
+        ar += cr * x.x - ci * x.y;
+        ai += cr * x.y + ci * x.x;
+      }
     }
   }
   V out;
@@ -151,19 +170,18 @@ template <> __device__ inline const double2* a_table<double2>(const Desc& D) { r
 template <> __device__ inline const float2* a_table<float2>(const Desc& D) { return D.A32; }
 
 // Matvec over one work item.  PLAIN: q = L x;  DOT: q = L p, partial Re<p, q>;
-// RESID: r = f - L x (FP64), partials |r|^2, |f|^2.
+// RESID: r = f - L x (FP64), partials |r|^2, |f|^2.  Items with a window stage
+// x and |k|^2 of execution rows [w0, w0 + wlen) -- every class their rows
+// belong to -- in LDS once, so the gathers never leave the CU.
 template <typename NormT, typename V, int MODE>
-__device__ void mv_body(const Desc& D, int4 wk, int w, double* part, void* lds) {
+__device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) {
   V* As = (V*)lds;
-  NormT* nus = (NormT*)((char*)lds + 64 * sizeof(double2));
-  double* red = (double*)((char*)lds + 64 * sizeof(double2) + 64 * sizeof(int64_t));
+  NormT* nus = (NormT*)(lds + 64 * sizeof(double2));
+  double* red = (double*)(lds + 64 * sizeof(double2) + 64 * sizeof(int64_t));
+  const int nsl = wk.z & 0xffff, wlen = wk.z >> 16, w0 = wk.w;
+  V* xw = (V*)(lds + kLdsFixed);
+  NormT* nw = (NormT*)(lds + kLdsFixed + (size_t)wlen * sizeof(V));
   const int tid = threadIdx.x;
-  if (tid < 64) {
-    As[tid] = a_table<V>(D)[tid];
-    nus[tid] = (NormT)D.nu[tid];
-  }
-  __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
   const V* x;
   V* y;
   if (MODE == MV_DOT) {
@@ -176,28 +194,40 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, void* lds) 
     x = (const V*)(sizeof(V) == 16 ? (const void*)D.x64 : (const void*)D.x32);
     y = (V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
   }
+  const NormT* normv = (const NormT*)D.norm;
+  if (tid < 64) {
+    As[tid] = a_table<V>(D)[tid];
+    nus[tid] = (NormT)D.nu[tid];
+  }
+  for (int i = tid; i < wlen; i += kSolveBlock) {
+    xw[i] = x[w0 + i];
+    nw[i] = normv[w0 + i];
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
   double v0 = 0, v1 = 0;
-  if (wave < wk.z) {
-    const int64_t sl = wk.y + wave;
+  for (int sw = wave; sw < nsl; sw += kSolveWaves) {
+    const int64_t sl = wk.y + sw;
     const int64_t e = (sl - D.slice0) * kSlice + lane;
-    const NormT* normv = (const NormT*)D.norm;
     const uint32_t base = D.sptr[sl];
     const uint32_t width = (D.sptr[sl + 1] - base) / kSlice;
-    const V acc = sell_row<NormT, V>(D.sent, base, width, lane, normv[e], normv, x, As, nus);
+    const V acc = wlen > 0
+                      ? sell_row<true, NormT, V>(D.sent, base, width, lane, normv[e], nw, xw, w0, As, nus)
+                      : sell_row<false, NormT, V>(D.sent, base, width, lane, normv[e], normv, x, 0, As, nus);
     if (MODE == MV_PLAIN) {
       y[e] = acc;
     } else if (MODE == MV_DOT) {
       y[e] = acc;
       const V pe = x[e];
-      v0 = (double)pe.x * (double)acc.x + (double)pe.y * (double)acc.y;
+      v0 += (double)pe.x * (double)acc.x + (double)pe.y * (double)acc.y;
     } else {
       const double2 fe = D.f64[e];
       V r;
       r.x = fe.x - acc.x;
       r.y = fe.y - acc.y;
       y[e] = r;
-      v0 = (double)r.x * r.x + (double)r.y * r.y;
-      v1 = fe.x * fe.x + fe.y * fe.y;
+      v0 += (double)r.x * r.x + (double)r.y * r.y;
+      v1 += fe.x * fe.x + fe.y * fe.y;
     }
   }
   if (MODE != MV_PLAIN) {
@@ -210,11 +240,10 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, void* lds) 
   }
 }
 
-constexpr int kLdsBytes = 64 * 16 + 64 * 8 + 4 * 8;
 
 // only_final (RESID): 1 = problems being retired only, 0 = admissions and refinement steps only
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_mv(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_mv(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                int n_work, int per, double* part, int only_final = 0) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
@@ -234,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_mv(const Desc* __restrict__ descs, c
       if (!(D.init && D.prec == SS_FP64) && !outer) return;
     }
   }
-  __shared__ __align__(16) char lds[kLdsBytes];
+  extern __shared__ __align__(16) char lds[];
   const bool fp32 = MODE == MV_DOT ? D.prec != SS_FP64 : (MODE == MV_PLAIN && D.prec != SS_FP64);
   if (fp32) {
     if (D.wide) mv_body<int64_t, float2, MODE == MV_RESID ? MV_DOT : MODE>(D, wk, w, part, lds);
@@ -267,8 +296,8 @@ __device__ void update_body(const Desc& D, int4 wk, int w, const double* part_pq
   const V* q = (const V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double v0 = 0, v1 = 0;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const R a = (R)alpha;
     V xv = x[e], rv = r[e];
     const V pe = pv[e], qe = q[e];
@@ -279,8 +308,8 @@ __device__ void update_body(const Desc& D, int4 wk, int w, const double* part_pq
     x[e] = xv;
     r[e] = rv;
     const double rr = (double)rv.x * rv.x + (double)rv.y * rv.y;
-    v0 = rr * jacobi_inv(((const NormT*)D.norm)[e], D.a0);
-    v1 = rr;
+    v0 += rr * jacobi_inv(((const NormT*)D.norm)[e], D.a0);
+    v1 += rr;
   }
   const double s0 = block_sum(v0, red);
   const double s1 = block_sum(v1, red);
@@ -290,7 +319,7 @@ __device__ void update_body(const Desc& D, int4 wk, int w, const double* part_pq
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_update(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_cg_update(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                       int n_work, int per, const double* part_pq,
                                                       double* part_rz) {
   const int w = work_index(blockIdx.x, per);
@@ -298,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const Desc* __restrict__ d
   const int4 wk = work[w];
   const Desc& D = descs[wk.x];
   if (cg_idle(D)) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   if (D.prec == SS_FP64) {
     if (D.wide) update_body<int64_t, double2>(D, wk, w, part_pq, part_rz, red);
     else update_body<int32_t, double2>(D, wk, w, part_pq, part_rz, red);
@@ -333,8 +362,8 @@ __device__ void dir_body(const Desc& D, int4 wk, int w, const double* part_rz, d
   const V* r = (const V*)(sizeof(V) == 16 ? (void*)D.r64 : (void*)D.r32);
   V* pv = (V*)(sizeof(V) == 16 ? (void*)D.p64 : (void*)D.p32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const R dinv = (R)jacobi_inv(((const NormT*)D.norm)[e], D.a0);
     const R b = (R)beta;
     const V re = r[e];
@@ -345,14 +374,14 @@ __device__ void dir_body(const Desc& D, int4 wk, int w, const double* part_rz, d
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_dir(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_cg_dir(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                    int n_work, int per, const double* part_rz) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
   const int4 wk = work[w];
   const Desc& D = descs[wk.x];
   if (cg_idle(D)) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   if (D.prec == SS_FP64) {
     if (D.wide) dir_body<int64_t, double2>(D, wk, w, part_rz, red);
     else dir_body<int32_t, double2>(D, wk, w, part_rz, red);
@@ -370,8 +399,8 @@ __device__ void start_body(const Desc& D, int4 wk, int w, double* part_rz, doubl
   V* pv = (V*)(sizeof(V) == 16 ? (void*)D.p64 : (void*)D.p32);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double v0 = 0, v1 = 0;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const double di = jacobi_inv(((const NormT*)D.norm)[e], D.a0);
     const V re = r[e];
     V pe;
@@ -379,8 +408,8 @@ __device__ void start_body(const Desc& D, int4 wk, int w, double* part_rz, doubl
     pe.y = (R)di * re.y;
     pv[e] = pe;
     const double rr = (double)re.x * re.x + (double)re.y * re.y;
-    v0 = rr * di;
-    v1 = rr;
+    v0 += rr * di;
+    v1 += rr;
   }
   const double s0 = block_sum(v0, red);
   const double s1 = block_sum(v1, red);
@@ -390,14 +419,14 @@ __device__ void start_body(const Desc& D, int4 wk, int w, double* part_rz, doubl
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_start(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_cg_start(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                      int n_work, int per, double* part_rz) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
   const int4 wk = work[w];
   const Desc& D = descs[wk.x];
   if (!cg_state(D)->start) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   if (D.prec == SS_FP64) {
     if (D.wide) start_body<int64_t, double2>(D, wk, w, part_rz, red);
     else start_body<int32_t, double2>(D, wk, w, part_rz, red);
@@ -414,7 +443,7 @@ __global__ void k_cg_scalars(const Desc* __restrict__ descs, int n_desc, const d
   const Desc& D = descs[p];
   PState* cs = cg_state(D);
   if (!cs->start) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   const double rz = range_sum(part_rz, 0, D.wb, D.we, red);
   const double rr = range_sum(part_rz, 1, D.wb, D.we, red);
   if (threadIdx.x == 0) {
@@ -435,7 +464,7 @@ __global__ void k_cg_scalars(const Desc* __restrict__ descs, int n_desc, const d
 }
 
 // x64 += scale * x32 after a finished correction solve
-__global__ __launch_bounds__(kBlock) void k_refine_add(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_refine_add(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                        int n_work, int per) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
@@ -443,8 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_refine_add(const Desc* __restrict__ 
   const Desc& D = descs[wk.x];
   if (D.prec == SS_FP64 || D.ps->done || !D.ps_in->done || !D.ps_in->pending) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const double s = D.ps->scale;
     const float2 c = D.x32[e];
     double2 xv = D.x64[e];
@@ -462,7 +491,7 @@ __global__ void k_outer_scalars(const Desc* __restrict__ descs, int n_desc, cons
   const bool fp64_init = D.init && D.prec == SS_FP64;
   const bool outer = D.prec != SS_FP64 && !D.ps->done && D.ps_in->done;
   if (!fp64_init && !outer) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   const double rr = range_sum(part, 0, D.wb, D.we, red);
   const double ff = range_sum(part, 1, D.wb, D.we, red);
   if (threadIdx.x != 0) return;
@@ -488,7 +517,7 @@ __global__ void k_outer_scalars(const Desc* __restrict__ descs, int n_desc, cons
 }
 
 // r32 = r64 / scale, x32 = 0 for a correction solve being started
-__global__ __launch_bounds__(kBlock) void k_refine_start(const Desc* __restrict__ descs,
+__global__ __launch_bounds__(kSolveBlock) void k_refine_start(const Desc* __restrict__ descs,
                                                          const int4* __restrict__ work, int n_work, int per) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
@@ -496,8 +525,8 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(const Desc* __restrict_
   const Desc& D = descs[wk.x];
   if (D.prec == SS_FP64 || !D.ps_in->start) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const double s = 1.0 / D.ps->scale;
     const double2 rv = D.r64[e];
     D.r32[e] = make_float2((float)(rv.x * s), (float)(rv.y * s));
@@ -509,8 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(const Desc* __restrict_
 template <typename NormT>
 __device__ void admit_rows(const Desc& D, int4 wk) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const int64_t r = D.exec2canon[e];
     double2 fv = make_double2(0, 0), xv = make_double2(0, 0);
     if (r >= 0) {
@@ -522,7 +551,7 @@ __device__ void admit_rows(const Desc& D, int4 wk) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_admit(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_admit(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                   int n_work, int per) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
@@ -548,14 +577,14 @@ __global__ void k_state_init(const Desc* __restrict__ descs, int n_desc) {
 template <typename NormT>
 __device__ void retire_rows(const Desc& D, int4 wk) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (wave < wk.z) {
-    const int64_t e = (wk.y + wave - D.slice0) * kSlice + lane;
+  for (int sw = wave; sw < (wk.z & 0xffff); sw += kSolveWaves) {
+    const int64_t e = (wk.y + sw - D.slice0) * kSlice + lane;
     const int64_t r = D.exec2canon[e];
     if (r >= 0) D.u_canon[r] = ((const NormT*)D.norm)[e] > 0 ? D.x64[e] : make_double2(0, 0);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_retire(const Desc* __restrict__ descs, const int4* __restrict__ work,
+__global__ __launch_bounds__(kSolveBlock) void k_retire(const Desc* __restrict__ descs, const int4* __restrict__ work,
                                                    int n_work, int per) {
   const int w = work_index(blockIdx.x, per);
   if (w >= n_work) return;
@@ -571,7 +600,7 @@ __global__ void k_final_scalars(const Desc* __restrict__ descs, int n_desc, cons
   if (p >= n_desc) return;
   const Desc& D = descs[p];
   if (!D.final_) return;
-  __shared__ double red[4];
+  __shared__ double red[kSolveWaves];
   const double rr = range_sum(part, 0, D.wb, D.we, red);
   const double ff = range_sum(part, 1, D.wb, D.we, red);
   if (threadIdx.x == 0) {
@@ -605,6 +634,7 @@ struct LaunchList {
   size_t cap_desc = 0, cap_work = 0;
   int per = 1;
   unsigned grid = 8;
+  size_t lds_resid = 0, lds_dot = 0;   // dynamic LDS of the FP64-residual and CG / plain matvecs
 
   ~LaunchList() {
     dfree(d_descs);
@@ -618,7 +648,7 @@ struct LaunchList {
     work.clear();
     for (size_t k = 0; k < descs.size(); ++k) {
       descs[k].wb = (int32_t)work.size();
-      for (int4 it : items[k]) work.push_back(make_int4((int)k, it.y, it.z, 0));
+      for (int4 it : items[k]) work.push_back(make_int4((int)k, it.y, it.z, it.w));
       descs[k].we = (int32_t)work.size();
     }
     if (descs.size() > cap_desc) {
@@ -641,6 +671,15 @@ struct LaunchList {
       SS_HIP(hipMemcpyAsync(d_work, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     per = (int)std::max<int64_t>(1, ceil_div((int64_t)work.size(), 8));
     grid = (unsigned)(8 * per);
+    int64_t maxw = 0;
+    bool any64 = false, wide = false;
+    for (const int4& it : work) maxw = std::max<int64_t>(maxw, it.z >> 16);
+    for (const Desc& D : descs) {
+      any64 |= D.prec == SS_FP64;
+      wide |= D.wide != 0;
+    }
+    lds_resid = mv_lds_bytes(maxw, true, wide);
+    lds_dot = mv_lds_bytes(maxw, any64, wide);
     return SS_OK;
   }
   ss_status upload_descs(hipStream_t s) {
@@ -675,10 +714,10 @@ ss_status workspace(OpImpl* op, WS* w) {
   const int64_t n = op->n_exec;
   const size_t need = workspace_bytes(op);
   if (op->ws.bytes < need) {
-    if (op->ws.base) (void)hipFree(op->ws.base);
+    if (op->ws.base) pool_free(op->ws.base);
     op->ws.base = nullptr;
     op->ws.bytes = 0;
-    SS_HIP(hipMalloc(&op->ws.base, need));
+    SS_HIP(pool_alloc((void**)&op->ws.base, need));
     op->ws.bytes = need;
   }
   char* b = (char*)op->ws.base;
@@ -824,22 +863,22 @@ struct EngineImpl {
     LaunchList& L = list;
     const int nw = L.n_work(), nd = L.n_desc();
     k_state_init<<<grid_for(nd), kBlock, 0, s>>>(L.d_descs, nd);
-    k_admit<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
-    k_refine_add<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
-    k_mv<MV_RESID><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_c());
-    k_outer_scalars<<<nd, kBlock, 0, s>>>(L.d_descs, nd, L.part_c());
-    k_refine_start<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
-    k_cg_start<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
-    k_cg_scalars<<<nd, kBlock, 0, s>>>(L.d_descs, nd, L.part_b());
+    k_admit<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_refine_add<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_mv<MV_RESID><<<L.grid, kSolveBlock, L.lds_resid, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_c());
+    k_outer_scalars<<<nd, kSolveBlock, 0, s>>>(L.d_descs, nd, L.part_c());
+    k_refine_start<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per);
+    k_cg_start<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
+    k_cg_scalars<<<nd, kSolveBlock, 0, s>>>(L.d_descs, nd, L.part_b());
   }
 
   void launch_iterations(int iters) {
     LaunchList& L = list;
     const int nw = L.n_work();
     for (int it = 0; it < iters; ++it) {
-      k_mv<MV_DOT><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a());
-      k_cg_update<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a(), L.part_b());
-      k_cg_dir<<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
+      k_mv<MV_DOT><<<L.grid, kSolveBlock, L.lds_dot, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a());
+      k_cg_update<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_a(), L.part_b());
+      k_cg_dir<<<L.grid, kSolveBlock, 0, s>>>(L.d_descs, L.d_work, nw, L.per, L.part_b());
     }
   }
 
@@ -880,9 +919,10 @@ struct EngineImpl {
     for (int k : fin) list.descs[k].final_ = 1;
     SS_TRY(list.upload_descs(s));
     const int nw = list.n_work(), nd = list.n_desc();
-    k_mv<MV_RESID><<<list.grid, kBlock, 0, s>>>(list.d_descs, list.d_work, nw, list.per, list.part_c(), 1);
-    k_final_scalars<<<nd, kBlock, 0, s>>>(list.d_descs, nd, list.part_c(), list.d_states);
-    k_retire<<<list.grid, kBlock, 0, s>>>(list.d_descs, list.d_work, nw, list.per);
+    k_mv<MV_RESID><<<list.grid, kSolveBlock, list.lds_resid, s>>>(list.d_descs, list.d_work, nw, list.per,
+                                                             list.part_c(), 1);
+    k_final_scalars<<<nd, kSolveBlock, 0, s>>>(list.d_descs, nd, list.part_c(), list.d_states);
+    k_retire<<<list.grid, kSolveBlock, 0, s>>>(list.d_descs, list.d_work, nw, list.per);
     SS_HIP(hipMemcpyAsync(h_states, list.d_states, nd * sizeof(PState), hipMemcpyDeviceToHost, s));
     SS_HIP(hipStreamSynchronize(s));
     std::vector<char> gone(nd, 0);
@@ -1040,7 +1080,7 @@ ss_status apply_impl(const OpImpl* op_c, ss_precision prec, const void* x, void*
     c.prec = prec;
   }
   LaunchList& L = *c.list;
-  k_mv<MV_PLAIN><<<L.grid, kBlock, 0, s>>>(L.d_descs, L.d_work, L.n_work(), L.per, nullptr);
+  k_mv<MV_PLAIN><<<L.grid, kSolveBlock, L.lds_dot, s>>>(L.d_descs, L.d_work, L.n_work(), L.per, nullptr);
   SS_HIP(hipGetLastError());
   return SS_OK;
 }

@@ -37,6 +37,8 @@ constexpr uint32_t kColMask = (1u << kColBits) - 1;
 constexpr int kSlice = 64;            // SELL slice height = wavefront size
 constexpr int kBlock = 256;           // threads per block (4 wavefronts)
 constexpr int kSlicesPerBlock = kBlock / kSlice;
+constexpr int kSolveBlock = 512;      // threads per block of the matvec / CG kernels (8 wavefronts)
+constexpr int kSolveWaves = kSolveBlock / kSlice;
 constexpr int kWinRows = 2048;        // rows of x / |k|^2 a block stages in LDS
 constexpr int kMaxItemSlices = 64;    // slices per work item (window items)
 constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;

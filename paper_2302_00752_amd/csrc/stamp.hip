@@ -410,15 +410,18 @@ double app_a_count(int64_t n_f, int s, int N) {
 
 // Owns scratch device allocations of one build; frees them on every exit path.
 struct Scratch {
+  hipStream_t stream = nullptr;
   std::vector<void**> slots;
+  explicit Scratch(hipStream_t s) : stream(s) {}
   template <typename T>
   void hold(T*& p) {
     slots.push_back((void**)&p);
   }
   ~Scratch() {
+    (void)hipStreamSynchronize(stream);   // queued work may still use the blocks (error paths)
     for (void** s : slots)
       if (*s) {
-        (void)hipFree(*s);
+        pool_free(*s);
         *s = nullptr;
       }
   }
@@ -580,7 +583,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_HIP(hipMemcpyAsync(st->d_coef, z.data(), d * 8, hipMemcpyHostToDevice, stream));
 
   // ---- build scratch
-  Scratch sc;
+  Scratch sc(stream);
   int16_t* wk = nullptr;
   uint64_t* wh = nullptr;
   int32_t *wo = nullptr, *plev = nullptr, *err = nullptr;
@@ -684,7 +687,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
     if (need_tmp > tmp_bytes) {
       dfree(tmp);
-      SS_HIP(hipMalloc(&tmp, need_tmp));
+      SS_HIP(pool_alloc((void**)&tmp, need_tmp));
       tmp_bytes = need_tmp;
     }
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
@@ -766,7 +769,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
   if (!passes.empty()) {
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k64, k64b, perm, perm2, total, 0, 64, stream));
-    SS_HIP(hipMalloc(&tmp, tmp_bytes));
+    SS_HIP(pool_alloc((void**)&tmp, tmp_bytes));
   }
   for (size_t q = 0; q < passes.size(); ++q) {
     k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, perm, d_fields, passes[q].first,
@@ -841,7 +844,7 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   int16_t* dq = nullptr;
   int64_t* dout = nullptr;
   int32_t* dp = nullptr;
-  Scratch sc;
+  Scratch sc(stream);
   sc.hold(dq); sc.hold(dout); sc.hold(dp);
   SS_TRY(dalloc(&dq, (size_t)nq * st->d));
   SS_TRY(dalloc(&dout, nq));
