@@ -54,7 +54,8 @@ struct NbrArgs {
 // lanes compacts the hits to the front of the row's buffer in j order.
 __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_blocks = ceil_div(ceil_div(a.total, a.rows_per_wave), kBlock / 64);
+  const int64_t wave = (xcd_block(n_blocks) * kBlock + threadIdx.x) >> 6;
   const int rl = lane / a.smax, j = lane % a.smax;
   const int64_t r = wave * a.rows_per_wave + rl;
   const bool live = rl < a.rows_per_wave && r < a.total;
@@ -74,14 +75,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
         const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
         uint64_t pos = slot_first(h, base, mask);
         while (true) {
-          const uint64_t v = a.table[2 * pos];
-          if (v == 0) break;
-          if (a.table[2 * pos + 1] == h) {
-            const int64_t m = (int64_t)(v & kIdxMask);
-            const int16_t* km = a.keys + m * d;
-            bool eq = true;
-            for (int t = 0; t < d && eq; ++t) eq = (int)km[t] == (int)k[t] - (int)w[t];
-            if (eq) {
+          const ulonglong2 sv = reinterpret_cast<const ulonglong2*>(a.table)[pos];
+          if (sv.x == 0) break;
+          if (sv.y == h) {
+            const int64_t m = (int64_t)(sv.x & kIdxMask);
+            if (key_eq_shift(a.keys + m * d, k, w, -1, d)) {
               col = m;
               break;
             }
@@ -105,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
 
 __global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
                            const int64_t* __restrict__ crow, uint32_t* __restrict__ cent) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int64_t c0 = crow[r], n = crow[r + 1] - c0;
   for (int64_t q = 0; q < n; ++q) cent[c0 + q] = buf[r * smax + q];
@@ -120,7 +118,7 @@ __global__ void k_nnz_per_problem(int n_prob, const int64_t* __restrict__ rowoff
 __global__ void k_cc_prop(int64_t total, const int64_t* __restrict__ crow, const uint32_t* __restrict__ cent,
                           const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff, int64_t* label,
                           int32_t* changed) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int64_t base = rowoff[pid[r]];
   const int64_t own = label[r];
@@ -141,39 +139,39 @@ __global__ void k_cc_jump(int64_t total, int64_t* label) {
   label[r] = label[label[r]];
 }
 
-__global__ void k_fill_u64(int64_t n, unsigned long long* p, unsigned long long v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// class label -> smallest canonical slot of the class
-__global__ void k_cc_min(int64_t total, const int64_t* __restrict__ label, unsigned long long* cmin) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < total) atomicMin(&cmin[label[r]], (unsigned long long)r);
-}
-
-__global__ void k_cc_finish(int64_t total, const int64_t* __restrict__ label,
-                            const unsigned long long* __restrict__ cmin, const int32_t* __restrict__ pid,
-                            const int64_t* __restrict__ rowoff, int32_t* __restrict__ comp,
-                            int32_t* __restrict__ ncomp) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= total) return;
-  const int p = pid[r];
-  const int64_t m = (int64_t)cmin[label[r]];
-  comp[r] = (int32_t)(m - rowoff[p]);
-  if (m == r) atomicAdd(&ncomp[p], 1);
+// one wavefront per class (a run [cq[k], cq[k+1]) of the sorted rows): the class id is the
+// smallest canonical slot of the class, written to every member
+__global__ void k_class_min(int64_t n_cls, int64_t total, const int64_t* __restrict__ cq,
+                            const uint32_t* __restrict__ order, const int32_t* __restrict__ pid,
+                            const int64_t* __restrict__ rowoff, int32_t* __restrict__ comp) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= n_cls) return;
+  const int64_t q0 = cq[k], q1 = k + 1 < n_cls ? cq[k + 1] : total;
+  const int64_t base = rowoff[pid[order[q0]]];
+  int64_t m = INT64_MAX;
+  for (int64_t q = q0 + lane; q < q1; q += 64) {
+    const int64_t r = order[q];
+    m = r < m ? r : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(m, off, 64);
+    m = o < m ? o : m;
+  }
+  for (int64_t q = q0 + lane; q < q1; q += 64) comp[order[q]] = (int32_t)(m - base);
 }
 
 // sort key (problem, class, 63 - row length, canonical slot) packed with `lb` bits per local index
 __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ pid,
-                            const int64_t* __restrict__ rowoff, const int32_t* __restrict__ comp,
+                            const int64_t* __restrict__ rowoff, const int64_t* __restrict__ label,
                             const int64_t* __restrict__ rowlen, uint64_t* __restrict__ key,
                             uint32_t* __restrict__ val) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r];
   const uint64_t local = (uint64_t)(r - rowoff[p]);
-  key[r] = ((((((uint64_t)p << lb) | (uint64_t)comp[r]) << 6) | (uint64_t)(63 - rowlen[r])) << lb) | local;
+  const uint64_t cls = (uint64_t)(label[r] - rowoff[p]);
+  key[r] = ((((((uint64_t)p << lb) | cls) << 6) | (uint64_t)(63 - rowlen[r])) << lb) | local;
   val[r] = (uint32_t)r;
 }
 
@@ -196,21 +194,24 @@ __global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, co
   exec2canon[e] = r;
 }
 
+// width (in entries) of each 64-row slice: one wavefront per slice, one lane per row
 __global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec2canon,
                               const int64_t* __restrict__ rowlen, uint32_t* __restrict__ width) {
-  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t sl = g >> 6;
   if (sl >= n_slices) return;
-  int64_t w = 0;
-  for (int l = 0; l < kSlice; ++l) {
-    const int64_t r = exec2canon[sl * kSlice + l];
-    if (r >= 0) w = rowlen[r] > w ? rowlen[r] : w;
+  const int64_t r = exec2canon[g];
+  int w = r >= 0 ? (int)rowlen[r] : 0;
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(w, off, 64);
+    w = o > w ? o : w;
   }
-  width[sl] = (uint32_t)(w * kSlice);
+  if ((g & 63) == 0) width[sl] = (uint32_t)(w * kSlice);
 }
 
-// 1 where a position of `order` (sorted rows; -1 = none) starts a new class: first row of a
-// problem, or a class change
-__global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ order, const int32_t* __restrict__ comp,
+// 1 where a position of `order` (sorted rows) starts a new class: first row of a problem,
+// or a class change
+__global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ order, const int64_t* __restrict__ label,
                                     const int32_t* __restrict__ pid, uint32_t* __restrict__ flag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
@@ -218,15 +219,15 @@ __global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ orde
   uint32_t f = 1;
   if (q > 0) {
     const int64_t rp = order[q - 1];
-    f = (pid[rp] != pid[r] || comp[rp] != comp[r]) ? 1u : 0u;
+    f = (pid[rp] != pid[r] || label[rp] != label[r]) ? 1u : 0u;
   }
   flag[q] = f;
 }
 
-__global__ void k_compact_starts(int64_t n_exec, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+__global__ void k_compact_starts(int64_t n, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                                  int64_t* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n_exec && flag[e]) out[idx[e]] = e;
+  if (e < n && flag[e]) out[idx[e]] = e;
 }
 
 template <typename NormT>
@@ -237,7 +238,7 @@ __global__ void k_sell_fill(int64_t n_exec, const int64_t* __restrict__ exec2can
                             const int64_t* __restrict__ eoff, const int64_t* __restrict__ norm,
                             const uint32_t* __restrict__ sptr, uint32_t* __restrict__ sent,
                             NormT* __restrict__ norm_exec) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = xcd_block(ceil_div(n_exec, kBlock)) * kBlock + threadIdx.x;
   if (e >= n_exec) return;
   const int64_t sl = e / kSlice;
   const int lane = (int)(e % kSlice);
@@ -356,7 +357,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
              st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_table, nbr, rowlen};
   const int64_t n_waves = ceil_div(total, rpw);
-  k_neighbors<<<(unsigned)ceil_div(n_waves, kBlock / 64), kBlock, 0, stream>>>(na);
+  k_neighbors<<<xcd_grid(ceil_div(n_waves, kBlock / 64)), kBlock, 0, stream>>>(na);
   SS_TRY(dalloc(&op->d_crow, total + 1));
   {
     size_t tb = 0;
@@ -376,42 +377,29 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   SS_TRY(dalloc(&op->d_cent, op->nnz));
-  k_csr_copy<<<grid_for(total), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
+  k_csr_copy<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
 
   // ---- connected classes: labels start at each key's root forcing key (so classes that no
-  // coincidence merged are final at once), min-propagation with pointer jumping settles merges,
-  // then the label becomes the smallest canonical slot of the class
+  // coincidence merged are final at once); min-propagation with pointer jumping settles merges.
+  // The class id (smallest canonical slot of the class) is taken after the execution sort,
+  // which makes every class a contiguous run
   int64_t* label = nullptr;
   int32_t* changed = nullptr;
-  int32_t* ncomp = nullptr;
-  unsigned long long* cmin = nullptr;
   SS_TRY(dalloc(&label, total));
   track(label);
   SS_TRY(dalloc(&changed, 1));
   track(changed);
-  SS_TRY(dalloc(&ncomp, n_prob));
-  track(ncomp);
-  SS_TRY(dalloc(&cmin, total));
-  track(cmin);
   SS_HIP(hipMemcpyAsync(label, st->d_root, total * 8, hipMemcpyDeviceToDevice, stream));
   for (int it = 0; it < 100000; ++it) {
     int32_t h = 0;
     SS_HIP(hipMemsetAsync(changed, 0, 4, stream));
-    k_cc_prop<<<grid_for(total), kBlock, 0, stream>>>(total, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
-                                                       label, changed);
+    k_cc_prop<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, op->d_crow, op->d_cent, st->d_pid,
+                                                                          st->d_rowoff, label, changed);
     k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
     SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipStreamSynchronize(stream));
     if (!h) break;
   }
-  k_fill_u64<<<grid_for(total), kBlock, 0, stream>>>(total, cmin, ~0ull);
-  k_cc_min<<<grid_for(total), kBlock, 0, stream>>>(total, label, cmin);
-  SS_TRY(dalloc(&op->d_comp, total));
-  SS_HIP(hipMemsetAsync(ncomp, 0, n_prob * 4, stream));
-  k_cc_finish<<<grid_for(total), kBlock, 0, stream>>>(total, label, cmin, st->d_pid, st->d_rowoff, op->d_comp,
-                                                      ncomp);
-  op->comps.assign(n_prob, 0);
-  SS_HIP(hipMemcpyAsync(op->comps.data(), ncomp, n_prob * 4, hipMemcpyDeviceToHost, stream));
 
   // ---- execution order: (problem, class, -row length, canonical slot); a class whose
   // padding to a slice boundary costs at most 1/8 of its rows is padded, so the slices of
@@ -433,8 +421,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   int pb = 0;
   while ((1 << pb) < n_prob) ++pb;
   const int key_bits = pb + 2 * lb + 6;   // <= 14 + 44 + 6
-  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, op->d_comp, rowlen, ek,
-                                                      ev);
+  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, label, rowlen, ek, ev);
   {
     size_t tb = 0;
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
@@ -449,7 +436,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(cflag);
   SS_TRY(dalloc(&cidx, total + 1));
   track(cidx);
-  k_class_start_flags<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, op->d_comp, st->d_pid, cflag);
+  k_class_start_flags<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, label, st->d_pid, cflag);
   SS_HIP(hipMemsetAsync(cflag + total, 0, 4, stream));
   std::vector<int64_t> cq;   // sorted position of every class start
   {
@@ -466,10 +453,20 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     SS_TRY(dalloc(&d_cq, std::max<uint32_t>(n_cls, 1)));
     track(d_cq);
     k_compact_starts<<<grid_for(total), kBlock, 0, stream>>>(total, cflag, cidx, d_cq);
+    SS_TRY(dalloc(&op->d_comp, total));
+    if (n_cls)
+      k_class_min<<<(unsigned)ceil_div((int64_t)n_cls * 64, kBlock), kBlock, 0, stream>>>(
+          n_cls, total, d_cq, ev2, st->d_pid, st->d_rowoff, op->d_comp);
     cq.resize(n_cls);
     if (n_cls) SS_HIP(hipMemcpyAsync(cq.data(), d_cq, n_cls * 8, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipStreamSynchronize(stream));
   }
+  op->comps.assign(n_prob, 0);
+  for (int64_t q : cq) {
+    const int p = (int)(std::upper_bound(st->row_off.begin(), st->row_off.end(), q) - st->row_off.begin()) - 1;
+    op->comps[p] += 1;
+  }
+  op->n_components = (int64_t)cq.size();
   // exec layout of every class (host), per problem
   const int64_t n_cls = (int64_t)cq.size();
   std::vector<int64_t> ce0(n_cls);                       // global exec row of each class start
@@ -520,7 +517,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&width, op->n_slices + 1));
   track(width);
   SS_TRY(dalloc(&op->d_sptr, op->n_slices + 1));
-  k_slice_width<<<grid_for(op->n_slices), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen, width);
+  k_slice_width<<<grid_for(op->n_slices * kSlice), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen,
+                                                                        width);
   SS_HIP(hipMemsetAsync(width + op->n_slices, 0, 4, stream));
   {
     size_t tb = 0;
@@ -542,14 +540,14 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     int64_t* ne = nullptr;
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
-    k_sell_fill<int64_t><<<grid_for(op->n_exec), kBlock, 0, stream>>>(
+    k_sell_fill<int64_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
         op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
         op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
   } else {
     int32_t* ne = nullptr;
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
-    k_sell_fill<int32_t><<<grid_for(op->n_exec), kBlock, 0, stream>>>(
+    k_sell_fill<int32_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
         op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
         op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
   }

@@ -60,6 +60,24 @@ __host__ __device__ inline uint64_t fmix64(uint64_t k) {
   return k;
 }
 
+// a == b + sign * w over d int16 coordinates, in int arithmetic (no wrap-around).  No early
+// exit: every load is independent, so a wavefront keeps all of them in flight at once.
+__device__ inline bool key_eq_shift(const int16_t* __restrict__ a, const int16_t* __restrict__ b,
+                                    const int16_t* __restrict__ w, int sign, int d) {
+  int acc = 0;
+#pragma unroll 8
+  for (int t = 0; t < d; ++t) acc |= (int)a[t] ^ ((int)b[t] + sign * (int)w[t]);
+  return acc == 0;
+}
+// b1 + w1 == b2 + w2
+__device__ inline bool key_eq_shift2(const int16_t* __restrict__ b1, const int16_t* __restrict__ w1,
+                                     const int16_t* __restrict__ b2, const int16_t* __restrict__ w2, int d) {
+  int acc = 0;
+#pragma unroll 8
+  for (int t = 0; t < d; ++t) acc |= ((int)b1[t] + (int)w1[t]) ^ ((int)b2[t] + (int)w2[t]);
+  return acc == 0;
+}
+
 // linear probing inside one problem's power-of-two table region [base, base + mask + 1)
 __host__ __device__ inline uint64_t slot_first(uint64_t h, uint64_t base, uint64_t mask) {
   return base + (fmix64(h) & mask);
@@ -266,6 +284,16 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// XCD-aware block numbering: the hardware deals blocks to the 8 XCDs round-robin;
+// renumbering so each XCD gets a contiguous eighth of the logical blocks keeps the
+// data of neighbouring blocks (one problem's table region, keys, CSR) in one L2.
+// Launch with xcd_grid(n) blocks; a block whose logical index is >= n exits.
+inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(8 * ceil_div(nblocks, 8)); }
+__device__ inline int64_t xcd_block(int64_t nblocks) {
+  const int64_t per = (nblocks + 7) / 8;
+  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
 
 }  // namespace ss

@@ -48,27 +48,19 @@ __device__ inline uint64_t atomic_load_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline bool eq_shift(const int16_t* a, const int16_t* b, const int16_t* w, int d) {
-  for (int t = 0; t < d; ++t)
-    if ((int)a[t] != (int)b[t] + (int)w[t]) return false;
-  return true;
-}
-
-__device__ inline bool eq_shift2(const int16_t* b1, const int16_t* w1, const int16_t* b2,
-                                 const int16_t* w2, int d) {
-  for (int t = 0; t < d; ++t)
-    if ((int)b1[t] + (int)w1[t] != (int)b2[t] + (int)w2[t]) return false;
-  return true;
-}
-
 __global__ void k_hash_keys(int64_t n, int d, const int16_t* __restrict__ keys, const uint64_t* __restrict__ z,
-                            uint64_t* __restrict__ out) {
+                            uint64_t* __restrict__ out, int64_t* __restrict__ norm) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t h = 0;
+  int64_t nn = 0;
   const int16_t* k = keys + i * d;
-  for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
+  for (int t = 0; t < d; ++t) {
+    h += (uint64_t)(int64_t)k[t] * z[t];
+    nn += (int64_t)k[t] * k[t];
+  }
   out[i] = h;
+  norm[i] = nn;
 }
 
 __global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, const int32_t* __restrict__ pid,
@@ -111,7 +103,7 @@ struct ExpandArgs {
 };
 
 __global__ void k_expand(ExpandArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand) return;
   const int64_t i = a.f0 + t / a.smax1;
   const int j = (int)(t % a.smax1);
@@ -148,7 +140,7 @@ __global__ void k_expand(ExpandArgs a) {
     }
     if ((v & kTagMask) == kTagMain) {
       const int64_t m = (int64_t)(v & kIdxMask);
-      if (a.table[2 * pos + 1] == h && eq_shift(a.keys + m * d, k, w, d)) {
+      if (a.table[2 * pos + 1] == h && key_eq_shift(a.keys + m * d, k, w, 1, d)) {
         a.cpos[t] = kNoSlot;   // already in an earlier level
         return;
       }
@@ -156,7 +148,7 @@ __global__ void k_expand(ExpandArgs a) {
       const int64_t i2 = (int64_t)((v & kIdxMask) >> 6);
       const int j2 = (int)(v & 63);
       const uint64_t h2 = a.hash[i2] + a.whash[wo + j2];     // same problem: same region
-      if (h2 == h && eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo + j2) * d, k, w, d)) {
+      if (h2 == h && key_eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo + j2) * d, k, w, d)) {
         // equal key among this level's candidates: the smallest candidate keeps the slot
         while (my < v) {
           unsigned long long old = atomicCAS((unsigned long long*)&a.table[2 * pos], (unsigned long long)v,
@@ -175,7 +167,7 @@ __global__ void k_expand(ExpandArgs a) {
 __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint32_t* __restrict__ cpos,
                           const int32_t* __restrict__ pid, const int64_t* __restrict__ toff,
                           const uint64_t* __restrict__ table, uint32_t* __restrict__ flag) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_cand) return;
   uint32_t f = 0;
   if (cpos[t] != kNoSlot) {
@@ -188,8 +180,8 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
 
 __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                          int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out,
-                         int64_t* root) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                         int64_t* root, int64_t* norm_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand || !flag[t]) return;
   const int64_t i = a.f0 + t / a.smax1;
   const int j = (int)(t % a.smax1);
@@ -200,7 +192,13 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   const int16_t* k = a.keys + i * d;
   const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
   int16_t* o = keys_out + m * d;
-  for (int c = 0; c < d; ++c) o[c] = (int16_t)((int)k[c] + (int)w[c]);
+  int64_t nn = 0;
+  for (int c = 0; c < d; ++c) {
+    const int v = (int)k[c] + (int)w[c];
+    o[c] = (int16_t)v;
+    nn += (int64_t)v * v;
+  }
+  norm_out[m] = nn;
   const uint64_t h = a.hash[i] + a.whash[wo + j];
   hash_out[m] = h;
   pid_out[m] = p;
@@ -272,22 +270,25 @@ __global__ void k_iota_u32(int64_t n, uint32_t* p) {
   if (i < n) p[i] = (uint32_t)i;
 }
 
-__global__ void k_permute_out(int64_t n, int d, const uint32_t* __restrict__ perm,
-                              const int16_t* __restrict__ ukeys, const uint64_t* __restrict__ uhash,
-                              const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
-                              int16_t* keys, uint64_t* hash, int32_t* pid, uint8_t* lev, int64_t* norm,
-                              uint32_t* inv, unsigned long long* max_norm) {
+// sorted key rows: one thread per (row, coordinate), so reads of a source row and the
+// writes of the output are contiguous across neighbouring threads
+__global__ void k_permute_keys(int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
+                               int16_t* __restrict__ keys) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * d) return;
+  const int64_t r = g / d;
+  keys[g] = ukeys[(int64_t)perm[r] * d + (g - r * d)];
+}
+
+__global__ void k_permute_meta(int64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ uhash,
+                               const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
+                               const int64_t* __restrict__ unorm, uint64_t* hash, int32_t* pid, uint8_t* lev,
+                               int64_t* norm, uint32_t* inv, unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = 0;
   if (r < n) {
     const int64_t s = perm[r];
-    const int16_t* k = ukeys + s * d;
-    int16_t* o = keys + r * d;
-    for (int c = 0; c < d; ++c) {
-      const int v = k[c];
-      o[c] = (int16_t)v;
-      nn += (int64_t)v * v;
-    }
+    nn = unorm[s];
     hash[r] = uhash[s];
     pid[r] = upid[s];
     lev[r] = ulev[s];
@@ -348,13 +349,13 @@ __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32
   uint64_t pos = slot_first(h, base, mask);
   int64_t res = -1;
   while (true) {
-    const uint64_t v = table[2 * pos];
-    if (v == 0) break;
-    const int64_t m = (int64_t)(v & kIdxMask);
-    if (table[2 * pos + 1] == h) {
-      bool eq = true;
-      for (int t = 0; t < d && eq; ++t) eq = keys[m * d + t] == k[t];
-      if (eq) {
+    const ulonglong2 sv = reinterpret_cast<const ulonglong2*>(table)[pos];
+    if (sv.x == 0) break;
+    const int64_t m = (int64_t)(sv.x & kIdxMask);
+    if (sv.y == h) {
+      int acc = 0;
+      for (int t = 0; t < d; ++t) acc |= (int)keys[m * d + t] ^ (int)k[t];
+      if (acc == 0) {
         res = probs ? m : m - rowoff[pq];
         break;
       }
@@ -592,11 +593,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   int32_t* upid = nullptr;
   uint8_t* ulev = nullptr;
   int64_t* uroot = nullptr;
+  int64_t* unorm = nullptr;
   uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev); sc.hold(err);
-  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev); sc.hold(uroot);
+  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev); sc.hold(uroot); sc.hold(unorm);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
   SS_TRY(dalloc(&wk, wkeys.size()));
@@ -615,12 +617,13 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- level 0: F
   int64_t kcap = std::max<int64_t>(nF * 4, 1024);
-  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap;
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap, kcap_n = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
   SS_TRY(dalloc(&upid, kcap));
   SS_TRY(dalloc(&ulev, kcap));
   SS_TRY(dalloc(&uroot, kcap));
+  SS_TRY(dalloc(&unorm, kcap));
   {
     std::vector<int32_t> fpid(nF);
     for (int p = 0; p < n_prob; ++p)
@@ -629,7 +632,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipMemcpyAsync(upid, fpid.data(), nF * 4, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
     k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
-    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash);
+    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash, unorm);
     SS_HIP(hipStreamSynchronize(stream));   // fpid is a host temporary
   }
   // per-problem regions sized from the App. A count (grown below if coincidences are rarer than it assumes)
@@ -661,6 +664,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
     SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
     SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
+    SS_TRY(grow(&unorm, &kcap_n, need, total, 1, stream));
     bool relayout = false;
     for (int p = 0; p < n_prob; ++p) {
       const int64_t need_p = cnt[p] + (level[p] >= n ? fcount[p] * (s_of[p] - 1) : 0);
@@ -681,8 +685,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     }
     ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_toff, st->d_tmask,
                   st->d_table, cpos, err};
-    k_expand<<<grid_for(n_cand), kBlock, 0, stream>>>(ea);
-    k_winners<<<grid_for(n_cand), kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
+    const unsigned cg = grid_for(n_cand);
+    k_expand<<<cg, kBlock, 0, stream>>>(ea);
+    k_winners<<<cg, kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
     size_t need_tmp = 0;
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
     if (need_tmp > tmp_bytes) {
@@ -691,7 +696,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       tmp_bytes = need_tmp;
     }
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
-    k_append<<<grid_for(n_cand), kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot);
+    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot, unorm);
     SS_HIP(hipMemcpyAsync(d_fstart, fstart.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemcpyAsync(d_fcount, fcount.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
     k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, smax1, d_fstart, d_fcount, idx, flag, d_cnt);
@@ -790,8 +795,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint32_t* inv = perm2;
   unsigned long long* d_maxn = (unsigned long long*)k64;
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
-  k_permute_out<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, uhash, upid, ulev, st->d_keys,
-                                                        st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  k_permute_keys<<<grid_for(total * d), kBlock, 0, stream>>>(total, d, perm, ukeys, st->d_keys);
+  k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uhash, upid, ulev, unorm, st->d_hash,
+                                                         st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots, st->d_table,
                                                                                           inv);

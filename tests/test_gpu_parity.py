@@ -298,3 +298,43 @@ def test_warm_start_from_solution(ss):
     f = f_vector(ss, st, [oc["p"]])
     u, info = gpu_solve(ss, op, f, TOL64, "fp64", u0=oc["u"].copy())
     assert info[0]["iters"] <= 1 and rel(u, oc["u"]) <= ERR64
+
+
+def test_wide_norms_int64_path(ss):
+    # coordinates near 3e4 in d = 3 give |k|^2 > 2^30: the operator switches to int64 norms
+    p = P(3, [[0, 0, 0], [1, 2, 0], [-1, -2, 0], [0, 1, 3], [0, -1, -3]],
+          [2.0, 0.3 + 0.2j, 0.3 - 0.2j, 0.25j, -0.25j],
+          [[30000, -29000, 31000], [-30000, 29000, -31000], [29990, 29995, -30001]],
+          [1.0 + 1j, 1.0 - 1j, 0.5], 2)
+    assert 3 * 31000 ** 2 > 2 ** 30
+    keys, u = _check_against_oracle(ss, p)
+    _check_against_oracle(ss, p, precision="fp32_refine")
+    st, op = build(ss, [p])
+    em = op.exec_map()
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    M = og.matrix(keys, af, ah)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(op.n_total) + 1j * rng.standard_normal(op.n_total)
+    xe = np.zeros(op.n_exec, dtype=np.complex128)
+    xe[em >= 0] = x[em[em >= 0]]
+    xd = torch.from_numpy(xe).cuda()
+    yd = torch.zeros_like(xd)
+    op.apply(xd, yd, "fp64")
+    torch.cuda.synchronize()
+    y = np.zeros(op.n_total, dtype=np.complex128)
+    y[em[em >= 0]] = yd.cpu().numpy()[em >= 0]
+    assert np.all(np.abs(y - M @ x) <= 64 * np.finfo(np.float64).eps * (abs(M) @ np.abs(x)))
+
+
+def test_class_larger_than_lds_window(ss):
+    # d = 2 with a dense support merges everything into one class of several thousand rows:
+    # the matvec takes the global-gather items for it
+    w = [(1, 0), (0, 1), (1, 1), (2, -1)]
+    af = [[0, 0]] + [list(v) for v in w] + [[-a, -b] for a, b in w]
+    ah = [1.0] + [0.05 + 0.02j] * 4 + [0.05 - 0.02j] * 4
+    p = P(2, af, ah, [[3, 1], [-3, -1], [5, -7], [-5, 7]], [1.0, 1.0, 0.3j, -0.3j], 16)
+    keys, u = _check_against_oracle(ss, p)
+    assert len(keys) > 2048
+    st, op = build(ss, [p])
+    assert op.n_components < 4
+    _check_against_oracle(ss, p, precision="fp32_refine")
