@@ -271,11 +271,10 @@ ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double*
     const auto t0 = std::chrono::steady_clock::now();
     ATable at;
     SS_TRY(canonical_a(d, n_a, a_freqs, a_hat, true, &at));
-    const int32_t s = (int32_t)at.keys.size();
-    std::vector<int16_t> ak;
+    const int32_t s = at.size();
+    const std::vector<int16_t>& ak = at.keys;
     std::vector<double> ac;
     for (int j = 0; j < s; ++j) {
-      ak.insert(ak.end(), at.keys[j].begin(), at.keys[j].end());
       ac.push_back(at.coef[j].x);
       ac.push_back(at.coef[j].y);
     }

@@ -46,7 +46,7 @@ struct NbrArgs {
   const int64_t* toff;
   const uint64_t* tmask;
   const uint64_t* table;
-  uint32_t* buf;       // [total x smax] compact row entries: local canonical column | j << 26
+  uint32_t* buf;       // [smax x total] compact row entries (entry q of row r at q * total + r): local canonical column | j << 26
   int64_t* rowlen;     // [total]
 };
 
@@ -95,10 +95,141 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
   if (live) {
     if (col >= 0) {
       const int q = __popcll(seg & ((1ull << j) - 1));
-      a.buf[r * a.smax + q] = (uint32_t)(col - a.rowoff[p]) | ((uint32_t)j << kColBits);
+      a.buf[q * a.total + r] = (uint32_t)(col - a.rowoff[p]) | ((uint32_t)j << kColBits);
     }
     if (j == 0) a.rowlen[r] = __popcll(seg);
   }
+}
+
+constexpr int kNbrGroup = 4;   // slots per probe group (64 bytes)
+
+// One lane per row, for dimensions up to DMAX: the row's key and hash stay in registers while
+// the lane looks up k - w_j for every a-table entry in table order.  A lookup reads the aligned
+// group of G slots that holds its first probe position and scans it from there (linear probing
+// stays within the group for nearly every lookup at the table's load factor), so the lanes of a
+// wave finish together instead of waiting for the longest probe sequence among them; only a
+// lookup that runs past its group continues slot by slot.  A candidate c matches when
+// c + w = k coordinatewise (exact in int).  A wave whose rows all belong to one problem reads
+// that problem's a-table from LDS.  The output is the same as k_neighbors'.
+template <int DMAX, bool EVEN>
+__device__ __forceinline__ bool key_is_shift(const int16_t* __restrict__ cp, const int* kr, const int16_t* w, int d) {
+  int acc = 0;
+  if (EVEN) {
+#pragma unroll
+    for (int t2 = 0; t2 < DMAX / 2; ++t2)
+      if (2 * t2 < d) {
+        const uint32_t v = reinterpret_cast<const uint32_t*>(cp)[t2];
+        acc |= ((int)(int16_t)(v & 0xffff) + (int)w[2 * t2]) ^ kr[2 * t2];
+        acc |= ((int)(int16_t)(v >> 16) + (int)w[2 * t2 + 1]) ^ kr[2 * t2 + 1];
+      }
+  } else {
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t)
+      if (t < d) acc |= ((int)cp[t] + (int)w[t]) ^ kr[t];
+  }
+  return acc == 0;
+}
+
+template <int DMAX, bool EVEN, bool UNI, int G>
+__device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, const int16_t* wtab,
+                                        const uint64_t* htab) {
+  const int d = a.d;
+  int kr[DMAX];
+  const int16_t* kp = a.keys + r * d;
+  if (EVEN) {
+#pragma unroll
+    for (int t2 = 0; t2 < DMAX / 2; ++t2) {
+      const uint32_t v = 2 * t2 < d ? reinterpret_cast<const uint32_t*>(kp)[t2] : 0u;
+      kr[2 * t2] = (int16_t)(v & 0xffff);
+      kr[2 * t2 + 1] = (int16_t)(v >> 16);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t) kr[t] = t < d ? kp[t] : 0;
+  }
+  const int j0 = a.aoff[p], s = a.aoff[p + 1] - j0, z = a.azero[p];
+  const int64_t ro = a.rowoff[p];
+  const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
+  const ulonglong2* table = reinterpret_cast<const ulonglong2*>(a.table) + base;
+  const int16_t* wsrc = UNI ? wtab : a.akeys + (int64_t)j0 * d;
+  uint32_t* out = a.buf + r;
+  int q = 0;
+  for (int j = 0; j < s; ++j) {
+    int64_t m = -1;
+    if (j == z) {
+      m = r;
+    } else {
+      const int16_t* w = wsrc + j * d;
+      const uint64_t h = hr - (UNI ? htab[j] : a.ahash[j0 + j]);
+      const uint64_t pos = fmix64(h) & mask;
+      const uint64_t g0 = pos & ~(uint64_t)(G - 1);
+      ulonglong2 sv[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) sv[i] = table[g0 + i];
+      bool stop = false;         // an empty slot ends the probe sequence
+      int64_t cand = -1;         // first slot (local) in probe order whose hash matches
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if ((uint64_t)i >= pos - g0 && !stop && cand < 0) {
+          if (sv[i].x == 0)
+            stop = true;
+          else if (sv[i].y == h)
+            cand = (int64_t)g0 + i;
+        }
+      uint64_t next = g0 + G;    // where a probe sequence that left the group resumes
+      if (cand >= 0) {
+        const int64_t c = (int64_t)(table[cand].x & kIdxMask);
+        if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
+          m = c;
+          stop = true;
+        } else {
+          next = (uint64_t)cand + 1;   // a hash collision: keep probing after it
+          stop = false;
+        }
+      }
+      if (!stop) {
+        uint64_t pp = next & mask;
+        while (true) {
+          const ulonglong2 v = table[pp];
+          if (v.x == 0) break;
+          if (v.y == h) {
+            const int64_t c = (int64_t)(v.x & kIdxMask);
+            if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
+              m = c;
+              break;
+            }
+          }
+          pp = (pp + 1) & mask;
+        }
+      }
+    }
+    if (m >= 0) out[(q++) * a.total] = (uint32_t)(m - ro) | ((uint32_t)j << kColBits);
+  }
+  a.rowlen[r] = q;
+}
+
+template <int DMAX, bool EVEN>
+__global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
+  __shared__ int16_t s_w[kBlock / 64][kMaxA * DMAX];
+  __shared__ uint64_t s_h[kBlock / 64][kMaxA];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r = xcd_block(ceil_div(a.total, kBlock)) * kBlock + threadIdx.x;
+  const bool live = r < a.total;
+  const int p = live ? a.pid[r] : -1;
+  const int pu = __builtin_amdgcn_readfirstlane(p);
+  const bool uni = pu >= 0 && __all(!live || p == pu);
+  if (uni) {
+    const int j0 = a.aoff[pu], s = a.aoff[pu + 1] - j0;
+    for (int i = lane; i < s * a.d; i += 64) s_w[wv][i] = a.akeys[(int64_t)j0 * a.d + i];
+    for (int i = lane; i < s; i += 64) s_h[wv][i] = a.ahash[j0 + i];
+  }
+  __syncthreads();
+  if (!live) return;
+  constexpr int G = kNbrGroup;
+  if (uni)
+    nbr_row<DMAX, EVEN, true, G>(a, r, p, s_w[wv], s_h[wv]);
+  else
+    nbr_row<DMAX, EVEN, false, G>(a, r, p, nullptr, nullptr);
 }
 
 __global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
@@ -106,7 +237,7 @@ __global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restri
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int64_t c0 = crow[r], n = crow[r + 1] - c0;
-  for (int64_t q = 0; q < n; ++q) cent[c0 + q] = buf[r * smax + q];
+  for (int64_t q = 0; q < n; ++q) cent[c0 + q] = buf[q * total + r];
 }
 
 __global__ void k_nnz_per_problem(int n_prob, const int64_t* __restrict__ rowoff, const int64_t* __restrict__ crow,
@@ -311,9 +442,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     SS_TRY(canonical_a(d, n_a[p], a_freqs + pos * d, a_hat + 2 * pos, false, &at));
     pos += n_a[p];
     const int s = st->a_off[p + 1] - st->a_off[p];
-    bool same = (int)at.keys.size() == s;
-    for (int j = 0; same && j < s; ++j)
-      same = std::equal(at.keys[j].begin(), at.keys[j].end(), st->a_keys.begin() + (int64_t)(st->a_off[p] + j) * d);
+    const bool same = at.size() == s && std::equal(at.keys.begin(), at.keys.end(),
+                                                   st->a_keys.begin() + (int64_t)st->a_off[p] * d);
     if (!same) return fail(SS_EINVAL, "supp(a) differs from the one the stamping set was built with");
     smax = std::max(smax, s);
     double l1 = 0;
@@ -322,7 +452,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
       A64[(size_t)p * 64 + j] = make_double2(two_pi2 * c.x, two_pi2 * c.y);
       A32[(size_t)p * 64 + j] = make_float2((float)(two_pi2 * c.x), (float)(two_pi2 * c.y));
       int64_t nn = 0;
-      for (int t = 0; t < d; ++t) nn += (int64_t)at.keys[j][t] * at.keys[j][t];
+      for (int t = 0; t < d; ++t) nn += (int64_t)at.key(j)[t] * at.key(j)[t];
       nu[(size_t)p * 64 + j] = nn;
       if (j != at.zero) l1 += std::hypot(c.x, c.y);
     }
@@ -356,8 +486,20 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   const int rpw = 64 / smax;
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
              st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_table, nbr, rowlen};
-  const int64_t n_waves = ceil_div(total, rpw);
-  k_neighbors<<<xcd_grid(ceil_div(n_waves, kBlock / 64)), kBlock, 0, stream>>>(na);
+  {
+    const unsigned g = xcd_grid(ceil_div(total, kBlock));
+    const bool even = d % 2 == 0;
+    if (d <= 8)
+      even ? k_neighbors_row<8, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<8, false><<<g, kBlock, 0, stream>>>(na);
+    else if (d <= 16)
+      even ? k_neighbors_row<16, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false><<<g, kBlock, 0, stream>>>(na);
+    else if (d <= 32)
+      even ? k_neighbors_row<32, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false><<<g, kBlock, 0, stream>>>(na);
+    else if (d <= 64)
+      even ? k_neighbors_row<64, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false><<<g, kBlock, 0, stream>>>(na);
+    else
+      k_neighbors<<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
+  }
   SS_TRY(dalloc(&op->d_crow, total + 1));
   {
     size_t tb = 0;

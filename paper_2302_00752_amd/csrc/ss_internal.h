@@ -255,9 +255,12 @@ ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_preci
 
 // host-side canonicalisation of a-support (shared by stamp and op builders)
 struct ATable {
-  std::vector<std::vector<int16_t>> keys;   // lexicographic
-  std::vector<double2> coef;                // may be empty (support only)
-  int zero = -1;
+  int d = 0;
+  std::vector<int16_t> keys;   // [size x d], lexicographic
+  std::vector<double2> coef;   // one per key (1 when only the support was given)
+  int zero = -1;               // index of w = 0
+  int size() const { return d ? (int)(keys.size() / d) : 0; }
+  const int16_t* key(int j) const { return keys.data() + (size_t)j * d; }
 };
 ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
                       bool drop_zero_coef, ATable* out);

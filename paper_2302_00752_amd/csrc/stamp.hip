@@ -428,6 +428,11 @@ struct Scratch {
   }
 };
 
+// Slots per key when a region is sized: a load factor of at most 1/4 keeps linear-probe
+// sequences short (a lookup costs a cache line per probe; the lanes of a wave wait for the
+// longest sequence among them).  A region is grown when it would pass a load of 1/2.
+constexpr int kSlotsPerKey = 4;
+
 // Lay out per-problem table regions of the given capacities and insert keys [0, n).
 ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t n, const uint64_t* hash,
                        const int32_t* pid, hipStream_t stream) {
@@ -461,51 +466,68 @@ ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t 
 ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
                       bool drop_zero_coef, ATable* out) {
   if (n_a <= 0 || !freqs) return fail(SS_EINVAL, "supp(a) must be a non-empty list");
-  std::map<std::vector<int16_t>, double2> table;
+  // the given entries and their negations (conjugate coefficients), sorted lexicographically
+  const int n2 = 2 * n_a;
+  std::vector<int16_t> K((size_t)n2 * d);
+  std::vector<double2> C(n2);
   double scale = 0;
-  for (int32_t i = 0; i < n_a; ++i) {
-    std::vector<int16_t> w(freqs + (int64_t)i * d, freqs + (int64_t)(i + 1) * d);
-    double2 c = coef ? make_double2(coef[2 * i], coef[2 * i + 1]) : make_double2(1.0, 0.0);
+  for (int i = 0; i < n_a; ++i) {
+    const double2 c = coef ? make_double2(coef[2 * i], coef[2 * i + 1]) : make_double2(1.0, 0.0);
     if (!std::isfinite(c.x) || !std::isfinite(c.y)) return fail(SS_EINVAL, "a_hat is not finite");
-    if (!table.emplace(w, c).second) return fail(SS_EINVAL, "duplicate frequency in supp(a)");
     scale = std::max(scale, std::hypot(c.x, c.y));
-  }
-  std::vector<std::pair<std::vector<int16_t>, double2>> add;
-  for (auto& kv : table) {
-    std::vector<int16_t> nw(d);
     for (int t = 0; t < d; ++t) {
-      if (kv.first[t] == -32768) return fail(SS_ERANGE, "a frequency coordinate -32768 has no int16 negation");
-      nw[t] = (int16_t)(-kv.first[t]);
+      const int16_t v = freqs[(int64_t)i * d + t];
+      if (v == -32768) return fail(SS_ERANGE, "a frequency coordinate -32768 has no int16 negation");
+      K[(size_t)i * d + t] = v;
+      K[(size_t)(n_a + i) * d + t] = (int16_t)-v;
     }
-    auto it = table.find(nw);
-    double2 cj = make_double2(kv.second.x, -kv.second.y);
-    if (it == table.end()) {
-      add.emplace_back(nw, cj);
-    } else if (coef && std::hypot(it->second.x - cj.x, it->second.y - cj.y) > 1e-14 * scale) {
-      return fail(SS_EINVAL, "coefficients at w and -w are not complex conjugates (a must be real)");
-    }
+    C[i] = c;
+    C[n_a + i] = make_double2(c.x, -c.y);
   }
-  for (auto& kv : add) table.emplace(kv.first, kv.second);
-  std::vector<int16_t> zero(d, 0);
-  auto z = table.find(zero);
-  if (z == table.end()) return fail(SS_EINVAL, "0 must be in supp(a) (a_0 > 0 for a positive coefficient)");
-  if (coef) {
-    if (std::fabs(z->second.y) > 1e-14 * scale || z->second.x <= 0)
-      return fail(SS_EINVAL, "a_0 must be real and positive");
-    z->second.y = 0;
-  }
+  std::vector<int> idx(n2);
+  for (int i = 0; i < n2; ++i) idx[i] = i;
+  auto key_less = [&](int x, int y) {
+    const int16_t* a = &K[(size_t)x * d];
+    const int16_t* b = &K[(size_t)y * d];
+    for (int t = 0; t < d; ++t)
+      if (a[t] != b[t]) return a[t] < b[t];
+    return x < y;   // given entries (index < n_a) before derived ones
+  };
+  std::sort(idx.begin(), idx.end(), key_less);
+  auto same = [&](int x, int y) { return std::equal(&K[(size_t)x * d], &K[(size_t)x * d] + d, &K[(size_t)y * d]); };
+  out->d = d;
   out->keys.clear();
   out->coef.clear();
   out->zero = -1;
-  for (auto& kv : table) {
-    const bool is_zero = kv.first == zero;
-    if (coef && drop_zero_coef && !is_zero && kv.second.x == 0 && kv.second.y == 0) continue;
-    if (is_zero) out->zero = (int)out->keys.size();
-    out->keys.push_back(kv.first);
-    out->coef.push_back(kv.second);
+  for (int g0 = 0; g0 < n2;) {
+    int g1 = g0 + 1;
+    while (g1 < n2 && same(idx[g0], idx[g1])) ++g1;
+    int n_given = 0;
+    for (int q = g0; q < g1; ++q) n_given += idx[q] < n_a;
+    if (n_given > 1) return fail(SS_EINVAL, "duplicate frequency in supp(a)");
+    const double2 c = C[idx[g0]];   // the given coefficient if there is one, else the conjugate of -w's
+    if (coef)
+      for (int q = g0 + 1; q < g1; ++q) {
+        const double2 o = C[idx[q]];
+        if (std::hypot(o.x - c.x, o.y - c.y) > 1e-14 * scale)
+          return fail(SS_EINVAL, "coefficients at w and -w are not complex conjugates (a must be real)");
+      }
+    const int16_t* k = &K[(size_t)idx[g0] * d];
+    bool is_zero = true;
+    for (int t = 0; t < d; ++t) is_zero &= k[t] == 0;
+    double2 cv = c;
+    if (is_zero && coef) {
+      if (std::fabs(c.y) > 1e-14 * scale || c.x <= 0) return fail(SS_EINVAL, "a_0 must be real and positive");
+      cv.y = 0;
+    }
+    g0 = g1;
+    if (coef && drop_zero_coef && !is_zero && cv.x == 0 && cv.y == 0) continue;
+    if (is_zero) out->zero = out->size();
+    out->keys.insert(out->keys.end(), k, k + d);
+    out->coef.push_back(cv);
   }
-  if ((int)out->keys.size() > kMaxA)
-    return fail(SS_ERANGE, "|supp(a)| after closing under negation exceeds 63");
+  if (out->zero < 0) return fail(SS_EINVAL, "0 must be in supp(a) (a_0 > 0 for a positive coefficient)");
+  if (out->size() > kMaxA) return fail(SS_ERANGE, "|supp(a)| after closing under negation exceeds 63");
   return SS_OK;
 }
 
@@ -541,25 +563,26 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(canonical_a(d, n_a[p], a_freqs + a_pos * d, nullptr, false, &at));
     a_pos += n_a[p];
     st->a_zero.push_back(at.zero);
-    s_of[p] = (int32_t)at.keys.size();
-    for (size_t j = 0; j < at.keys.size(); ++j) {
-      st->a_keys.insert(st->a_keys.end(), at.keys[j].begin(), at.keys[j].end());
+    s_of[p] = at.size();
+    for (int j = 0; j < at.size(); ++j) {
+      const int16_t* kj = at.key(j);
+      st->a_keys.insert(st->a_keys.end(), kj, kj + d);
       uint64_t h = 0;
       int64_t nn = 0;
       for (int t = 0; t < d; ++t) {
-        h += (uint64_t)(int64_t)at.keys[j][t] * z[t];
-        nn += (int64_t)at.keys[j][t] * at.keys[j][t];
+        h += (uint64_t)(int64_t)kj[t] * z[t];
+        nn += (int64_t)kj[t] * kj[t];
       }
       ahash.push_back(h);
       anorm.push_back(nn);
-      if ((int)j != at.zero) {
-        wkeys.insert(wkeys.end(), at.keys[j].begin(), at.keys[j].end());
+      if (j != at.zero) {
+        wkeys.insert(wkeys.end(), kj, kj + d);
         whash.push_back(h);
       }
     }
-    st->a_off[p + 1] = st->a_off[p] + (int32_t)at.keys.size();
-    woff[p + 1] = woff[p] + (int32_t)at.keys.size() - 1;
-    smax1 = std::max<int>(smax1, (int)at.keys.size() - 1);
+    st->a_off[p + 1] = st->a_off[p] + at.size();
+    woff[p + 1] = woff[p] + at.size() - 1;
+    smax1 = std::max<int>(smax1, at.size() - 1);
     f_off[p + 1] = f_off[p] + n_f[p];
     std::set<std::vector<int16_t>> fs;
     for (int i = f_off[p]; i < f_off[p + 1]; ++i)
@@ -641,7 +664,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     const double bound = app_a_count(n_f[p], s_of[p], level[p]);
     const double first = (double)n_f[p] * s_of[p];
     const double want = bound <= (double)(1 << 22) ? bound : first;
-    cap[p] = next_pow2((uint64_t)std::max(64.0, 2.0 * want));
+    cap[p] = next_pow2((uint64_t)std::max(64.0, kSlotsPerKey * want));
   }
   SS_TRY(layout_table(st, cap, nF, uhash, upid, stream));
 
@@ -665,11 +688,16 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
     SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
     SS_TRY(grow(&unorm, &kcap_n, need, total, 1, stream));
+    // slots in use after this level: at most the worst case (every candidate new) and at most
+    // the App. A count, which bounds |S^n| for any a (the count of coefficient vectors over the
+    // +-w pairs with L1 norm <= n, per forcing frequency)
     bool relayout = false;
     for (int p = 0; p < n_prob; ++p) {
-      const int64_t need_p = cnt[p] + (level[p] >= n ? fcount[p] * (s_of[p] - 1) : 0);
+      const int64_t worst = cnt[p] + (level[p] >= n ? fcount[p] * (s_of[p] - 1) : 0);
+      const double bound = app_a_count(n_f[p], s_of[p], std::min(n, level[p]));
+      const int64_t need_p = bound < (double)worst ? (int64_t)std::ceil(bound) : worst;
       if ((uint64_t)need_p * 2 > cap[p]) {
-        cap[p] = next_pow2((uint64_t)need_p * 2);
+        cap[p] = next_pow2((uint64_t)need_p * kSlotsPerKey);
         relayout = true;
       }
     }
@@ -799,8 +827,21 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uhash, upid, ulev, unorm, st->d_hash,
                                                          st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
-  k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots, st->d_table,
-                                                                                          inv);
+  {
+    // regions sized for the build's worst case are re-laid out for the final counts;
+    // otherwise the slots are re-pointed at the canonical rows
+    std::vector<uint64_t> tight(n_prob);
+    bool shrink = false;
+    for (int p = 0; p < n_prob; ++p) {
+      tight[p] = next_pow2((uint64_t)std::max<int64_t>(64, kSlotsPerKey * cnt[p]));
+      shrink |= tight[p] < cap[p];
+    }
+    if (shrink)
+      SS_TRY(layout_table(st, tight, total, st->d_hash, st->d_pid, stream));
+    else
+      k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots,
+                                                                                            st->d_table, inv);
+  }
   k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff);
   unsigned long long maxn = 0;
   st->row_off.assign(n_prob + 1, 0);
