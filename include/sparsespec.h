@@ -117,6 +117,15 @@ ss_status ss_stamp_lookup(const ss_stamp* st, int32_t prob, int64_t nq,
 ss_status ss_stamp_lookup_batch(const ss_stamp* st, int64_t nq, const int32_t* prob,
                                 const int16_t* q, int64_t* slot_out);
 
+/* the right-hand side of the Galerkin system (Sec. 9, Eq. FiniteGalerkinOperator
+ * applied to u_N = f restricted to S^N; Alg. 1, step 4): f (device, complex128,
+ * n_total entries, canonical order) is set to f_hat[i] at the slot of the i-th
+ * forcing frequency given to the build and to 0 elsewhere.  f_hat (host,
+ * complex128) lists one coefficient per forcing frequency, in the order they
+ * were given (all problems concatenated).  F_p is contained in S^N, so every
+ * coefficient has a slot.  Synchronises `stream`. */
+ss_status ss_stamp_forcing(const ss_stamp* st, const double* f_hat, void* f, void* stream);
+
 void ss_free_stamp(ss_stamp* st);
 
 /* ---------------------------------------------------------------- operator

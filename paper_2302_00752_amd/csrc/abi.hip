@@ -125,6 +125,13 @@ ss_status ss_stamp_lookup_batch(const ss_stamp* st, int64_t nq, const int32_t* p
   });
 }
 
+ss_status ss_stamp_forcing(const ss_stamp* st, const double* f_hat, void* f, void* stream) {
+  return guarded([&]() -> ss_status {
+    if (!st || !st->impl) return fail(SS_EINVAL, "null stamp");
+    return stamp_forcing_impl(st->impl, f_hat, f, as_stream(stream));
+  });
+}
+
 void ss_free_stamp(ss_stamp* st) {
   if (!st) return;
   free_stamp_impl(st->impl);

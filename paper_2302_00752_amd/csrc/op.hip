@@ -431,14 +431,18 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
 
   // ---- coefficient tables (host), matched to the stamp's a-tables
   const double two_pi2 = 2.0 * M_PI * M_PI;
-  std::vector<double2> A64((size_t)n_prob * 64, make_double2(0, 0));
-  std::vector<float2> A32((size_t)n_prob * 64, make_float2(0, 0));
-  std::vector<int64_t> nu((size_t)n_prob * 64, 0);
+  // host staging reused across builds of a thread (fresh pages would be faulted in every time)
+  thread_local std::vector<double2> A64;
+  thread_local std::vector<float2> A32;
+  thread_local std::vector<int64_t> nu;
+  A64.assign((size_t)n_prob * 64, make_double2(0, 0));
+  A32.assign((size_t)n_prob * 64, make_float2(0, 0));
+  nu.assign((size_t)n_prob * 64, 0);
   std::vector<double> a0(n_prob);
   int smax = 1;
   int64_t pos = 0;
+  ATable at;   // reused across problems
   for (int p = 0; p < n_prob; ++p) {
-    ATable at;
     SS_TRY(canonical_a(d, n_a[p], a_freqs + pos * d, a_hat + 2 * pos, false, &at));
     pos += n_a[p];
     const int s = st->a_off[p + 1] - st->a_off[p];
@@ -454,7 +458,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
       int64_t nn = 0;
       for (int t = 0; t < d; ++t) nn += (int64_t)at.key(j)[t] * at.key(j)[t];
       nu[(size_t)p * 64 + j] = nn;
-      if (j != at.zero) l1 += std::hypot(c.x, c.y);
+      if (j != at.zero) l1 += cabs2d(c.x, c.y);
     }
     a0[p] = at.coef[at.zero].x;
     op->a0_host.push_back(a0[p]);
@@ -731,6 +735,46 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     }
     op->wrange[p].y = (int)op->work.size();
   }
+  // ---- solve units: greedy runs ending on the furthest class boundary that is also a slice
+  // boundary within kWinRows rows
+  op->urange.assign(n_prob, make_int2(-1, -1));
+  for (int p = 0; p < n_prob; ++p) {
+    const std::vector<int64_t>& cb = cbounds[p];
+    const int64_t rows = cb.back();
+    const size_t u0 = op->units.size();
+    int64_t start = 0;
+    bool ok = true;
+    while (start < rows) {
+      // candidates: boundaries in (start, start + kWinRows], scanned from the far end
+      auto it = std::upper_bound(cb.begin(), cb.end(), start + kWinRows);
+      int64_t cut = -1;
+      while (it != cb.begin()) {
+        --it;
+        if (*it <= start) break;
+        if (*it % kSlice == 0) {
+          cut = *it;
+          break;
+        }
+      }
+      if (cut < 0) {
+        ok = false;
+        break;
+      }
+      op->units.push_back(make_int4(p, (int)((op->eoff[p] + start) / kSlice), (int)((cut - start) / kSlice),
+                                    (int)start));
+      start = cut;
+    }
+    if (ok && op->units.size() > u0) {
+      op->urange[p] = make_int2((int)u0, (int)op->units.size());
+    } else {
+      op->units.resize(u0);
+    }
+  }
+  if (!op->units.empty()) {
+    SS_TRY(dalloc(&op->d_units, op->units.size()));
+    SS_HIP(hipMemcpyAsync(op->d_units, op->units.data(), op->units.size() * sizeof(int4), hipMemcpyHostToDevice,
+                          stream));
+  }
   SS_TRY(dalloc(&op->d_work, op->work.size()));
   SS_TRY(dalloc(&op->d_wrange, n_prob));
   SS_TRY(dalloc(&op->d_A64, A64.size()));
@@ -761,6 +805,7 @@ void free_op_impl(OpImpl* op) {
   op->d_norm = nullptr;
   dfree(op->d_eoff);
   dfree(op->d_work);
+  dfree(op->d_units);
   dfree(op->d_wrange);
   dfree(op->d_A64);
   dfree(op->d_A32);

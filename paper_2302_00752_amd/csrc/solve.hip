@@ -618,6 +618,352 @@ __global__ void k_gather_states(const Desc* __restrict__ descs, int n_desc, PSta
   if (p < n_desc) out[p] = *descs[p].ps;
 }
 
+// ---------------------------------------------------------------- class-resident CG
+// A solve unit is a run of whole classes (whole slices, at most kWinRows rows) of one problem.
+// Its rows couple to no row outside it (the operator is block diagonal over classes, Sec. 6,
+// proof of Prop. SolutionSupport), so one block can run the complete CG -- or the complete
+// FP32 + FP64 refinement -- on it: the search direction lives in an LDS window (the matvec
+// gathers from there), x, r and f of the block's own rows live in registers, and every inner
+// product is a block reduction.  Only the SELL entries come from memory, once per matvec.
+// Each unit stops on its own residual, |r_W| <= tol |f_W|, which summed over the problem's units
+// gives |r| <= tol |f|; a unit with f_W = 0 has the exact solution u_W = 0.
+constexpr int kUnitWaves = 16;                                  // wavefronts per unit block
+constexpr int kUnitThreads = kUnitWaves * 64;
+constexpr int kUnitSlots = kWinRows / kSlice / kUnitWaves;     // slices per wavefront in a unit
+
+struct UnitOut {
+  double rr;       // |f_W - L x_W|^2 of the returned iterate (FP64)
+  double ff;       // |f_W|^2
+  int32_t iters;   // CG iterations (FP32 + refinement: summed over correction solves)
+  int32_t outer;   // refinement steps
+  int32_t status;
+  int32_t pad;
+};
+
+// one problem of a class-resident launch
+struct UDesc {
+  const uint32_t* sent;          // its operator's SELL entries and slice offsets
+  const uint32_t* sptr;
+  const void* norm;              // operator execution order (op-global rows)
+  const int64_t* exec2canon;     // operator execution row -> operator canonical slot
+  const double2* A64;            // the problem's 64-entry tables
+  const float2* A32;
+  const int64_t* nu;
+  const double2* f;              // request: operator canonical f
+  double2* u;                    // request: operator canonical u (in: x0, out: solution)
+  double a0;
+  double tol2;
+  int32_t max_iter;
+  int32_t pad;
+};
+
+// one launch: units {problem (descriptor index), first slice, slices, first row (problem-local)}
+struct UnitArgs {
+  const UDesc* descs;
+  const int4* ulist;
+  int32_t ubase;                 // first unit of this launch within ulist
+  UnitOut* out;                  // per unit (ulist order)
+};
+
+// sum of (a, b) over the block, fixed order, returned to every thread
+__device__ inline double2 block_sum2(double a, double b, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave] = a;
+    red[kUnitWaves + wave] = b;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0;
+#pragma unroll
+  for (int w = 0; w < kUnitWaves; ++w) {
+    sa += red[w];
+    sb += red[kUnitWaves + w];
+  }
+  __syncthreads();
+  return make_double2(sa, sb);
+}
+
+// q = L v over the unit's slices owned by this wavefront (v, |k|^2 in the LDS window)
+template <typename NormT, typename V>
+__device__ inline void unit_mv(const UDesc& A, int s0, int ns, int w0, const V* As, const NormT* nus,
+                               const NormT* nw, const V* vw, const NormT* nk, V* acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    const int sw = wave + k * kUnitWaves;
+    if (sw < ns) {
+      const uint32_t base = A.sptr[s0 + sw];
+      const uint32_t width = (A.sptr[s0 + sw + 1] - base) / kSlice;
+      acc[k] = sell_row<true, NormT, V>(A.sent, base, width, lane, nk[k], nw, vw, w0, As, nus);
+    }
+  }
+}
+
+template <typename NormT, bool FP64>
+__global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
+  __shared__ __align__(16) double2 s_win[kWinRows];   // search direction / iterate window
+  __shared__ NormT s_norm[kWinRows];
+  __shared__ double2 s_A64[64];
+  __shared__ float2 s_A32[64];
+  __shared__ NormT s_nu[64];
+  __shared__ double red[2 * kUnitWaves];
+  float2* s_win32 = reinterpret_cast<float2*>(s_win);
+  const int ui = Args.ubase + blockIdx.x;
+  const int4 un = Args.ulist[ui];
+  const UDesc& A = Args.descs[un.x];
+  const int s0 = un.y, ns = un.z, w0 = un.w;
+  const int64_t E0 = (int64_t)s0 * kSlice;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const NormT* normg = (const NormT*)A.norm;
+  if (tid < 64) {
+    s_A64[tid] = A.A64[tid];
+    s_A32[tid] = A.A32[tid];
+    s_nu[tid] = (NormT)A.nu[tid];
+  }
+  for (int i = tid; i < ns * kSlice; i += kUnitThreads) s_norm[i] = normg[E0 + i];
+  const double a0 = A.a0;
+  const double tol2_in = kInnerTol * kInnerTol;
+  // the block's own rows: slice wave + k * kUnitWaves, lane
+  NormT nk[kUnitSlots];
+  double dinv[kUnitSlots];
+  int32_t cr[kUnitSlots];   // canonical slot (rows of a batch are below 2^31), -1 for padding
+  double2 x[kUnitSlots], r[kUnitSlots];
+  int nzx = 0;
+  double vff = 0;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    const int sw = wave + k * kUnitWaves;
+    nk[k] = 0;
+    cr[k] = -1;
+    x[k] = make_double2(0, 0);
+    if (sw < ns) {
+      const int64_t e = E0 + sw * kSlice + lane;
+      nk[k] = normg[e];
+      cr[k] = (int32_t)A.exec2canon[e];
+      if (cr[k] >= 0) {
+        const double2 fv = A.f[cr[k]];
+        vff += fv.x * fv.x + fv.y * fv.y;
+        if (nk[k] > 0) x[k] = A.u[cr[k]];
+      }
+      nzx |= (x[k].x != 0.0 || x[k].y != 0.0);
+    }
+    dinv[k] = jacobi_inv(nk[k], a0);
+  }
+  const double2 init = block_sum2(vff, (double)nzx, red);   // also orders the LDS staging above
+  const double ff = init.x;
+  const bool warm = init.y > 0;
+  const double thr2 = A.tol2 * ff;   // |r_W| <= tol |f_W|; summed over units: |r| <= tol |f|
+  int status = SS_OK, iters = 0, outer = 0;
+  double rr;
+  if (ff == 0) {   // the unit's classes decouple from the rest: f_W = 0 gives u_W = 0 exactly
+#pragma unroll
+    for (int k = 0; k < kUnitSlots; ++k) x[k] = make_double2(0, 0);
+    rr = 0;
+  }
+
+  // r = f - L x (FP64), |r|^2
+  auto residual = [&]() -> double {
+    double v = 0;
+    if (warm || outer > 0) {
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k)
+        if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = x[k];
+      __syncthreads();
+      double2 acc[kUnitSlots];
+      unit_mv<NormT, double2>(A, s0, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k) {
+        const double2 fk = cr[k] >= 0 ? A.f[cr[k]] : make_double2(0, 0);
+        r[k] = wave + k * kUnitWaves < ns ? make_double2(fk.x - acc[k].x, fk.y - acc[k].y) : make_double2(0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k) r[k] = cr[k] >= 0 ? A.f[cr[k]] : make_double2(0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < kUnitSlots; ++k) v += r[k].x * r[k].x + r[k].y * r[k].y;
+    return block_sum2(v, 0.0, red).x;   // its barriers also end every read of the window
+  };
+
+  if (ff == 0) {
+  } else if (FP64) {
+    rr = residual();
+    if (rr > thr2) {
+      double2 pv[kUnitSlots];
+      double rz = 0;
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k) {
+        pv[k] = make_double2(dinv[k] * r[k].x, dinv[k] * r[k].y);
+        if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = pv[k];
+        rz += (r[k].x * r[k].x + r[k].y * r[k].y) * dinv[k];
+      }
+      double rho = block_sum2(rz, 0.0, red).x;
+      while (true) {
+        double2 q[kUnitSlots];
+        unit_mv<NormT, double2>(A, s0, ns, w0, s_A64, s_nu, s_norm, s_win, nk, q);
+        double vpq = 0;
+#pragma unroll
+        for (int k = 0; k < kUnitSlots; ++k)
+          if (wave + k * kUnitWaves < ns) vpq += pv[k].x * q[k].x + pv[k].y * q[k].y;
+        const double pq = block_sum2(vpq, 0.0, red).x;
+        const double alpha = rho / pq;
+        if (!(pq > 0.0) || !isfinite(alpha)) {
+          status = SS_EBREAKDOWN;
+          break;
+        }
+        double v0 = 0, v1 = 0;
+#pragma unroll
+        for (int k = 0; k < kUnitSlots; ++k) {
+          if (wave + k * kUnitWaves < ns) {
+            x[k].x += alpha * pv[k].x;
+            x[k].y += alpha * pv[k].y;
+            r[k].x -= alpha * q[k].x;
+            r[k].y -= alpha * q[k].y;
+          }
+          const double t = r[k].x * r[k].x + r[k].y * r[k].y;
+          v0 += t * dinv[k];
+          v1 += t;
+        }
+        const double2 s2 = block_sum2(v0, v1, red);
+        ++iters;
+        rr = s2.y;
+        if (rr <= thr2) break;
+        if (iters >= A.max_iter) {
+          status = SS_ENOCONV;
+          break;
+        }
+        const double beta = s2.x / rho;
+        rho = s2.x;
+#pragma unroll
+        for (int k = 0; k < kUnitSlots; ++k) {
+          pv[k] = make_double2(dinv[k] * r[k].x + beta * pv[k].x, dinv[k] * r[k].y + beta * pv[k].y);
+          if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = pv[k];
+        }
+        __syncthreads();
+      }
+      // the true residual of the returned iterate
+      outer = 1;   // makes residual() run the matvec
+      rr = residual();
+      outer = 0;
+    }
+  } else {
+    bool broke = false;
+    while (true) {
+      rr = residual();
+      if (rr <= thr2) break;
+      if (outer >= kMaxOuter) {
+        status = broke ? SS_EBREAKDOWN : SS_ENOCONV;
+        break;
+      }
+      const double scale = sqrt(rr), inv = 1.0 / scale;
+      ++outer;
+      // correction solve L d = r / |r| in FP32 (FP64 inner products), d = 0 to start
+      float2 r32[kUnitSlots], p32[kUnitSlots], d32[kUnitSlots];
+      double rz = 0, r0 = 0;
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k) {
+        r32[k] = make_float2((float)(r[k].x * inv), (float)(r[k].y * inv));
+        d32[k] = make_float2(0.f, 0.f);
+        const float di = (float)dinv[k];
+        p32[k] = make_float2(di * r32[k].x, di * r32[k].y);
+        if (wave + k * kUnitWaves < ns) s_win32[(wave + k * kUnitWaves) * kSlice + lane] = p32[k];
+        const double t = (double)r32[k].x * r32[k].x + (double)r32[k].y * r32[k].y;
+        rz += t * dinv[k];
+        r0 += t;
+      }
+      const double2 s0v = block_sum2(rz, r0, red);
+      double rho = s0v.x;
+      const double ff_in = s0v.y;
+      int it = 0;
+      if (!(s0v.y <= tol2_in * ff_in)) {
+        while (true) {
+          float2 q[kUnitSlots];
+          unit_mv<NormT, float2>(A, s0, ns, w0, s_A32, s_nu, s_norm, s_win32, nk, q);
+          double vpq = 0;
+#pragma unroll
+          for (int k = 0; k < kUnitSlots; ++k)
+            if (wave + k * kUnitWaves < ns) vpq += (double)p32[k].x * q[k].x + (double)p32[k].y * q[k].y;
+          const double pq = block_sum2(vpq, 0.0, red).x;
+          const double alpha = rho / pq;
+          if (!(pq > 0.0) || !isfinite(alpha)) {
+            broke = true;
+            break;
+          }
+          const float a = (float)alpha;
+          double v0 = 0, v1 = 0;
+#pragma unroll
+          for (int k = 0; k < kUnitSlots; ++k) {
+            if (wave + k * kUnitWaves < ns) {
+              d32[k].x += a * p32[k].x;
+              d32[k].y += a * p32[k].y;
+              r32[k].x -= a * q[k].x;
+              r32[k].y -= a * q[k].y;
+            }
+            const double t = (double)r32[k].x * r32[k].x + (double)r32[k].y * r32[k].y;
+            v0 += t * dinv[k];
+            v1 += t;
+          }
+          const double2 s2 = block_sum2(v0, v1, red);
+          ++it;
+          if (s2.y <= tol2_in * ff_in || it >= A.max_iter) break;
+          const float b = (float)(s2.x / rho);
+          rho = s2.x;
+#pragma unroll
+          for (int k = 0; k < kUnitSlots; ++k) {
+            const float di = (float)dinv[k];
+            p32[k] = make_float2(di * r32[k].x + b * p32[k].x, di * r32[k].y + b * p32[k].y);
+            if (wave + k * kUnitWaves < ns) s_win32[(wave + k * kUnitWaves) * kSlice + lane] = p32[k];
+          }
+          __syncthreads();
+        }
+      }
+      iters += it;
+#pragma unroll
+      for (int k = 0; k < kUnitSlots; ++k) {
+        x[k].x += scale * (double)d32[k].x;
+        x[k].y += scale * (double)d32[k].y;
+      }
+      __syncthreads();   // every read of the FP32 window is done before residual() overwrites it
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k)
+    if (cr[k] >= 0) A.u[cr[k]] = nk[k] > 0 ? x[k] : make_double2(0, 0);
+  if (tid == 0) {
+    UnitOut o;
+    o.rr = rr;
+    o.ff = ff;
+    o.iters = iters;
+    o.outer = outer;
+    o.status = status;
+    o.pad = 0;
+    Args.out[ui] = o;
+  }
+}
+
+// one thread per problem: the problem's residual and counters from its units, in order
+struct UnitSum {
+  double rr, ff;
+  int32_t iters, outer, status, pad;
+};
+
+__global__ void k_unit_final(int n_prob, const int32_t* __restrict__ uoff, const UnitOut* __restrict__ uo,
+                             UnitSum* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_prob) return;
+  UnitSum s{0.0, 0.0, 0, 0, SS_OK, 0};
+  for (int i = uoff[q]; i < uoff[q + 1]; ++i) {
+    s.rr += uo[i].rr;
+    s.ff += uo[i].ff;
+    s.iters = max(s.iters, uo[i].iters);
+    s.outer = max(s.outer, uo[i].outer);
+    if (uo[i].status == SS_EBREAKDOWN || (uo[i].status == SS_ENOCONV && s.status == SS_OK)) s.status = uo[i].status;
+  }
+  out[q] = s;
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
 
 }  // namespace
@@ -773,6 +1119,140 @@ std::vector<int4> items_of(const OpImpl* op, int p) {
 }  // namespace
 
 // ---------------------------------------------------------------- engine
+// Problems solved by the class-resident CG in one go: gathered by add(), launched together
+// (one k_unit_solve launch per norm width and precision), results read after a sync.
+struct UnitBatch {
+  struct Item {
+    UDesc d;
+    OpImpl* op;
+    int prob;
+    int req;
+    int group;       // wide * 2 + fp32
+    int prec;
+  };
+  std::vector<Item> items;
+  // after launch(): per item (launch order), its results on the host once the stream is synced
+  std::vector<Item> launched;
+  UnitSum* h_sum = nullptr;       // pinned
+  size_t h_cap = 0;
+  std::vector<void*> dev;         // device blocks of the launch in flight
+
+  ~UnitBatch() {
+    release();
+    if (h_sum) (void)hipHostFree(h_sum);
+  }
+  void release() {
+    for (void* q : dev) pool_free(q);
+    dev.clear();
+  }
+
+  void add(OpImpl* op, int p, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter, int req) {
+    UDesc D{};
+    D.sent = op->d_sent;
+    D.sptr = op->d_sptr;
+    D.norm = op->d_norm;
+    D.exec2canon = op->d_exec2canon;
+    D.A64 = op->d_A64 + (size_t)p * 64;
+    D.A32 = op->d_A32 + (size_t)p * 64;
+    D.nu = op->d_nu + (size_t)p * 64;
+    D.f = (const double2*)f;
+    D.u = (double2*)u;
+    D.a0 = op->a0_host[p];
+    D.tol2 = tol * tol;
+    D.max_iter = max_iter;
+    items.push_back(Item{D, op, p, req, (op->wide_norm ? 2 : 0) + (prec != SS_FP64 ? 1 : 0), (int)prec});
+  }
+
+  template <typename T>
+  ss_status alloc(T** p, size_t n) {
+    SS_TRY(dalloc(p, std::max<size_t>(n, 1)));
+    dev.push_back(*p);
+    return SS_OK;
+  }
+
+  // launch every added problem on s (asynchronous); the caller syncs s before reading results
+  ss_status launch(hipStream_t s) {
+    launched.clear();
+    for (int g = 0; g < 4; ++g)
+      for (auto& it : items)
+        if (it.group == g) launched.push_back(it);
+    items.clear();
+    const int np = (int)launched.size();
+    if (np == 0) return SS_OK;
+    std::vector<UDesc> descs(np);
+    std::vector<int4> ul;
+    std::vector<int32_t> uoff{0};
+    int gbeg[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < np; ++i) {
+      const Item& it = launched[i];
+      descs[i] = it.d;
+      const int2 ur = it.op->urange[it.prob];
+      for (int k = ur.x; k < ur.y; ++k) {
+        const int4 un = it.op->units[k];
+        ul.push_back(make_int4(i, un.y, un.z, un.w));
+      }
+      uoff.push_back((int32_t)ul.size());
+      gbeg[it.group + 1] = (int)ul.size();
+    }
+    for (int g = 1; g <= 4; ++g) gbeg[g] = std::max(gbeg[g], gbeg[g - 1]);
+    const int nu = (int)ul.size();
+    UDesc* d_desc = nullptr;
+    int4* d_ul = nullptr;
+    int32_t* d_uoff = nullptr;
+    UnitOut* d_out = nullptr;
+    UnitSum* d_sum = nullptr;
+    SS_TRY(alloc(&d_desc, np));
+    SS_TRY(alloc(&d_ul, nu));
+    SS_TRY(alloc(&d_uoff, np + 1));
+    SS_TRY(alloc(&d_out, nu));
+    SS_TRY(alloc(&d_sum, np));
+    if ((size_t)np > h_cap) {
+      if (h_sum) (void)hipHostFree(h_sum);
+      h_sum = nullptr;
+      h_cap = std::max<size_t>(np, 2 * h_cap);
+      SS_HIP(hipHostMalloc((void**)&h_sum, h_cap * sizeof(UnitSum), hipHostMallocDefault));
+    }
+    SS_HIP(hipMemcpyAsync(d_desc, descs.data(), np * sizeof(UDesc), hipMemcpyHostToDevice, s));
+    SS_HIP(hipMemcpyAsync(d_ul, ul.data(), nu * sizeof(int4), hipMemcpyHostToDevice, s));
+    SS_HIP(hipMemcpyAsync(d_uoff, uoff.data(), (np + 1) * 4, hipMemcpyHostToDevice, s));
+    UnitArgs A{d_desc, d_ul, 0, d_out};
+    for (int g = 0; g < 4; ++g) {
+      const int n = gbeg[g + 1] - gbeg[g];
+      if (n == 0) continue;
+      A.ubase = gbeg[g];
+      switch (g) {
+        case 0: k_unit_solve<int32_t, true><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 1: k_unit_solve<int32_t, false><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 2: k_unit_solve<int64_t, true><<<n, kUnitThreads, 0, s>>>(A); break;
+        default: k_unit_solve<int64_t, false><<<n, kUnitThreads, 0, s>>>(A); break;
+      }
+    }
+    k_unit_final<<<grid_for(np), kBlock, 0, s>>>(np, d_uoff, d_out, d_sum);
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipMemcpyAsync(h_sum, d_sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
+    return SS_OK;
+  }
+
+  // the i-th launched problem's info (valid after the stream has been synced)
+  ss_solve_info info(int i) const {
+    const Item& it = launched[i];
+    const UnitSum& sm = h_sum[i];
+    const double rel = sm.ff > 0 ? std::sqrt(sm.rr / sm.ff) : 0.0;
+    int status = sm.status;
+    if (rel <= std::sqrt(it.d.tol2) || sm.ff == 0) status = SS_OK;
+    else if (status == SS_OK) status = SS_ENOCONV;
+    ss_solve_info in{};
+    in.iters = sm.iters;
+    in.outer_steps = it.prec == SS_FP64 ? 0 : sm.outer;
+    in.rel_residual = rel;
+    in.n = it.op->row_off[it.prob + 1] - it.op->row_off[it.prob];
+    in.nnz = it.op->nnz_p[it.prob];
+    in.n_components = it.op->comps[it.prob];
+    in.status = status;
+    return in;
+  }
+};
+
 struct Request {
   OpImpl* op;
   int64_t tag;
@@ -801,7 +1281,9 @@ struct EngineImpl {
   std::vector<Done> done;
   PState* h_states = nullptr;             // pinned
   size_t h_cap = 0;
+  UnitBatch units;                        // problems for the class-resident CG, launched next tick
   ~EngineImpl() {
+    if (!units.dev.empty()) (void)hipStreamSynchronize(s);   // a launch may still use its blocks
     if (h_states) (void)hipHostFree(h_states);
   }
 
@@ -814,19 +1296,25 @@ struct EngineImpl {
     return SS_OK;
   }
 
+  // A problem whose classes split into solve units runs the class-resident CG (launched at the
+  // next tick, finished within it); the others run the per-problem kernels tick by tick and
+  // need the operator's workspace.
   ss_status submit(OpImpl* op, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter,
                    int64_t tag) {
     if (!f || !u) return fail(SS_EINVAL, "null vector");
     if (!(tol > 0) || max_iter < 1) return fail(SS_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (prec != SS_FP64 && prec != SS_FP32_REFINE) return fail(SS_EINVAL, "unknown precision");
     if (op->busy) return fail(SS_EINVAL, "operator already has a solve in flight");
-    const int64_t bytes = op_device_bytes(op) + (int64_t)std::max(op->ws.bytes, workspace_bytes(op));
+    bool any_engine = false;
+    for (int p = 0; p < op->n_prob; ++p) any_engine |= op->urange[p].x < 0;
+    const int64_t bytes =
+        op_device_bytes(op) + (any_engine ? (int64_t)std::max(op->ws.bytes, workspace_bytes(op)) : 0);
     int active = 0;
     for (auto& r : reqs) active += r.op != nullptr;
     if (budget > 0 && bytes_in_use + bytes > budget) return fail(SS_ENOMEM, "HBM budget of the engine exceeded");
     if (max_slots > 0 && active >= max_slots) return fail(SS_ENOMEM, "no free engine slot");
-    WS w;
-    SS_TRY(workspace(op, &w));
+    WS w{};
+    if (any_engine) SS_TRY(workspace(op, &w));
     int ri;
     if (!free_req.empty()) {
       ri = free_req.back();
@@ -841,6 +1329,10 @@ struct EngineImpl {
     bytes_in_use += bytes;
     op->busy = true;
     for (int p = 0; p < op->n_prob; ++p) {
+      if (op->urange[p].x >= 0) {
+        units.add(op, p, f, u, tol, prec, max_iter, ri);
+        continue;
+      }
       Desc D = make_desc(op, w, p);
       D.f_canon = (const double2*)f;
       D.u_canon = (double2*)u;
@@ -883,13 +1375,38 @@ struct EngineImpl {
   }
 
   // one tick; *n_active = problems still active afterwards
+  // results of the class-resident launch of this tick (the stream has been synced)
+  void collect_units() {
+    for (size_t i = 0; i < units.launched.size(); ++i) {
+      const UnitBatch::Item& it = units.launched[i];
+      done.push_back(Done{reqs[it.req].tag, it.prob, units.info((int)i)});
+      finish_problem(it.req);
+    }
+    units.launched.clear();
+    units.release();
+  }
+
+  void finish_problem(int ri) {
+    if (--reqs[ri].n_left == 0) {
+      reqs[ri].op->busy = false;
+      bytes_in_use -= req_bytes[ri];
+      reqs[ri].op = nullptr;
+      free_req.push_back(ri);
+    }
+  }
+
   ss_status step(int iters, int* n_active) {
+    if (!units.items.empty()) SS_TRY(units.launch(s));
     if (dirty) {
       SS_TRY(list.upload(s, items));
       dirty = false;
     }
     const int nd = list.n_desc();
     if (nd == 0) {
+      if (!units.launched.empty()) {
+        SS_HIP(hipStreamSynchronize(s));
+        collect_units();
+      }
       *n_active = 0;
       return SS_OK;
     }
@@ -907,6 +1424,7 @@ struct EngineImpl {
     SS_HIP(hipMemcpyAsync(h_states, list.d_states, nd * sizeof(PState), hipMemcpyDeviceToHost, s));
     SS_HIP(hipStreamSynchronize(s));
     SS_HIP(hipGetLastError());
+    if (!units.launched.empty()) collect_units();
     std::vector<int> fin;
     for (int k = 0; k < nd; ++k)
       if (h_states[k].done) fin.push_back(k);
@@ -946,12 +1464,7 @@ struct EngineImpl {
       in.status = status;
       done.push_back(Done{reqs[ri].tag, p, in});
       gone[k] = 1;
-      if (--reqs[ri].n_left == 0) {
-        op->busy = false;
-        bytes_in_use -= req_bytes[ri];
-        reqs[ri].op = nullptr;
-        free_req.push_back(ri);
-      }
+      finish_problem(ri);
     }
     // compact the active set
     std::vector<Desc> nd_descs;
@@ -977,7 +1490,7 @@ int64_t op_device_bytes(const OpImpl* op) {
   const int64_t nb = op->wide_norm ? 8 : 4;
   return (op->total + 1) * 8 + op->nnz * 4 + op->total * 4 + op->n_exec * 8 + op->total * 8 + op->n_sell * 4 +
          (op->n_slices + 1) * 4 + op->n_exec * nb + (int64_t)op->n_prob * 64 * (16 + 8 + 8) +
-         (int64_t)op->work.size() * 16;
+         (int64_t)op->work.size() * 16 + (int64_t)op->units.size() * 16;
 }
 
 ss_status engine_create(int64_t budget, int32_t max_slots, hipStream_t s, EngineImpl** out) {

@@ -125,6 +125,8 @@ struct StampImpl {
   int32_t* d_pid = nullptr;            // [total]
   int64_t* d_root = nullptr;           // [total] canonical slot of the forcing key the first path started at
   int64_t* d_rowoff = nullptr;         // [n_prob+1]
+  int64_t n_f = 0;                     // forcing frequencies given to the build (all problems)
+  uint32_t* d_fslot = nullptr;         // [n_f] canonical slot of each, in the order given
   uint64_t* d_coef = nullptr;          // [d] hash multipliers
   uint64_t* d_table = nullptr;         // 2 words per slot: {MAIN | canonical index, hash}
   int64_t* d_toff = nullptr;           // [n_prob] first slot of each problem's region
@@ -188,6 +190,12 @@ struct OpImpl {
   std::vector<int4> work;               // {problem, first slice, slices | window rows << 16, window start row}
   std::vector<int2> wrange;
   int64_t max_window = 0;
+  // class-resident solve units: runs of whole slices that start and end on class boundaries,
+  // at most kWinRows rows: {problem, first slice, slices, first exec row (problem-local)}.
+  // urange[p] = [first, end) unit of problem p, or {-1, -1} when its classes do not split so.
+  std::vector<int4> units;
+  std::vector<int2> urange;
+  int4* d_units = nullptr;
   // canonical CSR (kept for export and tests)
   int64_t* d_crow = nullptr;           // [total+1]
   uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << 26
@@ -244,6 +252,8 @@ void free_stamp_impl(StampImpl* st);
 ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const int16_t* q,
                             int64_t* slot_out, hipStream_t stream, const int32_t* probs = nullptr);
 
+ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
+
 ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* a_freqs,
                         const double* a_hat, uint32_t flags, hipStream_t stream, OpImpl** out);
 void free_op_impl(OpImpl* op);
@@ -254,6 +264,15 @@ ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_preci
                         int32_t max_iter, hipStream_t stream, ss_solve_info* info);
 
 // host-side canonicalisation of a-support (shared by stamp and op builders)
+// |x + iy|: the plain formula where the squares cannot overflow or underflow to zero
+// (std::hypot's rescaling costs more than the rest of the host-side table work)
+inline double cabs2d(double x, double y) {
+  const double m = std::max(std::fabs(x), std::fabs(y));
+  if (m == 0) return 0;
+  if (m < 1e150 && m > 1e-150) return std::sqrt(x * x + y * y);
+  return std::hypot(x, y);
+}
+
 struct ATable {
   int d = 0;
   std::vector<int16_t> keys;   // [size x d], lexicographic

@@ -334,6 +334,18 @@ __global__ void k_iota_i64(int64_t n, int64_t* p) {
   if (i < n) p[i] = i;
 }
 
+// f in canonical order: zero, then each given forcing coefficient at its recorded slot
+__global__ void k_scatter_f(int64_t n_f, const uint32_t* __restrict__ slot, const double2* __restrict__ vals,
+                            double2* f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_f) f[slot[i]] = vals[i];
+}
+
+__global__ void k_zero_c128(int64_t n, double2* f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = make_double2(0.0, 0.0);
+}
+
 __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32_t prob,
                          const int32_t* __restrict__ probs, const uint64_t* __restrict__ z,
                          const int16_t* __restrict__ keys, const int64_t* __restrict__ toff,
@@ -466,55 +478,77 @@ ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t 
 ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double* coef,
                       bool drop_zero_coef, ATable* out) {
   if (n_a <= 0 || !freqs) return fail(SS_EINVAL, "supp(a) must be a non-empty list");
-  // the given entries and their negations (conjugate coefficients), sorted lexicographically
-  const int n2 = 2 * n_a;
-  std::vector<int16_t> K((size_t)n2 * d);
-  std::vector<double2> C(n2);
+  // the given entries (e < n_a) and their negations (e >= n_a, conjugate coefficients), sorted
+  // lexicographically: each key is packed big-endian into 64-bit words of four offset-binary
+  // coordinates, so comparing words compares keys
+  const int n2 = 2 * n_a, nw = (d + 3) / 4;
+  thread_local std::vector<uint64_t> W;
+  thread_local std::vector<int> idx;
+  thread_local std::vector<double2> C;
+  W.assign((size_t)n2 * nw, 0);
+  C.resize(n2);
+  idx.resize(n2);
   double scale = 0;
   for (int i = 0; i < n_a; ++i) {
     const double2 c = coef ? make_double2(coef[2 * i], coef[2 * i + 1]) : make_double2(1.0, 0.0);
     if (!std::isfinite(c.x) || !std::isfinite(c.y)) return fail(SS_EINVAL, "a_hat is not finite");
-    scale = std::max(scale, std::hypot(c.x, c.y));
-    for (int t = 0; t < d; ++t) {
-      const int16_t v = freqs[(int64_t)i * d + t];
-      if (v == -32768) return fail(SS_ERANGE, "a frequency coordinate -32768 has no int16 negation");
-      K[(size_t)i * d + t] = v;
-      K[(size_t)(n_a + i) * d + t] = (int16_t)-v;
-    }
+    scale = std::max(scale, cabs2d(c.x, c.y));
     C[i] = c;
     C[n_a + i] = make_double2(c.x, -c.y);
+    for (int t = 0; t < d; ++t) {
+      const int v = freqs[(int64_t)i * d + t];
+      if (v == -32768) return fail(SS_ERANGE, "a frequency coordinate -32768 has no int16 negation");
+      const int sh = 48 - 16 * (t & 3);
+      W[(size_t)i * nw + t / 4] |= (uint64_t)(uint16_t)(v + 32768) << sh;
+      W[(size_t)(n_a + i) * nw + t / 4] |= (uint64_t)(uint16_t)(-v + 32768) << sh;
+    }
   }
-  std::vector<int> idx(n2);
-  for (int i = 0; i < n2; ++i) idx[i] = i;
-  auto key_less = [&](int x, int y) {
-    const int16_t* a = &K[(size_t)x * d];
-    const int16_t* b = &K[(size_t)y * d];
-    for (int t = 0; t < d; ++t)
-      if (a[t] != b[t]) return a[t] < b[t];
-    return x < y;   // given entries (index < n_a) before derived ones
+  const uint64_t* Wp = W.data();
+  auto cmp = [&](int x, int y) {   // -1, 0, 1 on keys only
+    const uint64_t* a = Wp + (size_t)x * nw;
+    const uint64_t* b = Wp + (size_t)y * nw;
+    for (int q = 0; q < nw; ++q)
+      if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
+    return 0;
   };
-  std::sort(idx.begin(), idx.end(), key_less);
-  auto same = [&](int x, int y) { return std::equal(&K[(size_t)x * d], &K[(size_t)x * d] + d, &K[(size_t)y * d]); };
+  // sort the given entries; negation reverses lexicographic order, so the derived entries in
+  // ascending order are the negations of the given ones from the largest down; merge the two
+  // (on equal keys the given entry first)
+  thread_local std::vector<int> sg;
+  sg.resize(n_a);
+  for (int i = 0; i < n_a; ++i) sg[i] = i;
+  std::sort(sg.begin(), sg.end(), [&](int x, int y) {
+    const int c = cmp(x, y);
+    return c != 0 ? c < 0 : x < y;
+  });
+  for (int i = 0, k = n_a - 1, o = 0; i < n_a || k >= 0;) {
+    if (k < 0 || (i < n_a && cmp(sg[i], n_a + sg[k]) <= 0))
+      idx[o++] = sg[i++];
+    else
+      idx[o++] = n_a + sg[k--];
+  }
   out->d = d;
   out->keys.clear();
   out->coef.clear();
   out->zero = -1;
   for (int g0 = 0; g0 < n2;) {
     int g1 = g0 + 1;
-    while (g1 < n2 && same(idx[g0], idx[g1])) ++g1;
+    while (g1 < n2 && cmp(idx[g0], idx[g1]) == 0) ++g1;
     int n_given = 0;
     for (int q = g0; q < g1; ++q) n_given += idx[q] < n_a;
     if (n_given > 1) return fail(SS_EINVAL, "duplicate frequency in supp(a)");
-    const double2 c = C[idx[g0]];   // the given coefficient if there is one, else the conjugate of -w's
+    const int e = idx[g0];
+    const double2 c = C[e];   // the given coefficient if there is one, else the conjugate of -w's
     if (coef)
       for (int q = g0 + 1; q < g1; ++q) {
         const double2 o = C[idx[q]];
-        if (std::hypot(o.x - c.x, o.y - c.y) > 1e-14 * scale)
+        if (cabs2d(o.x - c.x, o.y - c.y) > 1e-14 * scale)
           return fail(SS_EINVAL, "coefficients at w and -w are not complex conjugates (a must be real)");
       }
-    const int16_t* k = &K[(size_t)idx[g0] * d];
+    const int16_t* src = freqs + (int64_t)(e < n_a ? e : e - n_a) * d;
+    const int sign = e < n_a ? 1 : -1;
     bool is_zero = true;
-    for (int t = 0; t < d; ++t) is_zero &= k[t] == 0;
+    for (int t = 0; t < d; ++t) is_zero &= src[t] == 0;
     double2 cv = c;
     if (is_zero && coef) {
       if (std::fabs(c.y) > 1e-14 * scale || c.x <= 0) return fail(SS_EINVAL, "a_0 must be real and positive");
@@ -523,7 +557,7 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
     g0 = g1;
     if (coef && drop_zero_coef && !is_zero && cv.x == 0 && cv.y == 0) continue;
     if (is_zero) out->zero = out->size();
-    out->keys.insert(out->keys.end(), k, k + d);
+    for (int t = 0; t < d; ++t) out->keys.push_back((int16_t)(sign * src[t]));
     out->coef.push_back(cv);
   }
   if (out->zero < 0) return fail(SS_EINVAL, "0 must be in supp(a) (a_0 > 0 for a positive coefficient)");
@@ -554,12 +588,13 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0), s_of(n_prob);
   int max_level = 0, smax1 = 1;
   int64_t a_pos = 0;
+  std::vector<int> fidx;
+  ATable at;   // reused across problems
   for (int p = 0; p < n_prob; ++p) {
     if (level[p] < 0 || level[p] > 255) return fail(SS_EINVAL, "level must be in [0, 255]");
     if (n_a[p] < 1) return fail(SS_EINVAL, "every problem needs a non-empty supp(a)");
     if (n_f[p] < 1) return fail(SS_EINVAL, "every problem needs at least one forcing frequency");
     max_level = std::max(max_level, level[p]);
-    ATable at;
     SS_TRY(canonical_a(d, n_a[p], a_freqs + a_pos * d, nullptr, false, &at));
     a_pos += n_a[p];
     st->a_zero.push_back(at.zero);
@@ -584,10 +619,16 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     woff[p + 1] = woff[p] + at.size() - 1;
     smax1 = std::max<int>(smax1, at.size() - 1);
     f_off[p + 1] = f_off[p] + n_f[p];
-    std::set<std::vector<int16_t>> fs;
-    for (int i = f_off[p]; i < f_off[p + 1]; ++i)
-      if (!fs.emplace(f_freqs + (int64_t)i * d, f_freqs + (int64_t)(i + 1) * d).second)
-        return fail(SS_EINVAL, "duplicate forcing frequency within a problem");
+    fidx.resize(n_f[p]);
+    for (int i = 0; i < n_f[p]; ++i) fidx[i] = f_off[p] + i;
+    const int16_t* fk = f_freqs;
+    auto fless = [&](int x, int y) {
+      return std::lexicographical_compare(fk + (int64_t)x * d, fk + (int64_t)(x + 1) * d, fk + (int64_t)y * d,
+                                          fk + (int64_t)(y + 1) * d);
+    };
+    std::sort(fidx.begin(), fidx.end(), fless);
+    for (int i = 1; i < n_f[p]; ++i)
+      if (!fless(fidx[i - 1], fidx[i])) return fail(SS_EINVAL, "duplicate forcing frequency within a problem");
   }
   const int64_t nF = f_off[n_prob];
   SS_HIP(hipGetDevice(&st->device));
@@ -827,6 +868,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uhash, upid, ulev, unorm, st->d_hash,
                                                          st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
+  // the forcing frequencies are the first nF unsorted keys, in the order given
+  st->n_f = nF;
+  SS_TRY(dalloc(&st->d_fslot, nF));
+  SS_HIP(hipMemcpyAsync(st->d_fslot, inv, nF * 4, hipMemcpyDeviceToDevice, stream));
   {
     // regions sized for the build's worst case are re-laid out for the final counts;
     // otherwise the slots are re-pointed at the canonical rows
@@ -861,6 +906,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
 void free_stamp_impl(StampImpl* st) {
   if (!st) return;
+  dfree(st->d_fslot);
   dfree(st->d_akeys);
   dfree(st->d_ahash);
   dfree(st->d_anorm);
@@ -905,6 +951,19 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   return SS_OK;
+}
+
+ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream) {
+  if (!f || (st->n_f > 0 && !f_hat)) return fail(SS_EINVAL, "null argument");
+  double2* dv = nullptr;
+  Scratch sc(stream);
+  sc.hold(dv);
+  SS_TRY(dalloc(&dv, st->n_f));
+  SS_HIP(hipMemcpyAsync(dv, f_hat, st->n_f * 16, hipMemcpyHostToDevice, stream));
+  double2* df = static_cast<double2*>(f);
+  k_zero_c128<<<grid_for(st->total), kBlock, 0, stream>>>(st->total, df);
+  k_scatter_f<<<grid_for(st->n_f), kBlock, 0, stream>>>(st->n_f, st->d_fslot, dv, df);
+  return SS_OK;   // Scratch synchronises the stream before releasing the staging block
 }
 
 }  // namespace ss

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_ERANGE", 4: "
 PRECISION = {"fp64": SS_FP64, "fp32_refine": SS_FP32_REFINE, SS_FP64: SS_FP64, SS_FP32_REFINE: SS_FP32_REFINE}
 
 EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp_keys", "ss_stamp_lookup",
-            "ss_stamp_lookup_batch",
+            "ss_stamp_lookup_batch", "ss_stamp_forcing",
             "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
@@ -61,6 +61,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_stamp_keys": [P, pi16, pu8],
         "ss_stamp_lookup": [P, i32, i64, pi16, pi64],
         "ss_stamp_lookup_batch": [P, i64, pi32, pi16, pi64],
+        "ss_stamp_forcing": [P, pd, P, P],
         "ss_build_op": [P, pi32, pi16, pd, u32, P, C.POINTER(P)],
         "ss_op_info": [P, pi64, pi64, pi64, pi64],
         "ss_op_csr": [P, pi64, pi32, pi32, pi32],
@@ -124,12 +125,39 @@ def _stream(stream) -> int:
     return int(stream)
 
 
+class Batch:
+    """Problems of one dimension packed once into the flat host arrays the C ABI
+    takes (objects with ``d, a_freqs, f_freqs, level`` and, where present,
+    ``a_hat, f_hat``).  Builds accept a ``Batch`` or the list of problems."""
+
+    def __init__(self, problems: Sequence):
+        d = int(problems[0].d)
+        if any(int(p.d) != d for p in problems):
+            raise SparseSpecError(SS_EINVAL, "a batch must share the dimension d")
+        self.d = d
+        self.n_prob = len(problems)
+        self.n_a = np.array([len(p.a_freqs) for p in problems], dtype=np.int32)
+        self.n_f = np.array([len(p.f_freqs) for p in problems], dtype=np.int32)
+        self.level = np.array([int(p.level) for p in problems], dtype=np.int32)
+        self.a_freqs = _i16(np.concatenate([np.asarray(p.a_freqs).reshape(-1, d) for p in problems]))
+        self.f_freqs = _i16(np.concatenate([np.asarray(p.f_freqs).reshape(-1, d) for p in problems]))
+        has_a = all(getattr(p, "a_hat", None) is not None for p in problems)
+        has_f = all(getattr(p, "f_hat", None) is not None for p in problems)
+        self.a_hat = _c128(np.concatenate([np.asarray(p.a_hat) for p in problems])) if has_a else None
+        self.f_hat = _c128(np.concatenate([np.asarray(p.f_hat) for p in problems])) if has_f else None
+
+
+def _batch(problems) -> Batch:
+    return problems if isinstance(problems, Batch) else Batch(problems)
+
+
 class Stamp:
     """Stamping sets S^N of a batch of problems of one dimension (device-resident)."""
 
-    def __init__(self, handle, d: int):
+    def __init__(self, handle, d: int, n_f: int = -1):
         self._h = handle
         self.d = d
+        self.n_f = n_f           # forcing frequencies given to the build
         n = C.c_int64()
         npb = C.c_int32()
         _check(_lib.ss_stamp_size(self._h, C.byref(n), C.byref(npb), None))
@@ -140,21 +168,14 @@ class Stamp:
         self.offsets = off
 
     @classmethod
-    def build(cls, problems: Sequence, stream=None) -> "Stamp":
-        """Build from objects with ``d, a_freqs, f_freqs, level`` (one dimension)."""
-        d = int(problems[0].d)
-        if any(int(p.d) != d for p in problems):
-            raise SparseSpecError(SS_EINVAL, "a batch must share the dimension d")
-        n_a = np.array([len(p.a_freqs) for p in problems], dtype=np.int32)
-        n_f = np.array([len(p.f_freqs) for p in problems], dtype=np.int32)
-        lev = np.array([int(p.level) for p in problems], dtype=np.int32)
-        af = _i16(np.concatenate([np.asarray(p.a_freqs).reshape(-1, d) for p in problems]))
-        ff = _i16(np.concatenate([np.asarray(p.f_freqs).reshape(-1, d) for p in problems]))
+    def build(cls, problems, stream=None) -> "Stamp":
+        """Build from a ``Batch`` or a list of problems of one dimension."""
+        b = _batch(problems)
         h = C.c_void_p()
-        _check(_lib.ss_build_stamp_batch(len(problems), d, _ptr(n_a, C.c_int32), _ptr(af, C.c_int16),
-                                         _ptr(n_f, C.c_int32), _ptr(ff, C.c_int16), _ptr(lev, C.c_int32),
-                                         C.c_void_p(_stream(stream)), C.byref(h)))
-        return cls(h, d)
+        _check(_lib.ss_build_stamp_batch(b.n_prob, b.d, _ptr(b.n_a, C.c_int32), _ptr(b.a_freqs, C.c_int16),
+                                         _ptr(b.n_f, C.c_int32), _ptr(b.f_freqs, C.c_int16),
+                                         _ptr(b.level, C.c_int32), C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h, b.d, int(b.n_f.sum()))
 
     def keys(self):
         k = np.zeros((self.n_total, self.d), dtype=np.int16)
@@ -177,17 +198,17 @@ class Stamp:
                                           _ptr(out, C.c_int64)))
         return out
 
-    def forcing_vector(self, problems, device=None):
-        """f in canonical slot order (complex128 tensor on ``device``) from each problem's F."""
+    def forcing_vector(self, problems, device=None, stream=None):
+        """f in canonical slot order (complex128 tensor on ``device``): each problem's
+        f_hat at the slots of its forcing frequencies (the batch the stamp was built from)."""
         import torch
-        prob = np.concatenate([np.full(len(p.f_freqs), i, dtype=np.int32) for i, p in enumerate(problems)])
-        q = np.concatenate([np.asarray(p.f_freqs).reshape(-1, self.d) for p in problems])
-        slots = self.lookup_batch(prob, q)
-        if np.any(slots < 0):
-            raise SparseSpecError(SS_EINVAL, "a forcing frequency is missing from its stamping set")
-        vals = np.concatenate([np.asarray(p.f_hat, dtype=np.complex128) for p in problems])
-        f = torch.zeros(self.n_total, dtype=torch.complex128, device=device or "cuda")
-        f[torch.from_numpy(slots).to(f.device)] = torch.from_numpy(vals).to(f.device)
+        vals = problems.f_hat if isinstance(problems, Batch) else \
+            _c128(np.concatenate([np.asarray(p.f_hat) for p in problems]))
+        if vals is None or len(vals) != 2 * self.n_f:
+            raise SparseSpecError(SS_EINVAL, "one f_hat coefficient per forcing frequency of the build is needed")
+        f = torch.empty(self.n_total, dtype=torch.complex128, device=device or "cuda")
+        _check(_lib.ss_stamp_forcing(self._h, _ptr(vals, C.c_double), C.c_void_p(f.data_ptr()),
+                                     C.c_void_p(_stream(stream))))
         return f
 
     def close(self):
@@ -214,14 +235,13 @@ class Operator:
         self.n_total, self.n_exec, self.nnz, self.n_components = [v.value for v in vals]
 
     @classmethod
-    def build(cls, stamp: Stamp, problems: Sequence, flags: int = 0, stream=None) -> "Operator":
-        d = stamp.d
-        n_a = np.array([len(p.a_freqs) for p in problems], dtype=np.int32)
-        af = _i16(np.concatenate([np.asarray(p.a_freqs).reshape(-1, d) for p in problems]))
-        ah = _c128(np.concatenate([np.asarray(p.a_hat) for p in problems]))
+    def build(cls, stamp: Stamp, problems, flags: int = 0, stream=None) -> "Operator":
+        b = _batch(problems)
+        if b.a_hat is None:
+            raise SparseSpecError(SS_EINVAL, "the operator needs a_hat of every problem")
         h = C.c_void_p()
-        _check(_lib.ss_build_op(stamp._h, _ptr(n_a, C.c_int32), _ptr(af, C.c_int16), _ptr(ah, C.c_double),
-                                int(flags), C.c_void_p(_stream(stream)), C.byref(h)))
+        _check(_lib.ss_build_op(stamp._h, _ptr(b.n_a, C.c_int32), _ptr(b.a_freqs, C.c_int16),
+                                _ptr(b.a_hat, C.c_double), int(flags), C.c_void_p(_stream(stream)), C.byref(h)))
         return cls(h, stamp)
 
     def csr(self):

@@ -95,6 +95,19 @@ def test_stamp_and_lookup_bit_exact(ss, config):
     assert np.all(got[expect == -1] == -1)
 
 
+def test_forcing_vector_matches_oracle_slots(ss):
+    # f_hat placed at the slots the build recorded for F equals the oracle's f on S^N
+    cases = [oracle_case(2, i, level=lv) for i, lv in ((0, 1), (1, 0), (2, 2))]
+    probs = [c["p"] for c in cases]
+    st = ss.Stamp.build(ss.Batch(probs))
+    f = st.forcing_vector(probs).cpu().numpy()
+    assert np.array_equal(f, np.concatenate([c["f"] for c in cases]))
+    f2 = st.forcing_vector(ss.Batch(probs)).cpu().numpy()
+    assert np.array_equal(f2, f)
+    with pytest.raises(ss.SparseSpecError):
+        st.forcing_vector(probs[:-1])
+
+
 @pytest.mark.parametrize("config", [1, 2, 3, 4])
 def test_neighbour_map_and_classes_bit_exact(ss, config):
     oc = oracle_case(config)
