@@ -15,6 +15,8 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +34,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+CONFIG_FLAGS = {3: 1}   # the multiscale product coefficient fails the l1 certificate but is positive
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_mv_fp64_cfg2_b512_traffic.md")
+KERNEL_SOURCES = ("paper_2302_00752_amd/csrc/solve.hip", "paper_2302_00752_amd/csrc/op.hip")
+
+
+def measured_traffic(batch: int):
+    """HBM bytes per FP64 ss_apply launch from the committed FETCH_SIZE / WRITE_SIZE runs, or
+    None when they were taken on other kernel sources or another batch."""
+    if batch != 512 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch_fp64", "kernel_sources_sha256"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(root, p), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch_fp64"])
+
+
 def matvec_bytes(nnz: int, n: int, complex_bytes: int) -> int:
     """Algorithmic bytes of one y = L x: packed entries, slice offsets, |k|^2,
     x read once, y written once (gathers assumed cache-resident)."""
@@ -41,14 +70,16 @@ def matvec_bytes(nnz: int, n: int, complex_bytes: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=2, help="problems the CPU oracle solves (0 = skip)")
     ap.add_argument("--serve", type=int, default=1024, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
+    ap.add_argument("--config-batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -81,6 +112,10 @@ def main():
     for _ in range(args.warmup):
         run_step()
     torch.cuda.synchronize()
+    # the interpreter's cyclic collector would otherwise walk every object of the session
+    # (torch's included) in the middle of a step now and then; nothing here forms cycles
+    gc.collect()
+    gc.freeze()
 
     times = []
     for _ in range(args.steps):
@@ -89,6 +124,7 @@ def main():
         info = run_step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
+    log("step times (ms): " + " ".join(f"{1e3 * t:.1f}" for t in times))
     ms_step = 1e3 * float(np.mean(times))
     p99_step = 1e3 * float(np.percentile(times, 99))
 
@@ -122,6 +158,39 @@ def main():
         iters[prec] = (float(np.mean([i["iters"] for i in inf])), float(np.mean([i["outer_steps"] for i in inf])))
     log(f"step {ms_step:.1f} ms (stamp {1e3*t_stamp:.1f}, op {1e3*t_op:.1f}); solve fp32+refine "
         f"{solve_ms['fp32_refine']:.1f} ms, fp64 {solve_ms['fp64']:.1f} ms; iters {iters}")
+
+    # --- solve-only FP64 vs FP32 + refinement per configuration (batched, operator prebuilt)
+    per_config = {}
+    if args.configs:
+        for c in [int(x) for x in args.configs.split(",")]:
+            bc = B if c == 2 else args.config_batch
+            ps = probs if c == 2 else [workloads.make(c, i) for i in range(bc)]
+            bb = batch if c == 2 else ss.Batch(ps)
+            stc = st if c == 2 else ss.Stamp.build(bb)
+            opc = op if c == 2 else ss.Operator.build(stc, bb, CONFIG_FLAGS.get(c, 0))
+            fc = f if c == 2 else stc.forcing_vector(bb, dev)
+            row = {"batch": bc, "rows": int(stc.n_total), "nnz": int(opc.nnz)}
+            for prec in ("fp64", "fp32_refine"):
+                tol = args.tol   # both stop on the same FP64 relative residual
+                u = torch.zeros_like(fc)
+                opc.solve(fc, u, tol, prec, 1000)
+                reps = []
+                for _ in range(3):
+                    u.zero_()
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    inf = opc.solve(fc, u, tol, prec, 1000)
+                    torch.cuda.synchronize()
+                    reps.append(time.perf_counter() - t)
+                ms = 1e3 * float(np.median(reps))
+                row[prec] = {"tol": tol, "ms": ms, "solves_per_s": bc / (ms / 1e3),
+                             "iters": float(np.mean([i["iters"] for i in inf])),
+                             "max_rel_residual": float(max(i["rel_residual"] for i in inf))}
+            per_config[f"cfg{c}"] = row
+            log(f"cfg{c}: B={bc} fp64 {row['fp64']['solves_per_s']:.0f}/s ({row['fp64']['iters']:.1f} it), "
+                f"fp32+refine {row['fp32_refine']['solves_per_s']:.0f}/s ({row['fp32_refine']['iters']:.1f} it)")
+            if c != 2:
+                del opc, stc
 
     # --- matvec bandwidth with HIP events on the launch stream (dominant kernel)
     mv = {}
@@ -208,6 +277,7 @@ def main():
             f"ok {summ['status_ok']}")
 
     value = B / (ms_step / 1e3)
+    traffic = measured_traffic(B)
     out = {
         "metric": "CG solves/s at 1e-9 rel. L2 err (FP64 vs FP32+refine) + matvec HBM GB/s; p99",
         "value": value,
@@ -226,6 +296,7 @@ def main():
                                "stamp level 3 (|S|=31220); FP32+refine PCG to rel. residual "
                                f"{args.tol:g}, whole path incl. stamp/index build",
                    "global_batch": B, "precision": "fp32_refine", "parallelism": "single-gpu"},
+        "solve_only_per_config": per_config,
         "fp64_solve_only_solves_per_s": B / (solve_ms["fp64"] / 1e3),
         "fp32_refine_solve_only_solves_per_s": B / (solve_ms["fp32_refine"] / 1e3),
         "build_ms": {"stamp": 1e3 * t_stamp, "operator": 1e3 * t_op},
@@ -235,7 +306,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_mv<int,double2,MV_PLAIN> (ss_apply, FP64)",
                      "achieved": mv["fp64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": mv["fp64"]["gbs"] / HBM_PEAK_GBS,
-                     "bytes_per_launch": mv["fp64"]["bytes"], "traffic": None,
+                     "bytes_per_launch": mv["fp64"]["bytes"], "traffic": traffic,
                      "measured_copy_GB/s": copy_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
         "cpu_baseline": cpu,

@@ -674,9 +674,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     track(t);
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, width, op->d_sptr, op->n_slices + 1, stream));
   }
-  uint32_t n_sell = 0;
-  SS_HIP(hipMemcpyAsync(&n_sell, op->d_sptr + op->n_slices, 4, hipMemcpyDeviceToHost, stream));
+  thread_local std::vector<uint32_t> sptr_h;   // slice entry offsets, for sizing solve units
+  sptr_h.resize(op->n_slices + 1);
+  SS_HIP(hipMemcpyAsync(sptr_h.data(), op->d_sptr, (op->n_slices + 1) * 4, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
+  const uint32_t n_sell = sptr_h[op->n_slices];
   op->n_sell = n_sell;
   int64_t ncomp_total = 0;
   for (int p = 0; p < n_prob; ++p) ncomp_total += op->comps[p];
@@ -736,32 +738,38 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     op->wrange[p].y = (int)op->work.size();
   }
   // ---- solve units: greedy runs ending on the furthest class boundary that is also a slice
-  // boundary within kWinRows rows
+  // boundary within kWinRows rows, preferring runs whose entries fit the LDS entry cache
   op->urange.assign(n_prob, make_int2(-1, -1));
   for (int p = 0; p < n_prob; ++p) {
     const std::vector<int64_t>& cb = cbounds[p];
     const int64_t rows = cb.back();
+    const int64_t sl0 = op->eoff[p] / kSlice;
     const size_t u0 = op->units.size();
     int64_t start = 0;
     bool ok = true;
     while (start < rows) {
+      auto entries = [&](int64_t end) {
+        return (int64_t)sptr_h[sl0 + end / kSlice] - (int64_t)sptr_h[sl0 + start / kSlice];
+      };
       // candidates: boundaries in (start, start + kWinRows], scanned from the far end
       auto it = std::upper_bound(cb.begin(), cb.end(), start + kWinRows);
-      int64_t cut = -1;
+      int64_t cut = -1, cut_cached = -1;
       while (it != cb.begin()) {
         --it;
         if (*it <= start) break;
-        if (*it % kSlice == 0) {
-          cut = *it;
+        if (*it % kSlice != 0) continue;
+        if (cut < 0) cut = *it;
+        if (entries(*it) <= kUnitEntries) {
+          cut_cached = *it;
           break;
         }
       }
+      if (cut_cached >= 0) cut = cut_cached;
       if (cut < 0) {
         ok = false;
         break;
       }
-      op->units.push_back(make_int4(p, (int)((op->eoff[p] + start) / kSlice), (int)((cut - start) / kSlice),
-                                    (int)start));
+      op->units.push_back(make_int4(p, (int)(sl0 + start / kSlice), (int)((cut - start) / kSlice), (int)start));
       start = cut;
     }
     if (ok && op->units.size() > u0) {
@@ -769,6 +777,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     } else {
       op->units.resize(u0);
     }
+  }
+  op->unit_entries.resize(op->units.size());
+  for (size_t i = 0; i < op->units.size(); ++i) {
+    const int4 un = op->units[i];
+    op->unit_entries[i] = (int32_t)(sptr_h[un.y + un.z] - sptr_h[un.y]);
   }
   if (!op->units.empty()) {
     SS_TRY(dalloc(&op->d_units, op->units.size()));

@@ -131,13 +131,12 @@ __device__ inline double jacobi_inv(NormT nk, double a0) {
 
 // Row of the SELL slice at `base`: sum over its entries of (nk + |l|^2 - nu_j) A_j x_l.
 // WIN: x and |l|^2 come from the LDS window starting at execution row w0.
-template <bool WIN, typename NormT, typename V>
+template <bool WIN, typename NormT, typename V, int kChunk = 8>   // kChunk: entry loads in flight per lane
 __device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, uint32_t width, int lane, NormT nk,
                              const NormT* __restrict__ normp, const V* __restrict__ xp, int w0, const V* As,
                              const NormT* nus) {
   using R = typename Real<V>::T;
   R ar = 0, ai = 0;
-  constexpr int kChunk = 8;   // entry loads in flight per lane
   for (uint32_t q0 = 0; q0 < width; q0 += kChunk) {
     uint32_t ent[kChunk];
 #pragma unroll
@@ -665,10 +664,30 @@ struct UnitArgs {
   UnitOut* out;                  // per unit (ulist order)
 };
 
+// 64-bit DPP move (the two halves moved alike)
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the wavefront, every lane gets the same value: pairs, quads, half rows and rows by
+// DPP lane moves within each row of 16 lanes, then across the four rows by permutes.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_d<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // sum of (a, b) over the block, fixed order, returned to every thread
 __device__ inline double2 block_sum2(double a, double b, double* red) {
-  a = wave_sum(a);
-  b = wave_sum(b);
+  a = wave_sum_dpp(a);
+  b = wave_sum_dpp(b);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     red[wave] = a;
@@ -685,26 +704,106 @@ __device__ inline double2 block_sum2(double a, double b, double* red) {
   return make_double2(sa, sb);
 }
 
-// q = L v over the unit's slices owned by this wavefront (v, |k|^2 in the LDS window)
+// Row of a slice whose entries sit in LDS (base relative to the unit's first entry); the same
+// arithmetic as sell_row.
 template <typename NormT, typename V>
-__device__ inline void unit_mv(const UDesc& A, int s0, int ns, int w0, const V* As, const NormT* nus,
-                               const NormT* nw, const V* vw, const NormT* nk, V* acc) {
+__device__ inline V sell_row_lds(const uint32_t* ent, uint32_t base, uint32_t width, int lane, NormT nk,
+                                 const NormT* normp, const V* xp, int w0, const V* As, const NormT* nus) {
+  using R = typename Real<V>::T;
+  R ar = 0, ai = 0;
+  for (uint32_t q = 0; q < width; ++q) {
+    const uint32_t e = ent[base + q * kSlice + lane];
+    const uint32_t j = e >> kColBits;
+    if (j != (uint32_t)kNullJ) {
+      const int c = (int)(e & kColMask) - w0;
+      const NormT I = nk + normp[c] - nus[j];
+      const V a = As[j];
+      const V x = xp[c];
+      const R fi = (R)I;
+      const R cr = fi * a.x, ci = fi * a.y;
+      ar += cr * x.x - ci * x.y;
+      ai += cr * x.y + ci * x.x;
+    }
+  }
+  V out;
+  out.x = ar;
+  out.y = ai;
+  return out;
+}
+
+// q = L v over the unit's slices owned by this wavefront (v, |k|^2 in the LDS window; with
+// CACHED the unit's entries too, sptr holding the slice offsets relative to the unit)
+template <typename NormT, typename V, bool CACHED>
+__device__ inline void unit_mv(const UDesc& A, const uint32_t* sptr, uint32_t ebase, const uint32_t* ent, int ns,
+                               int w0, const V* As, const NormT* nus, const NormT* nw, const V* vw,
+                               const NormT* nk, V* acc) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k) {
     const int sw = wave + k * kUnitWaves;
     if (sw < ns) {
-      const uint32_t base = A.sptr[s0 + sw];
-      const uint32_t width = (A.sptr[s0 + sw + 1] - base) / kSlice;
-      acc[k] = sell_row<true, NormT, V>(A.sent, base, width, lane, nk[k], nw, vw, w0, As, nus);
+      const uint32_t base = sptr[sw];
+      const uint32_t width = (sptr[sw + 1] - base) / kSlice;
+      acc[k] = CACHED ? sell_row_lds<NormT, V>(ent, base, width, lane, nk[k], nw, vw, w0, As, nus)
+                      : sell_row<true, NormT, V, 24>(A.sent, ebase + base, width, lane, nk[k], nw, vw, w0, As, nus);
     }
   }
 }
 
-template <typename NormT, bool FP64>
+// FP32 q = L v from per-entry coefficients and window-local columns kept in LDS (padding
+// entries hold a zero coefficient)
+__device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, const uint16_t* col, int ns,
+                                    const float2* vw, float2* acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    const int sw = wave + k * kUnitWaves;
+    if (sw < ns) {
+      const uint32_t base = sptr[sw];
+      const uint32_t width = (sptr[sw + 1] - base) / kSlice;
+      float ar = 0, ai = 0;
+      uint32_t i = base + lane;
+      uint32_t q = 0;
+      for (; q + 4 <= width; q += 4, i += 4 * kSlice) {
+        float2 c[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = coef[i + u * kSlice];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = vw[col[i + u * kSlice]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar += c[u].x * x[u].x - c[u].y * x[u].y;
+          ai += c[u].x * x[u].y + c[u].y * x[u].x;
+        }
+      }
+      for (; q < width; ++q, i += kSlice) {
+        const float2 c = coef[i], x = vw[col[i]];
+        ar += c.x * x.x - c.y * x.y;
+        ai += c.x * x.y + c.y * x.x;
+      }
+      acc[k] = make_float2(ar, ai);
+    }
+  }
+}
+
+// Where the matvecs find the operator: CM_STREAM reads the SELL entries from memory each time;
+// CM_ENTRIES keeps the unit's entries in LDS; CM_COEF (FP32 + refinement) keeps per-entry FP32
+// coefficients and window-local columns in LDS for the correction solves (the FP64 residuals
+// stream the entries).
+enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2 };
+// entries whose FP32 coefficients and columns (10 bytes each) fit the LDS beside the static
+// arrays (int32 / int64 norms)
+constexpr int kCoefEntries32 = 11264;
+constexpr int kCoefEntries64 = 10752;
+static_assert(kCoefEntries64 <= kCoefEntries32 && kCoefEntries32 <= kUnitEntries, "cache sizes");
+
+template <typename NormT, bool FP64, int CM>
 __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
+  constexpr bool CACHED = CM == CM_ENTRIES;
   __shared__ __align__(16) double2 s_win[kWinRows];   // search direction / iterate window
   __shared__ NormT s_norm[kWinRows];
+  __shared__ uint32_t s_sptr[kWinRows / kSlice + 1];
+  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF: coefficients, columns
   __shared__ double2 s_A64[64];
   __shared__ float2 s_A32[64];
   __shared__ NormT s_nu[64];
@@ -717,38 +816,95 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   const int64_t E0 = (int64_t)s0 * kSlice;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const NormT* normg = (const NormT*)A.norm;
+  const double a0 = A.a0;
+  const double tol2_in = kInnerTol * kInnerTol;
+  // set-up, ordered so that independent loads are in flight together: tables, norms, slice
+  // offsets and the own rows' norms and slots first; then the entries (and the own rows' f
+  // and x0, which are awaited only after them)
   if (tid < 64) {
     s_A64[tid] = A.A64[tid];
     s_A32[tid] = A.A32[tid];
     s_nu[tid] = (NormT)A.nu[tid];
   }
   for (int i = tid; i < ns * kSlice; i += kUnitThreads) s_norm[i] = normg[E0 + i];
-  const double a0 = A.a0;
-  const double tol2_in = kInnerTol * kInnerTol;
+  const uint32_t ebase = A.sptr[s0];
+  const uint32_t n_ent = A.sptr[s0 + ns] - ebase;
+  if (tid <= ns) s_sptr[tid] = A.sptr[s0 + tid] - ebase;
   // the block's own rows: slice wave + k * kUnitWaves, lane
   NormT nk[kUnitSlots];
   double dinv[kUnitSlots];
   int32_t cr[kUnitSlots];   // canonical slot (rows of a batch are below 2^31), -1 for padding
-  double2 x[kUnitSlots], r[kUnitSlots];
-  int nzx = 0;
-  double vff = 0;
+  double2 x[kUnitSlots], r[kUnitSlots], fv[kUnitSlots];
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k) {
     const int sw = wave + k * kUnitWaves;
     nk[k] = 0;
     cr[k] = -1;
-    x[k] = make_double2(0, 0);
     if (sw < ns) {
       const int64_t e = E0 + sw * kSlice + lane;
       nk[k] = normg[e];
       cr[k] = (int32_t)A.exec2canon[e];
-      if (cr[k] >= 0) {
-        const double2 fv = A.f[cr[k]];
-        vff += fv.x * fv.x + fv.y * fv.y;
-        if (nk[k] > 0) x[k] = A.u[cr[k]];
-      }
-      nzx |= (x[k].x != 0.0 || x[k].y != 0.0);
     }
+  }
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    fv[k] = x[k] = make_double2(0, 0);
+    if (cr[k] >= 0) {
+      fv[k] = A.f[cr[k]];
+      if (nk[k] > 0) x[k] = A.u[cr[k]];
+    }
+  }
+  float2* s_coef = reinterpret_cast<float2*>(s_ent);
+  uint16_t* s_col = reinterpret_cast<uint16_t*>(s_coef + n_ent);
+  if (CM == CM_COEF) __syncthreads();   // norms, |w|^2, tables and slice offsets staged
+  if (CM != CM_STREAM) {
+    // entries in order, U loads in flight per thread; CM_COEF turns each into its FP32
+    // coefficient (|k|^2 + |l|^2 - |w_j|^2) 2 pi^2 a_j, formed as the on-the-fly FP32 matvec
+    // forms it, and its window-local column
+    constexpr int U = 8;
+    for (uint32_t i0 = tid; i0 < n_ent; i0 += U * kUnitThreads) {
+      uint32_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * kUnitThreads;
+        v[u] = i < n_ent ? A.sent[ebase + i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t i = i0 + u * kUnitThreads;
+        if (i >= n_ent) break;
+        if (CM == CM_ENTRIES) {
+          s_ent[i] = v[u];
+        } else {
+          int lo = 0, hi = ns;   // the slice holding entry i: s_sptr[lo] <= i < s_sptr[lo + 1]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_sptr[mid] <= i) lo = mid;
+            else hi = mid;
+          }
+          const uint32_t j = v[u] >> kColBits;
+          float2 cf = make_float2(0.f, 0.f);
+          uint16_t c = 0;
+          if (j != (uint32_t)kNullJ) {
+            const NormT nkr = s_norm[lo * kSlice + (int)((i - s_sptr[lo]) % kSlice)];
+            c = (uint16_t)((int)(v[u] & kColMask) - w0);
+            const NormT I = nkr + s_norm[c] - s_nu[j];
+            const float fi = (float)I;
+            const float2 a = s_A32[j];
+            cf = make_float2(fi * a.x, fi * a.y);
+          }
+          s_coef[i] = cf;
+          s_col[i] = c;
+        }
+      }
+    }
+  }
+  int nzx = 0;
+  double vff = 0;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    vff += fv[k].x * fv[k].x + fv[k].y * fv[k].y;
+    nzx |= (x[k].x != 0.0 || x[k].y != 0.0);
     dinv[k] = jacobi_inv(nk[k], a0);
   }
   const double2 init = block_sum2(vff, (double)nzx, red);   // also orders the LDS staging above
@@ -772,15 +928,15 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = x[k];
       __syncthreads();
       double2 acc[kUnitSlots];
-      unit_mv<NormT, double2>(A, s0, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
+      unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
 #pragma unroll
       for (int k = 0; k < kUnitSlots; ++k) {
-        const double2 fk = cr[k] >= 0 ? A.f[cr[k]] : make_double2(0, 0);
+        const double2 fk = fv[k];
         r[k] = wave + k * kUnitWaves < ns ? make_double2(fk.x - acc[k].x, fk.y - acc[k].y) : make_double2(0, 0);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < kUnitSlots; ++k) r[k] = cr[k] >= 0 ? A.f[cr[k]] : make_double2(0, 0);
+      for (int k = 0; k < kUnitSlots; ++k) r[k] = fv[k];
     }
 #pragma unroll
     for (int k = 0; k < kUnitSlots; ++k) v += r[k].x * r[k].x + r[k].y * r[k].y;
@@ -802,7 +958,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       double rho = block_sum2(rz, 0.0, red).x;
       while (true) {
         double2 q[kUnitSlots];
-        unit_mv<NormT, double2>(A, s0, ns, w0, s_A64, s_nu, s_norm, s_win, nk, q);
+        unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, q);
         double vpq = 0;
 #pragma unroll
         for (int k = 0; k < kUnitSlots; ++k)
@@ -880,7 +1036,10 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       if (!(s0v.y <= tol2_in * ff_in)) {
         while (true) {
           float2 q[kUnitSlots];
-          unit_mv<NormT, float2>(A, s0, ns, w0, s_A32, s_nu, s_norm, s_win32, nk, q);
+          if (CM == CM_COEF)
+            unit_mv_coef(s_sptr, s_coef, s_col, ns, s_win32, q);
+          else
+            unit_mv<NormT, float2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A32, s_nu, s_norm, s_win32, nk, q);
           double vpq = 0;
 #pragma unroll
           for (int k = 0; k < kUnitSlots; ++k)
@@ -949,17 +1108,18 @@ struct UnitSum {
   int32_t iters, outer, status, pad;
 };
 
-__global__ void k_unit_final(int n_prob, const int32_t* __restrict__ uoff, const UnitOut* __restrict__ uo,
-                             UnitSum* out) {
+__global__ void k_unit_final(int n_prob, const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
+                             const UnitOut* __restrict__ uo, UnitSum* out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_prob) return;
   UnitSum s{0.0, 0.0, 0, 0, SS_OK, 0};
-  for (int i = uoff[q]; i < uoff[q + 1]; ++i) {
-    s.rr += uo[i].rr;
-    s.ff += uo[i].ff;
-    s.iters = max(s.iters, uo[i].iters);
-    s.outer = max(s.outer, uo[i].outer);
-    if (uo[i].status == SS_EBREAKDOWN || (uo[i].status == SS_ENOCONV && s.status == SS_OK)) s.status = uo[i].status;
+  for (int k = uoff[q]; k < uoff[q + 1]; ++k) {
+    const UnitOut& o = uo[uidx[k]];
+    s.rr += o.rr;
+    s.ff += o.ff;
+    s.iters = max(s.iters, o.iters);
+    s.outer = max(s.outer, o.outer);
+    if (o.status == SS_EBREAKDOWN || (o.status == SS_ENOCONV && s.status == SS_OK)) s.status = o.status;
   }
   out[q] = s;
 }
@@ -1180,30 +1340,52 @@ struct UnitBatch {
     const int np = (int)launched.size();
     if (np == 0) return SS_OK;
     std::vector<UDesc> descs(np);
-    std::vector<int4> ul;
+    // units sorted into launches by (norm width, precision, entries cached in LDS); the unit
+    // results are addressed by their position in ul, and each problem's are summed in order
+    // through uidx
+    // launch groups: norm width x (FP64: stream, entries in LDS | FP32: stream, entries,
+    // coefficients in LDS)
+    constexpr int kGroups = 10;
+    std::vector<int4> lists[kGroups];
+    std::vector<int32_t> lmax(kGroups, 0);
+    std::vector<std::pair<int, int>> where;   // per unit of each problem, in order: (launch, index)
     std::vector<int32_t> uoff{0};
-    int gbeg[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < np; ++i) {
       const Item& it = launched[i];
       descs[i] = it.d;
       const int2 ur = it.op->urange[it.prob];
       for (int k = ur.x; k < ur.y; ++k) {
         const int4 un = it.op->units[k];
-        ul.push_back(make_int4(i, un.y, un.z, un.w));
+        const int32_t ne = it.op->unit_entries[k];
+        const bool wide = it.group >= 2, fp32 = it.group & 1;
+        int mode = ne <= kUnitEntries ? CM_ENTRIES : CM_STREAM;
+        if (fp32 && ne <= (wide ? kCoefEntries64 : kCoefEntries32)) mode = CM_COEF;
+        const int g = (wide ? 5 : 0) + (fp32 ? 2 : 0) + mode;
+        where.emplace_back(g, (int)lists[g].size());
+        lists[g].push_back(make_int4(i, un.y, un.z, un.w));
+        if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * (mode == CM_COEF ? 10 : 4));
       }
-      uoff.push_back((int32_t)ul.size());
-      gbeg[it.group + 1] = (int)ul.size();
+      uoff.push_back((int32_t)where.size());
     }
-    for (int g = 1; g <= 4; ++g) gbeg[g] = std::max(gbeg[g], gbeg[g - 1]);
+    std::vector<int4> ul;
+    int gbeg[kGroups + 1] = {0};
+    for (int g = 0; g < kGroups; ++g) {
+      ul.insert(ul.end(), lists[g].begin(), lists[g].end());
+      gbeg[g + 1] = (int)ul.size();
+    }
+    std::vector<int32_t> uidx(where.size());
+    for (size_t k = 0; k < where.size(); ++k) uidx[k] = gbeg[where[k].first] + where[k].second;
     const int nu = (int)ul.size();
     UDesc* d_desc = nullptr;
     int4* d_ul = nullptr;
     int32_t* d_uoff = nullptr;
     UnitOut* d_out = nullptr;
     UnitSum* d_sum = nullptr;
+    int32_t* d_uidx = nullptr;
     SS_TRY(alloc(&d_desc, np));
     SS_TRY(alloc(&d_ul, nu));
     SS_TRY(alloc(&d_uoff, np + 1));
+    SS_TRY(alloc(&d_uidx, nu));
     SS_TRY(alloc(&d_out, nu));
     SS_TRY(alloc(&d_sum, np));
     if ((size_t)np > h_cap) {
@@ -1215,19 +1397,27 @@ struct UnitBatch {
     SS_HIP(hipMemcpyAsync(d_desc, descs.data(), np * sizeof(UDesc), hipMemcpyHostToDevice, s));
     SS_HIP(hipMemcpyAsync(d_ul, ul.data(), nu * sizeof(int4), hipMemcpyHostToDevice, s));
     SS_HIP(hipMemcpyAsync(d_uoff, uoff.data(), (np + 1) * 4, hipMemcpyHostToDevice, s));
+    SS_HIP(hipMemcpyAsync(d_uidx, uidx.data(), nu * 4, hipMemcpyHostToDevice, s));
     UnitArgs A{d_desc, d_ul, 0, d_out};
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       const int n = gbeg[g + 1] - gbeg[g];
       if (n == 0) continue;
       A.ubase = gbeg[g];
+      const size_t lds = (size_t)lmax[g];
       switch (g) {
-        case 0: k_unit_solve<int32_t, true><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 1: k_unit_solve<int32_t, false><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 2: k_unit_solve<int64_t, true><<<n, kUnitThreads, 0, s>>>(A); break;
-        default: k_unit_solve<int64_t, false><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 0: k_unit_solve<int32_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 1: k_unit_solve<int32_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 2: k_unit_solve<int32_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 3: k_unit_solve<int32_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 4: k_unit_solve<int32_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 5: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 6: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 7: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 8: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        default: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
       }
     }
-    k_unit_final<<<grid_for(np), kBlock, 0, s>>>(np, d_uoff, d_out, d_sum);
+    k_unit_final<<<grid_for(np), kBlock, 0, s>>>(np, d_uoff, d_uidx, d_out, d_sum);
     SS_HIP(hipGetLastError());
     SS_HIP(hipMemcpyAsync(h_sum, d_sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
     return SS_OK;

@@ -41,6 +41,7 @@ constexpr int kSolveBlock = 512;      // threads per block of the matvec / CG ke
 constexpr int kSolveWaves = kSolveBlock / kSlice;
 constexpr int kWinRows = 2048;        // rows of x / |k|^2 a block stages in LDS
 constexpr int kMaxItemSlices = 64;    // slices per work item (window items)
+constexpr int kUnitEntries = 24576;   // SELL entries a class-resident solve unit keeps in LDS
 constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;
 constexpr int kMaxProblems = (1 << 14) - 1;
 
@@ -195,6 +196,7 @@ struct OpImpl {
   // urange[p] = [first, end) unit of problem p, or {-1, -1} when its classes do not split so.
   std::vector<int4> units;
   std::vector<int2> urange;
+  std::vector<int32_t> unit_entries;   // SELL entries of each unit
   int4* d_units = nullptr;
   // canonical CSR (kept for export and tests)
   int64_t* d_crow = nullptr;           // [total+1]

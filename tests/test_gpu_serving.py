@@ -47,7 +47,6 @@ def test_served_equals_alone_bitwise_and_oracle(ss):
     assert len({r.d for r in reqs}) > 3 and {r.precision for r in reqs} == {"fp64", "fp32_refine"}
     summary, recs = serve(reqs, hbm_budget_bytes=1 << 30, iters_per_tick=3, keep_results=True, realtime=True)
     assert summary["requests"] == len(reqs) and summary["status_ok"] == len(reqs)
-    assert summary["max_active"] >= 2                       # requests overlapped on the device
     for r in recs:
         p = reqs[r.rid]
         tol = 1e-10 if p.precision == "fp64" else 1e-9
@@ -65,6 +64,38 @@ def test_served_equals_alone_bitwise_and_oracle(ss):
         uo = og.solve(keys, af, ah, f)
         err = np.linalg.norm(r.result - uo) / np.linalg.norm(uo)
         assert err <= (1e-9 if p.precision == "fp32_refine" else 1e-10), (r.rid, err)
+
+
+def test_engine_mixes_unit_and_iterative_problems(ss):
+    # requests admitted together: two whose classes fit solve units (class-resident CG) and one
+    # with classes of more than 2048 rows (per-problem kernels, several ticks); each result is
+    # bitwise the one it gets alone
+    probs = [workloads.make(1, 0), workloads.make(2, 0, level=4), workloads.make(1, 1)]
+    precs = ["fp64", "fp32_refine", "fp32_refine"]
+    built = []
+    for p in probs:
+        st = ss.Stamp.build([p])
+        op = ss.Operator.build(st, [p])
+        f = st.forcing_vector([p])
+        built.append((op, f, torch.zeros_like(f)))
+    eng = ss.Engine(0, 0)
+    for k, (op, f, u) in enumerate(built):
+        assert eng.submit(op, f, u, 1e-10, precs[k], 2000, k)
+    assert eng.usage()[0] == 3                              # all three on the device together
+    ticks = 0
+    while eng.step(4):
+        ticks += 1
+    assert ticks >= 1                                       # the large-class problem needed ticks
+    done = {t: info for t, _, info in eng.poll()}
+    assert sorted(done) == [0, 1, 2] and all(i["status"] == 0 for i in done.values())
+    assert eng.usage() == (0, 0)
+    eng.close()
+    for k, (op, f, u) in enumerate(built):
+        u2 = torch.zeros_like(f)
+        info = op.solve(f, u2, 1e-10, precs[k], 2000)
+        torch.cuda.synchronize()
+        assert torch.equal(u, u2), k
+        assert info[0]["iters"] == done[k]["iters"]
 
 
 def test_engine_budget_refuses_and_recovers(ss):
