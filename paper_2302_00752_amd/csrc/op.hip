@@ -104,13 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
 constexpr int kNbrGroup = 4;   // slots per probe group (64 bytes)
 
 // One lane per row, for dimensions up to DMAX: the row's key and hash stay in registers while
-// the lane looks up k - w_j for every a-table entry in table order.  A lookup reads the aligned
-// group of G slots that holds its first probe position and scans it from there (linear probing
-// stays within the group for nearly every lookup at the table's load factor), so the lanes of a
-// wave finish together instead of waiting for the longest probe sequence among them; only a
-// lookup that runs past its group continues slot by slot.  A candidate c matches when
+// the lane looks up k - w_j for the upper half of the a-table (see below).  A lookup reads the
+// aligned group of G slots that holds its first probe position and scans it from there (linear
+// probing stays within the group for nearly every lookup at the table's load factor), so the
+// lanes of a wave finish together instead of waiting for the longest probe sequence among them;
+// only a lookup that runs past its group continues slot by slot.  A candidate c matches when
 // c + w = k coordinatewise (exact in int).  A wave whose rows all belong to one problem reads
-// that problem's a-table from LDS.  The output is the same as k_neighbors'.
+// that problem's a-table from LDS.  The CSR built from the table equals k_neighbors'.
 template <int DMAX, bool EVEN>
 __device__ __forceinline__ bool key_is_shift(const int16_t* __restrict__ cp, const int* kr, const int16_t* w, int d) {
   int acc = 0;
@@ -129,6 +129,13 @@ __device__ __forceinline__ bool key_is_shift(const int16_t* __restrict__ cp, con
   }
   return acc == 0;
 }
+
+// The neighbour relation is symmetric (the a-table is closed under negation and sorted, so
+// w_{s-1-j} = -w_j and w_z = 0 at z = (s-1)/2): a row looks up k - w_j only for j > z, writes
+// that entry and, when l = k - w_j is present, the mirror entry (l, s-1-j) = k into l's row.
+// Entries go to a dense j-major table (entry j of row r at j * n + r; absent = kAbsent); the
+// lower half of it is cleared beforehand, the upper half and the diagonal are written here.
+constexpr uint32_t kAbsent = 0xffffffffu;
 
 template <int DMAX, bool EVEN, bool UNI, int G>
 __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, const int16_t* wtab,
@@ -152,13 +159,12 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
   const ulonglong2* table = reinterpret_cast<const ulonglong2*>(a.table) + base;
   const int16_t* wsrc = UNI ? wtab : a.akeys + (int64_t)j0 * d;
-  uint32_t* out = a.buf + r;
-  int q = 0;
-  for (int j = 0; j < s; ++j) {
+  uint32_t* D = a.buf;
+  const int64_t T = a.total;
+  D[(int64_t)z * T + r] = (uint32_t)(r - ro) | ((uint32_t)z << kColBits);
+  for (int j = z + 1; j < s; ++j) {
     int64_t m = -1;
-    if (j == z) {
-      m = r;
-    } else {
+    {
       const int16_t* w = wsrc + j * d;
       const uint64_t h = hr - (UNI ? htab[j] : a.ahash[j0 + j]);
       const uint64_t pos = fmix64(h) & mask;
@@ -203,9 +209,33 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
         }
       }
     }
-    if (m >= 0) out[(q++) * a.total] = (uint32_t)(m - ro) | ((uint32_t)j << kColBits);
+    D[(int64_t)j * T + r] = m >= 0 ? (uint32_t)(m - ro) | ((uint32_t)j << kColBits) : kAbsent;
+    if (m >= 0) D[(int64_t)(s - 1 - j) * T + m] = (uint32_t)(r - ro) | ((uint32_t)(s - 1 - j) << kColBits);
   }
-  a.rowlen[r] = q;
+}
+
+// present entries of each row of the dense table, in j order: the row lengths, then the CSR
+__global__ void k_row_count(int64_t total, const uint32_t* __restrict__ D, const int32_t* __restrict__ pid,
+                            const int32_t* __restrict__ aoff, int64_t* rowlen) {
+  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
+  if (r >= total) return;
+  const int p = pid[r], s = aoff[p + 1] - aoff[p];
+  int64_t c = 0;
+  for (int j = 0; j < s; ++j) c += D[(int64_t)j * total + r] != kAbsent;
+  rowlen[r] = c;
+}
+
+__global__ void k_csr_from_dense(int64_t total, const uint32_t* __restrict__ D, const int32_t* __restrict__ pid,
+                                 const int32_t* __restrict__ aoff, const int64_t* __restrict__ crow,
+                                 uint32_t* __restrict__ cent) {
+  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
+  if (r >= total) return;
+  const int p = pid[r], s = aoff[p + 1] - aoff[p];
+  int64_t q = crow[r];
+  for (int j = 0; j < s; ++j) {
+    const uint32_t v = D[(int64_t)j * total + r];
+    if (v != kAbsent) cent[q++] = v;
+  }
 }
 
 template <int DMAX, bool EVEN>
@@ -480,7 +510,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   } tmpmem{stream, {}};
   auto track = [&](void* q) { tmpmem.p.push_back(q); };
 
-  // ---- neighbour map (one lane per (row, j); rows compacted in j order)
+  // ---- neighbour map: for d <= 64, half the lookups into a dense j-major table (the other
+  // half mirrored); above, one lane per (row, j) with rows compacted in j order
   uint32_t* nbr = nullptr;
   int64_t* rowlen = nullptr;
   SS_TRY(dalloc(&nbr, (size_t)total * smax));
@@ -490,7 +521,19 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   const int rpw = 64 / smax;
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
              st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_table, nbr, rowlen};
-  {
+  // the mirrored half needs w_{s-1-j} = -w_j with w_z = 0 at z = (s-1)/2 in every a-table
+  bool dense = d <= 64;
+  for (int p = 0; dense && p < n_prob; ++p) {
+    const int s = st->a_off[p + 1] - st->a_off[p];
+    const int16_t* ak = st->a_keys.data() + (int64_t)st->a_off[p] * d;
+    dense = st->a_zero[p] * 2 == s - 1;
+    for (int j = 0; dense && j < s; ++j)
+      for (int t = 0; t < d; ++t) dense &= ak[(int64_t)j * d + t] == -ak[(int64_t)(s - 1 - j) * d + t];
+  }
+  if (dense) {
+    int zmax = 0;
+    for (int p = 0; p < n_prob; ++p) zmax = std::max(zmax, st->a_zero[p]);
+    SS_HIP(hipMemsetAsync(nbr, 0xff, (size_t)zmax * total * 4, stream));   // the mirrored half
     const unsigned g = xcd_grid(ceil_div(total, kBlock));
     const bool even = d % 2 == 0;
     if (d <= 8)
@@ -499,10 +542,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
       even ? k_neighbors_row<16, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false><<<g, kBlock, 0, stream>>>(na);
     else if (d <= 32)
       even ? k_neighbors_row<32, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false><<<g, kBlock, 0, stream>>>(na);
-    else if (d <= 64)
-      even ? k_neighbors_row<64, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false><<<g, kBlock, 0, stream>>>(na);
     else
-      k_neighbors<<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
+      even ? k_neighbors_row<64, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false><<<g, kBlock, 0, stream>>>(na);
+    k_row_count<<<g, kBlock, 0, stream>>>(total, nbr, st->d_pid, st->d_aoff, rowlen);
+  } else {
+    k_neighbors<<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
   }
   SS_TRY(dalloc(&op->d_crow, total + 1));
   {
@@ -523,7 +567,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   SS_TRY(dalloc(&op->d_cent, op->nnz));
-  k_csr_copy<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
+  if (dense)
+    k_csr_from_dense<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, nbr, st->d_pid, st->d_aoff,
+                                                                               op->d_crow, op->d_cent);
+  else
+    k_csr_copy<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
 
   // ---- connected classes: labels start at each key's root forcing key (so classes that no
   // coincidence merged are final at once); min-propagation with pointer jumping settles merges.
