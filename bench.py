@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
     ap.add_argument("--config-batch", type=int, default=256)
+    ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -103,11 +104,11 @@ def main():
     batch = ss.Batch(probs)     # host inputs packed once, as a caller holding flat arrays would
 
     def run_step(precision="fp32_refine"):
-        st = ss.Stamp.build(batch)
-        op = ss.Operator.build(st, batch)
-        f = st.forcing_vector(batch, dev)
-        u = torch.zeros_like(f)
-        return op.solve(f, u, args.tol, precision, 1000)
+        # the whole path from the packed host inputs to device-resident solutions, the batch split
+        # into parts built and solved concurrently
+        res, infos = ss.solve_batch(batch, args.tol, precision, 1000, 0, parts=args.parts)
+        res.close()
+        return infos
 
     for _ in range(args.warmup):
         run_step()
@@ -295,7 +296,8 @@ def main():
         "config": {"workload": "d=10 torus, 10 a-modes in [-16,16]^10 (1/|w|^2 decay, a>=0.5), 20 f-freqs, "
                                "stamp level 3 (|S|=31220); FP32+refine PCG to rel. residual "
                                f"{args.tol:g}, whole path incl. stamp/index build",
-                   "global_batch": B, "precision": "fp32_refine", "parallelism": "single-gpu"},
+                   "global_batch": B, "precision": "fp32_refine", "parallelism": "single-gpu",
+                   "concurrent_parts": args.parts},
         "solve_only_per_config": per_config,
         "fp64_solve_only_solves_per_s": B / (solve_ms["fp64"] / 1e3),
         "fp32_refine_solve_only_solves_per_s": B / (solve_ms["fp32_refine"] / 1e3),

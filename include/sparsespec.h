@@ -63,6 +63,7 @@ typedef enum { SS_FP64 = 0, SS_FP32_REFINE = 1 } ss_precision;
 
 typedef struct ss_stamp ss_stamp;  /* device-resident stamping sets of a batch of problems       */
 typedef struct ss_op ss_op;        /* device-resident operator(s) L_N built on an ss_stamp        */
+typedef struct ss_batch ss_batch;  /* device-resident solutions of a batch solve                  */
 
 typedef struct {
   int32_t iters;          /* CG iterations (summed over refinement steps for FP32_REFINE)     */
@@ -222,6 +223,35 @@ ss_status ss_engine_poll(ss_engine* e, int32_t cap, int64_t* tags, int32_t* prob
                          ss_solve_info* info, int32_t* n_out);
 ss_status ss_engine_usage(const ss_engine* e, int32_t* n_active_requests, int64_t* bytes);
 void ss_engine_free(ss_engine* e);
+
+/* ss_solve_batch -- Alg. 1, steps 3-5, for n_prob problems of one dimension d from host data:
+ * stamping sets (Sec. 6, Eq. StampSet), operators (Sec. 9, Eq. FiniteGalerkinOperator), right-hand
+ * sides and solves, with the problems split into n_parts contiguous parts (at most n_prob) that are
+ * built and solved concurrently, each by its own host thread on its own stream.
+ *   n_a, a_freqs, a_hat: supp(a_p) and its coefficients, all problems concatenated (host), as for
+ *     ss_build_stamp_batch and ss_build_op (a_hat interleaved complex128).
+ *   n_f, f_freqs, f_hat: F_p and f_hat on it, concatenated (host; f_hat complex128), as for
+ *     ss_build_stamp_batch and ss_stamp_forcing; f_0 must not be listed.
+ *   level[p], tol, prec, max_iter, flags: as for ss_build_stamp_batch, ss_solve_op and ss_build_op.
+ *   info (host, nullable): n_prob entries, filled for every problem that was solved.
+ * On SS_OK, and on SS_ENOCONV / SS_EBREAKDOWN (best iterates kept), *out holds every problem's
+ * u in canonical order; read it with ss_batch_size / ss_batch_solution and free it with
+ * ss_free_batch.  On any other error *out is NULL.  Each problem's u is bitwise the one it gets
+ * when solved alone.  Synchronous. */
+ss_status ss_solve_batch(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
+                         const double* a_hat, const int32_t* n_f, const int16_t* f_freqs,
+                         const double* f_hat, const int32_t* level, double tol, ss_precision prec,
+                         int32_t max_iter, uint32_t flags, int32_t n_parts, ss_batch** out,
+                         ss_solve_info* info);
+
+/* total rows of a batch solution and (host, nullable, n_prob+1 entries) each problem's first row */
+ss_status ss_batch_size(const ss_batch* b, int64_t* n_total, int64_t* offsets);
+
+/* copy the batch solution, all problems concatenated in canonical order, into u (device,
+ * complex128, n_total entries); asynchronous on `stream` */
+ss_status ss_batch_solution(const ss_batch* b, void* u, void* stream);
+
+void ss_free_batch(ss_batch* b);
 
 /* ---------------------------------------------------------------- one shot
  * ss_solve -- Alg. 1 steps 3-5 for one problem from host data.

@@ -18,6 +18,9 @@ struct ss_op {
 struct ss_engine {
   ss::EngineImpl* impl;
 };
+struct ss_batch {
+  ss::BatchImpl* impl;
+};
 
 namespace ss {
 
@@ -265,6 +268,46 @@ void ss_free_op(ss_op* op) {
   if (!op) return;
   free_op_impl(op->impl);
   delete op;
+}
+
+ss_status ss_solve_batch(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
+                         const double* a_hat, const int32_t* n_f, const int16_t* f_freqs, const double* f_hat,
+                         const int32_t* level, double tol, ss_precision prec, int32_t max_iter, uint32_t flags,
+                         int32_t n_parts, ss_batch** out, ss_solve_info* info) {
+  return guarded([&]() -> ss_status {
+    if (!out) return fail(SS_EINVAL, "out is null");
+    *out = nullptr;
+    if (d < 1 || d > 1024) return fail(SS_EINVAL, "d must be in [1, 1024]");
+    if (!(tol > 0) || max_iter < 1) return fail(SS_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (prec != SS_FP64 && prec != SS_FP32_REFINE) return fail(SS_EINVAL, "unknown precision");
+    BatchImpl* impl = nullptr;
+    const ss_status st = batch_solve_impl(n_prob, d, n_a, a_freqs, a_hat, n_f, f_freqs, f_hat, level, tol, prec,
+                                          max_iter, flags, n_parts, info, &impl);
+    if (impl) *out = new ss_batch{impl};
+    return st;
+  });
+}
+
+ss_status ss_batch_size(const ss_batch* b, int64_t* n_total, int64_t* offsets) {
+  return guarded([&]() -> ss_status {
+    if (!b || !b->impl) return fail(SS_EINVAL, "null batch");
+    if (n_total) *n_total = b->impl->offsets.back();
+    if (offsets) std::memcpy(offsets, b->impl->offsets.data(), b->impl->offsets.size() * 8);
+    return SS_OK;
+  });
+}
+
+ss_status ss_batch_solution(const ss_batch* b, void* u, void* stream) {
+  return guarded([&]() -> ss_status {
+    if (!b || !b->impl) return fail(SS_EINVAL, "null batch");
+    return batch_solution_impl(b->impl, u, as_stream(stream));
+  });
+}
+
+void ss_free_batch(ss_batch* b) {
+  if (!b) return;
+  free_batch_impl(b->impl);
+  delete b;
 }
 
 ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double* a_hat, int32_t n_f,

@@ -13,6 +13,7 @@ namespace ss {
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string& msg);
+const char* last_error_cstr();
 ss_status fail(ss_status st, const std::string& msg);
 
 #define SS_HIP(call)                                                               \
@@ -255,6 +256,26 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
                             int64_t* slot_out, hipStream_t stream, const int32_t* probs = nullptr);
 
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
+
+// whole-path batch solve, split into concurrently running parts
+struct BatchImpl {
+  struct Part {
+    int p0 = 0, p1 = 0;              // problems [p0, p1)
+    int64_t n = 0;                   // rows of the part
+    std::vector<int64_t> off;        // part-local problem offsets [p1 - p0 + 1]
+    double2* u = nullptr;            // device, canonical order
+  };
+  int32_t n_prob = 0, d = 0;
+  int device = 0;
+  std::vector<Part> parts;
+  std::vector<int64_t> offsets;      // [n_prob + 1] batch-global canonical offsets
+};
+ss_status batch_solve_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
+                           const double* a_hat, const int32_t* n_f, const int16_t* f_freqs, const double* f_hat,
+                           const int32_t* level, double tol, ss_precision prec, int32_t max_iter, uint32_t flags,
+                           int32_t n_parts, ss_solve_info* info, BatchImpl** out);
+ss_status batch_solution_impl(const BatchImpl* b, void* u, hipStream_t stream);
+void free_batch_impl(BatchImpl* b);
 
 ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* a_freqs,
                         const double* a_hat, uint32_t flags, hipStream_t stream, OpImpl** out);

@@ -28,7 +28,7 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
-            "ss_engine_free"]
+            "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch"]
 
 
 class SolveInfo(C.Structure):
@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_engine_step": [P, i32, pi32],
         "ss_engine_poll": [P, i32, pi64, pi32, C.POINTER(SolveInfo), pi32],
         "ss_engine_usage": [P, pi32, pi64],
+        "ss_solve_batch": [i32, i32, pi32, pi16, pd, pi32, pi16, pd, pi32, dbl, i32, i32, u32, i32, C.POINTER(P),
+                           C.POINTER(SolveInfo)],
+        "ss_batch_size": [P, pi64, pi64],
+        "ss_batch_solution": [P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -87,6 +91,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.ss_free_op.restype = None
     lib.ss_engine_free.argtypes = [P]
     lib.ss_engine_free.restype = None
+    lib.ss_free_batch.argtypes = [P]
+    lib.ss_free_batch.restype = None
     lib.ss_last_error.restype = C.c_char_p
     lib.ss_version.restype = C.c_char_p
     return lib
@@ -364,3 +370,51 @@ def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64",
 
 def version() -> str:
     return _lib.ss_version().decode()
+
+
+class BatchSolution:
+    """Device-resident solutions of ``solve_batch`` (every problem's u in canonical order)."""
+
+    def __init__(self, handle, n_prob: int):
+        self._h = handle
+        n = C.c_int64()
+        self.offsets = np.zeros(n_prob + 1, dtype=np.int64)
+        _check(_lib.ss_batch_size(self._h, C.byref(n), _ptr(self.offsets, C.c_int64)))
+        self.n_total = n.value
+
+    def solution(self, out=None, stream=None):
+        """u of all problems concatenated (complex128 tensor on the current device)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_total, dtype=torch.complex128, device="cuda")
+        _check(_lib.ss_batch_solution(self._h, C.c_void_p(out.data_ptr()), C.c_void_p(_stream(stream))))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.ss_free_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(problems, tol: float, precision="fp64", max_iter: int = 1000, flags: int = 0, parts: int = 4):
+    """Whole path for a batch of one dimension from host data, split into ``parts`` concurrent
+    parts.  Returns (BatchSolution, [info dict per problem]); raises on errors other than
+    non-convergence (then the infos tell which problems missed the tolerance)."""
+    b = _batch(problems)
+    if b.a_hat is None or b.f_hat is None:
+        raise SparseSpecError(SS_EINVAL, "a_hat and f_hat of every problem are needed")
+    info = (SolveInfo * b.n_prob)()
+    h = C.c_void_p()
+    st = _lib.ss_solve_batch(b.n_prob, b.d, _ptr(b.n_a, C.c_int32), _ptr(b.a_freqs, C.c_int16),
+                             _ptr(b.a_hat, C.c_double), _ptr(b.n_f, C.c_int32), _ptr(b.f_freqs, C.c_int16),
+                             _ptr(b.f_hat, C.c_double), _ptr(b.level, C.c_int32), float(tol),
+                             PRECISION[precision], int(max_iter), int(flags), int(parts), C.byref(h), info)
+    if st not in (SS_OK, SS_ENOCONV, SS_EBREAKDOWN) or not h.value:
+        _check(st)
+    return BatchSolution(h, b.n_prob), [i.as_dict() for i in info]

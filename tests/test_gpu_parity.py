@@ -95,6 +95,29 @@ def test_stamp_and_lookup_bit_exact(ss, config):
     assert np.all(got[expect == -1] == -1)
 
 
+def test_solve_batch_parts_equal_alone(ss):
+    # the whole path from host data, split into concurrent parts: each problem's u and counters
+    # are those of its solve alone, and the parts' solutions land at their canonical offsets
+    probs = [workloads.make(2, i, level=2) for i in range(7)]
+    res, infos = ss.solve_batch(probs, 1e-10, "fp32_refine", 1000, 0, parts=3)
+    u = res.solution().cpu().numpy()
+    assert res.n_total == u.shape[0] == res.offsets[-1]
+    for i, p in enumerate(probs):
+        st, op = build(ss, [p])
+        ua, info = gpu_solve(ss, op, f_vector(ss, st, [p]), 1e-10, "fp32_refine", 1000)
+        assert np.array_equal(u[res.offsets[i]:res.offsets[i + 1]], ua), i
+        assert infos[i]["iters"] == info[0]["iters"] and infos[i]["status"] == 0
+    res.close()
+    res1, infos1 = ss.solve_batch(probs[:2], 1e-10, "fp64", 1000, 0, parts=8)   # more parts than problems
+    assert res1.n_total == res.offsets[2] and all(i["status"] == 0 for i in infos1)
+    res1.close()
+    bad = workloads.make(2, 0, level=1)
+    bad.f_freqs = np.concatenate([bad.f_freqs, bad.f_freqs[:1]])
+    bad.f_hat = np.concatenate([bad.f_hat, bad.f_hat[:1]])
+    with pytest.raises(ss.SparseSpecError):
+        ss.solve_batch([probs[0], bad], 1e-10, "fp64", 1000, 0, parts=2)
+
+
 def test_forcing_vector_matches_oracle_slots(ss):
     # f_hat placed at the slots the build recorded for F equals the oracle's f on S^N
     cases = [oracle_case(2, i, level=lv) for i, lv in ((0, 1), (1, 0), (2, 2))]
