@@ -100,16 +100,25 @@ struct ExpandArgs {
   uint64_t* table;        // 2 words per slot
   uint32_t* cpos;         // [n_cand] slot of the candidate's key (region-relative), or kNoSlot
   int32_t* err;
+  const uint8_t* last;    // per key: a-list index of the step that created it (0 for F)
+  const uint8_t* full;    // [n_prob] 1: every candidate of the problem; 0: only j >= last of its key
+  const uint8_t* only;    // [n_prob] or null: a second pass over these problems, others untouched
 };
 
+// In generic position every key of level n has a unique representation f + sum of n entries of
+// the nonzero a-list, and it is generated exactly once when a key is extended only by entries at
+// or after the last one that created it.  A problem runs in that mode until a level yields fewer
+// new keys than the App. A count (a coincidence); that level is then completed by a second pass
+// with every candidate, and the problem keeps full generation from there on.
 __global__ void k_expand(ExpandArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand) return;
   const int64_t i = a.f0 + t / a.smax1;
   const int j = (int)(t % a.smax1);
   const int p = a.pid[i];
+  if (a.only && !a.only[p]) return;
   const int wo = a.woff[p];
-  if (j >= a.woff[p + 1] - wo || a.plevel[p] < a.level) {
+  if (j >= a.woff[p + 1] - wo || a.plevel[p] < a.level || (!a.full[p] && j < (int)a.last[i])) {
     a.cpos[t] = kNoSlot;
     return;
   }
@@ -180,7 +189,7 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
 
 __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                          int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out,
-                         int64_t* root, int64_t* norm_out) {
+                         int64_t* root, int64_t* norm_out, uint8_t* last_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand || !flag[t]) return;
   const int64_t i = a.f0 + t / a.smax1;
@@ -203,6 +212,7 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   hash_out[m] = h;
   pid_out[m] = p;
   lev_out[m] = (uint8_t)a.level;
+  last_out[m] = (uint8_t)j;
   root[m] = root[i];
   const uint64_t s = (uint64_t)a.toff[p] + a.cpos[t];
   a.table[2 * s] = kTagMain | (uint64_t)m;
@@ -656,6 +666,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint64_t* uhash = nullptr;
   int32_t* upid = nullptr;
   uint8_t* ulev = nullptr;
+  uint8_t* ulast = nullptr;
+  uint8_t *d_full = nullptr, *d_only = nullptr;
   int64_t* uroot = nullptr;
   int64_t* unorm = nullptr;
   uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
@@ -663,6 +675,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev); sc.hold(err);
   sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev); sc.hold(uroot); sc.hold(unorm);
+  sc.hold(ulast); sc.hold(d_full); sc.hold(d_only);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
   SS_TRY(dalloc(&wk, wkeys.size()));
@@ -673,6 +686,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&d_fstart, n_prob));
   SS_TRY(dalloc(&d_fcount, n_prob));
   SS_TRY(dalloc(&d_cnt, n_prob));
+  SS_TRY(dalloc(&d_full, n_prob));
+  SS_TRY(dalloc(&d_only, n_prob));
+  SS_HIP(hipMemsetAsync(d_full, 0, n_prob, stream));
   if (!wkeys.empty()) SS_HIP(hipMemcpyAsync(wk, wkeys.data(), wkeys.size() * 2, hipMemcpyHostToDevice, stream));
   if (!whash.empty()) SS_HIP(hipMemcpyAsync(wh, whash.data(), whash.size() * 8, hipMemcpyHostToDevice, stream));
   SS_HIP(hipMemcpyAsync(wo, woff.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
@@ -681,11 +697,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- level 0: F
   int64_t kcap = std::max<int64_t>(nF * 4, 1024);
-  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap, kcap_n = kcap;
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap, kcap_n = kcap, kcap_t = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
   SS_TRY(dalloc(&upid, kcap));
   SS_TRY(dalloc(&ulev, kcap));
+  SS_TRY(dalloc(&ulast, kcap));
   SS_TRY(dalloc(&uroot, kcap));
   SS_TRY(dalloc(&unorm, kcap));
   {
@@ -695,6 +712,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipMemcpyAsync(ukeys, f_freqs, (size_t)nF * d * 2, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemcpyAsync(upid, fpid.data(), nF * 4, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
+    SS_HIP(hipMemsetAsync(ulast, 0, nF, stream));
     k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
     k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash, unorm);
     SS_HIP(hipStreamSynchronize(stream));   // fpid is a host temporary
@@ -717,6 +735,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   }
   int64_t total = nF, f0 = 0, f1 = nF, ccap = 0;
   size_t tmp_bytes = 0;
+  std::vector<uint8_t> full(n_prob, 0), redo(n_prob, 0);   // host copies of d_full, d_only
   for (int n = 1; n <= max_level; ++n) {
     const int64_t n_front = f1 - f0;
     if (n_front == 0) break;
@@ -727,6 +746,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&uhash, &kcap_h, need, total, 1, stream));
     SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
     SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
+    SS_TRY(grow(&ulast, &kcap_t, need, total, 1, stream));
     SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
     SS_TRY(grow(&unorm, &kcap_n, need, total, 1, stream));
     // slots in use after this level: at most the worst case (every candidate new) and at most
@@ -753,28 +773,55 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       SS_TRY(dalloc(&idx, ccap));
     }
     ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_toff, st->d_tmask,
-                  st->d_table, cpos, err};
+                  st->d_table, cpos, err, ulast, d_full, nullptr};
     const unsigned cg = grid_for(n_cand);
-    k_expand<<<cg, kBlock, 0, stream>>>(ea);
-    k_winners<<<cg, kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
-    size_t need_tmp = 0;
-    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
-    if (need_tmp > tmp_bytes) {
-      dfree(tmp);
-      SS_HIP(pool_alloc((void**)&tmp, need_tmp));
-      tmp_bytes = need_tmp;
-    }
-    SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
-    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot, unorm);
     SS_HIP(hipMemcpyAsync(d_fstart, fstart.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
     SS_HIP(hipMemcpyAsync(d_fcount, fcount.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
-    k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, smax1, d_fstart, d_fcount, idx, flag, d_cnt);
     std::vector<int64_t> added(n_prob);
-    int32_t herr = 0;
-    SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
-    if (herr) return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
+    // winners, their positions and the new keys per problem of the candidates in cpos
+    auto count_level = [&]() -> ss_status {
+      k_winners<<<cg, kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
+      size_t need_tmp = 0;
+      SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
+      if (need_tmp > tmp_bytes) {
+        dfree(tmp);
+        SS_HIP(pool_alloc((void**)&tmp, need_tmp));
+        tmp_bytes = need_tmp;
+      }
+      SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
+      k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, smax1, d_fstart, d_fcount, idx, flag,
+                                                              d_cnt);
+      int32_t herr = 0;
+      SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
+      SS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream));
+      SS_HIP(hipStreamSynchronize(stream));
+      if (herr) return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
+      return SS_OK;
+    };
+    k_expand<<<cg, kBlock, 0, stream>>>(ea);
+    SS_TRY(count_level());
+    // a problem generating once per key that found fewer new keys than the App. A count met a
+    // coincidence: complete the level with every candidate, and keep doing so
+    bool again = false;
+    for (int p = 0; p < n_prob; ++p) {
+      redo[p] = 0;
+      if (full[p] || level[p] < n) continue;
+      const int64_t bound = std::llround(app_a_count(n_f[p], s_of[p], n)) -
+                            std::llround(app_a_count(n_f[p], s_of[p], n - 1));
+      if (added[p] != bound) {
+        full[p] = redo[p] = 1;
+        again = true;
+      }
+    }
+    if (again) {
+      SS_HIP(hipMemcpyAsync(d_full, full.data(), n_prob, hipMemcpyHostToDevice, stream));
+      SS_HIP(hipMemcpyAsync(d_only, redo.data(), n_prob, hipMemcpyHostToDevice, stream));
+      ExpandArgs eb = ea;
+      eb.only = d_only;
+      k_expand<<<cg, kBlock, 0, stream>>>(eb);
+      SS_TRY(count_level());
+    }
+    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot, unorm, ulast);
     f0 = total;
     for (int p = 0; p < n_prob; ++p) {
       fstart[p] = total;
