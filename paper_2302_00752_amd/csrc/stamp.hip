@@ -264,7 +264,7 @@ __global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys, con
                          uint64_t* __restrict__ out) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const int64_t s = perm[r];
+  const int64_t s = perm ? perm[r] : r;
   const int16_t* k = keys + s * d;
   uint64_t v = 0;
   for (int q = f0; q < f1; ++q) {
@@ -273,6 +273,12 @@ __global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys, con
     v |= (uint64_t)(uint32_t)(val - f.lo) << f.shift;
   }
   out[r] = v;
+}
+
+__global__ void k_gather_u64(int64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ src,
+                             uint64_t* __restrict__ dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) dst[r] = src[perm[r]];
 }
 
 __global__ void k_iota_u32(int64_t n, uint32_t* p) {
@@ -290,16 +296,22 @@ __global__ void k_permute_keys(int64_t n, int d, const uint32_t* __restrict__ pe
   keys[g] = ukeys[(int64_t)perm[r] * d + (g - r * d)];
 }
 
-__global__ void k_permute_meta(int64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ uhash,
-                               const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
-                               const int64_t* __restrict__ unorm, uint64_t* hash, int32_t* pid, uint8_t* lev,
+// problem id and level gathered; hash and |k|^2 recomputed from the sorted key row
+__global__ void k_permute_meta(int64_t n, int d, const uint32_t* __restrict__ perm, const int32_t* __restrict__ upid,
+                               const uint8_t* __restrict__ ulev, const int16_t* __restrict__ keys,
+                               const uint64_t* __restrict__ z, uint64_t* hash, int32_t* pid, uint8_t* lev,
                                int64_t* norm, uint32_t* inv, unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = 0;
   if (r < n) {
     const int64_t s = perm[r];
-    nn = unorm[s];
-    hash[r] = uhash[s];
+    uint64_t h = 0;
+    const int16_t* k = keys + r * d;
+    for (int t = 0; t < d; ++t) {
+      h += (uint64_t)(int64_t)k[t] * z[t];
+      nn += (int64_t)k[t] * k[t];
+    }
+    hash[r] = h;
     pid[r] = upid[s];
     lev[r] = ulev[s];
     norm[r] = nn;
@@ -892,9 +904,18 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k64, k64b, perm, perm2, total, 0, 64, stream));
     SS_HIP(pool_alloc((void**)&tmp, tmp_bytes));
   }
+  uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
+  sc.hold(wq);
+  if (passes.size() > 1) SS_TRY(dalloc(&wq, total));
   for (size_t q = 0; q < passes.size(); ++q) {
-    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, perm, d_fields, passes[q].first,
-                                                     passes[q].second, k64);
+    if (q == 0) {
+      k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, passes[q].first,
+                                                       passes[q].second, k64);
+    } else {
+      k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, passes[q].first,
+                                                       passes[q].second, wq);
+      k_gather_u64<<<grid_for(total), kBlock, 0, stream>>>(total, perm, wq, k64);
+    }
     size_t tb = tmp_bytes;
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, pass_bits[q], stream));
     std::swap(perm, perm2);
@@ -912,8 +933,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   unsigned long long* d_maxn = (unsigned long long*)k64;
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
   k_permute_keys<<<grid_for(total * d), kBlock, 0, stream>>>(total, d, perm, ukeys, st->d_keys);
-  k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uhash, upid, ulev, unorm, st->d_hash,
-                                                         st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, upid, ulev, st->d_keys, st->d_coef,
+                                                         st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   // the forcing frequencies are the first nF unsorted keys, in the order given
   st->n_f = nF;
