@@ -322,7 +322,8 @@ __global__ void k_class_min(int64_t n_cls, int64_t total, const int64_t* __restr
   for (int64_t q = q0 + lane; q < q1; q += 64) comp[order[q]] = (int32_t)(m - base);
 }
 
-// sort key (problem, class, 63 - row length, canonical slot) packed with `lb` bits per local index
+// sort key (problem, class, 63 - row length) packed with `lb` bits per local index; the rows
+// come in canonical order and the radix sort is stable, so the canonical slot breaks ties
 __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ pid,
                             const int64_t* __restrict__ rowoff, const int64_t* __restrict__ label,
                             const int64_t* __restrict__ rowlen, uint64_t* __restrict__ key,
@@ -330,9 +331,8 @@ __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ p
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r];
-  const uint64_t local = (uint64_t)(r - rowoff[p]);
   const uint64_t cls = (uint64_t)(label[r] - rowoff[p]);
-  key[r] = ((((((uint64_t)p << lb) | cls) << 6) | (uint64_t)(63 - rowlen[r])) << lb) | local;
+  key[r] = ((((uint64_t)p << lb) | cls) << 6) | (uint64_t)(63 - rowlen[r]);
   val[r] = (uint32_t)r;
 }
 
@@ -614,7 +614,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   while ((int64_t(1) << lb) < max_rows) ++lb;
   int pb = 0;
   while ((1 << pb) < n_prob) ++pb;
-  const int key_bits = pb + 2 * lb + 6;   // <= 14 + 44 + 6
+  const int key_bits = pb + lb + 6;   // <= 14 + 22 + 6
   k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, label, rowlen, ek, ev);
   {
     size_t tb = 0;
