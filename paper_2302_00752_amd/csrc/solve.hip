@@ -750,6 +750,39 @@ __device__ inline void unit_mv(const UDesc& A, const uint32_t* sptr, uint32_t eb
   }
 }
 
+// FP64 q = L v over the unit from window-local columns and a-table indices kept in LDS (the
+// coefficient formed as sell_row forms it); padding entries carry j = kNullJ
+template <typename NormT>
+__device__ inline void unit_mv_cj(const uint32_t* sptr, const uint16_t* col, const uint8_t* jj, int ns,
+                                  const double2* As, const NormT* nus, const NormT* nw, const double2* vw,
+                                  const NormT* nk, double2* acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    const int sw = wave + k * kUnitWaves;
+    if (sw < ns) {
+      const uint32_t base = sptr[sw];
+      const uint32_t width = (sptr[sw + 1] - base) / kSlice;
+      double ar = 0, ai = 0;
+      for (uint32_t q = 0; q < width; ++q) {
+        const uint32_t i = base + q * kSlice + lane;
+        const uint32_t j = jj[i];
+        if (j != (uint32_t)kNullJ) {
+          const int c = col[i];
+          const NormT I = nk[k] + nw[c] - nus[j];
+          const double2 a = As[j];
+          const double2 x = vw[c];
+          const double fi = (double)I;
+          const double cr = fi * a.x, ci = fi * a.y;
+          ar += cr * x.x - ci * x.y;
+          ai += cr * x.y + ci * x.x;
+        }
+      }
+      acc[k] = make_double2(ar, ai);
+    }
+  }
+}
+
 // FP32 q = L v from per-entry coefficients and window-local columns kept in LDS (padding
 // entries hold a zero coefficient)
 __device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, const uint16_t* col, int ns,
@@ -788,13 +821,14 @@ __device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, co
 
 // Where the matvecs find the operator: CM_STREAM reads the SELL entries from memory each time;
 // CM_ENTRIES keeps the unit's entries in LDS; CM_COEF (FP32 + refinement) keeps per-entry FP32
-// coefficients and window-local columns in LDS for the correction solves (the FP64 residuals
-// stream the entries).
+// coefficients, window-local columns and a-table indices in LDS (the correction solves use the
+// coefficients, the FP64 residuals the columns and indices).
 enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2 };
 // entries whose FP32 coefficients and columns (10 bytes each) fit the LDS beside the static
 // arrays (int32 / int64 norms)
-constexpr int kCoefEntries32 = 11264;
-constexpr int kCoefEntries64 = 10752;
+constexpr int kCoefBytes = 11;   // FP32 coefficient, 16-bit column, 8-bit a-table index
+constexpr int kCoefEntries32 = 10880;
+constexpr int kCoefEntries64 = 10112;
 static_assert(kCoefEntries64 <= kCoefEntries32 && kCoefEntries32 <= kUnitEntries, "cache sizes");
 
 template <typename NormT, bool FP64, int CM>
@@ -803,7 +837,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   __shared__ __align__(16) double2 s_win[kWinRows];   // search direction / iterate window
   __shared__ NormT s_norm[kWinRows];
   __shared__ uint32_t s_sptr[kWinRows / kSlice + 1];
-  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF: coefficients, columns
+  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF: coefficients, columns, j
   __shared__ double2 s_A64[64];
   __shared__ float2 s_A32[64];
   __shared__ NormT s_nu[64];
@@ -856,6 +890,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   }
   float2* s_coef = reinterpret_cast<float2*>(s_ent);
   uint16_t* s_col = reinterpret_cast<uint16_t*>(s_coef + n_ent);
+  uint8_t* s_j = reinterpret_cast<uint8_t*>(s_col + n_ent);
   if (CM == CM_COEF) __syncthreads();   // norms, |w|^2, tables and slice offsets staged
   if (CM != CM_STREAM) {
     // entries in order, U loads in flight per thread; CM_COEF turns each into its FP32
@@ -895,6 +930,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
           }
           s_coef[i] = cf;
           s_col[i] = c;
+          s_j[i] = (uint8_t)j;
         }
       }
     }
@@ -928,7 +964,10 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = x[k];
       __syncthreads();
       double2 acc[kUnitSlots];
-      unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
+      if (CM == CM_COEF)
+        unit_mv_cj<NormT>(s_sptr, s_col, s_j, ns, s_A64, s_nu, s_norm, s_win, nk, acc);
+      else
+        unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
 #pragma unroll
       for (int k = 0; k < kUnitSlots; ++k) {
         const double2 fk = fv[k];
@@ -1363,7 +1402,7 @@ struct UnitBatch {
         const int g = (wide ? 5 : 0) + (fp32 ? 2 : 0) + mode;
         where.emplace_back(g, (int)lists[g].size());
         lists[g].push_back(make_int4(i, un.y, un.z, un.w));
-        if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * (mode == CM_COEF ? 10 : 4));
+        if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * (mode == CM_COEF ? kCoefBytes : 4));
       }
       uoff.push_back((int32_t)where.size());
     }
