@@ -891,7 +891,14 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   float2* s_coef = reinterpret_cast<float2*>(s_ent);
   uint16_t* s_col = reinterpret_cast<uint16_t*>(s_coef + n_ent);
   uint8_t* s_j = reinterpret_cast<uint8_t*>(s_col + n_ent);
-  if (CM == CM_COEF) __syncthreads();   // norms, |w|^2, tables and slice offsets staged
+  // CM_COEF: the slice of every group of 64 entries (a slice's entries are whole groups)
+  __shared__ uint8_t s_gslice[kCoefEntries32 / kSlice + 1];
+  if (CM == CM_COEF) {
+    __syncthreads();   // slice offsets staged
+    if (tid < ns)
+      for (uint32_t g = s_sptr[tid] / kSlice; g < s_sptr[tid + 1] / kSlice; ++g) s_gslice[g] = (uint8_t)tid;
+    __syncthreads();   // norms, |w|^2, tables and the group map staged
+  }
   if (CM != CM_STREAM) {
     // entries in order, U loads in flight per thread; CM_COEF turns each into its FP32
     // coefficient (|k|^2 + |l|^2 - |w_j|^2) 2 pi^2 a_j, formed as the on-the-fly FP32 matvec
@@ -911,17 +918,12 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         if (CM == CM_ENTRIES) {
           s_ent[i] = v[u];
         } else {
-          int lo = 0, hi = ns;   // the slice holding entry i: s_sptr[lo] <= i < s_sptr[lo + 1]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_sptr[mid] <= i) lo = mid;
-            else hi = mid;
-          }
+          const int sl = s_gslice[i / kSlice];   // entry (q, lane) of a slice sits at base + q * 64 + lane
           const uint32_t j = v[u] >> kColBits;
           float2 cf = make_float2(0.f, 0.f);
           uint16_t c = 0;
           if (j != (uint32_t)kNullJ) {
-            const NormT nkr = s_norm[lo * kSlice + (int)((i - s_sptr[lo]) % kSlice)];
+            const NormT nkr = s_norm[sl * kSlice + (int)(i % kSlice)];
             c = (uint16_t)((int)(v[u] & kColMask) - w0);
             const NormT I = nkr + s_norm[c] - s_nu[j];
             const float fi = (float)I;
