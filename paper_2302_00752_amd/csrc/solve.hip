@@ -783,10 +783,11 @@ __device__ inline void unit_mv_cj(const uint32_t* sptr, const uint16_t* col, con
   }
 }
 
-// FP32 q = L v from per-entry coefficients and window-local columns kept in LDS (padding
-// entries hold a zero coefficient)
-__device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, const uint16_t* col, int ns,
-                                    const float2* vw, float2* acc) {
+// FP32 q = L v from per-entry integer brackets (as FP32), window-local columns and a-table
+// indices kept in LDS; the coefficient fi * a_j is formed as sell_row forms it (padding entries
+// hold fi = 0, column 0 and the null index, whose table entry is 0)
+__device__ inline void unit_mv_coef(const uint32_t* sptr, const float* fiv, const uint16_t* col, const uint8_t* jj,
+                                    int ns, const float2* As, const float2* vw, float2* acc) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k) {
@@ -798,21 +799,27 @@ __device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, co
       uint32_t i = base + lane;
       uint32_t q = 0;
       for (; q + 4 <= width; q += 4, i += 4 * kSlice) {
-        float2 c[4], x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = coef[i + u * kSlice];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = vw[col[i + u * kSlice]];
+        float fi[4];
+        float2 a[4], x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          ar += c[u].x * x[u].x - c[u].y * x[u].y;
-          ai += c[u].x * x[u].y + c[u].y * x[u].x;
+          fi[u] = fiv[i + u * kSlice];
+          a[u] = As[jj[i + u * kSlice]];
+          x[u] = vw[col[i + u * kSlice]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float cr = fi[u] * a[u].x, ci = fi[u] * a[u].y;
+          ar += cr * x[u].x - ci * x[u].y;
+          ai += cr * x[u].y + ci * x[u].x;
         }
       }
       for (; q < width; ++q, i += kSlice) {
-        const float2 c = coef[i], x = vw[col[i]];
-        ar += c.x * x.x - c.y * x.y;
-        ai += c.x * x.y + c.y * x.x;
+        const float f = fiv[i];
+        const float2 a = As[jj[i]], x = vw[col[i]];
+        const float cr = f * a.x, ci = f * a.y;
+        ar += cr * x.x - ci * x.y;
+        ai += cr * x.y + ci * x.x;
       }
       acc[k] = make_float2(ar, ai);
     }
@@ -826,10 +833,10 @@ __device__ inline void unit_mv_coef(const uint32_t* sptr, const float2* coef, co
 enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2 };
 // entries whose FP32 coefficients and columns (10 bytes each) fit the LDS beside the static
 // arrays (int32 / int64 norms)
-constexpr int kCoefBytes = 11;   // FP32 coefficient, 16-bit column, 8-bit a-table index
-constexpr int kCoefEntries32 = 10880;
-constexpr int kCoefEntries64 = 10112;
-static_assert(kCoefEntries64 <= kCoefEntries32 && kCoefEntries32 <= kUnitEntries, "cache sizes");
+constexpr int kCoefBytes = 7;   // FP32 bracket, 16-bit column, 8-bit a-table index
+constexpr int kCoefEntries32 = 17152;
+constexpr int kCoefEntries64 = 15936;
+static_assert(kUnitEntries <= kCoefEntries64 && kCoefEntries64 <= kCoefEntries32, "units must fit every cache");
 
 template <typename NormT, bool FP64, int CM>
 __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
@@ -888,8 +895,8 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       if (nk[k] > 0) x[k] = A.u[cr[k]];
     }
   }
-  float2* s_coef = reinterpret_cast<float2*>(s_ent);
-  uint16_t* s_col = reinterpret_cast<uint16_t*>(s_coef + n_ent);
+  float* s_fi = reinterpret_cast<float*>(s_ent);
+  uint16_t* s_col = reinterpret_cast<uint16_t*>(s_fi + n_ent);
   uint8_t* s_j = reinterpret_cast<uint8_t*>(s_col + n_ent);
   // CM_COEF: the slice of every group of 64 entries (a slice's entries are whole groups)
   __shared__ uint8_t s_gslice[kCoefEntries32 / kSlice + 1];
@@ -920,17 +927,14 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         } else {
           const int sl = s_gslice[i / kSlice];   // entry (q, lane) of a slice sits at base + q * 64 + lane
           const uint32_t j = v[u] >> kColBits;
-          float2 cf = make_float2(0.f, 0.f);
+          float fi = 0.f;
           uint16_t c = 0;
           if (j != (uint32_t)kNullJ) {
             const NormT nkr = s_norm[sl * kSlice + (int)(i % kSlice)];
             c = (uint16_t)((int)(v[u] & kColMask) - w0);
-            const NormT I = nkr + s_norm[c] - s_nu[j];
-            const float fi = (float)I;
-            const float2 a = s_A32[j];
-            cf = make_float2(fi * a.x, fi * a.y);
+            fi = (float)(nkr + s_norm[c] - s_nu[j]);
           }
-          s_coef[i] = cf;
+          s_fi[i] = fi;
           s_col[i] = c;
           s_j[i] = (uint8_t)j;
         }
@@ -1078,7 +1082,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         while (true) {
           float2 q[kUnitSlots];
           if (CM == CM_COEF)
-            unit_mv_coef(s_sptr, s_coef, s_col, ns, s_win32, q);
+            unit_mv_coef(s_sptr, s_fi, s_col, s_j, ns, s_A32, s_win32, q);
           else
             unit_mv<NormT, float2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A32, s_nu, s_norm, s_win32, nk, q);
           double vpq = 0;

@@ -42,7 +42,7 @@ constexpr int kSolveBlock = 512;      // threads per block of the matvec / CG ke
 constexpr int kSolveWaves = kSolveBlock / kSlice;
 constexpr int kWinRows = 2048;        // rows of x / |k|^2 a block stages in LDS
 constexpr int kMaxItemSlices = 64;    // slices per work item (window items)
-constexpr int kUnitEntries = 24576;   // SELL entries a class-resident solve unit keeps in LDS
+constexpr int kUnitEntries = 15936;   // SELL entries of a class-resident solve unit kept in LDS
 constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;
 constexpr int kMaxProblems = (1 << 14) - 1;
 
