@@ -962,8 +962,9 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   }
 
   // r = f - L x (FP64), |r|^2
+  double rzr = 0;   // <r, D^-1 r> of the last residual, reduced with |r|^2
   auto residual = [&]() -> double {
-    double v = 0;
+    double v = 0, vz = 0;
     if (warm || outer > 0) {
 #pragma unroll
       for (int k = 0; k < kUnitSlots; ++k)
@@ -984,8 +985,14 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       for (int k = 0; k < kUnitSlots; ++k) r[k] = fv[k];
     }
 #pragma unroll
-    for (int k = 0; k < kUnitSlots; ++k) v += r[k].x * r[k].x + r[k].y * r[k].y;
-    return block_sum2(v, 0.0, red).x;   // its barriers also end every read of the window
+    for (int k = 0; k < kUnitSlots; ++k) {
+      const double t = r[k].x * r[k].x + r[k].y * r[k].y;
+      v += t;
+      vz += t * dinv[k];
+    }
+    const double2 sv = block_sum2(v, vz, red);   // its barriers also end every read of the window
+    rzr = sv.y;
+    return sv.x;
   };
 
   if (ff == 0) {
@@ -1061,8 +1068,8 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       const double scale = sqrt(rr), inv = 1.0 / scale;
       ++outer;
       // correction solve L d = r / |r| in FP32 (FP64 inner products), d = 0 to start
+      // its starting scalars are those of the FP64 residual, scaled (no further reduction)
       float2 r32[kUnitSlots], p32[kUnitSlots], d32[kUnitSlots];
-      double rz = 0, r0 = 0;
 #pragma unroll
       for (int k = 0; k < kUnitSlots; ++k) {
         r32[k] = make_float2((float)(r[k].x * inv), (float)(r[k].y * inv));
@@ -1070,15 +1077,12 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         const float di = (float)dinv[k];
         p32[k] = make_float2(di * r32[k].x, di * r32[k].y);
         if (wave + k * kUnitWaves < ns) s_win32[(wave + k * kUnitWaves) * kSlice + lane] = p32[k];
-        const double t = (double)r32[k].x * r32[k].x + (double)r32[k].y * r32[k].y;
-        rz += t * dinv[k];
-        r0 += t;
       }
-      const double2 s0v = block_sum2(rz, r0, red);
-      double rho = s0v.x;
-      const double ff_in = s0v.y;
+      __syncthreads();
+      double rho = rzr * inv * inv;
+      const double ff_in = 1.0;
       int it = 0;
-      if (!(s0v.y <= tol2_in * ff_in)) {
+      {
         while (true) {
           float2 q[kUnitSlots];
           if (CM == CM_COEF)
