@@ -827,9 +827,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     }
   }
   op->unit_entries.resize(op->units.size());
+  op->unit_ebase.resize(op->units.size());
   for (size_t i = 0; i < op->units.size(); ++i) {
     const int4 un = op->units[i];
     op->unit_entries[i] = (int32_t)(sptr_h[un.y + un.z] - sptr_h[un.y]);
+    op->unit_ebase[i] = sptr_h[un.y];
   }
   if (!op->units.empty()) {
     SS_TRY(dalloc(&op->d_units, op->units.size()));

@@ -44,7 +44,11 @@ namespace ss {
 namespace {
 
 constexpr double kFourPi2 = 4.0 * M_PI * M_PI;
-constexpr double kInnerTol = 1e-5;   // FP32 correction solves
+// A correction solve (FP32) stops once its residual is below kInnerTol relative to its right-hand
+// side, or earlier when kInnerMargin times the reduction that the outer target still asks for is
+// reached: a last correction then does no more than the FP64 stop test needs.
+constexpr double kInnerTol = 1e-5;
+constexpr double kInnerMargin = 0.5;
 constexpr int kMaxOuter = 30;
 
 enum { MV_PLAIN = 0, MV_DOT = 1, MV_RESID = 2 };
@@ -345,7 +349,7 @@ __device__ void dir_body(const Desc& D, int4 wk, int w, const double* part_rz, d
   const double rr = range_sum(part_rz, 1, D.wb, D.we, red);
   const int it = cs->iter;
   const double beta = rz / cs->rho[it & 1];
-  const double tol2 = D.prec == SS_FP64 ? D.tol2 : D.tol2_in;
+  const double tol2 = D.prec == SS_FP64 ? D.tol2 : cs->tin2;
   const bool conv = rr <= tol2 * cs->ff;
   const bool out_of_iters = it + 1 >= D.max_iter;
   if (w == D.wb && threadIdx.x == 0) {
@@ -457,7 +461,7 @@ __global__ void k_cg_scalars(const Desc* __restrict__ descs, int n_desc, const d
     cs->iters = 0;
     cs->start = 0;
     cs->status = SS_OK;
-    const double tol2 = D.prec == SS_FP64 ? D.tol2 : D.tol2_in;
+    const double tol2 = D.prec == SS_FP64 ? D.tol2 : cs->tin2;
     cs->done = rr <= tol2 * cs->ff ? 1 : 0;
   }
 }
@@ -512,6 +516,7 @@ __global__ void k_outer_scalars(const Desc* __restrict__ descs, int n_desc, cons
   }
   ps->scale = sqrt(rr);
   ps->outer += 1;
+  D.ps_in->tin2 = fmax(D.tol2_in, kInnerMargin * kInnerMargin * D.tol2 * ff / rr);
   D.ps_in->start = 1;
 }
 
@@ -660,32 +665,53 @@ struct UDesc {
 struct UnitArgs {
   const UDesc* descs;
   const int4* ulist;
+  const uint2* uent;             // per unit: first SELL entry (operator-global), entries
   int32_t ubase;                 // first unit of this launch within ulist
   UnitOut* out;                  // per unit (ulist order)
 };
 
-// 64-bit DPP move (the two halves moved alike)
-template <int CTRL>
+// 64-bit DPP move (the two halves moved alike); lanes of rows outside ROW_MASK get 0
+template <int CTRL, int ROW_MASK = 0xf>
 __device__ inline double dpp_d(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false));
 }
 
-// Sum over the wavefront, every lane gets the same value: pairs, quads, half rows and rows by
-// DPP lane moves within each row of 16 lanes, then across the four rows by permutes.
-__device__ inline double wave_sum_dpp(double v) {
+// the value of lane L, as a wave-uniform scalar
+template <int L>
+__device__ inline double readlane_d(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), L),
+                          __builtin_amdgcn_readlane(__double2loint(v), L));
+}
+
+// Sum within each row of 16 lanes, every lane of the row gets it: pairs, quads, half rows and
+// rows by DPP lane moves.
+__device__ inline double row_sum_dpp(double v) {
   v += dpp_d<0xb1>(v);    // quad_perm [1,0,3,2]
   v += dpp_d<0x4e>(v);    // quad_perm [2,3,0,1]
   v += dpp_d<0x141>(v);   // row_half_mirror
   v += dpp_d<0x140>(v);   // row_mirror
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
   return v;
 }
 
-// sum of (a, b) over the block, fixed order, returned to every thread
+// Sum over the wavefront as a scalar: row sums; rows 1 and 3 add the last lane of rows 0 and 2
+// (row broadcast 15), then rows 2 and 3 add the last lane of row 1 (row broadcast 31), which
+// leaves the total in lane 63.
+__device__ inline double wave_sum_dpp(double v) {
+  v = row_sum_dpp(v);
+  v += dpp_d<0x142, 0xa>(v);
+  v += dpp_d<0x143, 0xc>(v);
+  return readlane_d<63>(v);
+}
+
+// Sum of (a, b) over the block, fixed order, returned to every thread.  red holds the 2 x 16
+// wavefront totals.  One barrier: the caller alternates between two such buffers, and a buffer
+// is written again only after the barrier of the next reduction, which every thread reaches
+// after its reads of this one.  The barrier also orders every LDS access before the call
+// against every one after it.
 __device__ inline double2 block_sum2(double a, double b, double* red) {
+  static_assert(kUnitWaves == 16, "the second stage sums one row of 16 lanes per value");
   a = wave_sum_dpp(a);
   b = wave_sum_dpp(b);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -694,14 +720,9 @@ __device__ inline double2 block_sum2(double a, double b, double* red) {
     red[kUnitWaves + wave] = b;
   }
   __syncthreads();
-  double sa = 0, sb = 0;
-#pragma unroll
-  for (int w = 0; w < kUnitWaves; ++w) {
-    sa += red[w];
-    sb += red[kUnitWaves + w];
-  }
-  __syncthreads();
-  return make_double2(sa, sb);
+  // row 0 sums the totals of a, row 1 those of b
+  const double t = row_sum_dpp(lane < 2 * kUnitWaves ? red[lane] : 0.0);
+  return make_double2(readlane_d<0>(t), readlane_d<16>(t));
 }
 
 // Row of a slice whose entries sit in LDS (base relative to the unit's first entry); the same
@@ -848,45 +869,59 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   __shared__ double2 s_A64[64];
   __shared__ float2 s_A32[64];
   __shared__ NormT s_nu[64];
-  __shared__ double red[2 * kUnitWaves];
+  __shared__ double s_red[2][2 * kUnitWaves];   // reductions alternate between the two
+  int rsel = 0;
+  auto red_next = [&]() -> double* { rsel ^= 1; return s_red[rsel]; };
   float2* s_win32 = reinterpret_cast<float2*>(s_win);
   const int ui = Args.ubase + blockIdx.x;
   const int4 un = Args.ulist[ui];
+  const uint2 ue = Args.uent[ui];
   const UDesc& A = Args.descs[un.x];
   const int s0 = un.y, ns = un.z, w0 = un.w;
+  const uint32_t ebase = ue.x, n_ent = ue.y;
   const int64_t E0 = (int64_t)s0 * kSlice;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const NormT* normg = (const NormT*)A.norm;
   const double a0 = A.a0;
   const double tol2_in = kInnerTol * kInnerTol;
-  // set-up, ordered so that independent loads are in flight together: tables, norms, slice
-  // offsets and the own rows' norms and slots first; then the entries (and the own rows' f
-  // and x0, which are awaited only after them)
-  if (tid < 64) {
-    s_A64[tid] = A.A64[tid];
-    s_A32[tid] = A.A32[tid];
-    s_nu[tid] = (NormT)A.nu[tid];
-  }
-  for (int i = tid; i < ns * kSlice; i += kUnitThreads) s_norm[i] = normg[E0 + i];
-  const uint32_t ebase = A.sptr[s0];
-  const uint32_t n_ent = A.sptr[s0 + ns] - ebase;
-  if (tid <= ns) s_sptr[tid] = A.sptr[s0 + tid] - ebase;
-  // the block's own rows: slice wave + k * kUnitWaves, lane
+  // Set-up.  Every load whose address is known at the start is issued first, together: the own
+  // rows' |k|^2 and canonical slots, the unit's entries, the tables and the slice offsets; the
+  // own rows' f and x0 follow once the slots arrive.  The own rows (slice wave + k * kUnitWaves,
+  // lane) are window rows tid + k * kUnitThreads, so their |k|^2 also fill the LDS norms.
   NormT nk[kUnitSlots];
   double dinv[kUnitSlots];
   int32_t cr[kUnitSlots];   // canonical slot (rows of a batch are below 2^31), -1 for padding
   double2 x[kUnitSlots], r[kUnitSlots], fv[kUnitSlots];
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k) {
-    const int sw = wave + k * kUnitWaves;
     nk[k] = 0;
     cr[k] = -1;
-    if (sw < ns) {
-      const int64_t e = E0 + sw * kSlice + lane;
+    if (wave + k * kUnitWaves < ns) {
+      const int64_t e = E0 + tid + k * kUnitThreads;
       nk[k] = normg[e];
       cr[k] = (int32_t)A.exec2canon[e];
     }
   }
+  constexpr int kCap = CM == CM_COEF ? (sizeof(NormT) == 8 ? kCoefEntries64 : kCoefEntries32) : kUnitEntries;
+  constexpr int kStage = CM == CM_STREAM ? 1 : (kCap + kUnitThreads - 1) / kUnitThreads;
+  uint32_t v[kStage];
+  if (CM != CM_STREAM) {
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const uint32_t i = tid + u * kUnitThreads;
+      v[u] = i < n_ent ? A.sent[ebase + i] : 0u;
+    }
+  }
+  double2 tA64 = make_double2(0, 0);
+  float2 tA32 = make_float2(0.f, 0.f);
+  NormT tnu = 0;
+  uint32_t tsp = 0;
+  if (tid < 64) {
+    tA64 = A.A64[tid];
+    tA32 = A.A32[tid];
+    tnu = (NormT)A.nu[tid];
+  }
+  if (tid <= ns) tsp = A.sptr[s0 + tid] - ebase;   // ns <= 32: wavefront 0 only
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k) {
     fv[k] = x[k] = make_double2(0, 0);
@@ -895,49 +930,52 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       if (nk[k] > 0) x[k] = A.u[cr[k]];
     }
   }
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k)
+    if (wave + k * kUnitWaves < ns) s_norm[tid + k * kUnitThreads] = nk[k];
+  if (tid < 64) {
+    s_A64[tid] = tA64;
+    s_A32[tid] = tA32;
+    s_nu[tid] = tnu;
+  }
+  if (tid <= ns) s_sptr[tid] = tsp;
   float* s_fi = reinterpret_cast<float*>(s_ent);
   uint16_t* s_col = reinterpret_cast<uint16_t*>(s_fi + n_ent);
   uint8_t* s_j = reinterpret_cast<uint8_t*>(s_col + n_ent);
   // CM_COEF: the slice of every group of 64 entries (a slice's entries are whole groups)
   __shared__ uint8_t s_gslice[kCoefEntries32 / kSlice + 1];
-  if (CM == CM_COEF) {
-    __syncthreads();   // slice offsets staged
-    if (tid < ns)
-      for (uint32_t g = s_sptr[tid] / kSlice; g < s_sptr[tid + 1] / kSlice; ++g) s_gslice[g] = (uint8_t)tid;
-    __syncthreads();   // norms, |w|^2, tables and the group map staged
+  if (CM == CM_COEF && wave == 0) {
+    const uint32_t next = __shfl_down(tsp, 1, 64);
+    if (lane < ns)
+      for (uint32_t g = tsp / kSlice; g < next / kSlice; ++g) s_gslice[g] = (uint8_t)lane;
   }
-  if (CM != CM_STREAM) {
-    // entries in order, U loads in flight per thread; CM_COEF turns each into its FP32
-    // coefficient (|k|^2 + |l|^2 - |w_j|^2) 2 pi^2 a_j, formed as the on-the-fly FP32 matvec
-    // forms it, and its window-local column
-    constexpr int U = 8;
-    for (uint32_t i0 = tid; i0 < n_ent; i0 += U * kUnitThreads) {
-      uint32_t v[U];
+  if (CM == CM_ENTRIES) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t i = i0 + u * kUnitThreads;
-        v[u] = i < n_ent ? A.sent[ebase + i] : 0u;
-      }
+    for (int u = 0; u < kStage; ++u) {
+      const uint32_t i = tid + u * kUnitThreads;
+      if (i < n_ent) s_ent[i] = v[u];
+    }
+  } else if (CM == CM_COEF) {
+    // each entry's FP32 coefficient (|k|^2 + |l|^2 - |w_j|^2) 2 pi^2 a_j, formed as the
+    // on-the-fly FP32 matvec forms it, its window-local column and its a-table index; entry
+    // (q, lane) of a slice sits at slice base + q * 64 + lane, so entry i is in the row of lane
+    // i % 64 of slice s_gslice[i / 64]
+    __syncthreads();   // norms, |w|^2 and the group map staged
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t i = i0 + u * kUnitThreads;
-        if (i >= n_ent) break;
-        if (CM == CM_ENTRIES) {
-          s_ent[i] = v[u];
-        } else {
-          const int sl = s_gslice[i / kSlice];   // entry (q, lane) of a slice sits at base + q * 64 + lane
-          const uint32_t j = v[u] >> kColBits;
-          float fi = 0.f;
-          uint16_t c = 0;
-          if (j != (uint32_t)kNullJ) {
-            const NormT nkr = s_norm[sl * kSlice + (int)(i % kSlice)];
-            c = (uint16_t)((int)(v[u] & kColMask) - w0);
-            fi = (float)(nkr + s_norm[c] - s_nu[j]);
-          }
-          s_fi[i] = fi;
-          s_col[i] = c;
-          s_j[i] = (uint8_t)j;
+    for (int u = 0; u < kStage; ++u) {
+      const uint32_t i = tid + u * kUnitThreads;
+      if (i < n_ent) {
+        const uint32_t j = v[u] >> kColBits;
+        float fi = 0.f;
+        uint16_t c = 0;
+        if (j != (uint32_t)kNullJ) {
+          const NormT nkr = s_norm[s_gslice[i / kSlice] * kSlice + lane];
+          c = (uint16_t)((int)(v[u] & kColMask) - w0);
+          fi = (float)(nkr + s_norm[c] - s_nu[j]);
         }
+        s_fi[i] = fi;
+        s_col[i] = c;
+        s_j[i] = (uint8_t)j;
       }
     }
   }
@@ -949,7 +987,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
     nzx |= (x[k].x != 0.0 || x[k].y != 0.0);
     dinv[k] = jacobi_inv(nk[k], a0);
   }
-  const double2 init = block_sum2(vff, (double)nzx, red);   // also orders the LDS staging above
+  const double2 init = block_sum2(vff, (double)nzx, red_next());   // also orders the LDS staging above
   const double ff = init.x;
   const bool warm = init.y > 0;
   const double thr2 = A.tol2 * ff;   // |r_W| <= tol |f_W|; summed over units: |r| <= tol |f|
@@ -990,7 +1028,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       v += t;
       vz += t * dinv[k];
     }
-    const double2 sv = block_sum2(v, vz, red);   // its barriers also end every read of the window
+    const double2 sv = block_sum2(v, vz, red_next());   // its barrier also ends every read of the window
     rzr = sv.y;
     return sv.x;
   };
@@ -1000,14 +1038,13 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
     rr = residual();
     if (rr > thr2) {
       double2 pv[kUnitSlots];
-      double rz = 0;
 #pragma unroll
       for (int k = 0; k < kUnitSlots; ++k) {
         pv[k] = make_double2(dinv[k] * r[k].x, dinv[k] * r[k].y);
         if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = pv[k];
-        rz += (r[k].x * r[k].x + r[k].y * r[k].y) * dinv[k];
       }
-      double rho = block_sum2(rz, 0.0, red).x;
+      __syncthreads();
+      double rho = rzr;   // <r, D^-1 r>, reduced with |r|^2
       while (true) {
         double2 q[kUnitSlots];
         unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, q);
@@ -1015,7 +1052,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
 #pragma unroll
         for (int k = 0; k < kUnitSlots; ++k)
           if (wave + k * kUnitWaves < ns) vpq += pv[k].x * q[k].x + pv[k].y * q[k].y;
-        const double pq = block_sum2(vpq, 0.0, red).x;
+        const double pq = block_sum2(vpq, 0.0, red_next()).x;
         const double alpha = rho / pq;
         if (!(pq > 0.0) || !isfinite(alpha)) {
           status = SS_EBREAKDOWN;
@@ -1034,7 +1071,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
           v0 += t * dinv[k];
           v1 += t;
         }
-        const double2 s2 = block_sum2(v0, v1, red);
+        const double2 s2 = block_sum2(v0, v1, red_next());
         ++iters;
         rr = s2.y;
         if (rr <= thr2) break;
@@ -1066,6 +1103,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         break;
       }
       const double scale = sqrt(rr), inv = 1.0 / scale;
+      const double tin2 = fmax(tol2_in, kInnerMargin * kInnerMargin * thr2 / rr);
       ++outer;
       // correction solve L d = r / |r| in FP32 (FP64 inner products), d = 0 to start
       // its starting scalars are those of the FP64 residual, scaled (no further reduction)
@@ -1093,7 +1131,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
 #pragma unroll
           for (int k = 0; k < kUnitSlots; ++k)
             if (wave + k * kUnitWaves < ns) vpq += (double)p32[k].x * q[k].x + (double)p32[k].y * q[k].y;
-          const double pq = block_sum2(vpq, 0.0, red).x;
+          const double pq = block_sum2(vpq, 0.0, red_next()).x;
           const double alpha = rho / pq;
           if (!(pq > 0.0) || !isfinite(alpha)) {
             broke = true;
@@ -1113,9 +1151,9 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
             v0 += t * dinv[k];
             v1 += t;
           }
-          const double2 s2 = block_sum2(v0, v1, red);
+          const double2 s2 = block_sum2(v0, v1, red_next());
           ++it;
-          if (s2.y <= tol2_in * ff_in || it >= A.max_iter) break;
+          if (s2.y <= tin2 * ff_in || it >= A.max_iter) break;
           const float b = (float)(s2.x / rho);
           rho = s2.x;
 #pragma unroll
@@ -1396,6 +1434,7 @@ struct UnitBatch {
     // coefficients in LDS)
     constexpr int kGroups = 10;
     std::vector<int4> lists[kGroups];
+    std::vector<uint2> ents[kGroups];
     std::vector<int32_t> lmax(kGroups, 0);
     std::vector<std::pair<int, int>> where;   // per unit of each problem, in order: (launch, index)
     std::vector<int32_t> uoff{0};
@@ -1412,14 +1451,17 @@ struct UnitBatch {
         const int g = (wide ? 5 : 0) + (fp32 ? 2 : 0) + mode;
         where.emplace_back(g, (int)lists[g].size());
         lists[g].push_back(make_int4(i, un.y, un.z, un.w));
+        ents[g].push_back(make_uint2(it.op->unit_ebase[k], (uint32_t)ne));
         if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * (mode == CM_COEF ? kCoefBytes : 4));
       }
       uoff.push_back((int32_t)where.size());
     }
     std::vector<int4> ul;
+    std::vector<uint2> ue;
     int gbeg[kGroups + 1] = {0};
     for (int g = 0; g < kGroups; ++g) {
       ul.insert(ul.end(), lists[g].begin(), lists[g].end());
+      ue.insert(ue.end(), ents[g].begin(), ents[g].end());
       gbeg[g + 1] = (int)ul.size();
     }
     std::vector<int32_t> uidx(where.size());
@@ -1427,12 +1469,14 @@ struct UnitBatch {
     const int nu = (int)ul.size();
     UDesc* d_desc = nullptr;
     int4* d_ul = nullptr;
+    uint2* d_ue = nullptr;
     int32_t* d_uoff = nullptr;
     UnitOut* d_out = nullptr;
     UnitSum* d_sum = nullptr;
     int32_t* d_uidx = nullptr;
     SS_TRY(alloc(&d_desc, np));
     SS_TRY(alloc(&d_ul, nu));
+    SS_TRY(alloc(&d_ue, nu));
     SS_TRY(alloc(&d_uoff, np + 1));
     SS_TRY(alloc(&d_uidx, nu));
     SS_TRY(alloc(&d_out, nu));
@@ -1445,9 +1489,10 @@ struct UnitBatch {
     }
     SS_HIP(hipMemcpyAsync(d_desc, descs.data(), np * sizeof(UDesc), hipMemcpyHostToDevice, s));
     SS_HIP(hipMemcpyAsync(d_ul, ul.data(), nu * sizeof(int4), hipMemcpyHostToDevice, s));
+    SS_HIP(hipMemcpyAsync(d_ue, ue.data(), nu * sizeof(uint2), hipMemcpyHostToDevice, s));
     SS_HIP(hipMemcpyAsync(d_uoff, uoff.data(), (np + 1) * 4, hipMemcpyHostToDevice, s));
     SS_HIP(hipMemcpyAsync(d_uidx, uidx.data(), nu * 4, hipMemcpyHostToDevice, s));
-    UnitArgs A{d_desc, d_ul, 0, d_out};
+    UnitArgs A{d_desc, d_ul, d_ue, 0, d_out};
     for (int g = 0; g < kGroups; ++g) {
       const int n = gbeg[g + 1] - gbeg[g];
       if (n == 0) continue;

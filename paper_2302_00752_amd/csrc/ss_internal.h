@@ -145,7 +145,7 @@ struct PState {
   double ff;            // |rhs|^2 of the current CG run (|f|^2 for FP64 / outer)
   double rr;            // |r|^2 of the current residual
   double scale;         // refinement: |r64| that normalises the FP32 right-hand side
-  double rr0;
+  double tin2;          // refinement, inner state: squared relative stop of the running correction solve
   int32_t iter;         // index of the running iteration (read by update / dir)
   int32_t iters;        // completed iterations of the current CG run
   int32_t done;
@@ -198,6 +198,7 @@ struct OpImpl {
   std::vector<int4> units;
   std::vector<int2> urange;
   std::vector<int32_t> unit_entries;   // SELL entries of each unit
+  std::vector<uint32_t> unit_ebase;    // first SELL entry of each unit
   int4* d_units = nullptr;
   // canonical CSR (kept for export and tests)
   int64_t* d_crow = nullptr;           // [total+1]
