@@ -847,17 +847,59 @@ __device__ inline void unit_mv_coef(const uint32_t* sptr, const float* fiv, cons
   }
 }
 
+// FP32 q = L v from per-entry complex FP32 coefficients (the bracket times the a-table entry,
+// rounded as unit_mv_coef rounds it) and window-local columns kept in LDS; padding entries hold
+// a zero coefficient and column 0
+__device__ inline void unit_mv_cplx(const uint32_t* sptr, const float2* cf, const uint16_t* col, int ns,
+                                    const float2* vw, float2* acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kUnitSlots; ++k) {
+    const int sw = wave + k * kUnitWaves;
+    if (sw < ns) {
+      const uint32_t base = sptr[sw];
+      const uint32_t width = (sptr[sw + 1] - base) / kSlice;
+      float ar = 0, ai = 0;
+      uint32_t i = base + lane;
+      uint32_t q = 0;
+      for (; q + 4 <= width; q += 4, i += 4 * kSlice) {
+        float2 c[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = cf[i + u * kSlice];
+          x[u] = vw[col[i + u * kSlice]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar += c[u].x * x[u].x - c[u].y * x[u].y;
+          ai += c[u].x * x[u].y + c[u].y * x[u].x;
+        }
+      }
+      for (; q < width; ++q, i += kSlice) {
+        const float2 c = cf[i], x = vw[col[i]];
+        ar += c.x * x.x - c.y * x.y;
+        ai += c.x * x.y + c.y * x.x;
+      }
+      acc[k] = make_float2(ar, ai);
+    }
+  }
+}
+
 // Where the matvecs find the operator: CM_STREAM reads the SELL entries from memory each time;
-// CM_ENTRIES keeps the unit's entries in LDS; CM_COEF (FP32 + refinement) keeps per-entry FP32
-// coefficients, window-local columns and a-table indices in LDS (the correction solves use the
-// coefficients, the FP64 residuals the columns and indices).
-enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2 };
-// entries whose FP32 coefficients and columns (10 bytes each) fit the LDS beside the static
-// arrays (int32 / int64 norms)
-constexpr int kCoefBytes = 7;   // FP32 bracket, 16-bit column, 8-bit a-table index
+// CM_ENTRIES keeps the unit's entries in LDS.  FP32 + refinement: CM_COEF keeps per-entry FP32
+// brackets, window-local columns and a-table indices in LDS, CM_CPLX (units small enough) the
+// complex FP32 coefficients in place of the brackets; the correction solves use the brackets or
+// coefficients and the columns, the FP64 residuals the columns and indices.
+enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2, CM_CPLX = 3 };
+// entries whose caches fit the LDS beside the static arrays (int32 / int64 norms); CM_CPLX is
+// further capped at run time by the LDS the kernel leaves
+constexpr int kCoefBytes = 7;    // FP32 bracket, 16-bit column, 8-bit a-table index
+constexpr int kCplxBytes = 11;   // complex FP32 coefficient, 16-bit column, 8-bit a-table index
 constexpr int kCoefEntries32 = 17152;
 constexpr int kCoefEntries64 = 15936;
+constexpr int kCplxEntries = 10944;
 static_assert(kUnitEntries <= kCoefEntries64 && kCoefEntries64 <= kCoefEntries32, "units must fit every cache");
+static_assert(kCplxEntries <= kCoefEntries64, "the group map covers every cache");
 
 template <typename NormT, bool FP64, int CM>
 __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
@@ -865,7 +907,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   __shared__ __align__(16) double2 s_win[kWinRows];   // search direction / iterate window
   __shared__ NormT s_norm[kWinRows];
   __shared__ uint32_t s_sptr[kWinRows / kSlice + 1];
-  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF: coefficients, columns, j
+  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF, CM_CPLX: brackets or coefficients, columns, j
   __shared__ double2 s_A64[64];
   __shared__ float2 s_A32[64];
   __shared__ NormT s_nu[64];
@@ -902,7 +944,9 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       cr[k] = (int32_t)A.exec2canon[e];
     }
   }
-  constexpr int kCap = CM == CM_COEF ? (sizeof(NormT) == 8 ? kCoefEntries64 : kCoefEntries32) : kUnitEntries;
+  constexpr int kCap = CM == CM_COEF   ? (sizeof(NormT) == 8 ? kCoefEntries64 : kCoefEntries32)
+                      : CM == CM_CPLX ? kCplxEntries
+                                      : kUnitEntries;
   constexpr int kStage = CM == CM_STREAM ? 1 : (kCap + kUnitThreads - 1) / kUnitThreads;
   uint32_t v[kStage];
   if (CM != CM_STREAM) {
@@ -939,12 +983,14 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
     s_nu[tid] = tnu;
   }
   if (tid <= ns) s_sptr[tid] = tsp;
-  float* s_fi = reinterpret_cast<float*>(s_ent);
-  uint16_t* s_col = reinterpret_cast<uint16_t*>(s_fi + n_ent);
+  constexpr bool kCoefs = CM == CM_COEF || CM == CM_CPLX;
+  float* s_fi = reinterpret_cast<float*>(s_ent);     // CM_COEF
+  float2* s_cf = reinterpret_cast<float2*>(s_ent);   // CM_CPLX
+  uint16_t* s_col = CM == CM_CPLX ? reinterpret_cast<uint16_t*>(s_cf + n_ent) : reinterpret_cast<uint16_t*>(s_fi + n_ent);
   uint8_t* s_j = reinterpret_cast<uint8_t*>(s_col + n_ent);
-  // CM_COEF: the slice of every group of 64 entries (a slice's entries are whole groups)
+  // CM_COEF, CM_CPLX: the slice of every group of 64 entries (a slice's entries are whole groups)
   __shared__ uint8_t s_gslice[kCoefEntries32 / kSlice + 1];
-  if (CM == CM_COEF && wave == 0) {
+  if (kCoefs && wave == 0) {
     const uint32_t next = __shfl_down(tsp, 1, 64);
     if (lane < ns)
       for (uint32_t g = tsp / kSlice; g < next / kSlice; ++g) s_gslice[g] = (uint8_t)lane;
@@ -955,12 +1001,12 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       const uint32_t i = tid + u * kUnitThreads;
       if (i < n_ent) s_ent[i] = v[u];
     }
-  } else if (CM == CM_COEF) {
-    // each entry's FP32 coefficient (|k|^2 + |l|^2 - |w_j|^2) 2 pi^2 a_j, formed as the
-    // on-the-fly FP32 matvec forms it, its window-local column and its a-table index; entry
-    // (q, lane) of a slice sits at slice base + q * 64 + lane, so entry i is in the row of lane
-    // i % 64 of slice s_gslice[i / 64]
-    __syncthreads();   // norms, |w|^2 and the group map staged
+  } else if (kCoefs) {
+    // each entry's FP32 bracket |k|^2 + |l|^2 - |w_j|^2 (CM_CPLX: times the FP32 a-table entry,
+    // both formed as the on-the-fly FP32 matvec forms them), its window-local column and its
+    // a-table index; entry (q, lane) of a slice sits at slice base + q * 64 + lane, so entry i
+    // is in the row of lane i % 64 of slice s_gslice[i / 64]
+    __syncthreads();   // norms, |w|^2, tables and the group map staged
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const uint32_t i = tid + u * kUnitThreads;
@@ -973,7 +1019,12 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
           c = (uint16_t)((int)(v[u] & kColMask) - w0);
           fi = (float)(nkr + s_norm[c] - s_nu[j]);
         }
-        s_fi[i] = fi;
+        if (CM == CM_CPLX) {
+          const float2 a = j != (uint32_t)kNullJ ? s_A32[j] : make_float2(0.f, 0.f);
+          s_cf[i] = make_float2(fi * a.x, fi * a.y);
+        } else {
+          s_fi[i] = fi;
+        }
         s_col[i] = c;
         s_j[i] = (uint8_t)j;
       }
@@ -1009,7 +1060,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
         if (wave + k * kUnitWaves < ns) s_win[(wave + k * kUnitWaves) * kSlice + lane] = x[k];
       __syncthreads();
       double2 acc[kUnitSlots];
-      if (CM == CM_COEF)
+      if (kCoefs)
         unit_mv_cj<NormT>(s_sptr, s_col, s_j, ns, s_A64, s_nu, s_norm, s_win, nk, acc);
       else
         unit_mv<NormT, double2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A64, s_nu, s_norm, s_win, nk, acc);
@@ -1123,7 +1174,9 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
       {
         while (true) {
           float2 q[kUnitSlots];
-          if (CM == CM_COEF)
+          if (CM == CM_CPLX)
+            unit_mv_cplx(s_sptr, s_cf, s_col, ns, s_win32, q);
+          else if (CM == CM_COEF)
             unit_mv_coef(s_sptr, s_fi, s_col, s_j, ns, s_A32, s_win32, q);
           else
             unit_mv<NormT, float2, CACHED>(A, s_sptr, ebase, s_ent, ns, w0, s_A32, s_nu, s_norm, s_win32, nk, q);
@@ -1212,6 +1265,25 @@ __global__ void k_unit_final(int n_prob, const int32_t* __restrict__ uoff, const
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
+
+// entries a CM_CPLX unit may hold: what the LDS leaves beside the kernel's static arrays, at
+// most kCplxEntries (0 if the device cannot be queried)
+template <typename NormT>
+int unit_cplx_cap() {
+  static const int cap = [] {
+    int dev = 0, lds = 0;
+    hipFuncAttributes fa{};
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_unit_solve<NormT, false, CM_CPLX>)) != hipSuccess) {
+      (void)hipGetLastError();   // not left for the launch checks that follow
+      return 0;
+    }
+    const int fit = (lds - (int)fa.sharedSizeBytes) / kCplxBytes;
+    return std::max(0, std::min(fit, kCplxEntries));
+  }();
+  return cap;
+}
 
 }  // namespace
 
@@ -1431,8 +1503,9 @@ struct UnitBatch {
     // results are addressed by their position in ul, and each problem's are summed in order
     // through uidx
     // launch groups: norm width x (FP64: stream, entries in LDS | FP32: stream, entries,
-    // coefficients in LDS)
-    constexpr int kGroups = 10;
+    // brackets, complex coefficients in LDS)
+    constexpr int kGroups = 12;
+    const int cplx_cap[2] = {unit_cplx_cap<int32_t>(), unit_cplx_cap<int64_t>()};
     std::vector<int4> lists[kGroups];
     std::vector<uint2> ents[kGroups];
     std::vector<int32_t> lmax(kGroups, 0);
@@ -1447,12 +1520,14 @@ struct UnitBatch {
         const int32_t ne = it.op->unit_entries[k];
         const bool wide = it.group >= 2, fp32 = it.group & 1;
         int mode = ne <= kUnitEntries ? CM_ENTRIES : CM_STREAM;
-        if (fp32 && ne <= (wide ? kCoefEntries64 : kCoefEntries32)) mode = CM_COEF;
-        const int g = (wide ? 5 : 0) + (fp32 ? 2 : 0) + mode;
+        if (fp32 && ne <= cplx_cap[wide]) mode = CM_CPLX;
+        else if (fp32 && ne <= (wide ? kCoefEntries64 : kCoefEntries32)) mode = CM_COEF;
+        const int g = (wide ? 6 : 0) + (fp32 ? 2 : 0) + mode;
         where.emplace_back(g, (int)lists[g].size());
         lists[g].push_back(make_int4(i, un.y, un.z, un.w));
         ents[g].push_back(make_uint2(it.op->unit_ebase[k], (uint32_t)ne));
-        if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * (mode == CM_COEF ? kCoefBytes : 4));
+        const int bytes = mode == CM_CPLX ? kCplxBytes : mode == CM_COEF ? kCoefBytes : 4;
+        if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * bytes);
       }
       uoff.push_back((int32_t)where.size());
     }
@@ -1504,11 +1579,13 @@ struct UnitBatch {
         case 2: k_unit_solve<int32_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
         case 3: k_unit_solve<int32_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
         case 4: k_unit_solve<int32_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 5: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 6: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 7: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 8: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        default: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 5: k_unit_solve<int32_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 6: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 7: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 8: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+        case 9: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+        case 10: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
+        default: k_unit_solve<int64_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
       }
     }
     k_unit_final<<<grid_for(np), kBlock, 0, s>>>(np, d_uoff, d_uidx, d_out, d_sum);
