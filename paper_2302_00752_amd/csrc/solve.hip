@@ -168,6 +168,25 @@ __device__ inline V sell_row(const uint32_t* __restrict__ sent, uint32_t base, u
   return out;
 }
 
+// Streaming accesses that are not to stay in the caches (the matvec's window staging and its
+// output): nontemporal loads and stores of whole complex values.
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ inline void st_nt(double2* p, double2 v) {
+  __builtin_nontemporal_store(d2v_t{v.x, v.y}, reinterpret_cast<d2v_t*>(p));
+}
+__device__ inline void st_nt(float2* p, float2 v) {
+  __builtin_nontemporal_store(f2v_t{v.x, v.y}, reinterpret_cast<f2v_t*>(p));
+}
+__device__ inline double2 ld_nt(const double2* p) {
+  const d2v_t v = __builtin_nontemporal_load(reinterpret_cast<const d2v_t*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ inline float2 ld_nt(const float2* p) {
+  const f2v_t v = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));
+  return make_float2(v.x, v.y);
+}
+
 template <typename V> __device__ inline const V* a_table(const Desc& D);
 template <> __device__ inline const double2* a_table<double2>(const Desc& D) { return D.A64; }
 template <> __device__ inline const float2* a_table<float2>(const Desc& D) { return D.A32; }
@@ -202,9 +221,29 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) 
     As[tid] = a_table<V>(D)[tid];
     nus[tid] = (NormT)D.nu[tid];
   }
-  for (int i = tid; i < wlen; i += kSolveBlock) {
-    xw[i] = x[w0 + i];
-    nw[i] = normv[w0 + i];
+  {
+    // the window, U rows per thread in flight
+    constexpr int U = 4;
+    for (int i0 = tid; i0 < wlen; i0 += U * kSolveBlock) {
+      V xv[U];
+      NormT nv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kSolveBlock;
+        if (i < wlen) {
+          xv[u] = ld_nt(x + w0 + i);
+          nv[u] = __builtin_nontemporal_load(normv + w0 + i);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kSolveBlock;
+        if (i < wlen) {
+          xw[i] = xv[u];
+          nw[i] = nv[u];
+        }
+      }
+    }
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
@@ -218,7 +257,7 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) 
                       ? sell_row<true, NormT, V>(D.sent, base, width, lane, normv[e], nw, xw, w0, As, nus)
                       : sell_row<false, NormT, V>(D.sent, base, width, lane, normv[e], normv, x, 0, As, nus);
     if (MODE == MV_PLAIN) {
-      y[e] = acc;
+      st_nt(y + e, acc);
     } else if (MODE == MV_DOT) {
       y[e] = acc;
       const V pe = x[e];

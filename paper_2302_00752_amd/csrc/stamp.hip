@@ -233,24 +233,6 @@ __global__ void k_level_counts(int n_prob, int64_t f0, int32_t smax1, const int6
   out[p] = (int64_t)idx[c1 - 1] + flag[c1 - 1] - (int64_t)idx[c0];
 }
 
-__global__ void k_minmax(int64_t n, int d, const int16_t* __restrict__ keys, int32_t* mn, int32_t* mx) {
-  // thread g scans coordinate g % d of a chunk of 1024 keys, then one atomic pair
-  constexpr int64_t kChunk = 1024;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = (int)(g % d);
-  const int64_t k0 = (g / d) * kChunk;
-  if (k0 >= n) return;
-  const int64_t k1 = k0 + kChunk < n ? k0 + kChunk : n;
-  int lo = 32767, hi = -32768;
-  for (int64_t k = k0; k < k1; ++k) {
-    const int v = keys[k * d + c];
-    lo = v < lo ? v : lo;
-    hi = v > hi ? v : hi;
-  }
-  atomicMin(&mn[c], lo);
-  atomicMax(&mx[c], hi);
-}
-
 // one packed field of a radix pass: coordinate t (or -1 = problem id), minus `lo`, at bit `shift`
 struct Field {
   int32_t t;
@@ -345,10 +327,12 @@ __global__ void k_remap_table(uint64_t n_slots, uint64_t* table, const uint32_t*
   if ((v & kTagMask) == kTagMain) table[2 * s] = kTagMain | (uint64_t)inv[v & kIdxMask];
 }
 
-__global__ void k_rowoff(int64_t n, const int32_t* __restrict__ pid, int64_t* rowoff) {
+// first row of every problem (every problem has keys: F is not empty), and n after the last
+__global__ void k_rowoff(int64_t n, int n_prob, const int32_t* __restrict__ pid, int64_t* rowoff) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   if (r == 0 || pid[r] != pid[r - 1]) rowoff[pid[r]] = r;
+  if (r == n - 1) rowoff[n_prob] = n;
 }
 
 __global__ void k_iota_i64(int64_t n, int64_t* p) {
@@ -610,6 +594,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0), s_of(n_prob);
   int max_level = 0, smax1 = 1;
   int64_t a_pos = 0;
+  // coordinate ranges of the stamped keys: S^n holds f + n w for every f in F and w in supp(a)
+  // (0 in supp(a) gives every shorter sum), so coordinate t spans exactly
+  // [min_f f_t + n min_w w_t, max_f f_t + n max_w w_t] over the batch
+  std::vector<int64_t> kmin(d, INT64_MAX), kmax(d, INT64_MIN);
   std::vector<int> fidx;
   ATable at;   // reused across problems
   for (int p = 0; p < n_prob; ++p) {
@@ -638,6 +626,19 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       }
     }
     st->a_off[p + 1] = st->a_off[p] + at.size();
+    for (int t = 0; t < d; ++t) {
+      int64_t wlo = 0, whi = 0, flo = INT64_MAX, fhi = INT64_MIN;
+      for (int j = 0; j < at.size(); ++j) {
+        wlo = std::min<int64_t>(wlo, at.key(j)[t]);
+        whi = std::max<int64_t>(whi, at.key(j)[t]);
+      }
+      for (int i = f_off[p]; i < f_off[p] + n_f[p]; ++i) {
+        flo = std::min<int64_t>(flo, f_freqs[(int64_t)i * d + t]);
+        fhi = std::max<int64_t>(fhi, f_freqs[(int64_t)i * d + t]);
+      }
+      kmin[t] = std::min(kmin[t], flo + (int64_t)level[p] * wlo);
+      kmax[t] = std::max(kmax[t], fhi + (int64_t)level[p] * whi);
+    }
     woff[p + 1] = woff[p] + at.size() - 1;
     smax1 = std::max<int>(smax1, at.size() - 1);
     f_off[p + 1] = f_off[p] + n_f[p];
@@ -653,6 +654,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       if (!fless(fidx[i - 1], fidx[i])) return fail(SS_EINVAL, "duplicate forcing frequency within a problem");
   }
   const int64_t nF = f_off[n_prob];
+  for (int t = 0; t < d; ++t)
+    if (kmin[t] < INT16_MIN || kmax[t] > INT16_MAX)
+      return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
   SS_HIP(hipGetDevice(&st->device));
 
   // ---- device a-tables (kept by the stamp)
@@ -851,17 +855,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- canonical order: LSD radix sort over packed, range-biased coordinates, then problem id
   st->total = total;
-  std::vector<int32_t> mn(d, 32767), mx(d, -32768);
-  int32_t *d_mn = nullptr, *d_mx = nullptr;
-  sc.hold(d_mn); sc.hold(d_mx);
-  SS_TRY(dalloc(&d_mn, d));
-  SS_TRY(dalloc(&d_mx, d));
-  SS_HIP(hipMemcpyAsync(d_mn, mn.data(), d * 4, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(d_mx, mx.data(), d * 4, hipMemcpyHostToDevice, stream));
-  k_minmax<<<grid_for(ceil_div(total, 1024) * d), kBlock, 0, stream>>>(total, d, ukeys, d_mn, d_mx);
-  SS_HIP(hipMemcpyAsync(mn.data(), d_mn, d * 4, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipMemcpyAsync(mx.data(), d_mx, d * 4, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
+  std::vector<int32_t> mn(d), mx(d);
+  for (int t = 0; t < d; ++t) {
+    mn[t] = (int32_t)kmin[t];
+    mx[t] = (int32_t)kmax[t];
+  }
   // words of <= 64 bits, filled from the least significant coordinate up; the problem id on top
   std::vector<Field> fields;
   std::vector<std::pair<int, int>> passes;   // [first field, end field), bits
@@ -955,14 +953,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots,
                                                                                             st->d_table, inv);
   }
-  k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, st->d_pid, st->d_rowoff);
+  k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, n_prob, st->d_pid, st->d_rowoff);
   unsigned long long maxn = 0;
   st->row_off.assign(n_prob + 1, 0);
   SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, n_prob * 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
-  st->row_off[n_prob] = total;
-  SS_HIP(hipMemcpyAsync(st->d_rowoff + n_prob, &st->row_off[n_prob], 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 1) * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   st->max_norm = (int64_t)maxn;
   for (int p = 0; p < n_prob; ++p)
