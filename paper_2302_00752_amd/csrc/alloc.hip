@@ -9,6 +9,8 @@
 // after the work that used it has completed (every release point in the
 // library follows a stream synchronisation), so handing it to another stream
 // needs no event.
+#include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -87,6 +89,105 @@ void pool_free(void* p) {
   P.free_blocks[it->second].push_back(p);
   P.cached_bytes += it->second.second;
   P.live.erase(it);
+}
+
+// ---------------------------------------------------------------- pinned staging of uploads
+// A copy from pageable host memory is staged by the runtime and holds the calling thread until
+// the stream has reached it, which drains the stream before the next launch is even issued.
+// Uploads are therefore copied into pinned host memory first; the device copy then only queues.
+// A thread takes a ring of pinned chunks from a shared list on its first upload and gives it back
+// when it ends (rings live as long as the process, so short-lived threads allocate nothing).  A
+// chunk holds the copies of one stream, and its event, recorded behind each of them, covers them
+// all; a chunk is refilled only after its event has completed.  Events belong to the device
+// current when the chunk was first used.
+
+namespace {
+
+struct PinChunk {
+  char* host = nullptr;
+  size_t cap = 0, used = 0;
+  hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+constexpr int kPinRing = 3;
+constexpr size_t kPinChunk = size_t(4) << 20;
+
+struct PinRing {
+  PinChunk chunk[kPinRing];
+  int cur = 0;
+};
+
+std::mutex g_pin_mu;
+std::vector<PinRing*> g_pin_free;
+
+struct PinHolder {
+  PinRing* ring = nullptr;
+  ~PinHolder() {   // no device calls here: it may run while the process ends
+    if (!ring) return;
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_free.push_back(ring);
+  }
+};
+
+PinRing* pin_ring() {
+  thread_local PinHolder holder;
+  if (!holder.ring) {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    if (!g_pin_free.empty()) {
+      holder.ring = g_pin_free.back();
+      g_pin_free.pop_back();
+    } else {
+      holder.ring = new PinRing();   // never destroyed: copies may be in flight at teardown
+    }
+  }
+  return holder.ring;
+}
+
+}  // namespace
+
+hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  PinRing& ring = *pin_ring();
+  PinChunk* c = &ring.chunk[ring.cur];
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (c->stream != stream || c->used + need > c->cap) {
+    if (c->used > 0) {   // move on; the next chunk is refilled once its copies are done
+      ring.cur = (ring.cur + 1) % kPinRing;
+      c = &ring.chunk[ring.cur];
+      if (c->used > 0) {
+        const hipError_t e = hipEventSynchronize(c->ev);
+        if (e != hipSuccess) return e;
+        c->used = 0;
+      }
+    }
+    c->stream = stream;
+  }
+  if (!c->ev) {
+    const hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      c->ev = nullptr;
+      return e;
+    }
+  }
+  if (need > c->cap) {   // the chunk is empty here
+    if (c->host) (void)hipHostFree(c->host);
+    c->host = nullptr;
+    c->cap = 0;
+    const size_t cap = std::max(kPinChunk, need);
+    const hipError_t e = hipHostMalloc((void**)&c->host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      c->host = nullptr;
+      return e;
+    }
+    c->cap = cap;
+  }
+  char* h = c->host + c->used;
+  std::memcpy(h, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(c->ev, stream);
+  if (e == hipSuccess) c->used += need;
+  return e;
 }
 
 }  // namespace ss

@@ -689,22 +689,21 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   if (op->n_slices * (int64_t)kMaxA * kSlice >= (int64_t(1) << 32))
     return fail(SS_ERANGE, "batch too large for 32-bit SELL offsets (split it)");
   SS_TRY(dalloc(&op->d_eoff, n_prob + 1));
-  SS_HIP(hipMemcpyAsync(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, stream));
   int64_t *d_cq0 = nullptr, *d_ce0 = nullptr;
   SS_TRY(dalloc(&d_cq0, std::max<int64_t>(n_cls, 1)));
   track(d_cq0);
   SS_TRY(dalloc(&d_ce0, std::max<int64_t>(n_cls, 1)));
   track(d_ce0);
   if (n_cls) {
-    SS_HIP(hipMemcpyAsync(d_cq0, cq.data(), n_cls * 8, hipMemcpyHostToDevice, stream));
-    SS_HIP(hipMemcpyAsync(d_ce0, ce0.data(), n_cls * 8, hipMemcpyHostToDevice, stream));
+    SS_HIP(h2d(d_cq0, cq.data(), n_cls * 8, stream));
+    SS_HIP(h2d(d_ce0, ce0.data(), n_cls * 8, stream));
   }
   SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
   SS_TRY(dalloc(&op->d_canon2exec, total));
   k_fill_i64<<<grid_for(op->n_exec), kBlock, 0, stream>>>(op->n_exec, op->d_exec2canon, -1);
   k_exec_map<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, cflag, cidx, d_cq0, d_ce0, op->d_canon2exec,
                                                       op->d_exec2canon);
-  SS_HIP(hipStreamSynchronize(stream));   // host class tables above are temporaries
 
   // ---- SELL-64 slices
   uint32_t* width = nullptr;
@@ -835,8 +834,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   }
   if (!op->units.empty()) {
     SS_TRY(dalloc(&op->d_units, op->units.size()));
-    SS_HIP(hipMemcpyAsync(op->d_units, op->units.data(), op->units.size() * sizeof(int4), hipMemcpyHostToDevice,
-                          stream));
+    SS_HIP(h2d(op->d_units, op->units.data(), op->units.size() * sizeof(int4), stream));
   }
   SS_TRY(dalloc(&op->d_work, op->work.size()));
   SS_TRY(dalloc(&op->d_wrange, n_prob));
@@ -844,12 +842,12 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&op->d_A32, A32.size()));
   SS_TRY(dalloc(&op->d_nu, nu.size()));
   SS_TRY(dalloc(&op->d_a0, n_prob));
-  SS_HIP(hipMemcpyAsync(op->d_work, op->work.data(), op->work.size() * sizeof(int4), hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(op->d_wrange, op->wrange.data(), n_prob * sizeof(int2), hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(op->d_A64, A64.data(), A64.size() * sizeof(double2), hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(op->d_A32, A32.data(), A32.size() * sizeof(float2), hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(op->d_nu, nu.data(), nu.size() * 8, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(op->d_a0, a0.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(op->d_work, op->work.data(), op->work.size() * sizeof(int4), stream));
+  SS_HIP(h2d(op->d_wrange, op->wrange.data(), n_prob * sizeof(int2), stream));
+  SS_HIP(h2d(op->d_A64, A64.data(), A64.size() * sizeof(double2), stream));
+  SS_HIP(h2d(op->d_A32, A32.data(), A32.size() * sizeof(float2), stream));
+  SS_HIP(h2d(op->d_nu, nu.data(), nu.size() * 8, stream));
+  SS_HIP(h2d(op->d_a0, a0.data(), n_prob * 8, stream));
   SS_HIP(hipStreamSynchronize(stream));
   *out = guard.release();
   return SS_OK;

@@ -1370,9 +1370,9 @@ struct LaunchList {
       SS_TRY(dalloc(&part, 6 * cap_work));
     }
     if (!descs.empty())
-      SS_HIP(hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(Desc), hipMemcpyHostToDevice, s));
+      SS_HIP(h2d(d_descs, descs.data(), descs.size() * sizeof(Desc), s));
     if (!work.empty())
-      SS_HIP(hipMemcpyAsync(d_work, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      SS_HIP(h2d(d_work, work.data(), work.size() * sizeof(int4), s));
     per = (int)std::max<int64_t>(1, ceil_div((int64_t)work.size(), 8));
     grid = (unsigned)(8 * per);
     int64_t maxw = 0;
@@ -1388,7 +1388,7 @@ struct LaunchList {
   }
   ss_status upload_descs(hipStream_t s) {
     if (!descs.empty())
-      SS_HIP(hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(Desc), hipMemcpyHostToDevice, s));
+      SS_HIP(h2d(d_descs, descs.data(), descs.size() * sizeof(Desc), s));
     return SS_OK;
   }
   int n_work() const { return (int)work.size(); }
@@ -1601,11 +1601,11 @@ struct UnitBatch {
       h_cap = std::max<size_t>(np, 2 * h_cap);
       SS_HIP(hipHostMalloc((void**)&h_sum, h_cap * sizeof(UnitSum), hipHostMallocDefault));
     }
-    SS_HIP(hipMemcpyAsync(d_desc, descs.data(), np * sizeof(UDesc), hipMemcpyHostToDevice, s));
-    SS_HIP(hipMemcpyAsync(d_ul, ul.data(), nu * sizeof(int4), hipMemcpyHostToDevice, s));
-    SS_HIP(hipMemcpyAsync(d_ue, ue.data(), nu * sizeof(uint2), hipMemcpyHostToDevice, s));
-    SS_HIP(hipMemcpyAsync(d_uoff, uoff.data(), (np + 1) * 4, hipMemcpyHostToDevice, s));
-    SS_HIP(hipMemcpyAsync(d_uidx, uidx.data(), nu * 4, hipMemcpyHostToDevice, s));
+    SS_HIP(h2d(d_desc, descs.data(), np * sizeof(UDesc), s));
+    SS_HIP(h2d(d_ul, ul.data(), nu * sizeof(int4), s));
+    SS_HIP(h2d(d_ue, ue.data(), nu * sizeof(uint2), s));
+    SS_HIP(h2d(d_uoff, uoff.data(), (np + 1) * 4, s));
+    SS_HIP(h2d(d_uidx, uidx.data(), nu * 4, s));
     UnitArgs A{d_desc, d_ul, d_ue, 0, d_out};
     for (int g = 0; g < kGroups; ++g) {
       const int n = gbeg[g + 1] - gbeg[g];

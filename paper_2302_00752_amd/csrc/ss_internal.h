@@ -311,6 +311,9 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
 // device memory: a caching allocator (see alloc.hip)
 hipError_t pool_alloc(void** out, size_t bytes);
 void pool_free(void* p);
+// Host-to-device copy of `bytes` from pageable host memory, queued on `stream` without holding the
+// calling thread: the bytes are first copied into a pinned buffer of the thread.
+hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 template <typename T>
 ss_status dalloc(T** p, size_t count) {

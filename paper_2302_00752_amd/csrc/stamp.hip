@@ -270,28 +270,38 @@ __global__ void k_iota_u32(int64_t n, uint32_t* p) {
 
 // sorted key rows: one thread per (row, coordinate), so reads of a source row and the
 // writes of the output are contiguous across neighbouring threads
-__global__ void k_permute_keys(int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
-                               int16_t* __restrict__ keys) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n * d) return;
-  const int64_t r = g / d;
-  keys[g] = ukeys[(int64_t)perm[r] * d + (g - r * d)];
-}
-
-// problem id and level gathered; hash and |k|^2 recomputed from the sorted key row
-__global__ void k_permute_meta(int64_t n, int d, const uint32_t* __restrict__ perm, const int32_t* __restrict__ upid,
-                               const uint8_t* __restrict__ ulev, const int16_t* __restrict__ keys,
-                               const uint64_t* __restrict__ z, uint64_t* hash, int32_t* pid, uint8_t* lev,
-                               int64_t* norm, uint32_t* inv, unsigned long long* max_norm) {
+// Sorted row r from unsorted row perm[r]: the key (copied in 32-bit words when d is even), the
+// problem id and level; hash and |k|^2 formed from the key on the way; inv[perm[r]] = r; the
+// block maximum of |k|^2, one atomic per block.
+__global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
+                               const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
+                               const uint64_t* __restrict__ z, int16_t* __restrict__ keys, uint64_t* hash,
+                               int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv,
+                               unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = 0;
   if (r < n) {
     const int64_t s = perm[r];
+    const int16_t* src = ukeys + s * d;
+    int16_t* dst = keys + r * d;
     uint64_t h = 0;
-    const int16_t* k = keys + r * d;
-    for (int t = 0; t < d; ++t) {
-      h += (uint64_t)(int64_t)k[t] * z[t];
-      nn += (int64_t)k[t] * k[t];
+    if ((d & 1) == 0) {
+      const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+      uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+      for (int t = 0; t < d; t += 2) {
+        const uint32_t w = s32[t >> 1];
+        d32[t >> 1] = w;
+        const int64_t lo = (int16_t)(w & 0xffffu), hi = (int16_t)(w >> 16);
+        h += (uint64_t)lo * z[t] + (uint64_t)hi * z[t + 1];
+        nn += lo * lo + hi * hi;
+      }
+    } else {
+      for (int t = 0; t < d; ++t) {
+        const int64_t v = src[t];
+        dst[t] = (int16_t)v;
+        h += (uint64_t)v * z[t];
+        nn += v * v;
+      }
     }
     hash[r] = h;
     pid[r] = upid[s];
@@ -299,7 +309,6 @@ __global__ void k_permute_meta(int64_t n, int d, const uint32_t* __restrict__ pe
     norm[r] = nn;
     inv[s] = (uint32_t)r;
   }
-  // block maximum of |k|^2, one atomic per block
   for (int off = 32; off > 0; off >>= 1) {
     const int64_t o = __shfl_xor(nn, off, 64);
     nn = o > nn ? o : nn;
@@ -431,13 +440,25 @@ double app_a_count(int64_t n_f, int s, int N) {
 struct Scratch {
   hipStream_t stream = nullptr;
   std::vector<void**> slots;
+  std::vector<void*> retired;   // no longer used by the host, maybe still by queued work
   explicit Scratch(hipStream_t s) : stream(s) {}
   template <typename T>
   void hold(T*& p) {
     slots.push_back((void**)&p);
   }
+  // p goes back to the pool at the next release_retired(), which follows a stream sync
+  template <typename T>
+  void retire(T*& p) {
+    if (p) retired.push_back((void*)p);
+    p = nullptr;
+  }
+  void release_retired() {
+    for (void* q : retired) pool_free(q);
+    retired.clear();
+  }
   ~Scratch() {
     (void)hipStreamSynchronize(stream);   // queued work may still use the blocks (error paths)
+    release_retired();
     for (void** s : slots)
       if (*s) {
         pool_free(*s);
@@ -464,17 +485,19 @@ ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t 
     total += cap[p];
   }
   if (total >= (uint64_t(1) << 40)) return fail(SS_ERANGE, "hash table too large");
-  dfree(st->d_table);
+  if (st->d_table) {   // queued work (the last k_append) may still write the old table
+    SS_HIP(hipStreamSynchronize(stream));
+    dfree(st->d_table);
+  }
   SS_TRY(dalloc(&st->d_table, 2 * total));
   if (!st->d_toff) SS_TRY(dalloc(&st->d_toff, np));
   if (!st->d_tmask) SS_TRY(dalloc(&st->d_tmask, np));
   SS_HIP(hipMemsetAsync(st->d_table, 0, 2 * total * 8, stream));
-  SS_HIP(hipMemcpyAsync(st->d_toff, off.data(), np * 8, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_tmask, mask.data(), np * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(st->d_toff, off.data(), np * 8, stream));
+  SS_HIP(h2d(st->d_tmask, mask.data(), np * 8, stream));
   st->n_slots = total;
   st->tcap = cap;
   if (n > 0) k_insert_main<<<grid_for(n), kBlock, 0, stream>>>(n, hash, pid, st->d_toff, st->d_tmask, st->d_table);
-  SS_HIP(hipStreamSynchronize(stream));   // host vectors above are temporaries
   return SS_OK;
 }
 
@@ -666,12 +689,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&st->d_aoff, n_prob + 1));
   SS_TRY(dalloc(&st->d_azero, n_prob));
   SS_TRY(dalloc(&st->d_coef, d));
-  SS_HIP(hipMemcpyAsync(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_ahash, ahash.data(), ahash.size() * 8, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_anorm, anorm.data(), anorm.size() * 8, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_aoff, st->a_off.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_azero, st->a_zero.data(), n_prob * 4, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(st->d_coef, z.data(), d * 8, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, stream));
+  SS_HIP(h2d(st->d_ahash, ahash.data(), ahash.size() * 8, stream));
+  SS_HIP(h2d(st->d_anorm, anorm.data(), anorm.size() * 8, stream));
+  SS_HIP(h2d(st->d_aoff, st->a_off.data(), (n_prob + 1) * 4, stream));
+  SS_HIP(h2d(st->d_azero, st->a_zero.data(), n_prob * 4, stream));
+  SS_HIP(h2d(st->d_coef, z.data(), d * 8, stream));
 
   // ---- build scratch
   Scratch sc(stream);
@@ -705,10 +728,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&d_full, n_prob));
   SS_TRY(dalloc(&d_only, n_prob));
   SS_HIP(hipMemsetAsync(d_full, 0, n_prob, stream));
-  if (!wkeys.empty()) SS_HIP(hipMemcpyAsync(wk, wkeys.data(), wkeys.size() * 2, hipMemcpyHostToDevice, stream));
-  if (!whash.empty()) SS_HIP(hipMemcpyAsync(wh, whash.data(), whash.size() * 8, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(wo, woff.data(), (n_prob + 1) * 4, hipMemcpyHostToDevice, stream));
-  SS_HIP(hipMemcpyAsync(plev, level, n_prob * 4, hipMemcpyHostToDevice, stream));
+  if (!wkeys.empty()) SS_HIP(h2d(wk, wkeys.data(), wkeys.size() * 2, stream));
+  if (!whash.empty()) SS_HIP(h2d(wh, whash.data(), whash.size() * 8, stream));
+  SS_HIP(h2d(wo, woff.data(), (n_prob + 1) * 4, stream));
+  SS_HIP(h2d(plev, level, n_prob * 4, stream));
   SS_HIP(hipMemsetAsync(err, 0, 4, stream));
 
   // ---- level 0: F
@@ -725,13 +748,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     std::vector<int32_t> fpid(nF);
     for (int p = 0; p < n_prob; ++p)
       for (int i = f_off[p]; i < f_off[p + 1]; ++i) fpid[i] = p;
-    SS_HIP(hipMemcpyAsync(ukeys, f_freqs, (size_t)nF * d * 2, hipMemcpyHostToDevice, stream));
-    SS_HIP(hipMemcpyAsync(upid, fpid.data(), nF * 4, hipMemcpyHostToDevice, stream));
+    SS_HIP(h2d(ukeys, f_freqs, (size_t)nF * d * 2, stream));
+    SS_HIP(h2d(upid, fpid.data(), nF * 4, stream));
     SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
     SS_HIP(hipMemsetAsync(ulast, 0, nF, stream));
     k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
     k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash, unorm);
-    SS_HIP(hipStreamSynchronize(stream));   // fpid is a host temporary
   }
   // per-problem regions sized from the App. A count (grown below if coincidences are rarer than it assumes)
   std::vector<uint64_t> cap(n_prob);
@@ -779,10 +801,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       }
     }
     if (relayout) SS_TRY(layout_table(st, cap, total, uhash, upid, stream));
-    if (n_cand > ccap) {
-      dfree(cpos);
-      dfree(flag);
-      dfree(idx);
+    if (n_cand > ccap) {   // the last level's k_append may still read them
+      sc.retire(cpos);
+      sc.retire(flag);
+      sc.retire(idx);
       ccap = n_cand;
       SS_TRY(dalloc(&cpos, ccap));
       SS_TRY(dalloc(&flag, ccap));
@@ -791,8 +813,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_toff, st->d_tmask,
                   st->d_table, cpos, err, ulast, d_full, nullptr};
     const unsigned cg = grid_for(n_cand);
-    SS_HIP(hipMemcpyAsync(d_fstart, fstart.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
-    SS_HIP(hipMemcpyAsync(d_fcount, fcount.data(), n_prob * 8, hipMemcpyHostToDevice, stream));
+    SS_HIP(h2d(d_fstart, fstart.data(), n_prob * 8, stream));
+    SS_HIP(h2d(d_fcount, fcount.data(), n_prob * 8, stream));
     std::vector<int64_t> added(n_prob);
     // winners, their positions and the new keys per problem of the candidates in cpos
     auto count_level = [&]() -> ss_status {
@@ -811,6 +833,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
       SS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream));
       SS_HIP(hipStreamSynchronize(stream));
+      sc.release_retired();
       if (herr) return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
       return SS_OK;
     };
@@ -830,8 +853,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       }
     }
     if (again) {
-      SS_HIP(hipMemcpyAsync(d_full, full.data(), n_prob, hipMemcpyHostToDevice, stream));
-      SS_HIP(hipMemcpyAsync(d_only, redo.data(), n_prob, hipMemcpyHostToDevice, stream));
+      SS_HIP(h2d(d_full, full.data(), n_prob, stream));
+      SS_HIP(h2d(d_only, redo.data(), n_prob, stream));
       ExpandArgs eb = ea;
       eb.only = d_only;
       k_expand<<<cg, kBlock, 0, stream>>>(eb);
@@ -847,10 +870,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     }
     f1 = total;
   }
-  dfree(cpos);
-  dfree(flag);
-  dfree(idx);
-  dfree(tmp);
+  sc.retire(cpos);   // the last k_append may still read them
+  sc.retire(flag);
+  sc.retire(idx);
+  dfree(tmp);        // its last user, a scan, is behind the last sync
   tmp_bytes = 0;
 
   // ---- canonical order: LSD radix sort over packed, range-biased coordinates, then problem id
@@ -888,7 +911,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   sc.hold(d_fields);
   SS_TRY(dalloc(&d_fields, std::max<size_t>(fields.size(), 1)));
   if (!fields.empty())
-    SS_HIP(hipMemcpyAsync(d_fields, fields.data(), fields.size() * sizeof(Field), hipMemcpyHostToDevice, stream));
+    SS_HIP(h2d(d_fields, fields.data(), fields.size() * sizeof(Field), stream));
 
   uint32_t *perm = nullptr, *perm2 = nullptr;
   uint64_t *k64 = nullptr, *k64b = nullptr;
@@ -930,8 +953,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint32_t* inv = perm2;
   unsigned long long* d_maxn = (unsigned long long*)k64;
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
-  k_permute_keys<<<grid_for(total * d), kBlock, 0, stream>>>(total, d, perm, ukeys, st->d_keys);
-  k_permute_meta<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, upid, ulev, st->d_keys, st->d_coef,
+  k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, upid, ulev, st->d_coef, st->d_keys,
                                                          st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   // the forcing frequencies are the first nF unsorted keys, in the order given
@@ -1006,9 +1028,9 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   SS_TRY(dalloc(&dout, nq));
   if (probs) {
     SS_TRY(dalloc(&dp, nq));
-    SS_HIP(hipMemcpyAsync(dp, probs, nq * 4, hipMemcpyHostToDevice, stream));
+    SS_HIP(h2d(dp, probs, nq * 4, stream));
   }
-  SS_HIP(hipMemcpyAsync(dq, q, (size_t)nq * st->d * 2, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(dq, q, (size_t)nq * st->d * 2, stream));
   k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_toff,
                                                  st->d_tmask, st->d_table, st->d_rowoff, dout);
   SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
@@ -1022,7 +1044,7 @@ ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, 
   Scratch sc(stream);
   sc.hold(dv);
   SS_TRY(dalloc(&dv, st->n_f));
-  SS_HIP(hipMemcpyAsync(dv, f_hat, st->n_f * 16, hipMemcpyHostToDevice, stream));
+  SS_HIP(h2d(dv, f_hat, st->n_f * 16, stream));
   double2* df = static_cast<double2*>(f);
   k_zero_c128<<<grid_for(st->total), kBlock, 0, stream>>>(st->total, df);
   k_scatter_f<<<grid_for(st->n_f), kBlock, 0, stream>>>(st->n_f, st->d_fslot, dv, df);
