@@ -215,13 +215,22 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
 }
 
 // present entries of each row of the dense table, in j order: the row lengths, then the CSR
+// (the table is read kDenseChunk entries per row at a time, every load of a chunk in flight)
+constexpr int kDenseChunk = 8;
+
 __global__ void k_row_count(int64_t total, const uint32_t* __restrict__ D, const int32_t* __restrict__ pid,
                             const int32_t* __restrict__ aoff, int64_t* rowlen) {
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r], s = aoff[p + 1] - aoff[p];
   int64_t c = 0;
-  for (int j = 0; j < s; ++j) c += D[(int64_t)j * total + r] != kAbsent;
+  for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
+    uint32_t v[kDenseChunk];
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kAbsent;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) c += v[u] != kAbsent;
+  }
   rowlen[r] = c;
 }
 
@@ -232,9 +241,13 @@ __global__ void k_csr_from_dense(int64_t total, const uint32_t* __restrict__ D, 
   if (r >= total) return;
   const int p = pid[r], s = aoff[p + 1] - aoff[p];
   int64_t q = crow[r];
-  for (int j = 0; j < s; ++j) {
-    const uint32_t v = D[(int64_t)j * total + r];
-    if (v != kAbsent) cent[q++] = v;
+  for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
+    uint32_t v[kDenseChunk];
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kAbsent;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u)
+      if (v[u] != kAbsent) cent[q++] = v[u];
   }
 }
 
@@ -284,9 +297,16 @@ __global__ void k_cc_prop(int64_t total, const int64_t* __restrict__ crow, const
   const int64_t base = rowoff[pid[r]];
   const int64_t own = label[r];
   int64_t l = own;
-  for (int64_t e = crow[r]; e < crow[r + 1]; ++e) {
-    const int64_t lc = label[base + (cent[e] & kColMask)];
-    l = lc < l ? lc : l;
+  const int64_t e1 = crow[r + 1];
+  for (int64_t e0 = crow[r]; e0 < e1; e0 += kDenseChunk) {   // entries, then labels, a chunk at a time
+    uint32_t c[kDenseChunk];
+    int64_t lc[kDenseChunk];
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) c[u] = e0 + u < e1 ? cent[e0 + u] & kColMask : 0u;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) lc[u] = e0 + u < e1 ? label[base + c[u]] : own;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) l = lc[u] < l ? lc[u] : l;
   }
   if (l < own) {
     label[r] = l;
@@ -415,14 +435,19 @@ __global__ void k_sell_fill(int64_t n_exec, const int64_t* __restrict__ exec2can
   const int p = pid[r];
   const int64_t len = rowlen[r];
   const int64_t c0 = crow[r];
-  for (uint32_t q = 0; q < w; ++q) {
-    uint32_t out = null_ent;
-    if ((int64_t)q < len) {
-      const uint32_t ent = cent[c0 + q];
-      const int64_t cg = rowoff[p] + (ent & kColMask);
-      out = (uint32_t)(canon2exec[cg] - eoff[p]) | (ent & ~kColMask);
-    }
-    sent[base + q * kSlice + lane] = out;
+  const int64_t ro = rowoff[p], eo = eoff[p];
+  // a chunk of the row's entries, then their execution columns, each round of loads in flight
+  for (uint32_t q0 = 0; q0 < w; q0 += kDenseChunk) {
+    uint32_t ent[kDenseChunk];
+    int64_t col[kDenseChunk];
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) ent[u] = (int64_t)(q0 + u) < len ? cent[c0 + q0 + u] : null_ent;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u)
+      col[u] = (int64_t)(q0 + u) < len ? canon2exec[ro + (ent[u] & kColMask)] - eo : 0;
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u)
+      if (q0 + u < w) sent[base + (q0 + u) * kSlice + lane] = (int64_t)(q0 + u) < len ? (uint32_t)col[u] | (ent[u] & ~kColMask) : null_ent;
   }
   norm_exec[e] = (NormT)norm[r];
 }
