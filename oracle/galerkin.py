@@ -11,6 +11,11 @@
                    with the dot product k . l formed directly in exact
                    integers, stored as a scipy sparse matrix.
 * ``apply``        y = L_N x.
+* ``proxy_error``  the relative proxy error |f - L u^N|_2 / |f|_2 of Sec. 10.1
+                   (Lemma ProxyError), with L the untruncated operator: every
+                   term 4 pi^2 (k . l) a_{k-l} u_l for l in S^N and k - l in
+                   supp(a) is summed at its k (Prop. LExpansion: L u^N lives
+                   on S^N + supp(a) = S^{N+1}), so the l2 norm is exact.
 * ``solve``        the mean-zero solution of L_N u = f on S^N (Alg. 1, step 5):
                    one dense complex LU solve per class; the row and column of
                    k = 0 vanish identically and u_0 = 0 (Sec. 3, space H;
@@ -95,6 +100,32 @@ def matrix(keys, a_freqs, a_hat, nbr=None):
 def apply(keys, a_freqs, a_hat, x):
     """y = L_N x on S^N."""
     return matrix(keys, a_freqs, a_hat) @ np.asarray(x, dtype=np.complex128)
+
+
+def proxy_error(keys, u, a_freqs, a_hat, f_freqs, f_hat):
+    """|f - L u|_2 / |f|_2 for u given on the keys (Sec. 10.1, Lemma ProxyError).
+
+    L u is formed term by term without truncation: each (l, w) pair, l a key
+    and w in supp(a), adds 4 pi^2 (k . l) a_w u_l at k = l + w.  Terms are
+    gathered per distinct k; f enters at its own frequencies.
+    """
+    keys = np.asarray(keys, dtype=np.int64)
+    u = np.asarray(u, dtype=np.complex128)
+    a_freqs = np.asarray(a_freqs, dtype=np.int64)
+    a_hat = np.asarray(a_hat, dtype=np.complex128)
+    f_freqs = np.asarray(f_freqs, dtype=np.int64)
+    f_hat = np.asarray(f_hat, dtype=np.complex128)
+    n, s, d = len(keys), len(a_freqs), keys.shape[1]
+    k = (keys[:, None, :] + a_freqs[None, :, :]).reshape(n * s, d)       # k = l + w
+    l = np.repeat(keys, s, axis=0)
+    k_dot_l = np.einsum("ij,ij->i", k, l)                                  # exact int64
+    terms = FOUR_PI2 * k_dot_l.astype(np.float64) * np.tile(a_hat, n) * np.repeat(u, s)
+    allk = np.concatenate([k, f_freqs])
+    vals = np.concatenate([-terms, f_hat])                                 # f - L u
+    uniq, inv = np.unique(allk, axis=0, return_inverse=True)
+    res = np.zeros(len(uniq), dtype=np.complex128)
+    np.add.at(res, inv.ravel(), vals)
+    return float(np.linalg.norm(res) / np.linalg.norm(f_hat))
 
 
 def _pcg(M, f, D, tol=1e-15, max_iter=100000):

@@ -29,6 +29,10 @@ Workload recipes (all seeded with numpy PCG64, ``seed = 1000*config + instance``
   nonzero coordinates in {-8..8}\\{0}, level chosen so the stamp set holds
   1e3..1e5 frequencies, precision FP64 or FP32+refine with probability 1/2,
   Poisson arrival times.
+* ``lowsparsity``  the exactly sparse low-sparsity problem of Sec. 10.3.1:
+  a = 4 + c_a cos(2 pi k_a.x) with c_a ~ U[-1, 1], f = sin(2 pi k_f.x), k_a and
+  k_f ~ U([-499, 500]^d), nonzero and k_f != +-k_a; any d (the paper runs d = 1
+  to 1024) and level N (the paper: N = 1..5).  Seed ``7000 + 10007 d + instance``.
 """
 from __future__ import annotations
 
@@ -249,6 +253,17 @@ def manufactured_solution(n: int, seed: int, density: float = 0.3,
     if zero_index is not None:
         u[zero_index] = 0
     return u
+
+
+def lowsparsity(d: int, level: int, instance: int = 0) -> Problem:
+    rng = np.random.Generator(np.random.PCG64(7000 + 10007 * d + instance))
+    c_a = float(rng.uniform(-1.0, 1.0))
+    draw = lambda: rng.integers(-499, 501, size=d)
+    k_a = _distinct_modes(rng, 1, draw)
+    k_f = _distinct_modes(rng, 1, draw, forbid=k_a)
+    af, ah = _real_from_half(d, k_a, np.array([c_a / 2], dtype=np.complex128), a0=4.0)
+    ff, fh = _real_from_half(d, k_f, np.array([-0.5j], dtype=np.complex128))
+    return Problem(d, af, ah, ff, fh, level=level, name=f"lowsparsity/d{d}/N{level}/{instance}")
 
 
 CONFIGS = {1: cfg1, 2: cfg2, 3: cfg3, 4: cfg4}
