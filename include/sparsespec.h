@@ -183,6 +183,25 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
                       ss_precision prec, int32_t max_iter, void* stream,
                       ss_solve_info* info);
 
+/* Exact proxy error of Sec. 10.1 (Lemma ProxyError) for every problem of a batch:
+ * err_out[p] = |f - L u^N|_2 / |f|_2 with L the untruncated operator, u^N the
+ * level-N solution extended by zero.  L u^N is supported on S^{N+1} (Prop.
+ * LExpansion), so the norm is taken exactly there, by one FP64 matvec of the
+ * level-(N+1) operator.
+ *   st_next, op_next: stamping sets and operator built on the same problems
+ *          (same a, same F in the same order) at level N_p + 1 each; every
+ *          level must be >= 1.  Their keys of first-appearance level <= N_p
+ *          are S^{N_p}, in the same canonical order.
+ *   u_dev, n_u: device complex128, the level-N solutions in the canonical order
+ *          of the level-N stamp (n_u = sum over p of |S^{N_p}| entries; read
+ *          only).
+ *   f_hat: host complex128 forcing coefficients, as for ss_stamp_forcing.
+ *   err_out: host double [n_prob]; 0 for a problem with f = 0.
+ * Errors: SS_EINVAL (null argument, op_next not built on st_next, a level 0,
+ * n_u not the number of keys of level <= N_p).  Synchronises `stream`. */
+ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const void* u_dev,
+                         int64_t n_u, const double* f_hat, double* err_out, void* stream);
+
 void ss_free_op(ss_op* op);
 
 /* device bytes held by op, including its solver workspace once a solve ran */

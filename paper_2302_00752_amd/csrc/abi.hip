@@ -200,6 +200,14 @@ ss_status ss_apply(const ss_op* op, ss_precision prec, const void* x_dev, void* 
   });
 }
 
+ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const void* u_dev, int64_t n_u,
+                         const double* f_hat, double* err_out, void* stream) {
+  return guarded([&]() -> ss_status {
+    if (!st_next || !st_next->impl || !op_next || !op_next->impl) return fail(SS_EINVAL, "null stamp or operator");
+    return proxy_error_impl(st_next->impl, op_next->impl, u_dev, n_u, f_hat, err_out, as_stream(stream));
+  });
+}
+
 ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double tol, ss_precision prec,
                       int32_t max_iter, void* stream, ss_solve_info* info) {
   return guarded([&]() -> ss_status {

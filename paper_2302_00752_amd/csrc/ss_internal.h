@@ -257,6 +257,10 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
                             int64_t* slot_out, hipStream_t stream, const int32_t* probs = nullptr);
 
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
+// proxy error of level-N solutions u (canonical order of the level-N stamp) from the stamp and
+// operator built at level N + 1 (proxy.hip); err: host [n_prob]
+ss_status proxy_error_impl(const StampImpl* st, const OpImpl* op, const void* u, int64_t n_u, const double* f_hat,
+                           double* err, hipStream_t stream);
 
 // whole-path batch solve, split into concurrently running parts
 struct BatchImpl {

@@ -28,7 +28,8 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_free_stamp", "ss_build_op", "ss_op_info", "ss_op_csr", "ss_op_exec_map", "ss_apply",
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
-            "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch"]
+            "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
+            "ss_proxy_error"]
 
 
 class SolveInfo(C.Structure):
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                            C.POINTER(SolveInfo)],
         "ss_batch_size": [P, pi64, pi64],
         "ss_batch_solution": [P, P, P],
+        "ss_proxy_error": [P, P, P, i64, pd, pd, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -345,6 +347,21 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+
+def proxy_error(stamp_next: Stamp, op_next: Operator, u, problems, stream=None) -> np.ndarray:
+    """Exact proxy error |f - L u^N|_2 / |f|_2 of every problem (Sec. 10.1, Lemma ProxyError).
+
+    ``stamp_next`` and ``op_next`` are built on the same problems at level N + 1; ``u`` is the
+    device complex128 tensor of the level-N solutions in the level-N stamp's canonical order."""
+    vals = problems.f_hat if isinstance(problems, Batch) else \
+        _c128(np.concatenate([np.asarray(p.f_hat) for p in problems]))
+    if vals is None or len(vals) != 2 * stamp_next.n_f:
+        raise SparseSpecError(SS_EINVAL, "one f_hat coefficient per forcing frequency of the build is needed")
+    err = np.zeros(stamp_next.n_prob, dtype=np.float64)
+    _check(_lib.ss_proxy_error(stamp_next._h, op_next._h, C.c_void_p(u.data_ptr()), int(u.numel()),
+                               _ptr(vals, C.c_double), _ptr(err, C.c_double), C.c_void_p(_stream(stream))))
+    return err
 
 
 def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64", max_iter=2000, flags=0,

@@ -1,0 +1,118 @@
+"""GPU parity of the exact proxy error (Sec. 10.1, Lemma ProxyError) through
+the C ABI against the oracle's term-by-term formula, on the same level-N
+solutions: the low-sparsity problem of Sec. 10.3.1 in d = 1 .. 1024 at
+N = 1..5 (levels mixed in one batch), and the configurations of the other
+parity tests.  Bar: |err_gpu - err_oracle| <= 1e-12 + 1e-9 err_oracle (the
+Galerkin part of the residual on S^N is a difference of O(1) numbers, so its
+last digits are rounding; the level-(N+1) part has no cancellation).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import galerkin as og
+from oracle import stamp as ost
+from paper_2302_00752_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_00752_amd import sparsespec
+    return sparsespec
+
+
+def _raised(problems):
+    out = []
+    for p in problems:
+        q = copy.copy(p)
+        q.level = p.level + 1
+        out.append(q)
+    return out
+
+
+def _gpu_proxy(ss, problems, flags=0, tol=1e-12):
+    """Level-N solve, then the proxy error from the level-(N+1) build."""
+    st = ss.Stamp.build(problems)
+    op = ss.Operator.build(st, problems, flags)
+    f = st.forcing_vector(problems)
+    u = torch.zeros_like(f)
+    op.solve(f, u, tol, "fp64", 5000)
+    nxt = _raised(problems)
+    st1 = ss.Stamp.build(nxt)
+    op1 = ss.Operator.build(st1, nxt, flags)
+    err = ss.proxy_error(st1, op1, u, nxt)
+    torch.cuda.synchronize()
+    keys, _ = st.keys()
+    return err, u.cpu().numpy(), keys, st.offsets
+
+
+def _oracle_proxy(p, keys, u):
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    return og.proxy_error(keys, u, af, ah, p.f_freqs, p.f_hat)
+
+
+def _check(problems, err, u, keys, off):
+    for i, p in enumerate(problems):
+        ref = _oracle_proxy(p, keys[off[i]:off[i + 1]], u[off[i]:off[i + 1]])
+        assert abs(err[i] - ref) <= 1e-12 + 1e-9 * ref, (p.name, err[i], ref)
+
+
+@pytest.mark.parametrize("d", [1, 4, 16, 64, 256, 1024])
+def test_lowsparsity_proxy_matches_oracle(ss, d):
+    problems = [workloads.lowsparsity(d, N) for N in range(1, 6)]
+    err, u, keys, off = _gpu_proxy(ss, problems)
+    _check(problems, err, u, keys, off)
+    assert np.all(err[1:] < 0.5 * err[:-1])        # geometric decay in N (Fig. 4a)
+
+
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
+def test_config_proxy_matches_oracle(ss, config):
+    flags = {3: 1}.get(config, 0)
+    problems = [workloads.make(config, 0)]
+    err, u, keys, off = _gpu_proxy(ss, problems, flags, tol=1e-11)
+    _check(problems, err, u, keys, off)
+
+
+def test_proxy_of_zero_and_of_exact_poisson_solution(ss):
+    d, a0 = 3, 2.5
+    F = np.array([[1, -2, 3], [-1, 2, -3], [4, 0, 1], [-4, 0, -1]], dtype=np.int16)
+    fh = np.array([0.3 - 0.2j, 0.3 + 0.2j, -1.0j, 1.0j])
+    p = workloads.Problem(d, np.zeros((1, d), dtype=np.int16), np.array([a0 + 0j]), F, fh, level=1)
+    st = ss.Stamp.build([p])
+    keys, _ = st.keys()
+    f = st.forcing_vector([p]).cpu().numpy()
+    nk = (keys.astype(np.int64) ** 2).sum(1)
+    u_exact = np.where(nk > 0, f / (4 * np.pi ** 2 * a0 * np.maximum(nk, 1)), 0)
+    q = copy.copy(p)
+    q.level = 2
+    st1 = ss.Stamp.build([q])
+    op1 = ss.Operator.build(st1, [q])
+    e = ss.proxy_error(st1, op1, torch.from_numpy(u_exact).cuda(), [q])
+    assert e[0] <= 1e-15
+    e0 = ss.proxy_error(st1, op1, torch.zeros(len(keys), dtype=torch.complex128, device="cuda"), [q])
+    assert e0[0] == pytest.approx(1.0, abs=1e-15)
+
+
+def test_proxy_rejects_level_zero_and_foreign_operator(ss):
+    p = workloads.lowsparsity(4, 0)
+    st = ss.Stamp.build([p])
+    op = ss.Operator.build(st, [p])
+    u = torch.zeros(st.n_total, dtype=torch.complex128, device="cuda")
+    with pytest.raises(ss.SparseSpecError):
+        ss.proxy_error(st, op, u, [p])            # level 0: there is no S^{-1}
+    q = workloads.lowsparsity(4, 2)
+    st2 = ss.Stamp.build([q])
+    with pytest.raises(ss.SparseSpecError):
+        ss.proxy_error(st2, op, u, [q])           # operator of another stamp
+    q3 = workloads.lowsparsity(4, 3)
+    st3 = ss.Stamp.build([q3])
+    op3 = ss.Operator.build(st3, [q3])
+    with pytest.raises(ss.SparseSpecError):
+        ss.proxy_error(st3, op3, u, [q3])         # u is not one entry per key of S^2
