@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
+    ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -259,6 +260,67 @@ def main():
         err = {k: max(v) for k, v in errs.items()}
         log(f"cpu oracle {cpu['value']:.3f} solves/s on {cores} threads; max rel err {err}")
 
+    # --- exact proxy error (Sec. 10.1) of level-N solutions, from the level-(N+1) build
+    proxy = None
+    if args.proxy:
+        import copy
+
+        def raised(problems):
+            out = []
+            for p in problems:
+                q = copy.copy(p)
+                q.level = p.level + 1
+                out.append(q)
+            return out
+
+        def proxy_run(problems, tol=1e-12, reps=3):
+            st0 = ss.Stamp.build(problems)
+            op0 = ss.Operator.build(st0, problems, 0)
+            f0 = st0.forcing_vector(problems, dev)
+            u0 = torch.zeros_like(f0)
+            op0.solve(f0, u0, tol, "fp64", 5000)
+            nxt = raised(problems)
+            times = {"build_next_ms": [], "proxy_ms": []}
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st1 = ss.Stamp.build(nxt)
+                op1 = ss.Operator.build(st1, nxt, 0)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                e = ss.proxy_error(st1, op1, u0, nxt)
+                t2 = time.perf_counter()
+                times["build_next_ms"].append(1e3 * (t1 - t))
+                times["proxy_ms"].append(1e3 * (t2 - t1))
+                n1, ne1 = st1.n_total, op1.n_exec
+                st1.close()
+                op1.close()
+            med = {k: float(np.median(v)) for k, v in times.items()}
+            return e, med, n1, ne1
+
+        decay = {}
+        for d in (1, 16, 256, 1024):   # instance 5: c_a = -0.63, near the paper's example value
+            e, _, _, _ = proxy_run([workloads.lowsparsity(d, N, 5) for N in range(1, 6)], reps=1)
+            decay[f"d={d}"] = [float(v) for v in e]
+        Bl = 1024
+        lows = [workloads.lowsparsity(1024, 1 + i % 5, i) for i in range(Bl)]
+        e_l, med_l, n_l, _ = proxy_run(lows)
+        Bc = 64
+        c2 = [workloads.make(2, i) for i in range(Bc)]
+        e_c, med_c, n_c, _ = proxy_run(c2, tol=args.tol)
+        proxy = {
+            "decay_low_sparsity_N1_to_5": decay,
+            "low_sparsity_d1024": {"batch": Bl, "levels": "N = 1..5 cycling", "rows_next": int(n_l), **med_l,
+                                   "proxy_errors_per_s": Bl / ((med_l["build_next_ms"] + med_l["proxy_ms"]) / 1e3),
+                                   "max_proxy": float(e_l.max())},
+            "cfg2_level3": {"batch": Bc, "rows_next": int(n_c), **med_c,
+                            "proxy_errors_per_s": Bc / ((med_c["build_next_ms"] + med_c["proxy_ms"]) / 1e3),
+                            "median_proxy": float(np.median(e_c))},
+        }
+        log(f"proxy error: low-sparsity d=1024 B={Bl}: build {med_l['build_next_ms']:.1f} ms + proxy "
+            f"{med_l['proxy_ms']:.2f} ms; cfg2 B={Bc} (S^4: {n_c} rows): build {med_c['build_next_ms']:.1f} ms + "
+            f"proxy {med_c['proxy_ms']:.2f} ms; decay d=1024 {['%.2e' % v for v in decay['d=1024']]}")
+
     # --- serving: Poisson stream of heterogeneous requests, continuous batching
     serving = None
     if args.serve > 0:
@@ -311,6 +373,7 @@ def main():
                      "bytes_per_launch": mv["fp64"]["bytes"], "traffic": traffic,
                      "measured_copy_GB/s": copy_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
+        "proxy_error": proxy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -30,9 +30,11 @@ Workload recipes (all seeded with numpy PCG64, ``seed = 1000*config + instance``
   1e3..1e5 frequencies, precision FP64 or FP32+refine with probability 1/2,
   Poisson arrival times.
 * ``lowsparsity``  the exactly sparse low-sparsity problem of Sec. 10.3.1:
-  a = 4 + c_a cos(2 pi k_a.x) with c_a ~ U[-1, 1], f = sin(2 pi k_f.x), k_a and
-  k_f ~ U([-499, 500]^d), nonzero and k_f != +-k_a; any d (the paper runs d = 1
-  to 1024) and level N (the paper: N = 1..5).  Seed ``7000 + 10007 d + instance``.
+  a = 4 + c_a cos(2 pi k_a.x) with c_a ~ U[-1, 1] drawn once per instance and
+  kept for every d (as the paper does), f = sin(2 pi k_f.x), k_a and k_f ~
+  U([-499, 500]^d), nonzero and k_f != +-k_a; any d (the paper runs d = 1 to
+  1024) and level N (the paper: N = 1..5).  Seeds ``7000 + instance`` for c_a and
+  ``7000 + 10007 d + instance`` for the frequencies.
 """
 from __future__ import annotations
 
@@ -256,8 +258,8 @@ def manufactured_solution(n: int, seed: int, density: float = 0.3,
 
 
 def lowsparsity(d: int, level: int, instance: int = 0) -> Problem:
+    c_a = float(np.random.Generator(np.random.PCG64(7000 + instance)).uniform(-1.0, 1.0))
     rng = np.random.Generator(np.random.PCG64(7000 + 10007 * d + instance))
-    c_a = float(rng.uniform(-1.0, 1.0))
     draw = lambda: rng.integers(-499, 501, size=d)
     k_a = _distinct_modes(rng, 1, draw)
     k_f = _distinct_modes(rng, 1, draw, forbid=k_a)

@@ -66,7 +66,8 @@ def _check(problems, err, u, keys, off):
 
 @pytest.mark.parametrize("d", [1, 4, 16, 64, 256, 1024])
 def test_lowsparsity_proxy_matches_oracle(ss, d):
-    problems = [workloads.lowsparsity(d, N) for N in range(1, 6)]
+    # instance 5 draws c_a = -0.63, close to the value of the paper's example (-0.6)
+    problems = [workloads.lowsparsity(d, N, 5) for N in range(1, 6)]
     err, u, keys, off = _gpu_proxy(ss, problems)
     _check(problems, err, u, keys, off)
     assert np.all(err[1:] < 0.5 * err[:-1])        # geometric decay in N (Fig. 4a)
