@@ -249,6 +249,12 @@ __global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys, con
   out[r] = v;
 }
 
+// flag = 1 if two neighbours of the sorted words are equal
+__global__ void k_adjacent_ties(int64_t n, const uint64_t* __restrict__ w, int32_t* flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 1 && r < n && w[r] == w[r - 1]) *flag = 1;
+}
+
 __global__ void k_gather_u64(int64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ src,
                              uint64_t* __restrict__ dst) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -894,6 +900,27 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       pass_bits.push_back(used);
     }
   }
+  // With more than two words (large d), one word packed from the most significant side first:
+  // the problem id on top, then coordinates 0, 1, ... while they fit.  If no two keys share it,
+  // sorting by it alone gives the canonical order and the LSD passes are skipped.
+  const int nf = (int)fields.size();
+  int top_bits = 0;
+  if (passes.size() > 2) {
+    std::vector<std::pair<int, int>> items{{-1, bits_for((uint64_t)(n_prob - 1))}};   // (t, bits)
+    int used = items[0].second;
+    for (int t = 0; t < d; ++t) {
+      const int b = bits_for((uint64_t)(mx[t] - mn[t]));
+      if (used + b > 64) break;
+      items.emplace_back(t, b);
+      used += b;
+    }
+    int shift = used;
+    for (const auto& it : items) {
+      shift -= it.second;
+      if (it.second > 0) fields.push_back(Field{it.first, it.first >= 0 ? mn[it.first] : 0, shift, 0});
+    }
+    top_bits = used;
+  }
   Field* d_fields = nullptr;
   sc.hold(d_fields);
   SS_TRY(dalloc(&d_fields, std::max<size_t>(fields.size(), 1)));
@@ -912,10 +939,31 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k64, k64b, perm, perm2, total, 0, 64, stream));
     SS_HIP(pool_alloc((void**)&tmp, tmp_bytes));
   }
+  bool done = false;
+  if (top_bits > 0) {
+    int32_t* d_tie = nullptr;
+    sc.hold(d_tie);
+    SS_TRY(dalloc(&d_tie, 1));
+    SS_HIP(hipMemsetAsync(d_tie, 0, 4, stream));
+    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, nf,
+                                                     (int)fields.size(), k64);
+    size_t tb = tmp_bytes;
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, top_bits, stream));
+    k_adjacent_ties<<<grid_for(total), kBlock, 0, stream>>>(total, k64b, d_tie);
+    int32_t tie = 1;
+    SS_HIP(hipMemcpyAsync(&tie, d_tie, 4, hipMemcpyDeviceToHost, stream));
+    SS_HIP(hipStreamSynchronize(stream));
+    if (!tie) {
+      std::swap(perm, perm2);
+      done = true;
+    } else {
+      k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
+    }
+  }
   uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
   sc.hold(wq);
-  if (passes.size() > 1) SS_TRY(dalloc(&wq, total));
-  for (size_t q = 0; q < passes.size(); ++q) {
+  if (passes.size() > 1 && !done) SS_TRY(dalloc(&wq, total));
+  for (size_t q = 0; q < passes.size() && !done; ++q) {
     if (q == 0) {
       k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, passes[q].first,
                                                        passes[q].second, k64);

@@ -117,3 +117,18 @@ def test_proxy_rejects_level_zero_and_foreign_operator(ss):
     op3 = ss.Operator.build(st3, [q3])
     with pytest.raises(ss.SparseSpecError):
         ss.proxy_error(st3, op3, u, [q3])         # u is not one entry per key of S^2
+
+
+@pytest.mark.parametrize("d", [256, 1024])
+def test_high_dimension_stamp_bit_exact(ss, d):
+    # many int16 coordinates: keys and levels, batch order and lexicographic order within each
+    # problem, bit-exact against the oracle's brute-force sets
+    problems = [workloads.lowsparsity(d, N, i) for i in range(4) for N in range(0, 5)]
+    st = ss.Stamp.build(problems)
+    keys, lev = st.keys()
+    off = st.offsets
+    for i, p in enumerate(problems):
+        af, _ = ost.canonical_a(p.a_freqs, p.a_hat)
+        ok, ol = ost.stamp(p.f_freqs, af, p.level)
+        assert np.array_equal(keys[off[i]:off[i + 1]].astype(np.int64), np.asarray(ok)), p.name
+        assert np.array_equal(lev[off[i]:off[i + 1]].astype(np.int64), np.asarray(ol)), p.name
