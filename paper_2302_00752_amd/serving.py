@@ -34,10 +34,24 @@ class Finished:
     done: float
     info: dict
     result: object = None
+    prob: int = 0           # problem of the unit's handle that answered this request (grouped builds)
 
     @property
     def latency(self) -> float:
         return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class _Unit:
+    """What the engine admits in one submit: a handle whose problems answer one or more requests.
+    ``reqs`` holds [rid, arrival, problems left]; with ``per_problem`` request i is problem i."""
+    tag: int
+    handle: object
+    reqs: list
+    n_prob: int
+    per_problem: bool
+    admitted: float = 0.0
+    left: int = 0
 
 
 class Scheduler:
@@ -45,32 +59,41 @@ class Scheduler:
 
     ``engine`` must provide ``submit(handle, tag) -> bool`` (False when the
     budget or slots are exhausted), ``step(iters) -> n_active`` and
-    ``poll() -> [(tag, prob, info)]``.  ``handle`` is whatever the builder made
-    for a request; a request is finished when all ``n_prob`` of its problems
-    have been polled.
+    ``poll() -> [(tag, prob, info)]``.  ``handle`` is whatever the builder made;
+    with ``offer`` it answers one request, finished when all ``n_prob`` of its
+    problems have been polled; with ``offer_group`` (one build for several
+    requests) problem i answers request i.  Handles whose problems are all done
+    are listed in ``retired`` for the caller to release.
     """
 
     def __init__(self, engine, iters_per_tick: int = 4, clock: Callable[[], float] = time.perf_counter):
         self.engine = engine
         self.iters = iters_per_tick
         self.clock = clock
-        self.ready: collections.deque = collections.deque()      # (rid, arrival, handle, n_prob)
-        self.active: Dict[int, list] = {}                          # rid -> [arrival, admitted, handle, left]
+        self.ready: collections.deque = collections.deque()      # _Unit, in arrival order
+        self.active: Dict[int, _Unit] = {}                         # tag -> unit
         self.finished: List[Finished] = []
+        self.retired: List[object] = []
         self.max_active = 0
 
     def offer(self, rid: int, arrival: float, handle, n_prob: int = 1):
-        self.ready.append((rid, arrival, handle, n_prob))
+        self.ready.append(_Unit(rid, handle, [[rid, arrival, n_prob]], n_prob, False))
+
+    def offer_group(self, tag: int, handle, reqs):
+        """``reqs``: [(rid, arrival)] answered by problems 0, 1, ... of ``handle``."""
+        self.ready.append(_Unit(tag, handle, [[rid, arr, 1] for rid, arr in reqs], len(reqs), True))
 
     def admit(self) -> int:
-        """Admit ready requests in arrival order until the engine refuses one."""
+        """Admit ready units in arrival order until the engine refuses one."""
         n = 0
         while self.ready:
-            rid, arrival, handle, n_prob = self.ready[0]
-            if not self.engine.submit(handle, rid):
+            u = self.ready[0]
+            if not self.engine.submit(u.handle, u.tag):
                 break
             self.ready.popleft()
-            self.active[rid] = [arrival, self.clock(), handle, n_prob]
+            u.admitted = self.clock()
+            u.left = u.n_prob
+            self.active[u.tag] = u
             n += 1
         self.max_active = max(self.max_active, len(self.active))
         return n
@@ -82,12 +105,17 @@ class Scheduler:
         self.engine.step(self.iters)
         done = 0
         for tag, prob, info in self.engine.poll():
-            rec = self.active[tag]
-            rec[3] -= 1
-            if rec[3] == 0:
-                arrival, admitted, handle, _ = self.active.pop(tag)
-                self.finished.append(Finished(tag, arrival, admitted, self.clock(), info, handle))
+            u = self.active[tag]
+            req = u.reqs[prob] if u.per_problem else u.reqs[0]
+            req[2] -= 1
+            if req[2] == 0:
+                self.finished.append(Finished(req[0], req[1], u.admitted, self.clock(), info, u.handle,
+                                              prob if u.per_problem else 0))
                 done += 1
+            u.left -= 1
+            if u.left == 0:
+                self.active.pop(tag)
+                self.retired.append(u.handle)
         return done
 
     def idle(self) -> bool:
@@ -97,14 +125,16 @@ class Scheduler:
 # ---------------------------------------------------------------------------- GPU serving
 @dataclasses.dataclass
 class Built:
-    rid: int
-    problem: object
+    """One build (stamps, operator, f, u) answering the requests ``rids``: problem i is request
+    rids[i], its entries of f and u at [offsets[i], offsets[i+1])."""
+    tag: int
+    rids: list
     op: object
     f: object
     u: object
+    offsets: object
     tol: float
     precision: str
-    n_total: int
     build_ms: float
 
 
@@ -123,13 +153,29 @@ class _EngineAdapter:
         return self.e.poll()
 
 
+def _padded(p, d: int):
+    """The same problem on the d-torus, d >= p.d: every frequency gets zero coordinates appended.
+    Its stamping set, operator and solution are those of p, keys padded alike (all dot products and
+    norms are unchanged, and lexicographic order is kept)."""
+    if p.d == d:
+        return p
+    q = dataclasses.replace(p)
+    q.d = d
+    q.a_freqs = np.pad(np.asarray(p.a_freqs), ((0, 0), (0, d - p.d)))
+    q.f_freqs = np.pad(np.asarray(p.f_freqs), ((0, 0), (0, d - p.d)))
+    return q
+
+
 def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 0, iters_per_tick: int = 4,
           build_threads: int = 2, ready_depth: int = 16, tol64: float = 1e-10, tol32: float = 1e-9,
-          max_iter: int = 2000, keep_results: bool = False, realtime: bool = True, flags_for=None):
+          max_iter: int = 2000, keep_results: bool = False, realtime: bool = True, flags_for=None,
+          max_group: int = 8):
     """Serve ``requests`` (objects with ``d, a_freqs, a_hat, f_freqs, f_hat, level,
-    precision, arrival_s``) on the current GPU.  Returns a summary dict and the
-    list of ``Finished`` records (with ``result`` = host solution when
-    ``keep_results``)."""
+    precision, arrival_s``) on the current GPU.  A builder takes the next request once it
+    has arrived together with every later one already arrived (at most ``max_group``) and
+    builds each precision's share as one batch, dimensions padded to the largest.  Returns
+    a summary dict and the list of ``Finished`` records (with ``result`` = host solution
+    when ``keep_results``)."""
     import torch
 
     from . import sparsespec as ss
@@ -142,6 +188,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     t0 = time.perf_counter()
     arrivals = [t0 + requests[i].arrival_s if realtime else t0 for i in range(len(requests))]
     next_job = [0]
+    next_tag = [0]
     lock = threading.Lock()
     errors: List[BaseException] = []
     in_ready = threading.Semaphore(ready_depth)
@@ -152,42 +199,58 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
             with lock:
                 if next_job[0] >= len(order):
                     return
-                i = order[next_job[0]]
+                first = order[next_job[0]]
                 next_job[0] += 1
-            wait = arrivals[i] - time.perf_counter()
+            wait = arrivals[first] - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-            in_ready.acquire()
-            try:
+            group = [first]
+            with lock:   # every request that has arrived meanwhile joins the build
+                now = time.perf_counter()
+                while next_job[0] < len(order) and len(group) < max_group and arrivals[order[next_job[0]]] <= now:
+                    group.append(order[next_job[0]])
+                    next_job[0] += 1
+            shares = collections.OrderedDict()
+            for i in group:
                 p = requests[i]
-                tb = time.perf_counter()
-                with torch.cuda.stream(stream):
-                    st = ss.Stamp.build([p], stream=stream.cuda_stream)
-                    flags = flags_for(p) if flags_for else 0
-                    op = ss.Operator.build(st, [p], flags, stream=stream.cuda_stream)
-                    f = st.forcing_vector([p], dev)
-                    u = torch.zeros_like(f)
-                    stream.synchronize()
-                n_total = st.n_total
-                st.close()
-                tol = tol64 if p.precision == "fp64" else tol32
-                built_q.put(Built(i, p, op, f, u, tol, p.precision, n_total, 1e3 * (time.perf_counter() - tb)))
-            except BaseException as e:   # surfaced by the scheduler loop
-                errors.append(e)
-                in_ready.release()
-                return
+                shares.setdefault((p.precision, flags_for(p) if flags_for else 0), []).append(i)
+            for (prec, flags), rids in shares.items():
+                in_ready.acquire()
+                try:
+                    tb = time.perf_counter()
+                    dmax = max(requests[i].d for i in rids)
+                    probs = [_padded(requests[i], dmax) for i in rids]
+                    with torch.cuda.stream(stream):
+                        st = ss.Stamp.build(probs, stream=stream.cuda_stream)
+                        op = ss.Operator.build(st, probs, flags, stream=stream.cuda_stream)
+                        f = st.forcing_vector(probs, dev, stream=stream.cuda_stream)
+                        u = torch.zeros_like(f)
+                        stream.synchronize()
+                    offsets = st.offsets.copy()
+                    st.close()
+                    with lock:
+                        tag = next_tag[0]
+                        next_tag[0] += 1
+                    tol = tol64 if prec == "fp64" else tol32
+                    built_q.put(Built(tag, rids, op, f, u, offsets, tol, prec, 1e3 * (time.perf_counter() - tb)))
+                except BaseException as e:   # surfaced by the scheduler loop
+                    errors.append(e)
+                    in_ready.release()
+                    return
 
     threads = [threading.Thread(target=builder, daemon=True) for _ in range(build_threads)]
     for t in threads:
         t.start()
     n_done = 0
     build_ms = []
+    group_sizes = []
     ticks = 0
     results = {}
 
     def take(b: Built):
-        sched.offer(b.rid, arrivals[b.rid], b)
+        sched.offer_group(b.tag, b, [(rid, arrivals[rid]) for rid in b.rids])
         build_ms.append(b.build_ms)
+        group_sizes.append(len(b.rids))
 
     while n_done < len(requests):
         if errors:
@@ -210,9 +273,11 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
             for r in sched.finished[before:]:
                 b: Built = r.result
                 if keep_results:
-                    results[r.rid] = b.u.cpu().numpy()
-                b.op.close()            # frees the operator and its workspace
+                    results[r.rid] = b.u[int(b.offsets[r.prob]):int(b.offsets[r.prob + 1])].cpu().numpy()
                 r.result = None
+            for b in sched.retired:
+                b.op.close()            # frees the operator and its workspace
+            sched.retired.clear()
             n_done = len(sched.finished)
         elif not moved:
             try:
@@ -236,6 +301,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
         "max_active": sched.max_active,
         "ticks": ticks,
         "build_ms_mean": float(np.mean(build_ms)) if build_ms else 0.0,
+        "requests_per_build_mean": float(np.mean(group_sizes)) if group_sizes else 0.0,
         "status_ok": int(sum(1 for r in recs if r.info["status"] == 0)),
         "fp32_refine": int(sum(1 for i in range(len(requests)) if requests[i].precision != "fp64")),
         "hbm_budget_bytes": int(hbm_budget_bytes),
