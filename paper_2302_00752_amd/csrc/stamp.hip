@@ -900,12 +900,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       pass_bits.push_back(used);
     }
   }
-  // With more than two words (large d), one word packed from the most significant side first:
+  // With two words or more, one word packed from the most significant side first:
   // the problem id on top, then coordinates 0, 1, ... while they fit.  If no two keys share it,
   // sorting by it alone gives the canonical order and the LSD passes are skipped.
   const int nf = (int)fields.size();
   int top_bits = 0;
-  if (passes.size() > 2) {
+  if (passes.size() >= 2) {
     std::vector<std::pair<int, int>> items{{-1, bits_for((uint64_t)(n_prob - 1))}};   // (t, bits)
     int used = items[0].second;
     for (int t = 0; t < d; ++t) {
