@@ -180,7 +180,7 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
 }
 
 __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
-                         int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out, uint8_t* lev_out,
+                         int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out,
                          int64_t* root, int64_t* norm_out, uint8_t* last_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand || !flag[t]) return;
@@ -203,7 +203,6 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   const uint64_t h = a.hash[i] + a.whash[wo + j];
   hash_out[m] = h;
   pid_out[m] = p;
-  lev_out[m] = (uint8_t)a.level;
   last_out[m] = (uint8_t)j;
   root[m] = root[i];
   const uint64_t s = (uint64_t)a.toff[p] + a.cpos[t];
@@ -268,14 +267,16 @@ __global__ void k_iota_u32(int64_t n, uint32_t* p) {
 
 // sorted key rows: one thread per (row, coordinate), so reads of a source row and the
 // writes of the output are contiguous across neighbouring threads
-// Sorted row r from unsorted row perm[r]: the key (copied in 32-bit words when d is even), the
-// problem id and level; hash and |k|^2 formed from the key on the way; inv[perm[r]] = r; the
-// block maximum of |k|^2, one atomic per block.
+// Sorted row r from unsorted row perm[r]: the key (copied in 32-bit words when d is even); the
+// problem id from the top bits of the row's sorted word; the level from where the unsorted row
+// lies (levels were appended in order: level n holds rows [lstart[n], lstart[n+1])); hash and
+// |k|^2 formed from the key on the way; inv[perm[r]] = r; the block maximum of |k|^2, one atomic
+// per block.
 __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
-                               const int32_t* __restrict__ upid, const uint8_t* __restrict__ ulev,
-                               const uint64_t* __restrict__ z, int16_t* __restrict__ keys, uint64_t* hash,
-                               int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv,
-                               unsigned long long* max_norm) {
+                               const uint64_t* __restrict__ words, int pid_shift, int pid_bits,
+                               const int64_t* __restrict__ lstart, int n_lev, const uint64_t* __restrict__ z,
+                               int16_t* __restrict__ keys, uint64_t* hash, int32_t* pid, uint8_t* lev, int64_t* norm,
+                               uint32_t* inv, unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = 0;
   if (r < n) {
@@ -301,9 +302,11 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
         nn += v * v;
       }
     }
+    int lv = 0;
+    for (int q = 1; q < n_lev; ++q) lv = lstart[q] <= s ? q : lv;
     hash[r] = h;
-    pid[r] = upid[s];
-    lev[r] = ulev[s];
+    pid[r] = pid_bits > 0 ? (int32_t)((words[r] >> pid_shift) & ((uint64_t(1) << pid_bits) - 1)) : 0;
+    lev[r] = (uint8_t)lv;
     norm[r] = nn;
     inv[s] = (uint32_t)r;
   }
@@ -702,7 +705,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   int16_t* ukeys = nullptr;
   uint64_t* uhash = nullptr;
   int32_t* upid = nullptr;
-  uint8_t* ulev = nullptr;
   uint8_t* ulast = nullptr;
   uint8_t *d_full = nullptr, *d_only = nullptr;
   int64_t* uroot = nullptr;
@@ -711,7 +713,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev);
-  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(ulev); sc.hold(uroot); sc.hold(unorm);
+  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot); sc.hold(unorm);
   sc.hold(ulast); sc.hold(d_full); sc.hold(d_only);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
@@ -732,11 +734,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- level 0: F
   int64_t kcap = std::max<int64_t>(nF * 4, 1024);
-  int64_t kcap_h = kcap, kcap_p = kcap, kcap_l = kcap, kcap_r = kcap, kcap_n = kcap, kcap_t = kcap;
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_r = kcap, kcap_n = kcap, kcap_t = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
   SS_TRY(dalloc(&upid, kcap));
-  SS_TRY(dalloc(&ulev, kcap));
   SS_TRY(dalloc(&ulast, kcap));
   SS_TRY(dalloc(&uroot, kcap));
   SS_TRY(dalloc(&unorm, kcap));
@@ -746,7 +747,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       for (int i = f_off[p]; i < f_off[p + 1]; ++i) fpid[i] = p;
     SS_HIP(h2d(ukeys, f_freqs, (size_t)nF * d * 2, stream));
     SS_HIP(h2d(upid, fpid.data(), nF * 4, stream));
-    SS_HIP(hipMemsetAsync(ulev, 0, nF, stream));
     SS_HIP(hipMemsetAsync(ulast, 0, nF, stream));
     k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
     k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash, unorm);
@@ -768,6 +768,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     fcount[p] = n_f[p];
   }
   int64_t total = nF, f0 = 0, f1 = nF, ccap = 0;
+  std::vector<int64_t> lstart{0};   // first unsorted row of each level
   size_t tmp_bytes = 0;
   std::vector<uint8_t> full(n_prob, 0), redo(n_prob, 0);   // host copies of d_full, d_only
   for (int n = 1; n <= max_level; ++n) {
@@ -779,7 +780,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&ukeys, &kcap, need, total, d, stream));
     SS_TRY(grow(&uhash, &kcap_h, need, total, 1, stream));
     SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
-    SS_TRY(grow(&ulev, &kcap_l, need, total, 1, stream));
     SS_TRY(grow(&ulast, &kcap_t, need, total, 1, stream));
     SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
     SS_TRY(grow(&unorm, &kcap_n, need, total, 1, stream));
@@ -853,8 +853,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_expand<<<cg, kBlock, 0, stream>>>(eb);
       SS_TRY(count_level());
     }
-    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, ulev, uroot, unorm, ulast);
+    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, unorm, ulast);
     f0 = total;
+    lstart.push_back(total);
     for (int p = 0; p < n_prob; ++p) {
       fstart[p] = total;
       fcount[p] = added[p];
@@ -988,8 +989,16 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint32_t* inv = perm2;
   unsigned long long* d_maxn = (unsigned long long*)k64;
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
-  k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, upid, ulev, st->d_coef, st->d_keys,
-                                                         st->d_hash, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  // the problem id sits at the top of the words the last sort ordered (k64b)
+  const int pid_bits = bits_for((uint64_t)(n_prob - 1));
+  const int pid_shift = (done ? top_bits : (passes.empty() ? 0 : pass_bits.back())) - pid_bits;
+  int64_t* d_lstart = nullptr;
+  sc.hold(d_lstart);
+  SS_TRY(dalloc(&d_lstart, lstart.size()));
+  SS_HIP(h2d(d_lstart, lstart.data(), lstart.size() * sizeof(int64_t), stream));
+  k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart,
+                                                         (int)lstart.size(), st->d_coef, st->d_keys, st->d_hash,
+                                                         st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   // the forcing frequencies are the first nF unsorted keys, in the order given
   st->n_f = nF;
