@@ -49,18 +49,13 @@ __device__ inline uint64_t atomic_load_u64(const uint64_t* p) {
 }
 
 __global__ void k_hash_keys(int64_t n, int d, const int16_t* __restrict__ keys, const uint64_t* __restrict__ z,
-                            uint64_t* __restrict__ out, int64_t* __restrict__ norm) {
+                            uint64_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t h = 0;
-  int64_t nn = 0;
   const int16_t* k = keys + i * d;
-  for (int t = 0; t < d; ++t) {
-    h += (uint64_t)(int64_t)k[t] * z[t];
-    nn += (int64_t)k[t] * k[t];
-  }
+  for (int t = 0; t < d; ++t) h += (uint64_t)(int64_t)k[t] * z[t];
   out[i] = h;
-  norm[i] = nn;
 }
 
 __global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, const int32_t* __restrict__ pid,
@@ -181,7 +176,7 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
 
 __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                          int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out,
-                         int64_t* root, int64_t* norm_out, uint8_t* last_out) {
+                         int64_t* root, uint8_t* last_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_cand || !flag[t]) return;
   const int64_t i = a.f0 + t / a.smax1;
@@ -193,13 +188,19 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   const int16_t* k = a.keys + i * d;
   const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
   int16_t* o = keys_out + m * d;
-  int64_t nn = 0;
-  for (int c = 0; c < d; ++c) {
-    const int v = (int)k[c] + (int)w[c];
-    o[c] = (int16_t)v;
-    nn += (int64_t)v * v;
+  if ((d & 1) == 0) {   // rows are 4-byte aligned: two coordinates per load and store
+    const uint32_t* k32 = reinterpret_cast<const uint32_t*>(k);
+    const uint32_t* w32 = reinterpret_cast<const uint32_t*>(w);
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(o);
+    for (int c = 0; c < d; c += 2) {
+      const uint32_t x = k32[c >> 1], y = w32[c >> 1];
+      const uint32_t lo = (uint32_t)(uint16_t)((int16_t)(x & 0xffffu) + (int16_t)(y & 0xffffu));
+      const uint32_t hi = (uint32_t)(uint16_t)((int16_t)(x >> 16) + (int16_t)(y >> 16));
+      o32[c >> 1] = lo | (hi << 16);
+    }
+  } else {
+    for (int c = 0; c < d; ++c) o[c] = (int16_t)((int)k[c] + (int)w[c]);
   }
-  norm_out[m] = nn;
   const uint64_t h = a.hash[i] + a.whash[wo + j];
   hash_out[m] = h;
   pid_out[m] = p;
@@ -708,12 +709,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint8_t* ulast = nullptr;
   uint8_t *d_full = nullptr, *d_only = nullptr;
   int64_t* uroot = nullptr;
-  int64_t* unorm = nullptr;
   uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev);
-  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot); sc.hold(unorm);
+  sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot);
   sc.hold(ulast); sc.hold(d_full); sc.hold(d_only);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
@@ -734,13 +734,12 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- level 0: F
   int64_t kcap = std::max<int64_t>(nF * 4, 1024);
-  int64_t kcap_h = kcap, kcap_p = kcap, kcap_r = kcap, kcap_n = kcap, kcap_t = kcap;
+  int64_t kcap_h = kcap, kcap_p = kcap, kcap_r = kcap, kcap_t = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
   SS_TRY(dalloc(&upid, kcap));
   SS_TRY(dalloc(&ulast, kcap));
   SS_TRY(dalloc(&uroot, kcap));
-  SS_TRY(dalloc(&unorm, kcap));
   {
     std::vector<int32_t> fpid(nF);
     for (int p = 0; p < n_prob; ++p)
@@ -749,7 +748,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(h2d(upid, fpid.data(), nF * 4, stream));
     SS_HIP(hipMemsetAsync(ulast, 0, nF, stream));
     k_iota_i64<<<grid_for(nF), kBlock, 0, stream>>>(nF, uroot);
-    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash, unorm);
+    k_hash_keys<<<grid_for(nF), kBlock, 0, stream>>>(nF, d, ukeys, st->d_coef, uhash);
   }
   // per-problem regions sized from the App. A count (grown below if coincidences are rarer than it assumes)
   std::vector<uint64_t> cap(n_prob);
@@ -782,7 +781,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(grow(&upid, &kcap_p, need, total, 1, stream));
     SS_TRY(grow(&ulast, &kcap_t, need, total, 1, stream));
     SS_TRY(grow(&uroot, &kcap_r, need, total, 1, stream));
-    SS_TRY(grow(&unorm, &kcap_n, need, total, 1, stream));
     // slots in use after this level: at most the worst case (every candidate new) and at most
     // the App. A count, which bounds |S^n| for any a (the count of coefficient vectors over the
     // +-w pairs with L1 norm <= n, per forcing frequency)
@@ -853,7 +851,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_expand<<<cg, kBlock, 0, stream>>>(eb);
       SS_TRY(count_level());
     }
-    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, unorm, ulast);
+    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, ulast);
     f0 = total;
     lstart.push_back(total);
     for (int p = 0; p < n_prob; ++p) {
