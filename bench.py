@@ -279,7 +279,7 @@ def main():
             f0 = st0.forcing_vector(problems, dev)
             u0 = torch.zeros_like(f0)
             op0.solve(f0, u0, tol, "fp64", 5000)
-            nxt = raised(problems)
+            nxt = ss.Batch(raised(problems))   # host arrays packed once
             times = {"build_next_ms": [], "proxy_ms": []}
             for _ in range(reps):
                 torch.cuda.synchronize()
