@@ -75,10 +75,10 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
         const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
         uint64_t pos = slot_first(h, base, mask);
         while (true) {
-          const ulonglong2 sv = reinterpret_cast<const ulonglong2*>(a.table)[pos];
-          if (sv.x == 0) break;
-          if (sv.y == h) {
-            const int64_t m = (int64_t)(sv.x & kIdxMask);
+          const uint64_t v = a.table[pos];
+          if (v == 0) break;
+          if (lslot_fp_eq(v, h)) {
+            const int64_t m = lslot_idx(v);
             if (key_eq_shift(a.keys + m * d, k, w, -1, d)) {
               col = m;
               break;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
   }
 }
 
-constexpr int kNbrGroup = 4;   // slots per probe group (64 bytes)
+constexpr int kNbrGroup = 8;   // lookup-table words per probe group (64 bytes)
 
 // One lane per row, for dimensions up to DMAX: the row's key and hash stay in registers while
 // the lane looks up k - w_j for the upper half of the a-table (see below).  A lookup reads the
@@ -157,7 +157,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   const int j0 = a.aoff[p], s = a.aoff[p + 1] - j0, z = a.azero[p];
   const int64_t ro = a.rowoff[p];
   const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
-  const ulonglong2* table = reinterpret_cast<const ulonglong2*>(a.table) + base;
+  const uint64_t* table = a.table + base;   // lookup table: one word per slot
   const int16_t* wsrc = UNI ? wtab : a.akeys + (int64_t)j0 * d;
   uint32_t* D = a.buf;
   const int64_t T = a.total;
@@ -168,38 +168,45 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
       const int16_t* w = wsrc + j * d;
       const uint64_t h = hr - (UNI ? htab[j] : a.ahash[j0 + j]);
       const uint64_t pos = fmix64(h) & mask;
-      const uint64_t g0 = pos & ~(uint64_t)(G - 1);
-      ulonglong2 sv[G];
+      const uint64_t g0 = pos & ~(uint64_t)(G - 1);   // regions are multiples of 64 slots: aligned
+      uint64_t sv[G];
 #pragma unroll
-      for (int i = 0; i < G; ++i) sv[i] = table[g0 + i];
+      for (int i = 0; i < G; i += 2) {
+        const ulonglong2 two = *reinterpret_cast<const ulonglong2*>(table + g0 + i);
+        sv[i] = two.x;
+        sv[i + 1] = two.y;
+      }
       bool stop = false;         // an empty slot ends the probe sequence
-      int64_t cand = -1;         // first slot (local) in probe order whose hash matches
+      int64_t cand = -1;         // first slot (local) in probe order whose fingerprint matches
+      uint64_t cv = 0;
 #pragma unroll
       for (int i = 0; i < G; ++i)
         if ((uint64_t)i >= pos - g0 && !stop && cand < 0) {
-          if (sv[i].x == 0)
+          if (sv[i] == 0) {
             stop = true;
-          else if (sv[i].y == h)
+          } else if (lslot_fp_eq(sv[i], h)) {
             cand = (int64_t)g0 + i;
+            cv = sv[i];
+          }
         }
       uint64_t next = g0 + G;    // where a probe sequence that left the group resumes
       if (cand >= 0) {
-        const int64_t c = (int64_t)(table[cand].x & kIdxMask);
+        const int64_t c = lslot_idx(cv);
         if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
           m = c;
           stop = true;
         } else {
-          next = (uint64_t)cand + 1;   // a hash collision: keep probing after it
+          next = (uint64_t)cand + 1;   // a fingerprint collision: keep probing after it
           stop = false;
         }
       }
       if (!stop) {
         uint64_t pp = next & mask;
         while (true) {
-          const ulonglong2 v = table[pp];
-          if (v.x == 0) break;
-          if (v.y == h) {
-            const int64_t c = (int64_t)(v.x & kIdxMask);
+          const uint64_t v = table[pp];
+          if (v == 0) break;
+          if (lslot_fp_eq(v, h)) {
+            const int64_t c = lslot_idx(v);
             if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
               m = c;
               break;
@@ -545,7 +552,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(rowlen);
   const int rpw = 64 / smax;
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
-             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_table, nbr, rowlen};
+             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen};
   // the mirrored half needs w_{s-1-j} = -w_j with w_z = 0 at z = (s-1)/2 in every a-table
   bool dense = d <= 64;
   for (int p = 0; dense && p < n_prob; ++p) {

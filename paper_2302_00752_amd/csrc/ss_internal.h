@@ -84,6 +84,11 @@ __device__ inline bool key_eq_shift2(const int16_t* __restrict__ b1, const int16
 __host__ __device__ inline uint64_t slot_first(uint64_t h, uint64_t base, uint64_t mask) {
   return base + (fmix64(h) & mask);
 }
+// a lookup-table word: the key's fingerprint (high half of its hash) and its canonical index + 1
+__host__ __device__ inline uint64_t lslot(uint64_t h, uint64_t idx) { return (h >> 32 << 32) | (idx + 1); }
+__host__ __device__ inline bool lslot_fp_eq(uint64_t v, uint64_t h) { return (v >> 32) == (h >> 32); }
+__host__ __device__ inline int64_t lslot_idx(uint64_t v) { return (int64_t)(v & 0xffffffffull) - 1; }
+
 __host__ __device__ inline uint64_t slot_next(uint64_t pos, uint64_t base, uint64_t mask) {
   return base + ((pos - base + 1) & mask);
 }
@@ -130,7 +135,9 @@ struct StampImpl {
   int64_t n_f = 0;                     // forcing frequencies given to the build (all problems)
   uint32_t* d_fslot = nullptr;         // [n_f] canonical slot of each, in the order given
   uint64_t* d_coef = nullptr;          // [d] hash multipliers
-  uint64_t* d_table = nullptr;         // 2 words per slot: {MAIN | canonical index, hash}
+  uint64_t* d_table = nullptr;         // build only: 2 words per slot {MAIN | canonical index, hash}
+  uint64_t* d_ltable = nullptr;        // lookups: one word per slot, the same positions:
+                                       // (hash >> 32) << 32 | (canonical index + 1), 0 = empty
   int64_t* d_toff = nullptr;           // [n_prob] first slot of each problem's region
   uint64_t* d_tmask = nullptr;         // [n_prob] region size - 1
   uint64_t n_slots = 0;

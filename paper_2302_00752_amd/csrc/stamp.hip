@@ -331,12 +331,21 @@ __global__ void k_root_out(int64_t n, const uint32_t* __restrict__ perm, const i
   if (r < n) root[r] = inv[uroot[perm[r]]];
 }
 
-__global__ void k_remap_table(uint64_t n_slots, uint64_t* table, const uint32_t* __restrict__ inv) {
+// the lookup table from the build table: same slots, one word each; with inv the build table
+// still holds unsorted indices, which are mapped to canonical ones on the way
+__global__ void k_lookup_table(uint64_t n_slots, const uint64_t* __restrict__ table, const uint32_t* __restrict__ inv,
+                               uint64_t* __restrict__ lt) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_slots) return;
   const uint64_t v = table[2 * s];
-  if ((v & kTagMask) == kTagMain) table[2 * s] = kTagMain | (uint64_t)inv[v & kIdxMask];
+  uint64_t out = 0;
+  if ((v & kTagMask) == kTagMain) {
+    const uint64_t m = v & kIdxMask;
+    out = lslot(table[2 * s + 1], inv ? (uint64_t)inv[m] : m);
+  }
+  lt[s] = out;
 }
+
 
 // first row of every problem (every problem has keys: F is not empty), and n after the last
 __global__ void k_rowoff(int64_t n, int n_prob, const int32_t* __restrict__ pid, int64_t* rowoff) {
@@ -366,7 +375,7 @@ __global__ void k_zero_c128(int64_t n, double2* f) {
 __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32_t prob,
                          const int32_t* __restrict__ probs, const uint64_t* __restrict__ z,
                          const int16_t* __restrict__ keys, const int64_t* __restrict__ toff,
-                         const uint64_t* __restrict__ tmask, const uint64_t* __restrict__ table,
+                         const uint64_t* __restrict__ tmask, const uint64_t* __restrict__ lt,
                          const int64_t* rowoff, int64_t* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
@@ -378,10 +387,10 @@ __global__ void k_lookup(int64_t nq, int d, const int16_t* __restrict__ q, int32
   uint64_t pos = slot_first(h, base, mask);
   int64_t res = -1;
   while (true) {
-    const ulonglong2 sv = reinterpret_cast<const ulonglong2*>(table)[pos];
-    if (sv.x == 0) break;
-    const int64_t m = (int64_t)(sv.x & kIdxMask);
-    if (sv.y == h) {
+    const uint64_t v = lt[pos];
+    if (v == 0) break;
+    const int64_t m = lslot_idx(v);
+    if (lslot_fp_eq(v, h)) {
       int acc = 0;
       for (int t = 0; t < d; ++t) acc |= (int)keys[m * d + t] ^ (int)k[t];
       if (acc == 0) {
@@ -1011,11 +1020,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       tight[p] = next_pow2((uint64_t)std::max<int64_t>(64, kSlotsPerKey * cnt[p]));
       shrink |= tight[p] < cap[p];
     }
-    if (shrink)
-      SS_TRY(layout_table(st, tight, total, st->d_hash, st->d_pid, stream));
-    else
-      k_remap_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(st->n_slots,
-                                                                                            st->d_table, inv);
+    if (shrink) SS_TRY(layout_table(st, tight, total, st->d_hash, st->d_pid, stream));
+    // the lookup table (the build table goes once the stream has drained, below)
+    SS_TRY(dalloc(&st->d_ltable, st->n_slots));
+    k_lookup_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(
+        st->n_slots, st->d_table, shrink ? nullptr : inv, st->d_ltable);
   }
   k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, n_prob, st->d_pid, st->d_rowoff);
   unsigned long long maxn = 0;
@@ -1023,6 +1032,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 1) * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
+  dfree(st->d_table);
   st->max_norm = (int64_t)maxn;
   for (int p = 0; p < n_prob; ++p)
     if (st->row_off[p + 1] - st->row_off[p] > kMaxRowsPerProblem)
@@ -1048,6 +1058,7 @@ void free_stamp_impl(StampImpl* st) {
   dfree(st->d_rowoff);
   dfree(st->d_coef);
   dfree(st->d_table);
+  dfree(st->d_ltable);
   dfree(st->d_toff);
   dfree(st->d_tmask);
   delete st;
@@ -1074,7 +1085,7 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   }
   SS_HIP(h2d(dq, q, (size_t)nq * st->d * 2, stream));
   k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_toff,
-                                                 st->d_tmask, st->d_table, st->d_rowoff, dout);
+                                                 st->d_tmask, st->d_ltable, st->d_rowoff, dout);
   SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   return SS_OK;
