@@ -47,10 +47,16 @@ constexpr int64_t kMaxRowsPerProblem = (1 << 22) - 1;
 constexpr int kMaxProblems = (1 << 14) - 1;
 
 // hash-slot encoding
+// Build hash table: one word per slot.  MAIN: a key of an earlier level, its index (bits 0-30)
+// and fingerprint = hash >> 33 (bits 31-61); CAND: a candidate of the level being built,
+// (frontier key << 6) | a-table index in bits 0-61.  0 = empty.
 constexpr uint64_t kTagMain = 1ull << 62;
 constexpr uint64_t kTagCand = 2ull << 62;
 constexpr uint64_t kTagMask = 3ull << 62;
 constexpr uint64_t kIdxMask = ~kTagMask;
+constexpr uint64_t kMainIdxMask = 0x7fffffffull;
+__host__ __device__ inline uint64_t main_word(uint64_t h, uint64_t idx) { return kTagMain | (h >> 33 << 31) | idx; }
+__host__ __device__ inline bool main_fp_eq(uint64_t v, uint64_t h) { return ((v >> 31) & 0x7fffffffull) == (h >> 33); }
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
 __host__ __device__ inline uint64_t fmix64(uint64_t k) {
@@ -84,9 +90,10 @@ __device__ inline bool key_eq_shift2(const int16_t* __restrict__ b1, const int16
 __host__ __device__ inline uint64_t slot_first(uint64_t h, uint64_t base, uint64_t mask) {
   return base + (fmix64(h) & mask);
 }
-// a lookup-table word: the key's fingerprint (high half of its hash) and its canonical index + 1
-__host__ __device__ inline uint64_t lslot(uint64_t h, uint64_t idx) { return (h >> 32 << 32) | (idx + 1); }
-__host__ __device__ inline bool lslot_fp_eq(uint64_t v, uint64_t h) { return (v >> 32) == (h >> 32); }
+// a lookup-table word: the key's fingerprint (hash >> 33, as in the build table) in the high half and
+// its canonical index + 1 in the low half
+__host__ __device__ inline uint64_t lslot_from_fp(uint64_t fp, uint64_t idx) { return (fp << 32) | (idx + 1); }
+__host__ __device__ inline bool lslot_fp_eq(uint64_t v, uint64_t h) { return (v >> 32) == (h >> 33); }
 __host__ __device__ inline int64_t lslot_idx(uint64_t v) { return (int64_t)(v & 0xffffffffull) - 1; }
 
 __host__ __device__ inline uint64_t slot_next(uint64_t pos, uint64_t base, uint64_t mask) {
@@ -135,7 +142,7 @@ struct StampImpl {
   int64_t n_f = 0;                     // forcing frequencies given to the build (all problems)
   uint32_t* d_fslot = nullptr;         // [n_f] canonical slot of each, in the order given
   uint64_t* d_coef = nullptr;          // [d] hash multipliers
-  uint64_t* d_table = nullptr;         // build only: 2 words per slot {MAIN | canonical index, hash}
+  uint64_t* d_table = nullptr;         // build only: one word per slot (MAIN / CAND words)
   uint64_t* d_ltable = nullptr;        // lookups: one word per slot, the same positions:
                                        // (hash >> 32) << 32 | (canonical index + 1), 0 = empty
   int64_t* d_toff = nullptr;           // [n_prob] first slot of each problem's region

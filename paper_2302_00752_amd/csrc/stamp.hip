@@ -67,12 +67,8 @@ __global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, cons
   const uint64_t h = hash[i], base = (uint64_t)toff[p], mask = tmask[p];
   uint64_t pos = slot_first(h, base, mask);
   while (true) {
-    unsigned long long old = atomicCAS((unsigned long long*)&table[2 * pos], 0ull,
-                                       (unsigned long long)(kTagMain | (uint64_t)i));
-    if (old == 0ull) {
-      table[2 * pos + 1] = h;
-      return;
-    }
+    unsigned long long old = atomicCAS((unsigned long long*)&table[pos], 0ull, (unsigned long long)main_word(h, i));
+    if (old == 0ull) return;
     pos = slot_next(pos, base, mask);
   }
 }
@@ -92,7 +88,7 @@ struct ExpandArgs {
   int32_t level;          // level being built
   const int64_t* toff;    // [n_prob] first slot of each problem's region
   const uint64_t* tmask;  // [n_prob] region size - 1
-  uint64_t* table;        // 2 words per slot
+  uint64_t* table;        // one word per slot
   uint32_t* cpos;         // [n_cand] slot of the candidate's key (region-relative), or kNoSlot
   const uint8_t* last;    // per key: a-list index of the step that created it (0 for F)
   const uint8_t* full;    // [n_prob] 1: every candidate of the problem; 0: only j >= last of its key
@@ -125,9 +121,9 @@ __global__ void k_expand(ExpandArgs a) {
   const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
   uint64_t pos = slot_first(h, base, mask);
   while (true) {
-    uint64_t v = atomic_load_u64(&a.table[2 * pos]);
+    uint64_t v = atomic_load_u64(&a.table[pos]);
     if (v == 0) {
-      unsigned long long old = atomicCAS((unsigned long long*)&a.table[2 * pos], 0ull, (unsigned long long)my);
+      unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos], 0ull, (unsigned long long)my);
       if (old == 0ull) {
         a.cpos[t] = (uint32_t)(pos - base);
         return;
@@ -135,8 +131,8 @@ __global__ void k_expand(ExpandArgs a) {
       v = old;
     }
     if ((v & kTagMask) == kTagMain) {
-      const int64_t m = (int64_t)(v & kIdxMask);
-      if (a.table[2 * pos + 1] == h && key_eq_shift(a.keys + m * d, k, w, 1, d)) {
+      const int64_t m = (int64_t)(v & kMainIdxMask);
+      if (main_fp_eq(v, h) && key_eq_shift(a.keys + m * d, k, w, 1, d)) {
         a.cpos[t] = kNoSlot;   // already in an earlier level
         return;
       }
@@ -147,7 +143,7 @@ __global__ void k_expand(ExpandArgs a) {
       if (h2 == h && key_eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo + j2) * d, k, w, d)) {
         // equal key among this level's candidates: the smallest candidate keeps the slot
         while (my < v) {
-          unsigned long long old = atomicCAS((unsigned long long*)&a.table[2 * pos], (unsigned long long)v,
+          unsigned long long old = atomicCAS((unsigned long long*)&a.table[pos], (unsigned long long)v,
                                              (unsigned long long)my);
           if (old == (unsigned long long)v) break;
           v = old;
@@ -169,7 +165,7 @@ __global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint3
   if (cpos[t] != kNoSlot) {
     const int64_t i = f0 + t / smax1;
     const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)(t % smax1);
-    f = table[2 * ((uint64_t)toff[pid[i]] + cpos[t])] == my ? 1u : 0u;
+    f = table[(uint64_t)toff[pid[i]] + cpos[t]] == my ? 1u : 0u;
   }
   flag[t] = f;
 }
@@ -207,8 +203,7 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   last_out[m] = (uint8_t)j;
   root[m] = root[i];
   const uint64_t s = (uint64_t)a.toff[p] + a.cpos[t];
-  a.table[2 * s] = kTagMain | (uint64_t)m;
-  a.table[2 * s + 1] = h;
+  a.table[s] = main_word(h, (uint64_t)m);
 }
 
 // new keys per problem of the level just built (candidates are grouped by problem)
@@ -337,11 +332,11 @@ __global__ void k_lookup_table(uint64_t n_slots, const uint64_t* __restrict__ ta
                                uint64_t* __restrict__ lt) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_slots) return;
-  const uint64_t v = table[2 * s];
+  const uint64_t v = table[s];
   uint64_t out = 0;
   if ((v & kTagMask) == kTagMain) {
-    const uint64_t m = v & kIdxMask;
-    out = lslot(table[2 * s + 1], inv ? (uint64_t)inv[m] : m);
+    const uint64_t m = v & kMainIdxMask;
+    out = lslot_from_fp((v >> 31) & 0x7fffffffull, inv ? (uint64_t)inv[m] : m);
   }
   lt[s] = out;
 }
@@ -500,10 +495,10 @@ ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t 
     SS_HIP(hipStreamSynchronize(stream));
     dfree(st->d_table);
   }
-  SS_TRY(dalloc(&st->d_table, 2 * total));
+  SS_TRY(dalloc(&st->d_table, total));
   if (!st->d_toff) SS_TRY(dalloc(&st->d_toff, np));
   if (!st->d_tmask) SS_TRY(dalloc(&st->d_tmask, np));
-  SS_HIP(hipMemsetAsync(st->d_table, 0, 2 * total * 8, stream));
+  SS_HIP(hipMemsetAsync(st->d_table, 0, total * 8, stream));
   SS_HIP(h2d(st->d_toff, off.data(), np * 8, stream));
   SS_HIP(h2d(st->d_tmask, mask.data(), np * 8, stream));
   st->n_slots = total;
