@@ -419,10 +419,9 @@ __global__ void k_compact_starts(int64_t n, const uint32_t* __restrict__ flag, c
 }
 
 template <typename NormT>
-__global__ void k_sell_fill(int64_t n_exec, const int64_t* __restrict__ exec2canon,
-                            const int64_t* __restrict__ canon2exec, const int64_t* __restrict__ rowlen,
-                            const int64_t* __restrict__ crow, const uint32_t* __restrict__ cent,
-                            const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
+__global__ void k_sell_fill(int64_t n_exec, int n_prob, const int64_t* __restrict__ exec2canon,
+                            const int64_t* __restrict__ canon2exec, const int64_t* __restrict__ crow,
+                            const uint32_t* __restrict__ cent, const int64_t* __restrict__ rowoff,
                             const int64_t* __restrict__ eoff, const int64_t* __restrict__ norm,
                             const uint32_t* __restrict__ sptr, uint32_t* __restrict__ sent,
                             NormT* __restrict__ norm_exec) {
@@ -439,9 +438,17 @@ __global__ void k_sell_fill(int64_t n_exec, const int64_t* __restrict__ exec2can
     norm_exec[e] = 0;
     return;
   }
-  const int p = pid[r];
-  const int64_t len = rowlen[r];
-  const int64_t c0 = crow[r];
+  // the problem of this slice (slices never straddle problems): a binary search over the
+  // execution offsets on values that are the same in every lane of the wavefront
+  int lo = 0, hi = n_prob;
+  const int64_t e0 = sl * kSlice;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (eoff[mid] <= e0) lo = mid;
+    else hi = mid;
+  }
+  const int p = lo;
+  const int64_t c0 = crow[r], len = crow[r + 1] - c0;
   const int64_t ro = rowoff[p], eo = eoff[p];
   // a chunk of the row's entries, then their execution columns, each round of loads in flight
   for (uint32_t q0 = 0; q0 < w; q0 += kDenseChunk) {
@@ -768,15 +775,15 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
     k_sell_fill<int64_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
-        op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
-        op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
+        op->n_exec, n_prob, op->d_exec2canon, op->d_canon2exec, op->d_crow, op->d_cent, st->d_rowoff, op->d_eoff,
+        st->d_norm, op->d_sptr, op->d_sent, ne);
   } else {
     int32_t* ne = nullptr;
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
     k_sell_fill<int32_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
-        op->n_exec, op->d_exec2canon, op->d_canon2exec, rowlen, op->d_crow, op->d_cent, st->d_pid, st->d_rowoff,
-        op->d_eoff, st->d_norm, op->d_sptr, op->d_sent, ne);
+        op->n_exec, n_prob, op->d_exec2canon, op->d_canon2exec, op->d_crow, op->d_cent, st->d_rowoff, op->d_eoff,
+        st->d_norm, op->d_sptr, op->d_sent, ne);
   }
 
   // ---- work items: runs of slices of one problem whose rows' classes fit an LDS window
