@@ -133,11 +133,17 @@ __device__ __forceinline__ bool key_is_shift(const int16_t* __restrict__ cp, con
 // The neighbour relation is symmetric (the a-table is closed under negation and sorted, so
 // w_{s-1-j} = -w_j and w_z = 0 at z = (s-1)/2): a row looks up k - w_j only for j > z, writes
 // that entry and, when l = k - w_j is present, the mirror entry (l, s-1-j) = k into l's row.
-// Entries go to a dense j-major table (entry j of row r at j * n + r; absent = kAbsent); the
-// lower half of it is cleared beforehand, the upper half and the diagonal are written here.
-constexpr uint32_t kAbsent = 0xffffffffu;
+// Entries go to a dense j-major table (entry j of row r at j * n + r; absent = all ones); the
+// lower half of it is cleared beforehand, the upper half and the diagonal are written here.  An
+// entry is `local column | j << 26` (u32), or the local column alone (u16) when every problem has
+// fewer than 65535 keys (j is then the table row the entry sits in).
+template <typename E>
+__device__ inline E dense_entry(int64_t col, int j) {
+  if (sizeof(E) == 2) return (E)col;
+  return (E)((uint32_t)col | ((uint32_t)j << kColBits));
+}
 
-template <int DMAX, bool EVEN, bool UNI, int G>
+template <int DMAX, bool EVEN, bool UNI, int G, typename E>
 __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, const int16_t* wtab,
                                         const uint64_t* htab) {
   const int d = a.d;
@@ -159,9 +165,10 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
   const uint64_t* table = a.table + base;   // lookup table: one word per slot
   const int16_t* wsrc = UNI ? wtab : a.akeys + (int64_t)j0 * d;
-  uint32_t* D = a.buf;
+  E* D = reinterpret_cast<E*>(a.buf);
+  constexpr E kNone = (E)~(E)0;
   const int64_t T = a.total;
-  D[(int64_t)z * T + r] = (uint32_t)(r - ro) | ((uint32_t)z << kColBits);
+  D[(int64_t)z * T + r] = dense_entry<E>(r - ro, z);
   for (int j = z + 1; j < s; ++j) {
     int64_t m = -1;
     {
@@ -216,8 +223,8 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
         }
       }
     }
-    D[(int64_t)j * T + r] = m >= 0 ? (uint32_t)(m - ro) | ((uint32_t)j << kColBits) : kAbsent;
-    if (m >= 0) D[(int64_t)(s - 1 - j) * T + m] = (uint32_t)(r - ro) | ((uint32_t)(s - 1 - j) << kColBits);
+    D[(int64_t)j * T + r] = m >= 0 ? dense_entry<E>(m - ro, j) : kNone;
+    if (m >= 0) D[(int64_t)(s - 1 - j) * T + m] = dense_entry<E>(r - ro, s - 1 - j);
   }
 }
 
@@ -225,40 +232,44 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
 // (the table is read kDenseChunk entries per row at a time, every load of a chunk in flight)
 constexpr int kDenseChunk = 8;
 
-__global__ void k_row_count(int64_t total, const uint32_t* __restrict__ D, const int32_t* __restrict__ pid,
+template <typename E>
+__global__ void k_row_count(int64_t total, const E* __restrict__ D, const int32_t* __restrict__ pid,
                             const int32_t* __restrict__ aoff, int64_t* rowlen) {
+  constexpr E kNone = (E)~(E)0;
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r], s = aoff[p + 1] - aoff[p];
   int64_t c = 0;
   for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
-    uint32_t v[kDenseChunk];
+    E v[kDenseChunk];
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kAbsent;
+    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kNone;
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) c += v[u] != kAbsent;
+    for (int u = 0; u < kDenseChunk; ++u) c += v[u] != kNone;
   }
   rowlen[r] = c;
 }
 
-__global__ void k_csr_from_dense(int64_t total, const uint32_t* __restrict__ D, const int32_t* __restrict__ pid,
+template <typename E>
+__global__ void k_csr_from_dense(int64_t total, const E* __restrict__ D, const int32_t* __restrict__ pid,
                                  const int32_t* __restrict__ aoff, const int64_t* __restrict__ crow,
                                  uint32_t* __restrict__ cent) {
+  constexpr E kNone = (E)~(E)0;
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r], s = aoff[p + 1] - aoff[p];
   int64_t q = crow[r];
   for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
-    uint32_t v[kDenseChunk];
+    E v[kDenseChunk];
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kAbsent;
+    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kNone;
 #pragma unroll
     for (int u = 0; u < kDenseChunk; ++u)
-      if (v[u] != kAbsent) cent[q++] = v[u];
+      if (v[u] != kNone) cent[q++] = sizeof(E) == 2 ? (uint32_t)v[u] | ((uint32_t)(j0 + u) << kColBits) : (uint32_t)v[u];
   }
 }
 
-template <int DMAX, bool EVEN>
+template <int DMAX, bool EVEN, typename E>
 __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
   __shared__ int16_t s_w[kBlock / 64][kMaxA * DMAX];
   __shared__ uint64_t s_h[kBlock / 64][kMaxA];
@@ -277,9 +288,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
   if (!live) return;
   constexpr int G = kNbrGroup;
   if (uni)
-    nbr_row<DMAX, EVEN, true, G>(a, r, p, s_w[wv], s_h[wv]);
+    nbr_row<DMAX, EVEN, true, G, E>(a, r, p, s_w[wv], s_h[wv]);
   else
-    nbr_row<DMAX, EVEN, false, G>(a, r, p, nullptr, nullptr);
+    nbr_row<DMAX, EVEN, false, G, E>(a, r, p, nullptr, nullptr);
 }
 
 __global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
@@ -551,15 +562,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
 
   // ---- neighbour map: for d <= 64, half the lookups into a dense j-major table (the other
   // half mirrored); above, one lane per (row, j) with rows compacted in j order
-  uint32_t* nbr = nullptr;
-  int64_t* rowlen = nullptr;
-  SS_TRY(dalloc(&nbr, (size_t)total * smax));
-  track(nbr);
-  SS_TRY(dalloc(&rowlen, total + 1));
-  track(rowlen);
-  const int rpw = 64 / smax;
-  NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
-             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen};
+  int64_t max_rows = 1;
+  for (int p = 0; p < n_prob; ++p) max_rows = std::max(max_rows, st->row_off[p + 1] - st->row_off[p]);
+  const bool narrow = max_rows < 65535;   // 16-bit dense entries (0xffff = absent)
   // the mirrored half needs w_{s-1-j} = -w_j with w_z = 0 at z = (s-1)/2 in every a-table
   bool dense = d <= 64;
   for (int p = 0; dense && p < n_prob; ++p) {
@@ -569,21 +574,35 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     for (int j = 0; dense && j < s; ++j)
       for (int t = 0; t < d; ++t) dense &= ak[(int64_t)j * d + t] == -ak[(int64_t)(s - 1 - j) * d + t];
   }
+  uint32_t* nbr = nullptr;
+  int64_t* rowlen = nullptr;
+  SS_TRY(dalloc(&nbr, dense && narrow ? ceil_div((int64_t)total * smax, 2) : (int64_t)total * smax));
+  track(nbr);
+  SS_TRY(dalloc(&rowlen, total + 1));
+  track(rowlen);
+  const int rpw = 64 / smax;
+  NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
+             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen};
   if (dense) {
     int zmax = 0;
     for (int p = 0; p < n_prob; ++p) zmax = std::max(zmax, st->a_zero[p]);
-    SS_HIP(hipMemsetAsync(nbr, 0xff, (size_t)zmax * total * 4, stream));   // the mirrored half
+    SS_HIP(hipMemsetAsync(nbr, 0xff, (size_t)zmax * total * (narrow ? 2 : 4), stream));   // the mirrored half
     const unsigned g = xcd_grid(ceil_div(total, kBlock));
     const bool even = d % 2 == 0;
-    if (d <= 8)
-      even ? k_neighbors_row<8, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<8, false><<<g, kBlock, 0, stream>>>(na);
-    else if (d <= 16)
-      even ? k_neighbors_row<16, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false><<<g, kBlock, 0, stream>>>(na);
-    else if (d <= 32)
-      even ? k_neighbors_row<32, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false><<<g, kBlock, 0, stream>>>(na);
-    else
-      even ? k_neighbors_row<64, true><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false><<<g, kBlock, 0, stream>>>(na);
-    k_row_count<<<g, kBlock, 0, stream>>>(total, nbr, st->d_pid, st->d_aoff, rowlen);
+    auto launch = [&](auto entry) {
+      using E = decltype(entry);
+      if (d <= 8)
+        even ? k_neighbors_row<8, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<8, false, E><<<g, kBlock, 0, stream>>>(na);
+      else if (d <= 16)
+        even ? k_neighbors_row<16, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false, E><<<g, kBlock, 0, stream>>>(na);
+      else if (d <= 32)
+        even ? k_neighbors_row<32, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false, E><<<g, kBlock, 0, stream>>>(na);
+      else
+        even ? k_neighbors_row<64, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false, E><<<g, kBlock, 0, stream>>>(na);
+      k_row_count<E><<<g, kBlock, 0, stream>>>(total, reinterpret_cast<const E*>(nbr), st->d_pid, st->d_aoff, rowlen);
+    };
+    if (narrow) launch(uint16_t{});
+    else launch(uint32_t{});
   } else {
     k_neighbors<<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
   }
@@ -606,9 +625,13 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
   SS_TRY(dalloc(&op->d_cent, op->nnz));
-  if (dense)
-    k_csr_from_dense<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, nbr, st->d_pid, st->d_aoff,
-                                                                               op->d_crow, op->d_cent);
+  if (dense && narrow)
+    k_csr_from_dense<uint16_t><<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(
+        total, reinterpret_cast<const uint16_t*>(nbr), st->d_pid, st->d_aoff, op->d_crow, op->d_cent);
+  else if (dense)
+    k_csr_from_dense<uint32_t><<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, nbr, st->d_pid,
+                                                                                         st->d_aoff, op->d_crow,
+                                                                                         op->d_cent);
   else
     k_csr_copy<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
 
@@ -647,8 +670,6 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(ev);
   SS_TRY(dalloc(&ev2, total));
   track(ev2);
-  int64_t max_rows = 1;
-  for (int p = 0; p < n_prob; ++p) max_rows = std::max(max_rows, st->row_off[p + 1] - st->row_off[p]);
   int lb = 1;
   while ((int64_t(1) << lb) < max_rows) ++lb;
   int pb = 0;
