@@ -74,9 +74,9 @@ __global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, cons
 }
 
 struct ExpandArgs {
-  int64_t n_cand;         // frontier size * smax1
-  int64_t f0;             // first frontier key
-  int32_t smax1;          // max nonzero w per problem
+  int64_t n_cand;         // frontier size * smax1: an upper bound of the listed candidates
+  const uint32_t* n_act;  // the listed candidates (device)
+  const uint64_t* cand;   // [n_cand] listed candidates, (frontier key << 6) | a-table index
   int32_t d;
   const int16_t* keys;    // unsorted keys
   const uint64_t* hash;
@@ -84,15 +84,10 @@ struct ExpandArgs {
   const int16_t* wkeys;   // nonzero a-support, concatenated per problem
   const uint64_t* whash;
   const int32_t* woff;    // [n_prob+1]
-  const int32_t* plevel;  // [n_prob] stamping level of each problem
-  int32_t level;          // level being built
   const int64_t* toff;    // [n_prob] first slot of each problem's region
   const uint64_t* tmask;  // [n_prob] region size - 1
   uint64_t* table;        // one word per slot
   uint32_t* cpos;         // [n_cand] slot of the candidate's key (region-relative), or kNoSlot
-  const uint8_t* last;    // per key: a-list index of the step that created it (0 for F)
-  const uint8_t* full;    // [n_prob] 1: every candidate of the problem; 0: only j >= last of its key
-  const uint8_t* only;    // [n_prob] or null: a second pass over these problems, others untouched
 };
 
 // In generic position every key of level n has a unique representation f + sum of n entries of
@@ -102,22 +97,18 @@ struct ExpandArgs {
 // with every candidate, and the problem keeps full generation from there on.
 __global__ void k_expand(ExpandArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n_cand) return;
-  const int64_t i = a.f0 + t / a.smax1;
-  const int j = (int)(t % a.smax1);
+  if (t >= (int64_t)*a.n_act) return;
+  const uint64_t c = a.cand[t];
+  const int64_t i = (int64_t)(c >> 6);
+  const int j = (int)(c & 63);
   const int p = a.pid[i];
-  if (a.only && !a.only[p]) return;
   const int wo = a.woff[p];
-  if (j >= a.woff[p + 1] - wo || a.plevel[p] < a.level || (!a.full[p] && j < (int)a.last[i])) {
-    a.cpos[t] = kNoSlot;
-    return;
-  }
   const int d = a.d;
   const int16_t* k = a.keys + i * d;
   const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
   // (every candidate stays in the int16 range: the build checks the ranges of S^n beforehand)
   const uint64_t h = a.hash[i] + a.whash[wo + j];
-  const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)j;
+  const uint64_t my = kTagCand | c;
   const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
   uint64_t pos = slot_first(h, base, mask);
   while (true) {
@@ -156,16 +147,16 @@ __global__ void k_expand(ExpandArgs a) {
   }
 }
 
-__global__ void k_winners(int64_t n_cand, int64_t f0, int32_t smax1, const uint32_t* __restrict__ cpos,
-                          const int32_t* __restrict__ pid, const int64_t* __restrict__ toff,
-                          const uint64_t* __restrict__ table, uint32_t* __restrict__ flag) {
+__global__ void k_winners(int64_t n_cand, const uint32_t* __restrict__ n_act, const uint64_t* __restrict__ cand,
+                          const uint32_t* __restrict__ cpos, const int32_t* __restrict__ pid,
+                          const int64_t* __restrict__ toff, const uint64_t* __restrict__ table,
+                          uint32_t* __restrict__ flag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_cand) return;
   uint32_t f = 0;
-  if (cpos[t] != kNoSlot) {
-    const int64_t i = f0 + t / smax1;
-    const uint64_t my = kTagCand | ((uint64_t)i << 6) | (uint64_t)(t % smax1);
-    f = table[(uint64_t)toff[pid[i]] + cpos[t]] == my ? 1u : 0u;
+  if (t < (int64_t)*n_act && cpos[t] != kNoSlot) {
+    const uint64_t c = cand[t];
+    f = table[(uint64_t)toff[pid[c >> 6]] + cpos[t]] == (kTagCand | c) ? 1u : 0u;
   }
   flag[t] = f;
 }
@@ -174,9 +165,10 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
                          int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out,
                          int64_t* root, uint8_t* last_out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n_cand || !flag[t]) return;
-  const int64_t i = a.f0 + t / a.smax1;
-  const int j = (int)(t % a.smax1);
+  if (t >= (int64_t)*a.n_act || !flag[t]) return;
+  const uint64_t c = a.cand[t];
+  const int64_t i = (int64_t)(c >> 6);
+  const int j = (int)(c & 63);
   const int p = a.pid[i];
   const int wo = a.woff[p];
   const int d = a.d;
@@ -207,17 +199,44 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
 }
 
 // new keys per problem of the level just built (candidates are grouped by problem)
-__global__ void k_level_counts(int n_prob, int64_t f0, int32_t smax1, const int64_t* __restrict__ fstart,
-                               const int64_t* __restrict__ fcount, const uint32_t* __restrict__ idx,
-                               const uint32_t* __restrict__ flag, int64_t* __restrict__ out) {
+__global__ void k_level_counts(int n_prob, int64_t f0, const int64_t* __restrict__ fstart,
+                               const int64_t* __restrict__ fcount, const uint32_t* __restrict__ coff,
+                               const uint32_t* __restrict__ idx, const uint32_t* __restrict__ flag,
+                               int64_t* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_prob) return;
-  if (fcount[p] == 0) {
-    out[p] = 0;
+  const int64_t c0 = coff[fstart[p] - f0], c1 = coff[fstart[p] + fcount[p] - f0];
+  out[p] = c1 > c0 ? (int64_t)idx[c1 - 1] + flag[c1 - 1] - (int64_t)idx[c0] : 0;
+}
+
+// Candidates of a level, listed densely: frontier key f0 + t takes its nonzero a-table entries
+// from the one that created it on (every entry when its problem generates in full), none once
+// its problem's level is reached.  Counts first, then, from their exclusive sum, the list.
+__global__ void k_cand_count(int64_t n_front, int64_t f0, const int32_t* __restrict__ pid,
+                             const int32_t* __restrict__ woff, const int32_t* __restrict__ plevel, int level,
+                             const uint8_t* __restrict__ full, const uint8_t* __restrict__ last,
+                             uint32_t* __restrict__ cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n_front) return;
+  if (t == n_front) {   // the scan's last element: the total lands in coff[n_front]
+    cnt[t] = 0;
     return;
   }
-  const int64_t c0 = (fstart[p] - f0) * smax1, c1 = c0 + fcount[p] * smax1;
-  out[p] = (int64_t)idx[c1 - 1] + flag[c1 - 1] - (int64_t)idx[c0];
+  const int64_t i = f0 + t;
+  const int p = pid[i];
+  const int nw = woff[p + 1] - woff[p];
+  cnt[t] = plevel[p] < level ? 0u : (uint32_t)(full[p] ? nw : nw - (int)last[i]);
+}
+
+__global__ void k_cand_fill(int64_t n_front, int64_t f0, const int32_t* __restrict__ pid,
+                            const uint8_t* __restrict__ full, const uint8_t* __restrict__ last,
+                            const uint32_t* __restrict__ coff, uint64_t* __restrict__ cand) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_front) return;
+  const int64_t i = f0 + t;
+  const uint32_t c0 = coff[t], n = coff[t + 1] - c0;
+  const uint32_t lo = full[pid[i]] ? 0u : (uint32_t)last[i];
+  for (uint32_t q = 0; q < n; ++q) cand[c0 + q] = ((uint64_t)i << 6) | (uint64_t)(lo + q);
 }
 
 // one packed field of a radix pass: coordinate t (or -1 = problem id), minus `lo`, at bit `shift`
@@ -711,15 +730,16 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   uint64_t* uhash = nullptr;
   int32_t* upid = nullptr;
   uint8_t* ulast = nullptr;
-  uint8_t *d_full = nullptr, *d_only = nullptr;
+  uint8_t* d_full = nullptr;
   int64_t* uroot = nullptr;
-  uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr;
+  uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr, *ccnt = nullptr, *coff = nullptr;
+  uint64_t* cand = nullptr;
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev);
   sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot);
-  sc.hold(ulast); sc.hold(d_full); sc.hold(d_only);
-  sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp);
+  sc.hold(ulast); sc.hold(d_full);
+  sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp); sc.hold(ccnt); sc.hold(coff); sc.hold(cand);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
   SS_TRY(dalloc(&wk, wkeys.size()));
   SS_TRY(dalloc(&wh, whash.size()));
@@ -729,7 +749,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&d_fcount, n_prob));
   SS_TRY(dalloc(&d_cnt, n_prob));
   SS_TRY(dalloc(&d_full, n_prob));
-  SS_TRY(dalloc(&d_only, n_prob));
   SS_HIP(hipMemsetAsync(d_full, 0, n_prob, stream));
   if (!wkeys.empty()) SS_HIP(h2d(wk, wkeys.data(), wkeys.size() * 2, stream));
   if (!whash.empty()) SS_HIP(h2d(wh, whash.data(), whash.size() * 8, stream));
@@ -770,10 +789,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     fstart[p] = f_off[p];
     fcount[p] = n_f[p];
   }
-  int64_t total = nF, f0 = 0, f1 = nF, ccap = 0;
+  int64_t total = nF, f0 = 0, f1 = nF, ccap = 0, fcap = 0;
   std::vector<int64_t> lstart{0};   // first unsorted row of each level
   size_t tmp_bytes = 0;
-  std::vector<uint8_t> full(n_prob, 0), redo(n_prob, 0);   // host copies of d_full, d_only
+  std::vector<uint8_t> full(n_prob, 0), redo(n_prob, 0);   // host copy of d_full; problems completed again
   for (int n = 1; n <= max_level; ++n) {
     const int64_t n_front = f1 - f0;
     if (n_front == 0) break;
@@ -803,35 +822,57 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       sc.retire(cpos);
       sc.retire(flag);
       sc.retire(idx);
+      sc.retire(cand);
       ccap = n_cand;
       SS_TRY(dalloc(&cpos, ccap));
       SS_TRY(dalloc(&flag, ccap));
       SS_TRY(dalloc(&idx, ccap));
+      SS_TRY(dalloc(&cand, ccap));
     }
-    ExpandArgs ea{n_cand, f0, smax1, d, ukeys, uhash, upid, wk, wh, wo, plev, n, st->d_toff, st->d_tmask,
-                  st->d_table, cpos, ulast, d_full, nullptr};
+    if (n_front + 1 > fcap) {
+      sc.retire(ccnt);
+      sc.retire(coff);
+      fcap = n_front + 1;
+      SS_TRY(dalloc(&ccnt, fcap));
+      SS_TRY(dalloc(&coff, fcap));
+    }
+    ExpandArgs ea{n_cand, coff + n_front, cand, d, ukeys, uhash, upid, wk, wh, wo, st->d_toff, st->d_tmask,
+                  st->d_table, cpos};
     const unsigned cg = grid_for(n_cand);
     SS_HIP(h2d(d_fstart, fstart.data(), n_prob * 8, stream));
     SS_HIP(h2d(d_fcount, fcount.data(), n_prob * 8, stream));
     std::vector<int64_t> added(n_prob);
-    // winners, their positions and the new keys per problem of the candidates in cpos
-    auto count_level = [&]() -> ss_status {
-      k_winners<<<cg, kBlock, 0, stream>>>(n_cand, f0, smax1, cpos, upid, st->d_toff, st->d_table, flag);
+    auto scan_u32 = [&](const uint32_t* in, uint32_t* out, int64_t n_items) -> ss_status {
       size_t need_tmp = 0;
-      SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, flag, idx, n_cand, stream));
+      SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need_tmp, in, out, n_items, stream));
       if (need_tmp > tmp_bytes) {
-        dfree(tmp);
+        sc.retire(tmp);   // an earlier scan of this level may still be queued on it
         SS_HIP(pool_alloc((void**)&tmp, need_tmp));
         tmp_bytes = need_tmp;
       }
-      SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, n_cand, stream));
-      k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, smax1, d_fstart, d_fcount, idx, flag,
+      SS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, in, out, n_items, stream));
+      return SS_OK;
+    };
+    // the level's candidates, densely listed from the current generation modes
+    auto list_candidates = [&]() -> ss_status {
+      k_cand_count<<<grid_for(n_front + 1), kBlock, 0, stream>>>(n_front, f0, upid, wo, plev, n, d_full, ulast,
+                                                                 ccnt);
+      SS_TRY(scan_u32(ccnt, coff, n_front + 1));
+      k_cand_fill<<<grid_for(n_front), kBlock, 0, stream>>>(n_front, f0, upid, d_full, ulast, coff, cand);
+      return SS_OK;
+    };
+    // winners, their positions and the new keys per problem of the listed candidates
+    auto count_level = [&]() -> ss_status {
+      k_winners<<<cg, kBlock, 0, stream>>>(n_cand, coff + n_front, cand, cpos, upid, st->d_toff, st->d_table, flag);
+      SS_TRY(scan_u32(flag, idx, n_cand));
+      k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, d_fstart, d_fcount, coff, idx, flag,
                                                               d_cnt);
       SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
       SS_HIP(hipStreamSynchronize(stream));
       sc.release_retired();
       return SS_OK;
     };
+    SS_TRY(list_candidates());
     k_expand<<<cg, kBlock, 0, stream>>>(ea);
     SS_TRY(count_level());
     // a problem generating once per key that found fewer new keys than the App. A count met a
@@ -848,11 +889,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       }
     }
     if (again) {
+      // every candidate of those problems: the list is made again (candidates already inserted
+      // find their own or an equal smaller candidate's slot, so repeating them changes nothing)
       SS_HIP(h2d(d_full, full.data(), n_prob, stream));
-      SS_HIP(h2d(d_only, redo.data(), n_prob, stream));
-      ExpandArgs eb = ea;
-      eb.only = d_only;
-      k_expand<<<cg, kBlock, 0, stream>>>(eb);
+      SS_TRY(list_candidates());
+      k_expand<<<cg, kBlock, 0, stream>>>(ea);
       SS_TRY(count_level());
     }
     k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, ulast);
@@ -869,6 +910,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   sc.retire(cpos);   // the last k_append may still read them
   sc.retire(flag);
   sc.retire(idx);
+  sc.retire(cand);
+  sc.retire(ccnt);
+  sc.retire(coff);
   dfree(tmp);        // its last user, a scan, is behind the last sync
   tmp_bytes = 0;
 
