@@ -202,6 +202,32 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
 ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const void* u_dev,
                          int64_t n_u, const double* f_hat, double* err_out, void* stream);
 
+/* ss_solve_direct -- the paper's own solver (Alg. 1, steps 4-5: dense assembly of L_N and a
+ * direct solve), run per connected class (Sec. 6; the system is block diagonal over classes, proof
+ * of Prop. SolutionSupport).  Each class block is assembled densely in FP64 and factored as L L^H
+ * (Cholesky; the block is Hermitian positive definite on k != 0 by Prop.
+ * ExistenceUniquenessStability), then L y = f, L^H u = y.  The zero frequency gets u_0 = 0.
+ *   f_dev: device, n_total complex128 in canonical order (as for ss_solve_op; f_0 is ignored).
+ *   u_dev: device, n_total complex128 in canonical order; out only.
+ *   info (host, nullable): factorisation time and size, see ss_direct_info.
+ * Memory: the lower triangle of every class block, in chunks of consecutive classes of at most
+ * 6 GiB (one class per chunk at least).
+ * Errors: SS_ERANGE (a class of more than 8192 rows), SS_ENOTPD (a non-positive pivot: u is then
+ * not a solution), SS_ENOMEM, SS_EDEVICE.  Synchronises `stream`. */
+typedef struct {
+  double factor_ms;       /* device time of the factorisation kernels, summed over chunks       */
+  int64_t tiles;          /* 32 x 32 complex tiles of the lower triangles factored               */
+  int32_t chunks;         /* chunks the classes were factored in                                 */
+  int32_t reserved;
+} ss_direct_info;
+ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void* stream,
+                          ss_direct_info* info);
+
+/* rows of every connected class of op (Sec. 6), in execution order (problem by problem).
+ *   sizes (host, nullable): cap entries; n_out: the number of classes.  cap smaller than the
+ *   number of classes with sizes != NULL -> SS_EINVAL. */
+ss_status ss_op_class_sizes(const ss_op* op, int64_t cap, int64_t* sizes, int64_t* n_out);
+
 void ss_free_op(ss_op* op);
 
 /* device bytes held by op, including its solver workspace once a solve ran */

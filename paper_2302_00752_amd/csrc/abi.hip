@@ -208,6 +208,34 @@ ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const vo
   });
 }
 
+ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void* stream, ss_direct_info* info) {
+  return guarded([&]() -> ss_status {
+    if (!op || !op->impl) return fail(SS_EINVAL, "null operator");
+    DirectStats st;
+    const ss_status r = direct_solve_impl(op->impl, f_dev, u_dev, as_stream(stream), info ? &st : nullptr);
+    if (info) {
+      info->factor_ms = st.factor_ms;
+      info->tiles = st.tiles;
+      info->chunks = st.chunks;
+      info->reserved = 0;
+    }
+    return r;
+  });
+}
+
+ss_status ss_op_class_sizes(const ss_op* op, int64_t cap, int64_t* sizes, int64_t* n_out) {
+  return guarded([&]() -> ss_status {
+    if (!op || !op->impl || !n_out) return fail(SS_EINVAL, "null argument");
+    const std::vector<int64_t>& n = op->impl->cls_n;
+    *n_out = (int64_t)n.size();
+    if (sizes) {
+      if (cap < (int64_t)n.size()) return fail(SS_EINVAL, "sizes holds fewer entries than there are classes");
+      std::copy(n.begin(), n.end(), sizes);
+    }
+    return SS_OK;
+  });
+}
+
 ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double tol, ss_precision prec,
                       int32_t max_iter, void* stream, ss_solve_info* info) {
   return guarded([&]() -> ss_status {

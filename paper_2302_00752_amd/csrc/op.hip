@@ -726,6 +726,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   std::vector<int64_t> ce0(n_cls);                       // global exec row of each class start
   std::vector<std::vector<int64_t>> cbounds(n_prob);     // local class starts + problem end
   op->eoff.assign(n_prob + 1, 0);
+  op->cls_e0.clear();
+  op->cls_n.clear();
   {
     size_t k = 0;
     for (int p = 0; p < n_prob; ++p) {
@@ -735,6 +737,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
         const int64_t size = (k + 1 < cq.size() ? std::min(cq[k + 1], q1) : q1) - cq[k];
         const int64_t pad = (kSlice - size % kSlice) % kSlice;
         ce0[k] = op->eoff[p] + cur;
+        op->cls_e0.push_back(ce0[k]);
+        op->cls_n.push_back(size);
         cbounds[p].push_back(cur);
         cur += size + (pad * 8 <= size ? pad : 0);
         ++k;

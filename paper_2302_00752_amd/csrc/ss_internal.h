@@ -202,6 +202,8 @@ struct OpImpl {
   std::vector<int64_t> row_off;        // canonical offsets [n_prob+1]
   std::vector<int64_t> eoff;           // exec offsets [n_prob+1]
   std::vector<int32_t> comps;          // classes per problem
+  std::vector<int64_t> cls_e0;         // first global exec row of every class, in exec order
+  std::vector<int64_t> cls_n;          // rows of every class
   std::vector<int64_t> nnz_p;          // per problem
   std::vector<int4> work;               // {problem, first slice, slices | window rows << 16, window start row}
   std::vector<int2> wrange;
@@ -273,6 +275,12 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
 // proxy error of level-N solutions u (canonical order of the level-N stamp) from the stamp and
 // operator built at level N + 1 (proxy.hip); err: host [n_prob]
+struct DirectStats {
+  double factor_ms = 0;    // factorisation kernels (all tile columns), summed over chunks
+  int64_t tiles = 0;       // lower 32 x 32 tiles factored
+  int32_t chunks = 0;      // chunks of classes the workspace budget split the batch into
+};
+ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, hipStream_t s, DirectStats* stats);
 ss_status proxy_error_impl(const StampImpl* st, const OpImpl* op, const void* u, int64_t n_u, const double* f_hat,
                            double* err, hipStream_t stream);
 

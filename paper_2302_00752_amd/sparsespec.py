@@ -29,7 +29,7 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
             "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
-            "ss_proxy_error"]
+            "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes"]
 
 
 class SolveInfo(C.Structure):
@@ -39,6 +39,13 @@ class SolveInfo(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class DirectInfo(C.Structure):
+    _fields_ = [("factor_ms", C.c_double), ("tiles", C.c_int64), ("chunks", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class SparseSpecError(RuntimeError):
@@ -82,6 +89,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_batch_size": [P, pi64, pi64],
         "ss_batch_solution": [P, P, P],
         "ss_proxy_error": [P, P, P, i64, pd, pd, P],
+        "ss_solve_direct": [P, P, P, P, C.POINTER(DirectInfo)],
+        "ss_op_class_sizes": [P, i64, pi64, pi64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -280,6 +289,21 @@ class Operator:
         if raise_on_error:
             _check(st)
         return [i.as_dict() for i in info]
+
+    def solve_direct(self, f, u, stream=None) -> dict:
+        """Dense direct solve of L_N u = f per connected class (device complex128, canonical order)."""
+        info = DirectInfo()
+        _check(_lib.ss_solve_direct(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                    C.c_void_p(_stream(stream)), C.byref(info)))
+        return info.as_dict()
+
+    def class_sizes(self) -> np.ndarray:
+        """Rows of every connected class, in execution order."""
+        n = C.c_int64()
+        _check(_lib.ss_op_class_sizes(self._h, 0, None, C.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int64)
+        _check(_lib.ss_op_class_sizes(self._h, int(n.value), _ptr(out, C.c_int64), C.byref(n)))
+        return out[:n.value]
 
     def device_bytes(self) -> int:
         b = C.c_int64()
