@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # dense FP64 MFMA peak of one MI355X
 
 
 def log(*a):
@@ -82,6 +83,8 @@ def main():
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
     ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
+    ap.add_argument("--direct", type=int, default=16,
+                    help="d=10 problems for the dense direct (Cholesky) solve comparison (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -321,6 +324,56 @@ def main():
             f"{med_l['proxy_ms']:.2f} ms; cfg2 B={Bc} (S^4: {n_c} rows): build {med_c['build_next_ms']:.1f} ms + "
             f"proxy {med_c['proxy_ms']:.2f} ms; decay d=1024 {['%.2e' % v for v in decay['d=1024']]}")
 
+    # --- the paper's own solver: dense assembly + direct (Cholesky) solve per class, against PCG
+    direct = None
+    if args.direct > 0:
+        Bd = args.direct
+        dp = [workloads.make(2, i) for i in range(Bd)]
+        std = ss.Stamp.build(dp)
+        opd = ss.Operator.build(std, dp, 0)
+        fdv = std.forcing_vector(dp, dev)
+        sizes = opd.class_sizes()
+        flops = float(4.0 / 3.0 * (sizes.astype(np.float64) ** 3).sum())   # complex Cholesky, 4 n^3 / 3
+        ud = torch.zeros_like(fdv)
+        opd.solve_direct(fdv, ud)
+        t_dir, t_fac = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info_d = opd.solve_direct(fdv, ud)
+            t_dir.append(1e3 * (time.perf_counter() - t))
+            t_fac.append(info_d["factor_ms"])
+        t_pcg = {}
+        for prec in ("fp64", "fp32_refine"):
+            up = torch.zeros_like(fdv)
+            opd.solve(fdv, up, args.tol, prec, 1000)
+            ts = []
+            for _ in range(3):
+                up.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                opd.solve(fdv, up, args.tol, prec, 1000)
+                ts.append(1e3 * (time.perf_counter() - t))
+            t_pcg[prec] = float(np.median(ts))
+            if prec == "fp64":
+                diff = float(torch.linalg.norm(up - ud).item() / torch.linalg.norm(up).item())
+        med_d, med_f = float(np.median(t_dir)), float(np.median(t_fac))
+        tflops = flops / (med_f / 1e3) / 1e12
+        direct = {"batch": Bd, "classes": int(len(sizes)), "class_rows_max": int(sizes.max()),
+                  "solve_ms": med_d, "factor_ms": med_f, "chunks": int(info_d["chunks"]),
+                  "solves_per_s": Bd / (med_d / 1e3),
+                  "pcg_fp64_solves_per_s": Bd / (t_pcg["fp64"] / 1e3),
+                  "pcg_fp32_refine_solves_per_s": Bd / (t_pcg["fp32_refine"] / 1e3),
+                  "rel_diff_vs_pcg_fp64": diff,
+                  "roofline": {"bound": "mfma", "kernel": "k_dn_update + k_dn_panel (all tile columns)",
+                               "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": tflops / FP64_PEAK_TFLOPS, "flops_per_call": flops}}
+        log(f"direct: B={Bd} ({len(sizes)} classes of <= {sizes.max()} rows): {med_d:.1f} ms "
+            f"(factor {med_f:.1f} ms = {tflops:.1f} TFLOP/s), PCG fp64 {t_pcg['fp64']:.2f} ms; rel diff {diff:.1e}")
+        std.close()
+        opd.close()
+        del ud, fdv
+
     # --- serving: Poisson stream of heterogeneous requests, continuous batching
     serving = None
     if args.serve > 0:
@@ -374,6 +427,7 @@ def main():
                      "measured_copy_GB/s": copy_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
         "proxy_error": proxy,
+        "direct_solve": direct,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -210,8 +210,8 @@ ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const vo
  *   f_dev: device, n_total complex128 in canonical order (as for ss_solve_op; f_0 is ignored).
  *   u_dev: device, n_total complex128 in canonical order; out only.
  *   info (host, nullable): factorisation time and size, see ss_direct_info.
- * Memory: the lower triangle of every class block, in chunks of consecutive classes of at most
- * 6 GiB (one class per chunk at least).
+ * Memory: the lower triangle of every class block, in chunks of consecutive classes of about equal
+ * size and at most 16 GiB (one class per chunk at least).
  * Errors: SS_ERANGE (a class of more than 8192 rows), SS_ENOTPD (a non-positive pivot: u is then
  * not a solution), SS_ENOMEM, SS_EDEVICE.  Synchronises `stream`. */
 typedef struct {

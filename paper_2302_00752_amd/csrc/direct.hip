@@ -5,13 +5,14 @@
 // Each class block is Hermitian positive definite on the nonzero frequencies (the operator is
 // Hermitian, and coercive by Prop. ExistenceUniquenessStability); the zero frequency has an
 // all-zero row and column, and is given the identity instead (u_0 = 0).  The block is factored
-// by a tiled left-looking Cholesky, L L^H, in FP64:
-//   for every tile column j:  A_ij -= sum_{s<j} L_is L_js^H   (i >= j; FP64 MFMA, split over s)
-//                             L_jj = chol(A_jj);  L_ij = A_ij L_jj^{-H}   (i > j)
-// then L y = f and L^H u = y by tile substitution.  Storage: per class the lower triangle of
-// 32 x 32 complex tiles, each tile column-major and contiguous (16 KB), row-major over tiles:
-// tile (i, j), j <= i, is number i (i + 1) / 2 + j.  The factored diagonal tiles go to a
-// separate array, so a step that factors A_jj never writes a tile other blocks still read.
+// by a tiled left-looking Cholesky, L L^H, in FP64, two launches per tile column j:
+//   diagonal:   A_jj -= sum_{s<j} L_js L_js^H;  L_jj = chol(A_jj);  M_j = L_jj^{-1}
+//   below it:   A_ij -= sum_{s<j} L_is L_js^H;  L_ij = A_ij M_j^H                    (i > j)
+// (the products on FP64 MFMA, split over s across the waves of a block), then L y = f and
+// L^H u = y by tile substitution, the diagonal blocks applied as products with M_j.  Storage: per
+// class the lower triangle of 32 x 32 complex tiles, each tile column-major and contiguous
+// (16 KB), row-major over tiles: tile (i, j), j <= i, is number i (i + 1) / 2 + j.  The inverses
+// M_j go to an array of their own; the diagonal tiles keep the updated A_jj.
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
@@ -28,7 +29,7 @@ constexpr int kLdT = kT + 1;                  // LDS row stride of a staged tile
 constexpr int kDnBlock = 256;
 constexpr int kDnWaves = kDnBlock / 64;
 constexpr int64_t kDirectMaxRows = 8192;      // the substitution keeps one class vector in LDS
-constexpr int64_t kDirectBudget = int64_t(6) << 30;   // factor storage per chunk of classes
+constexpr int64_t kDirectBudget = int64_t(16) << 30;  // factor storage per chunk of classes
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -44,21 +45,6 @@ struct DClass {
 };
 
 __host__ __device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
-
-// block index -> (class, tile row).  With at least 8 classes every class keeps all of its blocks
-// on one XCD (block b runs on XCD b mod 8), so the L tiles a step rereads stay in that L2.
-__device__ inline bool dn_map(int nc, int per, bool xcd, int& c, int& t) {
-  const int64_t b = blockIdx.x;
-  if (xcd) {
-    const int64_t k = b >> 3;
-    c = (int)((b & 7) + 8 * (k / per));
-    t = (int)(k % per);
-  } else {
-    c = (int)(b / per);
-    t = (int)(b % per);
-  }
-  return c < nc;
-}
 
 // ---- assembly: row i of a class writes its entries (i, l) with l <= i; padding rows of the last
 // tile and the zero frequency get a unit diagonal.  Every entry is 4 pi^2 (k . l) a_{k-l},
@@ -114,56 +100,124 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_assemble(int nc, const DClass* 
   }
 }
 
-// ---- trailing products of tile column j: A_ij -= sum_{s<j} L_is L_js^H, i >= j.  Wave w takes
-// s = w, w + 4, ...; each wave holds the whole 32 x 32 product as 2 x 2 quadrants of 16 x 16 FP64
-// MFMA accumulators (real and imaginary part each), and the four partial products are summed in
-// LDS in a fixed order.  MFMA 16x16x4 operands: lane = row + 16 k for A (16 x 4) and column + 16 k
-// for B (4 x 16); the result holds (4 v + lane / 16, lane mod 16) in item v.
-__global__ __launch_bounds__(kDnBlock) void k_dn_update(int nc, int per, int j, bool xcd,
-                                                         const DClass* __restrict__ cls, double2* __restrict__ W) {
-  int c, t;
-  if (!dn_map(nc, per, xcd, c, t)) return;
-  const DClass C = cls[c];
-  const int i = j + t;
-  if (j >= C.nt || i >= C.nt) return;
-  double2* tiles = W + C.tbase * kTE;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  d4_t acc_re[2][2], acc_im[2][2];
+// ---- split-K tile products.  The wave w of a block accumulates sum_{s = w, w+4, ... < ns}
+// P_s Q_s^H, P_s and Q_s the tiles s of two tile rows of L (consecutive tiles, kTE apart), as
+// 2 x 2 quadrants of 16 x 16 FP64 MFMA accumulators, real and imaginary part each:
+//   (P Q^H)_re = Pre Qre^T + Pim Qim^T,   (P Q^H)_im = Pim Qre^T - Pre Qim^T.
+// MFMA 16x16x4 operands: lane = row + 16 k for A (16 x 4) and column + 16 k for B (4 x 16); the
+// result holds (4 v + lane / 16, lane mod 16) in item v.  Operands come in groups of four
+// k-steps (half a tile), the next group loaded while the current one is multiplied.
+struct Acc {
+  d4_t re[2][2], im[2][2];
+};
+
+__device__ inline void acc_zero(Acc& A) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      acc_re[a][b] = d4_t{0, 0, 0, 0};
-      acc_im[a][b] = d4_t{0, 0, 0, 0};
+      A.re[a][b] = d4_t{0, 0, 0, 0};
+      A.im[a][b] = d4_t{0, 0, 0, 0};
     }
-  for (int s = wave; s < j; s += kDnWaves) {
-    const double2* P = tiles + (tri(i) + s) * kTE;
-    const double2* Q = tiles + (tri(j) + s) * kTE;
-#pragma unroll 2
-    for (int kc = 0; kc < kT / 4; ++kc) {
-      const int col = 4 * kc + lk;
-      double2 p[2], q[2];
+}
+
+constexpr int kGroup = 2;   // k-steps of 4 per operand group   // k-steps of 4 per operand group   // k-steps of 4 per operand group   // k-steps of 4 per operand group
+
+struct Group {
+  double2 p[kGroup][2], q[kGroup][2];
+};
+
+__device__ inline void load_group(const double2* __restrict__ P, const double2* __restrict__ Q, int kc0, int lr,
+                                  int lk, Group& g) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        p[h] = P[col * kT + 16 * h + lr];
-        q[h] = Q[col * kT + 16 * h + lr];
+  for (int u = 0; u < kGroup; ++u) {
+    const int col = 4 * (kc0 + u) + lk;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      g.p[u][h] = P[col * kT + 16 * h + lr];
+      g.q[u][h] = Q[col * kT + 16 * h + lr];
+    }
+  }
+}
+
+// eight independent accumulators between the two products that feed each one
+__device__ inline void mma_group(const Group& g, Acc& A) {
+#pragma unroll
+  for (int u = 0; u < kGroup; ++u) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        A.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.p[u][a].x, g.q[u][b].x, A.re[a][b], 0, 0, 0);
+        A.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.p[u][a].y, g.q[u][b].x, A.im[a][b], 0, 0, 0);
       }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        A.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.p[u][a].y, g.q[u][b].y, A.re[a][b], 0, 0, 0);
+        A.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-g.p[u][a].x, g.q[u][b].y, A.im[a][b], 0, 0, 0);
+      }
+  }
+}
+
+__device__ void split_k(const double2* __restrict__ Prow, const double2* __restrict__ Qrow, int ns, Acc& A) {
+  constexpr int kPer = (kT / 4) / kGroup;   // groups per tile
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int cnt = ns > wave ? (ns - wave + kDnWaves - 1) / kDnWaves : 0;
+  const int G = kPer * cnt;
+  if (G == 0) return;
+  auto load = [&](int g, Group& dst) {
+    const int64_t s = wave + (int64_t)(g / kPer) * kDnWaves;
+    load_group(Prow + s * kTE, Qrow + s * kTE, (g % kPer) * kGroup, lr, lk, dst);
+  };
+  // two groups in flight ahead of the one being multiplied
+  Group cur, nx1, nx2;
+  load(0, cur);
+  if (G > 1) load(1, nx1);
+  for (int g = 0; g < G; ++g) {
+    if (g + 2 < G) load(g + 2, nx2);
+    mma_group(cur, A);
+    cur = nx1;
+    nx1 = nx2;
+  }
+}
+
+// C = A - (sum of the four waves' products), summed in wave order through one LDS tile `buf`,
+// into LDS (element (r, c) at c * ld + r)
+__device__ void reduce_into(Acc& A, const double2* __restrict__ Ag, double2* buf, double2* C, int ld) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int w = 1; w < kDnWaves; ++w) {
+    if (wave == w) {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          // (P Q^H)_re = Pre Qre^T + Pim Qim^T,  (P Q^H)_im = Pim Qre^T - Pre Qim^T
-          acc_re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].x, q[b].x, acc_re[a][b], 0, 0, 0);
-          acc_re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].y, q[b].y, acc_re[a][b], 0, 0, 0);
-          acc_im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].y, q[b].x, acc_im[a][b], 0, 0, 0);
-          acc_im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-p[a].x, q[b].y, acc_im[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * a + 4 * v + lk, cc = 16 * b + lr;
+            buf[cc * kT + r] = make_double2(A.re[a][b][v], A.im[a][b][v]);
+          }
     }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * a + 4 * v + lk, cc = 16 * b + lr;
+            const double2 o = buf[cc * kT + r];
+            A.re[a][b][v] += o.x;
+            A.im[a][b][v] += o.y;
+          }
+    }
+    __syncthreads();
   }
-  // partial products of waves 1..3 through LDS, summed by wave 0's layout owner in wave order
-  __shared__ double2 red[kDnWaves - 1][kTE];
-  if (wave > 0) {
+  if (wave == 0) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -171,32 +225,11 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_update(int nc, int per, int j, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * a + 4 * v + lk, cc = 16 * b + lr;
-          red[wave - 1][cc * kT + r] = make_double2(acc_re[a][b][v], acc_im[a][b][v]);
+          const double2 x = Ag[cc * kT + r];
+          C[cc * ld + r] = make_double2(x.x - A.re[a][b][v], x.y - A.im[a][b][v]);
         }
   }
   __syncthreads();
-  if (wave == 0) {
-    double2* A = tiles + (tri(i) + j) * kTE;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * a + 4 * v + lk, cc = 16 * b + lr;
-          double sr = acc_re[a][b][v], si = acc_im[a][b][v];
-#pragma unroll
-          for (int w = 0; w < kDnWaves - 1; ++w) {
-            const double2 o = red[w][cc * kT + r];
-            sr += o.x;
-            si += o.y;
-          }
-          double2 x = A[cc * kT + r];
-          x.x -= sr;
-          x.y -= si;
-          A[cc * kT + r] = x;
-        }
-  }
 }
 
 // In-LDS Cholesky of the lower triangle of a 32 x 32 tile (stride kLdT), as L D L^H with the
@@ -247,83 +280,154 @@ __device__ void tile_chol(double2* sA, double* sd, int* bad) {
   __syncthreads();
 }
 
-// ---- tile column j: factor the updated A_jj (every block, redundantly, in LDS); block i == j
-// stores L_jj, block i > j solves L_ij L_jj^H = A_ij in place
-__global__ __launch_bounds__(kDnBlock) void k_dn_panel(int nc, int per, int j, bool xcd,
-                                                        const DClass* __restrict__ cls, double2* __restrict__ W,
-                                                        double2* __restrict__ D, int* __restrict__ err) {
-  int c, t;
-  if (!dn_map(nc, per, xcd, c, t)) return;
-  const DClass C = cls[c];
-  const int i = j + t;
-  if (j >= C.nt || i >= C.nt) return;
-  double2* tiles = W + C.tbase * kTE;
-  __shared__ double2 sL[kT * kLdT];
-  __shared__ double2 sX[kT * kLdT];
-  __shared__ double s_piv[kT];
-  __shared__ int s_bad;
+// Factor the updated diagonal tile in sD (stride kLdT), invert the factor into sM (stride kLdT),
+// write M = L^{-1} (lower, column-major) to Mout.  *s_bad must be 0 on entry.
+__device__ void diag_tail(double2* sD, double2* sM, double* piv, int* s_bad, double2* __restrict__ Mout,
+                          int* __restrict__ err) {
   const int tid = threadIdx.x;
-  if (tid == 0) s_bad = 0;
-  const double2* Ajj = tiles + (tri(j) + j) * kTE;
-  for (int idx = tid; idx < kTE; idx += kDnBlock) {
-    const int r = idx & (kT - 1), q = idx >> 5;
-    sL[q * kLdT + r] = Ajj[idx];
-  }
-  tile_chol(sL, s_piv, &s_bad);
-  if (i == j) {
-    double2* Lj = D + (C.dbase + j) * kTE;
-    for (int idx = tid; idx < kTE; idx += kDnBlock) {
-      const int r = idx & (kT - 1), q = idx >> 5;
-      Lj[idx] = r >= q ? sL[q * kLdT + r] : make_double2(0.0, 0.0);
-    }
-    if (tid == 0 && s_bad) err[0] = 1;
-    return;
-  }
-  double2* Aij = tiles + (tri(i) + j) * kTE;
-  for (int idx = tid; idx < kTE; idx += kDnBlock) {
-    const int r = idx & (kT - 1), q = idx >> 5;
-    sX[q * kLdT + r] = Aij[idx];
-  }
-  // X L^H = A, column by column: x_rc = a_rc / L_cc, then a_rq -= x_rc conj(L_qc) for q > c
-  for (int cc = 0; cc < kT; ++cc) {
-    __syncthreads();
-    const double il = 1.0 / sL[cc * kLdT + cc].x;
-    for (int idx = tid; idx < kTE; idx += kDnBlock) {
-      const int r = idx & (kT - 1), q = idx >> 5;
-      if (q > cc) {
-        const double2 a = sX[cc * kLdT + r], l = sL[cc * kLdT + q];
-        const double xr = a.x * il, xi = a.y * il;
-        double2 v = sX[q * kLdT + r];
-        v.x -= xr * l.x + xi * l.y;
-        v.y -= xi * l.x - xr * l.y;
-        sX[q * kLdT + r] = v;
+  tile_chol(sD, piv, s_bad);
+  // one column per thread: M_rc = (delta_rc - sum_{c<=m<r} L_rm M_mc) / L_rr
+  if (tid < kT) {
+    const int cc = tid;
+    for (int r = 0; r < kT; ++r) {
+      if (r < cc) {
+        sM[cc * kLdT + r] = make_double2(0.0, 0.0);
+        continue;
       }
+      double xr = r == cc ? 1.0 : 0.0, xi = 0.0;
+      for (int m = cc; m < r; ++m) {
+        const double2 l = sD[m * kLdT + r], x = sM[cc * kLdT + m];
+        xr -= l.x * x.x - l.y * x.y;
+        xi -= l.x * x.y + l.y * x.x;
+      }
+      const double il = 1.0 / sD[r * kLdT + r].x;
+      sM[cc * kLdT + r] = make_double2(xr * il, xi * il);
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < kTE; idx += kDnBlock) {
-    const int r = idx & (kT - 1), q = idx >> 5;
-    const double il = 1.0 / sL[q * kLdT + q].x;
-    const double2 v = sX[q * kLdT + r];
-    Aij[idx] = make_double2(v.x * il, v.y * il);
+  for (int idx = tid; idx < kTE; idx += kDnBlock) Mout[idx] = sM[(idx >> 5) * kLdT + (idx & (kT - 1))];
+  if (tid == 0 && *s_bad) err[0] = 1;
+}
+
+// ---- tile column j, diagonal only: A_jj -= sum_{s<j} L_js L_js^H, L_jj = chol(A_jj), M_j =
+// L_jj^{-1}; one block per class (used for j = 0; later diagonals are done by k_dn_offdiag)
+__global__ __launch_bounds__(kDnBlock) void k_dn_diag(int nc, int j, const DClass* __restrict__ cls,
+                                                       const double2* __restrict__ W, double2* __restrict__ Minv,
+                                                       int* __restrict__ err) {
+  const int c = blockIdx.x;
+  if (c >= nc) return;
+  const DClass C = cls[c];
+  if (j >= C.nt) return;
+  const double2* tiles = W + C.tbase * kTE;
+  __shared__ double2 buf[kT * kLdT];
+  __shared__ double2 sD[kT * kLdT];
+  __shared__ double s_piv[kT];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  const double2* Arow = tiles + tri(j) * kTE;
+  Acc A;
+  acc_zero(A);
+  split_k(Arow, Arow, j, A);
+  reduce_into(A, Arow + (int64_t)j * kTE, buf, sD, kLdT);
+  diag_tail(sD, buf, s_piv, &s_bad, Minv + (C.dbase + j) * kTE, err);
+}
+
+// ---- tile column j, below the diagonal: A_ij -= sum_{s<j} L_is L_js^H, then L_ij = A_ij M_j^H
+// (the triangular solve L_ij L_jj^H = A_ij as a product with the inverse), both on MFMA.  The
+// block of i = j + 1 then does the next diagonal: A_{j+1,j+1} -= sum_{s<=j} L_{j+1,s} L_{j+1,s}^H
+// (the s = j term from the tile it just computed, in LDS), its factor and inverse M_{j+1}.  Blocks
+// go out tile row by tile row, so those come first.
+__global__ __launch_bounds__(kDnBlock) void k_dn_offdiag(int nc, int per, int j, bool xcd,
+                                                          const DClass* __restrict__ cls, double2* __restrict__ W,
+                                                          double2* __restrict__ Minv, int* __restrict__ err) {
+  const int64_t b = blockIdx.x;
+  int c, t;
+  if (xcd) {
+    const int64_t k = b >> 3, nc8 = (nc + 7) / 8;
+    t = (int)(k / nc8);
+    c = (int)((b & 7) + 8 * (k % nc8));
+  } else {
+    t = (int)(b / nc);
+    c = (int)(b % nc);
   }
+  if (c >= nc || t >= per) return;
+  const DClass C = cls[c];
+  const int i = j + 1 + t;
+  if (i >= C.nt) return;
+  double2* tiles = W + C.tbase * kTE;
+  __shared__ double2 buf[kT * kLdT];
+  __shared__ double2 sC[kT * kLdT];
+  __shared__ double2 sX[kTE];
+  __shared__ double s_piv[kT];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  Acc A;
+  acc_zero(A);
+  split_k(tiles + tri(i) * kTE, tiles + tri(j) * kTE, j, A);
+  double2* Aij = tiles + (tri(i) + j) * kTE;
+  reduce_into(A, Aij, buf, sC, kLdT);
+  // X = C M^H: wave (a, b) computes quadrant (a, b); A operand C from LDS, B operand M from HBM
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qa = wave >> 1, qb = wave & 1;
+  const double2* M = Minv + (C.dbase + j) * kTE;
+  d4_t xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+#pragma unroll
+  for (int kc = 0; kc < kT / 4; ++kc) {
+    const int col = 4 * kc + lk;
+    const double2 p = sC[col * kLdT + 16 * qa + lr];
+    const double2 q = M[col * kT + 16 * qb + lr];
+    xr = __builtin_amdgcn_mfma_f64_16x16x4f64(p.x, q.x, xr, 0, 0, 0);
+    xi = __builtin_amdgcn_mfma_f64_16x16x4f64(p.y, q.x, xi, 0, 0, 0);
+    xr = __builtin_amdgcn_mfma_f64_16x16x4f64(p.y, q.y, xr, 0, 0, 0);
+    xi = __builtin_amdgcn_mfma_f64_16x16x4f64(-p.x, q.y, xi, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 16 * qa + 4 * v + lk, cc = 16 * qb + lr;
+    Aij[cc * kT + r] = make_double2(xr[v], xi[v]);
+    sX[cc * kT + r] = make_double2(xr[v], xi[v]);
+  }
+  if (t != 0) return;
+  __syncthreads();
+  // next diagonal: the tiles s < j of row i from HBM, s = j (X) from LDS split over the waves by k
+  acc_zero(A);
+  split_k(tiles + tri(i) * kTE, tiles + tri(i) * kTE, j, A);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int col = 4 * (2 * wave + u) + lk;
+    double2 p[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) p[h] = sX[col * kT + 16 * h + lr];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        A.re[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].x, p[bb].x, A.re[a][bb], 0, 0, 0);
+        A.im[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].y, p[bb].x, A.im[a][bb], 0, 0, 0);
+        A.re[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[a].y, p[bb].y, A.re[a][bb], 0, 0, 0);
+        A.im[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-p[a].x, p[bb].y, A.im[a][bb], 0, 0, 0);
+      }
+  }
+  reduce_into(A, tiles + (tri(i) + i) * kTE, buf, sC, kLdT);
+  diag_tail(sC, buf, s_piv, &s_bad, Minv + (C.dbase + i) * kTE, err);
 }
 
 // ---- L y = f, then L^H u = y, one block per class, the class vector in LDS.  The diagonal
-// tile substitution runs on one wavefront (lane = tile row); the off-diagonal tile products are
-// spread over the block.
+// blocks are products with M_s (one thread per row); the off-diagonal tile products are spread
+// over the block.
 template <typename NormT>
 __global__ __launch_bounds__(kDnBlock) void k_dn_subst(int nc, const DClass* __restrict__ cls,
                                                         const NormT* __restrict__ norm,
                                                         const double2* __restrict__ W,
-                                                        const double2* __restrict__ D,
+                                                        const double2* __restrict__ Minv,
                                                         const int64_t* __restrict__ exec2canon,
                                                         const double2* __restrict__ f, double2* __restrict__ u) {
   const int c = blockIdx.x;
   if (c >= nc) return;
   const DClass C = cls[c];
   extern __shared__ __align__(16) double2 s_dn[];
-  double2* sT = s_dn;                 // staged diagonal factor, stride kLdT
+  double2* sT = s_dn;                 // staged inverse diagonal factor, stride kLdT
   double2* v = s_dn + kT * kLdT;      // the class vector, nt * kT entries
   const double2* tiles = W + C.tbase * kTE;
   const int tid = threadIdx.x;
@@ -339,25 +443,19 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_subst(int nc, const DClass* __r
   // forward: L y = f
   for (int s = 0; s < C.nt; ++s) {
     __syncthreads();
-    const double2* Ls = D + (C.dbase + s) * kTE;
-    for (int idx = tid; idx < kTE; idx += kDnBlock) sT[(idx >> 5) * kLdT + (idx & (kT - 1))] = Ls[idx];
+    const double2* Ms = Minv + (C.dbase + s) * kTE;
+    for (int idx = tid; idx < kTE; idx += kDnBlock) sT[(idx >> 5) * kLdT + (idx & (kT - 1))] = Ms[idx];
     __syncthreads();
-    if (tid < 64) {
-      const int r = tid & (kT - 1);
-      double2 b = v[s * kT + r];
+    double2 y = make_double2(0.0, 0.0);
+    if (tid < kT) {   // y_s = M_s b_s
       for (int cc = 0; cc < kT; ++cc) {
-        const double bx = __shfl(b.x, cc, 64), by = __shfl(b.y, cc, 64);
-        const double il = 1.0 / sT[cc * kLdT + cc].x;
-        const double yx = bx * il, yy = by * il;
-        if (r == cc) b = make_double2(yx, yy);
-        else if (r > cc) {
-          const double2 l = sT[cc * kLdT + r];
-          b.x -= l.x * yx - l.y * yy;
-          b.y -= l.x * yy + l.y * yx;
-        }
+        const double2 m = sT[cc * kLdT + tid], x = v[s * kT + cc];
+        y.x += m.x * x.x - m.y * x.y;
+        y.y += m.x * x.y + m.y * x.x;
       }
-      if (tid < kT) v[s * kT + r] = b;
     }
+    __syncthreads();
+    if (tid < kT) v[s * kT + tid] = y;
     __syncthreads();
     for (int R = (s + 1) * kT + tid; R < np; R += kDnBlock) {
       const int ti = R / kT, r = R % kT;
@@ -378,26 +476,19 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_subst(int nc, const DClass* __r
   // backward: L^H u = y
   for (int s = C.nt - 1; s >= 0; --s) {
     __syncthreads();
-    const double2* Ls = D + (C.dbase + s) * kTE;
-    for (int idx = tid; idx < kTE; idx += kDnBlock) sT[(idx >> 5) * kLdT + (idx & (kT - 1))] = Ls[idx];
+    const double2* Ms = Minv + (C.dbase + s) * kTE;
+    for (int idx = tid; idx < kTE; idx += kDnBlock) sT[(idx >> 5) * kLdT + (idx & (kT - 1))] = Ms[idx];
     __syncthreads();
-    if (tid < 64) {
-      const int r = tid & (kT - 1);
-      double2 b = v[s * kT + r];
-      for (int cc = kT - 1; cc >= 0; --cc) {
-        const double bx = __shfl(b.x, cc, 64), by = __shfl(b.y, cc, 64);
-        const double il = 1.0 / sT[cc * kLdT + cc].x;
-        const double ux = bx * il, uy = by * il;
-        if (r == cc) b = make_double2(ux, uy);
-        else if (r < cc) {
-          // (L^H)_{r,cc} = conj(L_{cc,r})
-          const double2 l = sT[r * kLdT + cc];
-          b.x -= l.x * ux + l.y * uy;
-          b.y -= l.x * uy - l.y * ux;
-        }
+    double2 y = make_double2(0.0, 0.0);
+    if (tid < kT) {   // u_s = M_s^H b_s, (M^H)_{r,c} = conj(M_{c,r})
+      for (int cc = 0; cc < kT; ++cc) {
+        const double2 m = sT[tid * kLdT + cc], x = v[s * kT + cc];
+        y.x += m.x * x.x + m.y * x.y;
+        y.y += m.x * x.y - m.y * x.x;
       }
-      if (tid < kT) v[s * kT + r] = b;
     }
+    __syncthreads();
+    if (tid < kT) v[s * kT + tid] = y;
     __syncthreads();
     for (int R = tid; R < s * kT; R += kDnBlock) {
       const int ti = R / kT, r = R % kT;
@@ -438,18 +529,27 @@ ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, hi
     cprob[k] = (int32_t)(std::upper_bound(op->eoff.begin(), op->eoff.end(), op->cls_e0[k]) - op->eoff.begin()) - 1;
   if (stats) *stats = DirectStats{};
   const OpDev od = op->dev();
+  // chunks of consecutive classes of about equal storage, each within the budget (a chunk holds
+  // one class at least), so no chunk is left with a few classes that cannot fill the device
+  auto class_bytes = [&](int64_t k) {
+    const int64_t nt = ceil_div(op->cls_n[k], kT);
+    return (tri(nt) + nt) * kTE * (int64_t)sizeof(double2);
+  };
+  int64_t total_bytes = 0;
+  for (int64_t k = 0; k < n_cls; ++k) total_bytes += class_bytes(k);
+  const int64_t n_chunks = std::max<int64_t>(1, ceil_div(total_bytes, kDirectBudget));
+  const int64_t target = ceil_div(total_bytes, n_chunks);
   int k0 = 0;
   ss_status result = SS_OK;
   while (k0 < n_cls) {
-    // a chunk of consecutive classes whose tiles fit the budget (at least one class)
     std::vector<DClass> ch;
     int64_t tiles = 0, dtiles = 0;
     int max_nt = 0;
     int64_t k = k0;
     for (; k < n_cls && (int64_t)ch.size() < 65535; ++k) {
       const int nt = (int)ceil_div(op->cls_n[k], kT);
-      const int64_t need = (tri(nt) + nt) * kTE * (int64_t)sizeof(double2);
-      if (!ch.empty() && (tiles + dtiles) * kTE * (int64_t)sizeof(double2) + need > kDirectBudget) break;
+      const int64_t need = class_bytes(k), have = (tiles + dtiles) * kTE * (int64_t)sizeof(double2);
+      if (!ch.empty() && (have + need > kDirectBudget || have >= target)) break;
       DClass dc;
       dc.e0 = op->cls_e0[k];
       dc.eb = op->eoff[cprob[k]];
@@ -466,7 +566,7 @@ ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, hi
     }
     k0 = (int)k;
     const int nc = (int)ch.size();
-    double2 *W = nullptr, *Dg = nullptr;
+    double2 *W = nullptr, *Dg = nullptr;   // lower tiles; inverses of the diagonal factors
     DClass* dcls = nullptr;
     int* err = nullptr;
     SS_TRY(dalloc(&W, (size_t)std::max<int64_t>(tiles, 1) * kTE));
@@ -499,11 +599,11 @@ ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, hi
       SS_HIP(hipEventCreate(&f1));
       SS_HIP(hipEventRecord(f0, s));
     }
-    for (int j = 0; j < max_nt; ++j) {
-      const int per = max_nt - j;
+    k_dn_diag<<<(unsigned)nc, kDnBlock, 0, s>>>(nc, 0, dcls, W, Dg, err);
+    for (int j = 0; j + 1 < max_nt; ++j) {
+      const int per = max_nt - j - 1;
       const int64_t nb = xcd ? 8 * ceil_div(nc, 8) * (int64_t)per : (int64_t)nc * per;
-      if (j > 0) k_dn_update<<<(unsigned)nb, kDnBlock, 0, s>>>(nc, per, j, xcd, dcls, W);
-      k_dn_panel<<<(unsigned)nb, kDnBlock, 0, s>>>(nc, per, j, xcd, dcls, W, Dg, err);
+      k_dn_offdiag<<<(unsigned)nb, kDnBlock, 0, s>>>(nc, per, j, xcd, dcls, W, Dg, err);
     }
     SS_HIP(hipGetLastError());
     if (stats) SS_HIP(hipEventRecord(f1, s));
