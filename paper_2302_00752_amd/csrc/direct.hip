@@ -172,16 +172,23 @@ __device__ void split_k(const double2* __restrict__ Prow, const double2* __restr
     const int64_t s = wave + (int64_t)(g / kPer) * kDnWaves;
     load_group(Prow + s * kTE, Qrow + s * kTE, (g % kPer) * kGroup, lr, lk, dst);
   };
-  // two groups in flight ahead of the one being multiplied
-  Group cur, nx1, nx2;
-  load(0, cur);
-  if (G > 1) load(1, nx1);
-  for (int g = 0; g < G; ++g) {
-    if (g + 2 < G) load(g + 2, nx2);
-    mma_group(cur, A);
-    cur = nx1;
-    nx1 = nx2;
+  // two groups in flight ahead of the one being multiplied, three buffers in rotation: the loop
+  // body is straight-line code (addresses past the last group are clamped to it), so each wait
+  // covers only the group about to be multiplied
+  Group b0, b1, b2;
+  load(0, b0);
+  load(min(1, G - 1), b1);
+  int g = 0;
+  for (; g + 3 <= G; g += 3) {
+    load(min(g + 2, G - 1), b2);
+    mma_group(b0, A);
+    load(min(g + 3, G - 1), b0);
+    mma_group(b1, A);
+    load(min(g + 4, G - 1), b1);
+    mma_group(b2, A);
   }
+  if (g < G) mma_group(b0, A);
+  if (g + 1 < G) mma_group(b1, A);
 }
 
 // C = A - (sum of the four waves' products), summed in wave order through one LDS tile `buf`,
