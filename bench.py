@@ -305,6 +305,10 @@ def main():
         for d in (1, 16, 256, 1024):   # instance 5: c_a = -0.63, near the paper's example value
             e, _, _, _ = proxy_run([workloads.lowsparsity(d, N, 5) for N in range(1, 6)], reps=1)
             decay[f"d={d}"] = [float(v) for v in e]
+        decay_high = {}
+        for d in (4, 64, 1024):        # Sec. 10.3.2: 25 cosine modes, N = 1..3
+            e, _, _, _ = proxy_run([workloads.highsparsity(d, N) for N in range(1, 4)], reps=1)
+            decay_high[f"d={d}"] = [float(v) for v in e]
         Bl = 1024
         lows = [workloads.lowsparsity(1024, 1 + i % 5, i) for i in range(Bl)]
         e_l, med_l, n_l, _ = proxy_run(lows)
@@ -313,6 +317,7 @@ def main():
         e_c, med_c, n_c, _ = proxy_run(c2, tol=args.tol)
         proxy = {
             "decay_low_sparsity_N1_to_5": decay,
+            "decay_high_sparsity_N1_to_3": decay_high,
             "low_sparsity_d1024": {"batch": Bl, "levels": "N = 1..5 cycling", "rows_next": int(n_l), **med_l,
                                    "proxy_errors_per_s": Bl / ((med_l["build_next_ms"] + med_l["proxy_ms"]) / 1e3),
                                    "max_proxy": float(e_l.max())},
@@ -322,7 +327,8 @@ def main():
         }
         log(f"proxy error: low-sparsity d=1024 B={Bl}: build {med_l['build_next_ms']:.1f} ms + proxy "
             f"{med_l['proxy_ms']:.2f} ms; cfg2 B={Bc} (S^4: {n_c} rows): build {med_c['build_next_ms']:.1f} ms + "
-            f"proxy {med_c['proxy_ms']:.2f} ms; decay d=1024 {['%.2e' % v for v in decay['d=1024']]}")
+            f"proxy {med_c['proxy_ms']:.2f} ms; decay d=1024 {['%.2e' % v for v in decay['d=1024']]}; "
+            f"high sparsity d=1024 {['%.2e' % v for v in decay_high['d=1024']]}")
 
     # --- the paper's own solver: dense assembly + direct (Cholesky) solve per class, against PCG
     direct = None
@@ -368,6 +374,36 @@ def main():
                   "roofline": {"bound": "mfma", "kernel": "k_dn_update + k_dn_panel (all tile columns)",
                                "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": tflops / FP64_PEAK_TFLOPS, "flops_per_call": flops}}
+        # the high-sparsity problem of Sec. 10.3.2 at d = 1024, level 2 (two classes of 1301 rows each)
+        Bh = 64
+        hp = [workloads.highsparsity(1024, 2, i) for i in range(Bh)]
+        sth = ss.Stamp.build(hp)
+        oph = ss.Operator.build(sth, hp, 0)
+        fh = sth.forcing_vector(hp, dev)
+        uh = torch.zeros_like(fh)
+        oph.solve_direct(fh, uh)
+        th_d, th_p = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            oph.solve_direct(fh, uh)
+            th_d.append(1e3 * (time.perf_counter() - t))
+            up = torch.zeros_like(fh)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            oph.solve(fh, up, args.tol, "fp64", 1000)
+            th_p.append(1e3 * (time.perf_counter() - t))
+        hs = oph.class_sizes()
+        direct["high_sparsity_d1024_level2"] = {
+            "batch": Bh, "classes": int(len(hs)), "class_rows_max": int(hs.max()),
+            "solves_per_s": Bh / (float(np.median(th_d)) / 1e3),
+            "pcg_fp64_solves_per_s": Bh / (float(np.median(th_p)) / 1e3),
+            "rel_diff_vs_pcg_fp64": float(torch.linalg.norm(up - uh).item() / torch.linalg.norm(up).item())}
+        sth.close()
+        oph.close()
+        hd = direct["high_sparsity_d1024_level2"]
+        log(f"direct, high sparsity d=1024 N=2 B={Bh}: {hd['solves_per_s']:.0f} solves/s vs PCG "
+            f"{hd['pcg_fp64_solves_per_s']:.0f}; rel diff {hd['rel_diff_vs_pcg_fp64']:.1e}")
         log(f"direct: B={Bd} ({len(sizes)} classes of <= {sizes.max()} rows): {med_d:.1f} ms "
             f"(factor {med_f:.1f} ms = {tflops:.1f} TFLOP/s), PCG fp64 {t_pcg['fp64']:.2f} ms; rel diff {diff:.1e}")
         std.close()

@@ -268,6 +268,22 @@ def lowsparsity(d: int, level: int, instance: int = 0) -> Problem:
     return Problem(d, af, ah, ff, fh, level=level, name=f"lowsparsity/d{d}/N{level}/{instance}")
 
 
+def highsparsity(d: int, level: int, instance: int = 0) -> Problem:
+    """The exactly sparse high-sparsity diffusion problem (Sec. 10.3.2): a = a_0 + sum over 25 modes
+    k of c_k cos(2 pi k.x), c ~ U[-1, 1]^25 drawn once and kept for every d and instance, a_0 =
+    4 ceil(|c|_2); f = sin(2 pi k_f.x); every frequency uniform in [-499, 500]^d (instance picks
+    the frequencies)."""
+    c = np.random.Generator(np.random.PCG64(8000)).uniform(-1.0, 1.0, size=25)
+    rng = np.random.Generator(np.random.PCG64(8000 + 10007 * d + instance))
+    draw = lambda: rng.integers(-499, 501, size=d)
+    k_a = _distinct_modes(rng, 25, draw)
+    k_f = _distinct_modes(rng, 1, draw, forbid=k_a)
+    a0 = 4.0 * float(np.ceil(np.linalg.norm(c)))
+    af, ah = _real_from_half(d, k_a, (c / 2).astype(np.complex128), a0=a0)
+    ff, fh = _real_from_half(d, k_f, np.array([-0.5j], dtype=np.complex128))
+    return Problem(d, af, ah, ff, fh, level=level, name=f"highsparsity/d{d}/N{level}/{instance}")
+
+
 CONFIGS = {1: cfg1, 2: cfg2, 3: cfg3, 4: cfg4}
 
 

@@ -153,3 +153,24 @@ def test_direct_errors(ss):
     with pytest.raises(ss.SparseSpecError) as e:
         op.solve_direct(f, torch.zeros_like(f))
     assert e.value.status == ss.SS_ENOTPD
+
+
+@pytest.mark.parametrize("d", [1, 4, 1024])
+def test_direct_high_sparsity(ss, d):
+    # the high-sparsity problem of Sec. 10.3.2 at level 2 (two classes of 1301 rows for d > 1, one
+    # merged class for d = 1; d = 1024: 2 KB keys, int64 norms): direct = PCG (and = the oracle at
+    # small d), residual at rounding level
+    p = workloads.highsparsity(d, 2)
+    st, op = build(ss, [p])
+    f = f_vector(ss, st, [p])
+    u, _ = direct(ss, op, f)
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd)
+    op.solve(fd, ud, 1e-13, "fp64", 5000)
+    torch.cuda.synchronize()
+    assert rel(u, ud.cpu().numpy()) <= 1e-11
+    assert residual(ss, op, f, u) <= 1e-12
+    if d <= 4:
+        af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+        keys, _ = ost.stamp(p.f_freqs, af, p.level)
+        assert rel(u, og.solve(keys, af, ah, f)) <= ERR64

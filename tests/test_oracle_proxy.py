@@ -109,3 +109,29 @@ def test_lowsparsity_proxy_decays_geometrically_and_lives_on_the_new_level(d):
         errs.append(e)
     ratios = np.array(errs[1:]) / np.array(errs[:-1])
     assert np.all(ratios < 0.5)
+
+
+def test_highsparsity_workload_and_its_proxy_decay():
+    # Sec. 10.3.2: 25 cosine modes with coefficients drawn once and kept for every d, a_0 = 4 ceil(|c|_2)
+    # (so the l1 certificate holds), f = sin(2 pi k_f.x); the exact proxy error falls with the level
+    c_ref = None
+    for d in (1, 4, 64):
+        p = workloads.highsparsity(d, 1)
+        af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+        assert len(af) == 51 and np.all(np.abs(p.a_freqs) <= 500)
+        z = np.all(af == 0, axis=1)
+        c = np.sort(2 * ah[~z].real)
+        assert np.all(ah[~z].imag == 0)
+        c_ref = c if c_ref is None else c_ref
+        assert np.array_equal(c, c_ref)                  # the same coefficients for every d
+        assert ah[z][0].real == 4 * np.ceil(np.linalg.norm(c) / np.sqrt(2))
+        assert p.a_min_bound() > 0
+        assert sorted(p.f_hat.tolist(), key=lambda v: v.imag) == [-0.5j, 0.5j]
+    errs = []
+    for N in range(3):
+        p = workloads.highsparsity(4, N)
+        af, ah, keys, lev = _setup(p)
+        f = _f_on(keys, p)
+        u = og.solve(keys, af, ah, f)
+        errs.append(og.proxy_error(keys, u, af, ah, p.f_freqs, p.f_hat))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.5 * errs[0]
