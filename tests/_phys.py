@@ -39,3 +39,17 @@ def grid_2d(G):
     x = np.arange(G) / G
     X, Y = np.meshgrid(x, x, indexing="ij")
     return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def eval_adr(points, a_freqs, a_hat, b_freqs, b_hat, c_freqs, c_hat, u_freqs, u_hat):
+    """-div(a grad u) + b . grad u + c u pointwise (Remark ADR, Eq. ADR); b_hat[i] is the
+    vector of the d components' coefficients at b_freqs[i]."""
+    pts = np.asarray(points, dtype=np.float64)
+    kf = np.asarray(u_freqs, dtype=np.float64)
+    Eu = np.exp(2j * np.pi * pts @ kf.T)
+    grad_u = Eu @ (2j * np.pi * kf * u_hat[:, None])                    # [P, d]
+    u = Eu @ u_hat
+    bf = np.asarray(b_freqs, dtype=np.float64)
+    b = np.exp(2j * np.pi * pts @ bf.T) @ np.asarray(b_hat)            # [P, d]
+    c = eval_series(pts, c_freqs, np.asarray(c_hat))
+    return eval_operator(pts, a_freqs, a_hat, u_freqs, u_hat) + (b * grad_u).sum(1) + c * u
