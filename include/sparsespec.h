@@ -228,6 +228,44 @@ ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void*
  *   number of classes with sizes != NULL -> SS_EINVAL. */
 ss_status ss_op_class_sizes(const ss_op* op, int64_t cap, int64_t* sizes, int64_t* n_out);
 
+/* ---------------------------------------------------------------- advection-diffusion-reaction
+ * -div(a grad u) + b . grad u + c u = f (Remark ADR, Eq. ADR).  With grad e_l = 2 pi i l e_l the
+ * operator's entry at (k, l) is 4 pi^2 (k . l) a_{k-l} + 2 pi i (l . b_{k-l}) + c_{k-l}.  Build the
+ * stamp and the operator with the diffusion calls on the union W = supp(a) u supp(b) u supp(c)
+ * (with 0 and closed under negation): pass W as the stamp's support, and to ss_build_op W with
+ * a's coefficients (0 where a has none).  One level adds W once (reading of the Remark's stamp:
+ * each application of the operator shifts a frequency by one element of one support).
+ *
+ * ss_build_adr adds the advection and reaction terms to op (which must outlive the handle).
+ *   n_b[p], b_freqs (host int16 [sum n_b x d]), b_hat (host complex128 [sum n_b x d]): for each
+ *     frequency w of problem p, the d components' coefficients (b_{1,w}, ..., b_{d,w}); list w and
+ *     -w (conjugate coefficients for a real field).
+ *   n_c[p], c_freqs, c_hat (complex128 [sum n_c]): c the same way; c_0 must be real and positive
+ *     (then the zero frequency is an ordinary unknown).
+ * Errors: SS_EINVAL (a frequency outside op's support, c_0 missing or not positive, not finite).
+ * Synchronises `stream`. */
+typedef struct ss_adr ss_adr;
+ss_status ss_build_adr(const ss_stamp* st, const ss_op* op, const int32_t* n_b, const int16_t* b_freqs,
+                       const double* b_hat, const int32_t* n_c, const int16_t* c_freqs, const double* c_hat,
+                       void* stream, ss_adr** out);
+
+/* y = L x with the advection and reaction terms, FP64; x_dev, y_dev: device complex128 [n_exec]
+ * in execution order (as ss_apply).  Asynchronous. */
+ss_status ss_adr_apply(const ss_adr* adr, const void* x_dev, void* y_dev, void* stream);
+
+/* Solve L u = f for every problem: Jacobi-preconditioned BiCGSTAB in FP64 (the operator is not
+ * Hermitian), per-problem scalars, stop when the true residual |f - L u|_2 <= tol |f|_2 (the
+ * recursively updated residual triggers the check; up to 3 restarts from the true residual).
+ *   f_dev, u_dev: device complex128 [n_total], canonical order; u is out only (start from 0).
+ *   max_iter: BiCGSTAB iterations (two matvecs each) over all restarts.
+ *   info (host, nullable): n_prob entries.
+ * Returns SS_ENOCONV / SS_EBREAKDOWN when a problem missed tol (u holds its last iterate).
+ * Synchronises `stream`. */
+ss_status ss_adr_solve(const ss_adr* adr, const void* f_dev, void* u_dev, double tol, int32_t max_iter,
+                       void* stream, ss_solve_info* info);
+
+void ss_free_adr(ss_adr* adr);
+
 void ss_free_op(ss_op* op);
 
 /* device bytes held by op, including its solver workspace once a solve ran */

@@ -21,6 +21,9 @@ struct ss_engine {
 struct ss_batch {
   ss::BatchImpl* impl;
 };
+struct ss_adr {
+  ss::AdrImpl* impl;
+};
 
 namespace ss {
 
@@ -221,6 +224,41 @@ ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void*
     }
     return r;
   });
+}
+
+ss_status ss_build_adr(const ss_stamp* st, const ss_op* op, const int32_t* n_b, const int16_t* b_freqs,
+                       const double* b_hat, const int32_t* n_c, const int16_t* c_freqs, const double* c_hat,
+                       void* stream, ss_adr** out) {
+  return guarded([&]() -> ss_status {
+    if (!out) return fail(SS_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!st || !st->impl || !op || !op->impl) return fail(SS_EINVAL, "null stamp or operator");
+    AdrImpl* impl = nullptr;
+    SS_TRY(adr_build_impl(st->impl, op->impl, n_b, b_freqs, b_hat, n_c, c_freqs, c_hat, as_stream(stream), &impl));
+    *out = new ss_adr{impl};
+    return SS_OK;
+  });
+}
+
+ss_status ss_adr_apply(const ss_adr* adr, const void* x_dev, void* y_dev, void* stream) {
+  return guarded([&]() -> ss_status {
+    if (!adr || !adr->impl) return fail(SS_EINVAL, "null ADR operator");
+    return adr_apply_impl(adr->impl, x_dev, y_dev, as_stream(stream));
+  });
+}
+
+ss_status ss_adr_solve(const ss_adr* adr, const void* f_dev, void* u_dev, double tol, int32_t max_iter,
+                       void* stream, ss_solve_info* info) {
+  return guarded([&]() -> ss_status {
+    if (!adr || !adr->impl) return fail(SS_EINVAL, "null ADR operator");
+    return adr_solve_impl(adr->impl, f_dev, u_dev, tol, max_iter, as_stream(stream), info);
+  });
+}
+
+void ss_free_adr(ss_adr* adr) {
+  if (!adr) return;
+  adr_free_impl(adr->impl);
+  delete adr;
 }
 
 ss_status ss_op_class_sizes(const ss_op* op, int64_t cap, int64_t* sizes, int64_t* n_out) {

@@ -275,6 +275,14 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
 // proxy error of level-N solutions u (canonical order of the level-N stamp) from the stamp and
 // operator built at level N + 1 (proxy.hip); err: host [n_prob]
+struct AdrImpl;
+ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n_b, const int16_t* b_freqs,
+                         const double* b_hat, const int32_t* n_c, const int16_t* c_freqs, const double* c_hat,
+                         hipStream_t s, AdrImpl** out);
+ss_status adr_apply_impl(const AdrImpl* A, const void* x, void* y, hipStream_t s);
+ss_status adr_solve_impl(const AdrImpl* A, const void* f, void* u, double tol, int32_t max_iter, hipStream_t s,
+                         ss_solve_info* info);
+void adr_free_impl(AdrImpl* A);
 struct DirectStats {
   double factor_ms = 0;    // factorisation kernels (all tile columns), summed over chunks
   int64_t tiles = 0;       // lower 32 x 32 tiles factored

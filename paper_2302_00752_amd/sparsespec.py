@@ -29,7 +29,8 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_solve_op", "ss_free_op", "ss_solve", "ss_last_error", "ss_version", "ss_op_bytes",
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
             "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
-            "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes"]
+            "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes", "ss_build_adr", "ss_adr_apply",
+            "ss_adr_solve", "ss_free_adr"]
 
 
 class SolveInfo(C.Structure):
@@ -91,6 +92,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_proxy_error": [P, P, P, i64, pd, pd, P],
         "ss_solve_direct": [P, P, P, P, C.POINTER(DirectInfo)],
         "ss_op_class_sizes": [P, i64, pi64, pi64],
+        "ss_build_adr": [P, P, pi32, pi16, pd, pi32, pi16, pd, P, C.POINTER(P)],
+        "ss_adr_apply": [P, P, P, P],
+        "ss_adr_solve": [P, P, P, dbl, i32, P, C.POINTER(SolveInfo)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -102,6 +106,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.ss_free_op.restype = None
     lib.ss_engine_free.argtypes = [P]
     lib.ss_engine_free.restype = None
+    lib.ss_free_adr.argtypes = [P]
+    lib.ss_free_adr.restype = None
     lib.ss_free_batch.argtypes = [P]
     lib.ss_free_batch.restype = None
     lib.ss_last_error.restype = C.c_char_p
@@ -313,6 +319,56 @@ class Operator:
     def close(self):
         if self._h:
             _lib.ss_free_op(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AdrOperator:
+    """Advection-diffusion-reaction operators (Remark ADR) on a stamp and operator built on the
+    union support (``problem.diffusion_on_union()``); the operator must outlive this object."""
+
+    def __init__(self, handle, op: "Operator"):
+        self._h = handle
+        self.op = op
+        self.n_prob = op.n_prob
+
+    @classmethod
+    def build(cls, stamp: Stamp, op: "Operator", problems, stream=None) -> "AdrOperator":
+        d = stamp.d
+        n_b = np.array([len(p.b_freqs) for p in problems], dtype=np.int32)
+        n_c = np.array([len(p.c_freqs) for p in problems], dtype=np.int32)
+        bf = _i16(np.concatenate([np.asarray(p.b_freqs).reshape(-1, d) for p in problems]))
+        bh = _c128(np.concatenate([np.asarray(p.b_hat).reshape(-1, d) for p in problems]).ravel())
+        cf = _i16(np.concatenate([np.asarray(p.c_freqs).reshape(-1, d) for p in problems]))
+        ch = _c128(np.concatenate([np.asarray(p.c_hat) for p in problems]))
+        h = C.c_void_p()
+        _check(_lib.ss_build_adr(stamp._h, op._h, _ptr(n_b, C.c_int32), _ptr(bf, C.c_int16), _ptr(bh, C.c_double),
+                                 _ptr(n_c, C.c_int32), _ptr(cf, C.c_int16), _ptr(ch, C.c_double),
+                                 C.c_void_p(_stream(stream)), C.byref(h)))
+        return cls(h, op)
+
+    def apply(self, x, y, stream=None):
+        """y = L x (device complex128, execution order)."""
+        _check(_lib.ss_adr_apply(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                 C.c_void_p(_stream(stream))))
+
+    def solve(self, f, u, tol: float, max_iter: int = 2000, stream=None, raise_on_error: bool = True) -> List[dict]:
+        """Solve L u = f (device complex128, canonical order) by BiCGSTAB."""
+        info = (SolveInfo * self.n_prob)()
+        st = _lib.ss_adr_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), float(tol),
+                               int(max_iter), C.c_void_p(_stream(stream)), info)
+        if raise_on_error:
+            _check(st)
+        return [i.as_dict() for i in info]
+
+    def close(self):
+        if self._h:
+            _lib.ss_free_adr(self._h)
             self._h = None
 
     def __del__(self):

@@ -284,6 +284,85 @@ def highsparsity(d: int, level: int, instance: int = 0) -> Problem:
     return Problem(d, af, ah, ff, fh, level=level, name=f"highsparsity/d{d}/N{level}/{instance}")
 
 
+@dataclasses.dataclass
+class AdrProblem:
+    """-div(a grad u) + b . grad u + c u = f (Remark ADR).  b_hat[i] holds the d components'
+    coefficients at b_freqs[i]; every support is listed with its negation."""
+    d: int
+    a_freqs: np.ndarray
+    a_hat: np.ndarray
+    b_freqs: np.ndarray
+    b_hat: np.ndarray
+    c_freqs: np.ndarray
+    c_hat: np.ndarray
+    f_freqs: np.ndarray
+    f_hat: np.ndarray
+    level: int
+    name: str = ""
+
+    def union(self) -> np.ndarray:
+        """supp(a) u supp(b) u supp(c), closed under negation, with 0 (sorted rows)."""
+        pts = {tuple(int(v) for v in w) for fr in (self.a_freqs, self.b_freqs, self.c_freqs) for w in fr}
+        pts |= {tuple(-v for v in t) for t in pts}
+        pts.add(tuple([0] * self.d))
+        return np.array(sorted(pts), dtype=np.int16).reshape(-1, self.d)
+
+    def diffusion_on_union(self) -> Problem:
+        """The diffusion problem the stamp and operator are built from: support W = the union,
+        a's coefficients on it (0 where a has none)."""
+        W = self.union()
+        amap = {tuple(int(v) for v in w): c for w, c in zip(self.a_freqs, self.a_hat)}
+        ah = np.array([amap.get(tuple(int(v) for v in w), 0.0) for w in W], dtype=np.complex128)
+        return Problem(self.d, W, ah, self.f_freqs, self.f_hat, level=self.level, name=self.name)
+
+
+def _trig(rng, d, n_sin, n_cos, draw, coef, forbid=()):
+    """Frequencies and coefficients of sum c sin(2 pi k.x) + sum c cos(2 pi k.x) as a
+    conjugate-symmetric list (sin: -i c / 2 at k; cos: c / 2 at k)."""
+    modes = _distinct_modes(rng, n_sin + n_cos, draw, forbid)
+    c = coef(n_sin + n_cos)
+    amps = np.concatenate([-0.5j * c[:n_sin], 0.5 * c[n_sin:]]).astype(np.complex128)
+    fr, co = _real_from_half(d, modes, amps)
+    return fr, co, c
+
+
+def adr3d(level: int, instance: int = 0, n_b: int = 3, n_c: int = 3) -> AdrProblem:
+    """The exactly sparse 3-D ADR problem of Sec. 10.4: a = a_0 + 2 sine + 2 cosine modes, each b_j
+    and c (c with c_0) n_b resp. n_c sine + cosine modes each, f = 2 sine + 3 cosine modes; every
+    frequency uniform in [-49, 50]^3; a and f coefficients U[-1, 1], b and c coefficients U[0, 1];
+    a_0 = 4 ceil(|c_a|_2), c_0 = 4 ceil(|c_c|_2).  The paper takes 5 + 5 modes for b_j and c; the
+    union support then exceeds the 63 entries of the operator's table, so fewer are drawn by
+    default (3 + 3: 57 entries)."""
+    d = 3
+    rng = np.random.Generator(np.random.PCG64(9000 + instance))
+    draw = lambda: rng.integers(-49, 51, size=d)
+    u11 = lambda n: rng.uniform(-1.0, 1.0, size=n)
+    u01 = lambda n: rng.uniform(0.0, 1.0, size=n)
+    af, ah, ca = _trig(rng, d, 2, 2, draw, u11)
+    af = np.concatenate([np.zeros((1, d), dtype=np.int16), af])
+    ah = np.concatenate([[4.0 * np.ceil(np.linalg.norm(ca))], ah]).astype(np.complex128)
+    bf_list, bh_list = [], []
+    for j in range(d):
+        fr, co, _ = _trig(rng, d, n_b, n_b, draw, u01)
+        bh = np.zeros((len(fr), d), dtype=np.complex128)
+        bh[:, j] = co
+        bf_list.append(fr)
+        bh_list.append(bh)
+    # merge the components at shared frequencies
+    bmap = {}
+    for fr, bh in zip(bf_list, bh_list):
+        for w, v in zip(fr, bh):
+            t = tuple(int(x) for x in w)
+            bmap[t] = bmap.get(t, np.zeros(d, dtype=np.complex128)) + v
+    bf = np.array(sorted(bmap), dtype=np.int16).reshape(-1, d)
+    bh = np.array([bmap[tuple(int(x) for x in w)] for w in bf], dtype=np.complex128)
+    cf, ch, cc = _trig(rng, d, n_c, n_c, draw, u01)
+    cf = np.concatenate([np.zeros((1, d), dtype=np.int16), cf])
+    ch = np.concatenate([[4.0 * np.ceil(np.linalg.norm(cc))], ch]).astype(np.complex128)
+    ff, fh, _ = _trig(rng, d, 2, 3, draw, u11)
+    return AdrProblem(d, af, ah, bf, bh, cf, ch, ff, fh, level=level, name=f"adr3d/N{level}/{instance}")
+
+
 CONFIGS = {1: cfg1, 2: cfg2, 3: cfg3, 4: cfg4}
 
 
