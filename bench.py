@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
     ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
+    ap.add_argument("--adr", type=int, default=256,
+                    help="3-D advection-diffusion-reaction problems per batch (0 = skip)")
     ap.add_argument("--direct", type=int, default=16,
                     help="d=10 problems for the dense direct (Cholesky) solve comparison (0 = skip)")
     args = ap.parse_args()
@@ -410,6 +412,56 @@ def main():
         opd.close()
         del ud, fdv
 
+    # --- advection-diffusion-reaction (Remark ADR): BiCGSTAB on the 3-D exactly sparse workload
+    adr_out = None
+    if args.adr > 0:
+        adr_out = {}
+        for N, Ba in ((1, args.adr), (2, max(1, args.adr // 4))):
+            ap_ = [workloads.adr3d(N, i) for i in range(Ba)]
+            dps = [q.diffusion_on_union() for q in ap_]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sta = ss.Stamp.build(dps)
+            opa = ss.Operator.build(sta, dps, 0)
+            A = ss.AdrOperator.build(sta, opa, ap_)
+            torch.cuda.synchronize()
+            t_build = 1e3 * (time.perf_counter() - t0)
+            fa = sta.forcing_vector(dps, dev)
+            ua = torch.zeros_like(fa)
+            A.solve(fa, ua, 1e-12, 4000)
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                inf = A.solve(fa, ua, 1e-12, 4000)
+                ts.append(1e3 * (time.perf_counter() - t))
+            # the matvec alone: stored entries (4 B + 16 B coefficient), |k|^2 and x once, y once
+            xe = torch.ones(opa.n_exec, dtype=torch.complex128, device=dev)
+            ye = torch.empty_like(xe)
+            A.apply(xe, ye)
+            s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            s_ev.record()
+            for _ in range(10):
+                A.apply(xe, ye)
+            e_ev.record()
+            torch.cuda.synchronize()
+            mv_ms = s_ev.elapsed_time(e_ev) / 10
+            mv_bytes = opa.nnz * 20 + opa.n_total * (4 + 16 + 16)
+            med = float(np.median(ts))
+            adr_out[f"N={N}"] = {"batch": Ba, "rows": int(opa.n_total), "nnz": int(opa.nnz),
+                                 "support": int(len(ap_[0].union())), "build_ms": t_build, "solve_ms": med,
+                                 "solves_per_s": Ba / (med / 1e3),
+                                 "iters_median": float(np.median([i["iters"] for i in inf])),
+                                 "max_rel_residual": float(max(i["rel_residual"] for i in inf)),
+                                 "matvec_us": 1e3 * mv_ms, "matvec_GB/s": mv_bytes / (mv_ms / 1e3) / 1e9}
+            log(f"adr N={N} B={Ba}: rows {opa.n_total}, build {t_build:.1f} ms, solve {med:.1f} ms "
+                f"({Ba / (med / 1e3):.0f} solves/s, {np.median([i['iters'] for i in inf]):.0f} iters), matvec "
+                f"{1e3 * mv_ms:.0f} us = {mv_bytes / (mv_ms / 1e3) / 1e9:.0f} GB/s")
+            A.close()
+            opa.close()
+            sta.close()
+
     # --- serving: Poisson stream of heterogeneous requests, continuous batching
     serving = None
     if args.serve > 0:
@@ -464,6 +516,7 @@ def main():
         "serving": serving,
         "proxy_error": proxy,
         "direct_solve": direct,
+        "adr": adr_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
