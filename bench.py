@@ -435,7 +435,7 @@ def main():
                 t = time.perf_counter()
                 inf = A.solve(fa, ua, 1e-12, 4000)
                 ts.append(1e3 * (time.perf_counter() - t))
-            # the matvec alone: stored entries (4 B + 16 B coefficient), |k|^2 and x once, y once
+            # the matvec alone: stored entries (4 B + 16 B coefficient), x once, y once
             xe = torch.ones(opa.n_exec, dtype=torch.complex128, device=dev)
             ye = torch.empty_like(xe)
             A.apply(xe, ye)
@@ -447,7 +447,7 @@ def main():
             e_ev.record()
             torch.cuda.synchronize()
             mv_ms = s_ev.elapsed_time(e_ev) / 10
-            mv_bytes = opa.nnz * 20 + opa.n_total * (4 + 16 + 16)
+            mv_bytes = opa.nnz * 20 + opa.n_total * (16 + 16)
             med = float(np.median(ts))
             adr_out[f"N={N}"] = {"batch": Ba, "rows": int(opa.n_total), "nnz": int(opa.nnz),
                                  "support": int(len(ap_[0].union())), "build_ms": t_build, "solve_ms": med,

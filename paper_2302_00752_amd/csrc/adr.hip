@@ -3,8 +3,8 @@
 //   2 pi i (l . b_j) + c_j
 // beside the diffusion term 2 pi^2 (|k|^2 + |l|^2 - |w_j|^2) a_j.  The stamp and the operator are
 // built by the diffusion path on the union of the supports (closed under negation, with 0), with
-// a_j = 0 where w_j is not in supp(a); this module adds one complex FP64 coefficient per stored
-// SELL entry for the new terms, the full diagonal, the matvec, and a batched Jacobi-preconditioned
+// a_j = 0 where w_j is not in supp(a); this module stores the whole complex FP64 coefficient of every
+// SELL entry (the matvec streams it), the diagonal, and a batched Jacobi-preconditioned
 // BiCGSTAB (the operator is not Hermitian, so CG does not apply) in FP64 with per-problem scalars
 // and fixed-order per-problem reductions.  With c_0 > 0 the zero frequency is an ordinary unknown.
 #include <algorithm>
@@ -35,9 +35,9 @@ __global__ void k_adr_pid(int64_t n_exec, int n_prob, const int64_t* __restrict_
   pid[e] = lo;
 }
 
-// E[q] = 2 pi i (l . b_j) + c_j for every stored entry q of row e (l the key of the entry's
-// column), and the diagonal D[e] = the whole coefficient of the entry with w_j = 0.  Padding
-// rows get D = 1.
+// E[q] = 2 pi^2 (|k|^2 + |l|^2 - |w_j|^2) a_j + 2 pi i (l . b_j) + c_j, the whole coefficient of
+// every stored entry q of row e (l the key of the entry's column), and the diagonal D[e] = the
+// coefficient of the entry with w_j = 0.  Padding rows get D = 1.
 template <typename NormT>
 __global__ void k_adr_coef(int64_t n_exec, int d, const int32_t* __restrict__ pid, const int64_t* __restrict__ eoff,
                            const int64_t* __restrict__ exec2canon, const int16_t* __restrict__ keys,
@@ -78,26 +78,24 @@ __global__ void k_adr_coef(int64_t n_exec, int d, const int32_t* __restrict__ pi
         si += lt * b[t].y;
       }
       const double tp = 2.0 * M_PI;
-      v = make_double2(Cp[j].x - tp * si, Cp[j].y + tp * sr);
-      if ((int)j == zj) {
-        const NormT I = nk + norm[ge] - (NormT)nu[(int64_t)p * 64 + j];
-        const double2 a = A64[(int64_t)p * 64 + j];
-        diag = make_double2((double)I * a.x + v.x, (double)I * a.y + v.y);
-      }
+      const NormT I = nk + norm[ge] - (NormT)nu[(int64_t)p * 64 + j];
+      const double2 a = A64[(int64_t)p * 64 + j];
+      v = make_double2((double)I * a.x + (Cp[j].x - tp * si), (double)I * a.y + (Cp[j].y + tp * sr));
+      if ((int)j == zj) diag = v;
     }
     E[base + q * kSlice + lane] = v;
   }
   D[e] = diag;
 }
 
-// y = L x over every problem (execution order); padding rows get 0
-template <typename NormT>
+// y = L x over every problem (execution order), the stored coefficients streamed with
+// nontemporal loads; padding rows get 0
+typedef double adr_d2v __attribute__((ext_vector_type(2)));
 __global__ void k_adr_mv(int64_t n_exec, const int32_t* __restrict__ pid, const int64_t* __restrict__ eoff,
                          const int64_t* __restrict__ exec2canon, const uint32_t* __restrict__ sent,
-                         const uint32_t* __restrict__ sptr, const NormT* __restrict__ norm,
-                         const double2* __restrict__ A64, const int64_t* __restrict__ nu,
-                         const double2* __restrict__ E, const uint8_t* __restrict__ done,
-                         const double2* __restrict__ x, double2* __restrict__ y) {
+                         const uint32_t* __restrict__ sptr, const double2* __restrict__ E,
+                         const uint8_t* __restrict__ done, const double2* __restrict__ x,
+                         double2* __restrict__ y) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_exec) return;
   const int p = pid[e];
@@ -110,21 +108,30 @@ __global__ void k_adr_mv(int64_t n_exec, const int32_t* __restrict__ pid, const 
   const int lane = (int)(e % kSlice);
   const uint32_t base = sptr[sl];
   const uint32_t width = (sptr[sl + 1] - base) / kSlice;
-  const NormT nk = norm[e];
-  const int64_t e0 = eoff[p];
+  const double2* xp = x + eoff[p];
   double ar = 0, ai = 0;
-  for (uint32_t q = 0; q < width; ++q) {
-    const uint32_t ent = sent[base + q * kSlice + lane];
-    const uint32_t j = ent >> kColBits;
-    if (j == (uint32_t)kNullJ) continue;
-    const int64_t ge = e0 + (int64_t)(ent & kColMask);
-    const NormT I = nk + norm[ge] - (NormT)nu[(int64_t)p * 64 + j];
-    const double2 a = A64[(int64_t)p * 64 + j];
-    const double2 ex = E[base + q * kSlice + lane];
-    const double cr = (double)I * a.x + ex.x, ci = (double)I * a.y + ex.y;
-    const double2 xv = x[ge];
-    ar += cr * xv.x - ci * xv.y;
-    ai += cr * xv.y + ci * xv.x;
+  // eight entries in flight: their words, then their coefficients and x values, then the sums
+  constexpr int kU = 8;
+  for (uint32_t q0 = 0; q0 < width; q0 += kU) {
+    uint32_t ent[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      ent[u] = q0 + u < width ? __builtin_nontemporal_load(sent + base + (q0 + u) * kSlice + lane)
+                              : (uint32_t)kNullJ << kColBits;
+    adr_d2v c[kU];
+    double2 xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool live = (ent[u] >> kColBits) != (uint32_t)kNullJ;
+      c[u] = live ? __builtin_nontemporal_load(reinterpret_cast<const adr_d2v*>(E + base + (q0 + u) * kSlice + lane))
+                  : adr_d2v{0.0, 0.0};
+      xv[u] = live ? xp[ent[u] & kColMask] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      ar += c[u].x * xv[u].x - c[u].y * xv[u].y;
+      ai += c[u].x * xv[u].y + c[u].y * xv[u].x;
+    }
   }
   y[e] = make_double2(ar, ai);
 }
@@ -355,7 +362,7 @@ __global__ void k_adr_scatter(int64_t n, const int64_t* __restrict__ exec2canon,
 struct AdrImpl {
   const OpImpl* op = nullptr;
   int device = 0;
-  double2* E = nullptr;        // [n_sell] advection + reaction coefficient of every stored entry
+  double2* E = nullptr;        // [n_sell] whole coefficient of every stored entry
   double2* D = nullptr;        // [n_exec] diagonal
   int32_t* pid = nullptr;      // [n_exec]
 };
@@ -461,12 +468,8 @@ ss_status adr_mv(const AdrImpl* A, const uint8_t* done, const double2* x, double
   const OpImpl* op = A->op;
   const OpDev od = op->dev();
   const int64_t ne = op->n_exec;
-  if (op->wide_norm)
-    k_adr_mv<int64_t><<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, A->pid, op->d_eoff, op->d_exec2canon, od.sent, od.sptr,
-                                                         (const int64_t*)od.norm, od.A64, od.nu, A->E, done, x, y);
-  else
-    k_adr_mv<int32_t><<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, A->pid, op->d_eoff, op->d_exec2canon, od.sent, od.sptr,
-                                                         (const int32_t*)od.norm, od.A64, od.nu, A->E, done, x, y);
+  k_adr_mv<<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, A->pid, op->d_eoff, op->d_exec2canon, od.sent, od.sptr, A->E, done,
+                                              x, y);
   SS_HIP(hipGetLastError());
   return SS_OK;
 }

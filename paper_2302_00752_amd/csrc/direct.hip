@@ -13,8 +13,7 @@
 // class the lower triangle of 32 x 32 complex tiles, each tile column-major and contiguous
 // (16 KB), row-major over tiles: tile (i, j), j <= i, is number i (i + 1) / 2 + j.  The inverses
 // M_j go to an array of their own; the diagonal tiles keep the updated A_jj.
-#include <hipcub/hipcub.hpp>
-
+#include <algorithm>
 #include <cmath>
 
 #include "ss_internal.h"
