@@ -756,7 +756,14 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_HIP(h2d(plev, level, n_prob * 4, stream));
 
   // ---- level 0: F
-  int64_t kcap = std::max<int64_t>(nF * 4, 1024);
+  // The rows of every level fit the App. A count of the whole build (a bound on |S^N| for any a):
+  // when that is moderate the key arrays are allocated once at its size, else they grow per level
+  // for the worst case of the level (every candidate new).
+  double row_bound_d = 0;
+  for (int p = 0; p < n_prob; ++p) row_bound_d += app_a_count(n_f[p], s_of[p], level[p]);
+  const int64_t row_bound = row_bound_d <= (double)(int64_t(1) << 27) ? std::max<int64_t>((int64_t)row_bound_d, nF)
+                                                                        : INT64_MAX;
+  int64_t kcap = row_bound != INT64_MAX ? row_bound : std::max<int64_t>(nF * 4, 1024);
   int64_t kcap_h = kcap, kcap_p = kcap, kcap_r = kcap, kcap_t = kcap;
   SS_TRY(dalloc(&ukeys, (size_t)kcap * d));
   SS_TRY(dalloc(&uhash, kcap));
@@ -797,7 +804,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     const int64_t n_front = f1 - f0;
     if (n_front == 0) break;
     const int64_t n_cand = n_front * smax1;
-    const int64_t need = total + n_cand;       // worst case: every candidate is new
+    const int64_t need = std::min(total + n_cand, row_bound);   // worst case: every candidate is new
     if (need > (int64_t(1) << 31)) return fail(SS_ERANGE, "stamping sets exceed 2^31 keys in one batch");
     SS_TRY(grow(&ukeys, &kcap, need, total, d, stream));
     SS_TRY(grow(&uhash, &kcap_h, need, total, 1, stream));
