@@ -132,3 +132,27 @@ def test_adr_argument_errors(ss):
     with pytest.raises(ss.SparseSpecError) as e:
         ss.AdrOperator.build(st, op, [bad_b])
     assert e.value.status == ss.SS_EINVAL
+
+
+def _small(seed, d, lo=-3, hi=3, far=0):
+    af, ah, bf, bh, cf, ch, F = _problem(seed, d=d, lo=lo, hi=hi)
+    F = F + far * np.sign(F + 0.5).astype(np.int64)     # push F out to coordinates near `far`
+    rng = np.random.default_rng(700 + seed)
+    fh = rng.standard_normal(len(F) // 2) + 1j * rng.standard_normal(len(F) // 2)
+    fh = np.concatenate([fh, np.conj(fh)])
+    return workloads.AdrProblem(d, af.astype(np.int16), ah, bf.astype(np.int16), bh, cf.astype(np.int16), ch,
+                                F.astype(np.int16), fh, 2)
+
+
+@pytest.mark.parametrize("d,far", [(1, 0), (16, 0), (3, 30000)])
+def test_adr_other_dimensions_and_int64_norms(ss, d, far):
+    # d = 1 (one merged class), d = 16, and coordinates near 3e4 in d = 3 (|k|^2 > 2^30: int64 norms)
+    p = _small(d, d, far=far)
+    if far:
+        assert 3 * (far - 10) ** 2 > 2 ** 30
+    keys, M = oracle_of(p)
+    st, op, A, dps = build(ss, [p])
+    f = f_vector(ss, st, dps)
+    u, info = gpu_solve(A, f)
+    u_ref = adr.solve(keys, p.a_freqs, p.a_hat, p.b_freqs, p.b_hat, p.c_freqs, p.c_hat, f, M=M)
+    assert info[0]["status"] == ss.SS_OK and rel(u, u_ref) <= 1e-10, (rel(u, u_ref), info)
