@@ -174,3 +174,24 @@ def test_direct_high_sparsity(ss, d):
         af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
         keys, _ = ost.stamp(p.f_freqs, af, p.level)
         assert rel(u, og.solve(keys, af, ah, f)) <= ERR64
+
+
+def test_direct_class_near_the_row_limit(ss):
+    # one class of 7919 rows (248 tile rows, 506 MB of tiles, the substitution's class vector
+    # filling 144 KB of LDS), below the 8192-row limit: residual at rounding level, PCG agrees
+    w = [(1, 0), (0, 1), (1, 1), (2, -1)]
+    af = [[0, 0]] + [list(v) for v in w] + [[-a, -b] for a, b in w]
+    ah = [1.0] + [0.05 + 0.02j] * 4 + [0.05 - 0.02j] * 4
+    p = P(2, af, ah, [[3, 1]], [1.0 + 0.5j], 36)
+    st, op = build(ss, [p])
+    sizes = op.class_sizes()
+    assert sizes.max() == 7919 and len(sizes) == 1
+    f = f_vector(ss, st, [p])
+    u, info = direct(ss, op, f)
+    assert info["tiles"] == 248 * 249 // 2
+    assert residual(ss, op, f, u) <= 1e-12
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd)
+    op.solve(fd, ud, 1e-13, "fp64", 20000)
+    torch.cuda.synchronize()
+    assert rel(u, ud.cpu().numpy()) <= 1e-9
