@@ -3,7 +3,7 @@
 Bars: stamp keys, levels, slot lookups, the canonical neighbour map and
 class labels bit-exact; the matvec within a rounding bound derived from the
 absolute row sums (FP64: 64 eps64 |L| |x|; FP32: 1e-5 |L| |x| for x rounded
-to complex64); solves within the spec errors |u - u*| / |u*| <= 1e-10
+to complex64); solves within the target errors |u - u*| / |u*| <= 1e-10
 (FP64) and <= 1e-9 (FP32 + FP64 refinement), the paper's configurations at
 literal size; a batch gives each problem bitwise the result it gets alone.
 """

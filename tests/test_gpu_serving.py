@@ -1,7 +1,7 @@
 """GPU: the continuous-batching engine.  Requests of different dimension, size
 and precision served together give each request bitwise the result it gets
 when solved alone (fixed-order per-problem reductions, no cross-problem
-arithmetic), match the CPU oracle within the benchmark spec's tolerances, and the
+arithmetic), match the CPU oracle within the stated tolerances, and the
 engine never admits past its HBM budget."""
 import numpy as np
 import pytest

@@ -64,7 +64,7 @@ def test_app_a_count_is_exact_in_generic_position(d, half, n_f, N):
         assert int((lev == n).sum()) == shell
 
 
-def test_app_a_count_survey_case():
+def test_app_a_count_worked_case():
     # d = 40, |A| = 5, |F| = 6, N = 3 -> 1386 by the count
     assert ost.cardinality_bound(6, 11, 3) == 6 * (1 + 10 + (10 + 40) + (10 + 80 + 80))
 
