@@ -204,24 +204,29 @@ ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const vo
 
 /* ss_solve_direct -- the paper's own solver (Alg. 1, steps 4-5: dense assembly of L_N and a
  * direct solve), run per connected class (Sec. 6; the system is block diagonal over classes, proof
- * of Prop. SolutionSupport).  Each class block is assembled densely in FP64 and factored as L L^H
- * (Cholesky; the block is Hermitian positive definite on k != 0 by Prop.
+ * of Prop. SolutionSupport).  Each class block is assembled densely (entries formed in FP64) and
+ * factored as L L^H (Cholesky; the block is Hermitian positive definite on k != 0 by Prop.
  * ExistenceUniquenessStability), then L y = f, L^H u = y.  The zero frequency gets u_0 = 0.
+ *   prec: SS_FP64 -- factor and substitutions in FP64;  SS_FP32_REFINE -- factor and substitutions
+ *         in FP32, wrapped in iterative refinement with the FP64 residual f - L u and update.
+ *   tol:  > 0: refinement steps until every class has |f_c - L u_c|_2 <= tol |f_c|_2 (at most 30);
+ *         <= 0: one solve, no refinement.
  *   f_dev: device, n_total complex128 in canonical order (as for ss_solve_op; f_0 is ignored).
  *   u_dev: device, n_total complex128 in canonical order; out only.
- *   info (host, nullable): factorisation time and size, see ss_direct_info.
+ *   info (host, nullable): factorisation time and size, steps and residual, see ss_direct_info.
  * Memory: the lower triangle of every class block, in chunks of consecutive classes of about equal
- * size and at most 16 GiB (one class per chunk at least).
+ * size and at most 16 GiB (one class per chunk at least), plus four FP64 vectors of n_exec.
  * Errors: SS_ERANGE (a class of more than 8192 rows), SS_ENOTPD (a non-positive pivot: u is then
- * not a solution), SS_ENOMEM, SS_EDEVICE.  Synchronises `stream`. */
+ * not a solution), SS_ENOCONV (tol > 0 not reached), SS_ENOMEM, SS_EDEVICE.  Synchronises `stream`. */
 typedef struct {
   double factor_ms;       /* device time of the factorisation kernels, summed over chunks       */
   int64_t tiles;          /* 32 x 32 complex tiles of the lower triangles factored               */
   int32_t chunks;         /* chunks the classes were factored in                                 */
-  int32_t reserved;
+  int32_t refine_steps;   /* substitution steps (1 without refinement), most over the chunks     */
+  double rel_residual;    /* max over classes of |f_c - L_N u_c|_2 / |f_c|_2, in FP64            */
 } ss_direct_info;
-ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void* stream,
-                          ss_direct_info* info);
+ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, ss_precision prec, double tol,
+                          void* stream, ss_direct_info* info);
 
 /* rows of every connected class of op (Sec. 6), in execution order (problem by problem).
  *   sizes (host, nullable): cap entries; n_out: the number of classes.  cap smaller than the

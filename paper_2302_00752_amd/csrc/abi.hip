@@ -211,16 +211,18 @@ ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const vo
   });
 }
 
-ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, void* stream, ss_direct_info* info) {
+ss_status ss_solve_direct(const ss_op* op, const void* f_dev, void* u_dev, ss_precision prec, double tol,
+                          void* stream, ss_direct_info* info) {
   return guarded([&]() -> ss_status {
     if (!op || !op->impl) return fail(SS_EINVAL, "null operator");
     DirectStats st;
-    const ss_status r = direct_solve_impl(op->impl, f_dev, u_dev, as_stream(stream), info ? &st : nullptr);
+    const ss_status r = direct_solve_impl(op->impl, f_dev, u_dev, prec, tol, as_stream(stream), &st);
     if (info) {
       info->factor_ms = st.factor_ms;
       info->tiles = st.tiles;
       info->chunks = st.chunks;
-      info->reserved = 0;
+      info->refine_steps = st.refine_steps;
+      info->rel_residual = st.rel_residual;
     }
     return r;
   });

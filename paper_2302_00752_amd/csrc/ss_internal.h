@@ -287,8 +287,11 @@ struct DirectStats {
   double factor_ms = 0;    // factorisation kernels (all tile columns), summed over chunks
   int64_t tiles = 0;       // lower 32 x 32 tiles factored
   int32_t chunks = 0;      // chunks of classes the workspace budget split the batch into
+  int32_t refine_steps = 0;    // substitution steps of the chunk that needed most
+  double rel_residual = 0;     // max over classes of |f_c - L u_c| / |f_c|
 };
-ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, hipStream_t s, DirectStats* stats);
+ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, ss_precision prec, double tol,
+                            hipStream_t s, DirectStats* stats);
 ss_status proxy_error_impl(const StampImpl* st, const OpImpl* op, const void* u, int64_t n_u, const double* f_hat,
                            double* err, hipStream_t stream);
 

@@ -43,10 +43,11 @@ class SolveInfo(C.Structure):
 
 
 class DirectInfo(C.Structure):
-    _fields_ = [("factor_ms", C.c_double), ("tiles", C.c_int64), ("chunks", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("factor_ms", C.c_double), ("tiles", C.c_int64), ("chunks", C.c_int32), ("refine_steps", C.c_int32),
+                ("rel_residual", C.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SparseSpecError(RuntimeError):
@@ -90,7 +91,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_batch_size": [P, pi64, pi64],
         "ss_batch_solution": [P, P, P],
         "ss_proxy_error": [P, P, P, i64, pd, pd, P],
-        "ss_solve_direct": [P, P, P, P, C.POINTER(DirectInfo)],
+        "ss_solve_direct": [P, P, P, i32, dbl, P, C.POINTER(DirectInfo)],
         "ss_op_class_sizes": [P, i64, pi64, pi64],
         "ss_build_adr": [P, P, pi32, pi16, pd, pi32, pi16, pd, P, C.POINTER(P)],
         "ss_adr_apply": [P, P, P, P],
@@ -296,11 +297,12 @@ class Operator:
             _check(st)
         return [i.as_dict() for i in info]
 
-    def solve_direct(self, f, u, stream=None) -> dict:
-        """Dense direct solve of L_N u = f per connected class (device complex128, canonical order)."""
+    def solve_direct(self, f, u, precision="fp64", tol: float = 0.0, stream=None) -> dict:
+        """Dense direct solve of L_N u = f per connected class (device complex128, canonical order);
+        ``tol > 0`` refines until every class's relative residual is below it."""
         info = DirectInfo()
         _check(_lib.ss_solve_direct(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
-                                    C.c_void_p(_stream(stream)), C.byref(info)))
+                                    PRECISION[precision], float(tol), C.c_void_p(_stream(stream)), C.byref(info)))
         return info.as_dict()
 
     def class_sizes(self) -> np.ndarray:

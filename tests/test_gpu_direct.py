@@ -4,7 +4,8 @@ tiled Cholesky in FP64 through the C ABI against the oracle's per-class dense so
 Bars: |u - u_oracle| / |u_oracle| <= 1e-10 at the paper's configurations (cfg2 at its full
 level 3: 20 classes of 1561 rows, 49 tiles each), the residual |f - L u| / |f| <= 1e-12 by
 the FP64 matvec, agreement with FP64 PCG, each problem bitwise the same in a batch as alone,
-u_0 = 0, and the error paths (a class above the row limit, an indefinite operator).
+u_0 = 0, and the error paths (a class above the row limit, an indefinite operator).  The FP32
+factorisation with FP64 refinement to a residual of 1e-12 meets the same bars.
 """
 import numpy as np
 import pytest
@@ -27,10 +28,10 @@ def ss():
     return sparsespec
 
 
-def direct(ss, op, f):
+def direct(ss, op, f, precision="fp64", tol=0.0):
     fd = torch.from_numpy(f).cuda()
     ud = torch.full_like(fd, complex(np.nan, np.nan))
-    info = op.solve_direct(fd, ud)
+    info = op.solve_direct(fd, ud, precision, tol)
     torch.cuda.synchronize()
     return ud.cpu().numpy(), info
 
@@ -195,3 +196,42 @@ def test_direct_class_near_the_row_limit(ss):
     op.solve(fd, ud, 1e-13, "fp64", 20000)
     torch.cuda.synchronize()
     assert rel(u, ud.cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.parametrize("case", [(1, None), (2, 2), (2, None), (4, 1)])
+def test_direct_fp32_refine_matches_oracle(ss, case):
+    config, level = case
+    oc = oracle_case(config, 0, level)
+    st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+    f = f_vector(ss, st, [oc["p"]])
+    u, info = direct(ss, op, f, "fp32_refine", 1e-12)
+    assert info["refine_steps"] >= 2 and info["rel_residual"] <= 1e-12
+    assert rel(u, oc["u"]) <= ERR64, (rel(u, oc["u"]), info)
+    assert residual(ss, op, f, u) <= 1e-12
+    assert np.all(u[~np.any(oc["keys"] != 0, axis=1)] == 0)
+    # FP64 with the same tolerance: one step already meets it
+    u64, i64 = direct(ss, op, f, "fp64", 1e-12)
+    assert i64["refine_steps"] == 1 and i64["rel_residual"] <= 1e-12
+
+
+def test_direct_fp32_refine_batch_equals_alone_and_limits(ss):
+    # refinement stops per class, so each problem's u is bitwise its solve alone
+    probs = [workloads.make(2, i, level=2) for i in range(3)]
+    st, op = build(ss, probs)
+    u, _ = direct(ss, op, f_vector(ss, st, probs), "fp32_refine", 1e-12)
+    for i, p in enumerate(probs):
+        s1, o1 = build(ss, [p])
+        ua, _ = direct(ss, o1, f_vector(ss, s1, [p]), "fp32_refine", 1e-12)
+        assert np.array_equal(u[st.offsets[i]:st.offsets[i + 1]], ua), i
+    # a tolerance below rounding is reported, the last iterate kept
+    p = workloads.make(1, 0)
+    s1, o1 = build(ss, [p])
+    f = f_vector(ss, s1, [p])
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd)
+    with pytest.raises(ss.SparseSpecError) as e:
+        o1.solve_direct(fd, ud, "fp32_refine", 1e-30)
+    assert e.value.status == ss.SS_ENOCONV
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, _ = ost.stamp(p.f_freqs, af, p.level)
+    assert rel(ud.cpu().numpy(), og.solve(keys, af, ah, f)) <= ERR64
