@@ -5,14 +5,16 @@
 // Each class block is Hermitian positive definite on the nonzero frequencies (the operator is
 // Hermitian, and coercive by Prop. ExistenceUniquenessStability); the zero frequency has an
 // all-zero row and column, and is given the identity instead (u_0 = 0).  The block is factored
-// by a tiled left-looking Cholesky, L L^H, in FP64, two launches per tile column j:
-//   diagonal:   A_jj -= sum_{s<j} L_js L_js^H;  L_jj = chol(A_jj);  M_j = L_jj^{-1}
-//   below it:   A_ij -= sum_{s<j} L_is L_js^H;  L_ij = A_ij M_j^H                    (i > j)
-// (the products on FP64 MFMA, split over s across the waves of a block), then L y = f and
-// L^H u = y by tile substitution, the diagonal blocks applied as products with M_j.  Storage: per
-// class the lower triangle of 32 x 32 complex tiles, each tile column-major and contiguous
-// (16 KB), row-major over tiles: tile (i, j), j <= i, is number i (i + 1) / 2 + j.  The inverses
-// M_j go to an array of their own; the diagonal tiles keep the updated A_jj.
+// by a tiled left-looking Cholesky, L L^H, in FP64 or FP32, the launch of tile column j doing
+//   below the diagonal:  A_ij -= sum_{s<j} L_is L_js^H;  L_ij = A_ij M_j^H              (i > j)
+//   the next diagonal:   A_jj -= sum_{s<j} L_js L_js^H;  L_jj = chol(A_jj);  M_j = L_jj^{-1}
+// (the products on MFMA, split over s across the waves of a block), then L y = f and L^H u = y by
+// tile substitution, the diagonal blocks applied as products with M_j.  With an FP32 factor the
+// substitutions are steps of iterative refinement, u += solve(f - L u), the residual and u in
+// FP64.  Storage: per class the lower triangle of 32 x 32 complex tiles, each tile column-major
+// and contiguous (16 KB in FP64), row-major over tiles: tile (i, j), j <= i, is number
+// i (i + 1) / 2 + j.  The inverses M_j go to an array of their own; the diagonal tiles keep the
+// updated A_jj.
 #include <algorithm>
 #include <cmath>
 
