@@ -374,3 +374,23 @@ def test_class_larger_than_lds_window(ss):
     st, op = build(ss, [p])
     assert op.n_components < 4
     _check_against_oracle(ss, p, precision="fp32_refine")
+
+
+def test_empty_inputs_rejected(ss):
+    # no forcing frequency, an empty supp(a), no problem at all: argument errors before any work
+    import ctypes as C
+    with pytest.raises(ss.SparseSpecError) as e:
+        ss.Stamp.build([P(2, [[0, 0], [1, 0], [-1, 0]], [1.0, 0.1, 0.1], np.zeros((0, 2)), [], 1)])
+    assert e.value.status == ss.SS_EINVAL
+    with pytest.raises(ss.SparseSpecError) as e:
+        ss.Stamp.build([P(2, np.zeros((0, 2)), [], [[1, 0]], [1.0], 1)])
+    assert e.value.status == ss.SS_EINVAL
+    h = C.c_void_p()
+    z32 = np.zeros(1, dtype=np.int32)
+    z16 = np.zeros(2, dtype=np.int16)
+    st = ss._lib.ss_build_stamp_batch(0, 2, z32.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      z16.ctypes.data_as(C.POINTER(C.c_int16)),
+                                      z32.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      z16.ctypes.data_as(C.POINTER(C.c_int16)),
+                                      z32.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(h))
+    assert st == ss.SS_EINVAL and not h.value
