@@ -327,7 +327,7 @@ def _trig(rng, d, n_sin, n_cos, draw, coef, forbid=()):
 
 
 def adr3d(level: int, instance: int = 0, n_b: int = 3, n_c: int = 3) -> AdrProblem:
-    """The exactly sparse 3-D ADR problem of Sec. 10.4: a = a_0 + 2 sine + 2 cosine modes, each b_j
+    """The exactly sparse 3-D ADR problem of Sec. 10.5: a = a_0 + 2 sine + 2 cosine modes, each b_j
     and c (c with c_0) n_b resp. n_c sine + cosine modes each, f = 2 sine + 3 cosine modes; every
     frequency uniform in [-49, 50]^3; a and f coefficients U[-1, 1], b and c coefficients U[0, 1];
     a_0 = 4 ceil(|c_a|_2), c_0 = 4 ceil(|c_c|_2).  The paper takes 5 + 5 modes for b_j and c; the
