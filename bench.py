@@ -423,9 +423,41 @@ def main():
             "rel_diff_vs_pcg_fp64": float(torch.linalg.norm(up - uh).item() / torch.linalg.norm(up).item())}
         sth.close()
         oph.close()
+        # level 3: two classes of about 22 k rows per problem (the case the paper reports at the limit of
+        # its memory with dense assembly), FP32 factor refined in FP64
+        B3 = 4
+        hp3 = [workloads.highsparsity(1024, 3, i) for i in range(B3)]
+        st3 = ss.Stamp.build(hp3)
+        op3 = ss.Operator.build(st3, hp3, 0)
+        f3 = st3.forcing_vector(hp3, dev)
+        u3 = torch.zeros_like(f3)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        i3 = op3.solve_direct(f3, u3, "fp32_refine", args.tol)
+        t3 = 1e3 * (time.perf_counter() - t)
+        p3 = torch.zeros_like(f3)
+        op3.solve(f3, p3, args.tol, "fp64", 1000)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        op3.solve(f3, p3, args.tol, "fp64", 1000)
+        torch.cuda.synchronize()
+        tp3 = 1e3 * (time.perf_counter() - t)
+        s3 = op3.class_sizes()
+        direct["high_sparsity_d1024_level3"] = {
+            "batch": B3, "classes": int(len(s3)), "class_rows_max": int(s3.max()), "precision": "fp32_refine",
+            "solve_ms": t3, "factor_ms": float(i3["factor_ms"]), "pcg_fp64_ms": tp3,
+            "tiles_GB": float(i3["tiles"]) * 8192 / 1e9,
+            "rel_diff_vs_pcg_fp64": float(torch.linalg.norm(u3 - p3).item() / torch.linalg.norm(p3).item())}
+        st3.close()
+        op3.close()
+        del u3, p3, f3
         hd = direct["high_sparsity_d1024_level2"]
         log(f"direct, high sparsity d=1024 N=2 B={Bh}: {hd['solves_per_s']:.0f} solves/s vs PCG "
             f"{hd['pcg_fp64_solves_per_s']:.0f}; rel diff {hd['rel_diff_vs_pcg_fp64']:.1e}")
+        h3 = direct["high_sparsity_d1024_level3"]
+        log(f"direct, high sparsity d=1024 N=3 B={B3} ({h3['classes']} classes of {h3['class_rows_max']} rows, "
+            f"{h3['tiles_GB']:.1f} GB of FP32 tiles): {h3['solve_ms']:.0f} ms (factor {h3['factor_ms']:.0f} ms) vs PCG "
+            f"{h3['pcg_fp64_ms']:.1f} ms; rel diff {h3['rel_diff_vs_pcg_fp64']:.1e}")
         log(f"direct fp32+refine: {med_d32:.1f} ms (factor {med_f32:.1f} ms = {tflops32:.1f} TFLOP/s), "
             f"{int(info32['refine_steps'])} steps, residual {info32['rel_residual']:.1e}, vs fp64 direct {diff32:.1e}")
         log(f"direct: B={Bd} ({len(sizes)} classes of <= {sizes.max()} rows): {med_d:.1f} ms "

@@ -216,7 +216,7 @@ ss_status ss_proxy_error(const ss_stamp* st_next, const ss_op* op_next, const vo
  *   info (host, nullable): factorisation time and size, steps and residual, see ss_direct_info.
  * Memory: the lower triangle of every class block, in chunks of consecutive classes of about equal
  * size and at most 16 GiB (one class per chunk at least), plus four FP64 vectors of n_exec.
- * Errors: SS_ERANGE (a class of more than 8192 rows), SS_ENOTPD (a non-positive pivot: u is then
+ * Errors: SS_ERANGE (a class of more than 32768 rows), SS_ENOTPD (a non-positive pivot: u is then
  * not a solution), SS_ENOCONV (tol > 0 not reached), SS_ENOMEM, SS_EDEVICE.  Synchronises `stream`. */
 typedef struct {
   double factor_ms;       /* device time of the factorisation kernels, summed over chunks       */

@@ -29,7 +29,8 @@ constexpr int kTE = kT * kT;                  // entries per tile
 constexpr int kLdT = kT + 1;                  // LDS row stride of a staged tile
 constexpr int kDnBlock = 256;
 constexpr int kDnWaves = kDnBlock / 64;
-constexpr int64_t kDirectMaxRows = 8192;      // the substitution keeps one class vector in LDS
+constexpr int64_t kDirectMaxRows = 32768;     // rows of one class (4.3 GB of FP32, 8.6 GB of FP64 tiles)
+constexpr size_t kSubstLds = 150 * 1024;     // LDS the substitution may take for the class vector
 constexpr int64_t kDirectBudget = int64_t(16) << 30;  // factor storage per chunk of classes
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -466,7 +467,8 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_offdiag(int nc, int per, int j,
 
 // ---- L y = b, then L^H d = y, one block per class, the class vector in LDS in the factorisation
 // precision.  The diagonal blocks are products with M_s (one thread per row); the off-diagonal
-// tile products are spread over the block.  One refinement step: b = r (execution order, FP64;
+// tile products are spread over the block (the vector in device memory when the class is too large
+// for LDS).  One refinement step: b = r (execution order, FP64;
 // the zero frequency's row gives 0), then x += d in FP64.  A class whose residual ratio is already
 // at most tol2 takes no step, so each class's iterate does not depend on the others'.
 template <typename NormT, typename T>
@@ -475,7 +477,8 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_subst(int nc, const DClass* __r
                                                         const typename Prec<T>::C* __restrict__ W,
                                                         const typename Prec<T>::C* __restrict__ Minv,
                                                         const double2* __restrict__ r, double2* __restrict__ x,
-                                                        const double* __restrict__ ratio, double tol2) {
+                                                        const double* __restrict__ ratio, double tol2,
+                                                        typename Prec<T>::C* __restrict__ gv) {
   typedef typename Prec<T>::C C2;
   const int c = blockIdx.x;
   if (c >= nc) return;
@@ -483,7 +486,9 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_subst(int nc, const DClass* __r
   const DClass C = cls[c];
   extern __shared__ __align__(16) char s_raw[];
   C2* sT = reinterpret_cast<C2*>(s_raw);   // staged inverse diagonal factor, stride kLdT
-  C2* v = sT + kT * kLdT;                  // the class vector, nt * kT entries
+  // the class vector, nt * kT entries: in LDS, or for classes too large for it in device memory
+  // (at the class's diagonal-tile offset; the block's barriers order its accesses there as well)
+  C2* v = gv ? gv + C.dbase * kT : sT + kT * kLdT;
   const C2* tiles = W + C.tbase * kTE;
   const int tid = threadIdx.x;
   const int np = C.nt * kT;
@@ -698,7 +703,22 @@ ss_status run_chunk(const OpImpl* op, const std::vector<DClass>& ch, int64_t til
   }
   if (h_err[1]) return fail(SS_EDEVICE, "dense assembly found a column outside its class");
   if (h_err[0]) *not_pd = true;
-  const size_t lds = (size_t)(kT * kLdT + max_nt * kT) * sizeof(C2);
+  size_t lds = (size_t)(kT * kLdT + max_nt * kT) * sizeof(C2);
+  C2* gv = nullptr;
+  if (lds > kSubstLds) {
+    SS_TRY(dalloc(&gv, (size_t)dtiles * kT));
+    lds = (size_t)kT * kLdT * sizeof(C2);
+  }
+  struct ReleaseV {
+    hipStream_t s;
+    void* p;
+    ~ReleaseV() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        pool_free(p);
+      }
+    }
+  } relv{s, gv};
   const double tol2 = tol * tol;
   std::vector<double> h_ratio(nc);
   const double2* rhs = fe;   // the first step solves with f itself (x = 0)
@@ -707,10 +727,10 @@ ss_status run_chunk(const OpImpl* op, const std::vector<DClass>& ch, int64_t til
   for (;;) {
     if (op->wide_norm)
       k_dn_subst<int64_t, T><<<(unsigned)nc, kDnBlock, lds, s>>>(nc, dcls, (const int64_t*)od.norm, W, Dg, rhs, x,
-                                                                  gate, tol2);
+                                                                  gate, tol2, gv);
     else
       k_dn_subst<int32_t, T><<<(unsigned)nc, kDnBlock, lds, s>>>(nc, dcls, (const int32_t*)od.norm, W, Dg, rhs, x,
-                                                                  gate, tol2);
+                                                                  gate, tol2, gv);
     SS_HIP(hipGetLastError());
     ++step;
     SS_TRY(apply_impl(op, SS_FP64, x, y, s));
@@ -744,7 +764,7 @@ ss_status direct_solve_impl(const OpImpl* op, const void* f_dev, void* u_dev, ss
   int64_t max_n = 0;
   for (int64_t k = 0; k < n_cls; ++k) max_n = std::max(max_n, op->cls_n[k]);
   if (max_n > kDirectMaxRows)
-    return fail(SS_ERANGE, "a class has more than 8192 rows: too large for the dense direct solve");
+    return fail(SS_ERANGE, "a class has more than 32768 rows: too large for the dense direct solve");
   // the problem of every class, from the execution offsets
   std::vector<int32_t> cprob(n_cls);
   for (int64_t k = 0; k < n_cls; ++k)

@@ -4,7 +4,8 @@ tiled Cholesky in FP64 through the C ABI against the oracle's per-class dense so
 Bars: |u - u_oracle| / |u_oracle| <= 1e-10 at the paper's configurations (cfg2 at its full
 level 3: 20 classes of 1561 rows, 49 tiles each), the residual |f - L u| / |f| <= 1e-12 by
 the FP64 matvec, agreement with FP64 PCG, each problem bitwise the same in a batch as alone,
-u_0 = 0, and the error paths (a class above the row limit, an indefinite operator).  The FP32
+u_0 = 0, classes too large for the substitution's LDS vector, and the error paths (a class above
+the row limit, an indefinite operator).  The FP32
 factorisation with FP64 refinement to a residual of 1e-12 meets the same bars.
 """
 import numpy as np
@@ -138,14 +139,17 @@ def test_direct_one_class_of_thousands_of_rows(ss):
 
 
 def test_direct_errors(ss):
-    # a class above 8192 rows (the d = 3 multiscale set merges into large classes)
-    oc = oracle_case(3)
-    st, op = build(ss, [oc["p"]], FLAGS[3])
-    f = torch.from_numpy(f_vector(ss, st, [oc["p"]])).cuda()
-    if op.class_sizes().max() > 8192:
-        with pytest.raises(ss.SparseSpecError) as e:
-            op.solve_direct(f, torch.zeros_like(f))
-        assert e.value.status == ss.SS_ERANGE
+    # a class above the 32 768-row limit: a dense support in d = 2 at level 78, one class of 36 815 rows
+    w = [(1, 0), (0, 1), (1, 1), (2, -1)]
+    af = [[0, 0]] + [list(v) for v in w] + [[-a, -b] for a, b in w]
+    ah = [1.0] + [0.05 + 0.02j] * 4 + [0.05 - 0.02j] * 4
+    p = P(2, af, ah, [[3, 1]], [1.0], 78)
+    st, op = build(ss, [p])
+    assert op.class_sizes().max() == 36815
+    f = torch.from_numpy(f_vector(ss, st, [p])).cuda()
+    with pytest.raises(ss.SparseSpecError) as e:
+        op.solve_direct(f, torch.zeros_like(f))
+    assert e.value.status == ss.SS_ERANGE
     # a = 0.1 + cos(2 pi x) changes sign: with the positivity check skipped the block is
     # indefinite and the factorisation reports it
     p = P(1, [[0], [1], [-1]], [0.1, 0.5, 0.5], [[1], [-1]], [1.0, 1.0], 6)
@@ -235,3 +239,21 @@ def test_direct_fp32_refine_batch_equals_alone_and_limits(ss):
     af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
     keys, _ = ost.stamp(p.f_freqs, af, p.level)
     assert rel(ud.cpu().numpy(), og.solve(keys, af, ah, f)) <= ERR64
+
+
+def test_direct_classes_beyond_lds(ss):
+    # the high-sparsity problem at level 3: two classes of 22 151 rows (693 tile rows), whose
+    # substitution keeps the class vector in device memory; FP32 factor refined in FP64
+    p = workloads.highsparsity(4, 3)
+    st, op = build(ss, [p])
+    sizes = op.class_sizes()
+    assert len(sizes) == 2 and sizes.min() == sizes.max() == 22151
+    f = f_vector(ss, st, [p])
+    u, info = direct(ss, op, f, "fp32_refine", 1e-12)
+    assert info["rel_residual"] <= 1e-12 and info["refine_steps"] >= 2
+    assert residual(ss, op, f, u) <= 1e-12
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.zeros_like(fd)
+    op.solve(fd, ud, 1e-13, "fp64", 5000)
+    torch.cuda.synchronize()
+    assert rel(u, ud.cpu().numpy()) <= 1e-9
