@@ -413,7 +413,7 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
     if (!c0 || !(Ct[(size_t)p * 64 + zj[p]].x > 0.0) || Ct[(size_t)p * 64 + zj[p]].y != 0.0)
       return fail(SS_EINVAL, "c_0 must be real and positive (the zero frequency is then an ordinary unknown)");
   }
-  std::unique_ptr<AdrImpl> A(new AdrImpl());
+  std::unique_ptr<AdrImpl, void (*)(AdrImpl*)> A(new AdrImpl(), adr_free_impl);   // frees on every error path
   A->op = op;
   A->device = op->device;
   double2 *dB = nullptr, *dC = nullptr;

@@ -17,6 +17,7 @@
 // updated A_jj.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "ss_internal.h"
 
@@ -650,19 +651,24 @@ ss_status run_chunk(const OpImpl* op, const std::vector<DClass>& ch, int64_t til
   DClass* dcls = nullptr;
   int* err = nullptr;
   double* ratio = nullptr;
-  SS_TRY(dalloc(&W, (size_t)std::max<int64_t>(tiles, 1) * kTE));
-  SS_TRY(dalloc(&Dg, (size_t)std::max<int64_t>(dtiles, 1) * kTE));
-  SS_TRY(dalloc((char**)&dcls, (size_t)nc * sizeof(DClass)));
-  SS_TRY(dalloc(&err, 2));
-  SS_TRY(dalloc(&ratio, (size_t)nc));
-  struct Release {
+  struct Release {   // every block this chunk allocated, returned on every exit path
     hipStream_t s;
-    void* p[5];
+    std::vector<void*> p;
     ~Release() {
       (void)hipStreamSynchronize(s);
       for (void* b : p) pool_free(b);
     }
-  } rel{s, {W, Dg, dcls, err, ratio}};
+  } rel{s, {}};
+  SS_TRY(dalloc(&W, (size_t)std::max<int64_t>(tiles, 1) * kTE));
+  rel.p.push_back(W);
+  SS_TRY(dalloc(&Dg, (size_t)std::max<int64_t>(dtiles, 1) * kTE));
+  rel.p.push_back(Dg);
+  SS_TRY(dalloc((char**)&dcls, (size_t)nc * sizeof(DClass)));
+  rel.p.push_back(dcls);
+  SS_TRY(dalloc(&err, 2));
+  rel.p.push_back(err);
+  SS_TRY(dalloc(&ratio, (size_t)nc));
+  rel.p.push_back(ratio);
   SS_HIP(h2d(dcls, ch.data(), (size_t)nc * sizeof(DClass), s));
   SS_HIP(hipMemsetAsync(W, 0, (size_t)tiles * kTE * sizeof(C2), s));
   SS_HIP(hipMemsetAsync(err, 0, 2 * sizeof(int), s));
@@ -707,18 +713,9 @@ ss_status run_chunk(const OpImpl* op, const std::vector<DClass>& ch, int64_t til
   C2* gv = nullptr;
   if (lds > kSubstLds) {
     SS_TRY(dalloc(&gv, (size_t)dtiles * kT));
+    rel.p.push_back(gv);
     lds = (size_t)kT * kLdT * sizeof(C2);
   }
-  struct ReleaseV {
-    hipStream_t s;
-    void* p;
-    ~ReleaseV() {
-      if (p) {
-        (void)hipStreamSynchronize(s);
-        pool_free(p);
-      }
-    }
-  } relv{s, gv};
   const double tol2 = tol * tol;
   std::vector<double> h_ratio(nc);
   const double2* rhs = fe;   // the first step solves with f itself (x = 0)
