@@ -147,6 +147,23 @@ def main():
     torch.cuda.synchronize()
     t_op = time.perf_counter() - t
     f = st.forcing_vector(batch, dev)
+    # rank-1 lattice on the same sets (Lemma RandomRank1Lattice): the indices k . z mod M of every
+    # key and the per-problem reconstructing check, at the Lemma's modulus for sigma = 0.01
+    lat_n = int(np.max(np.diff(st.offsets)))
+    lat_keys, _ = st.keys()
+    lat_K = int((lat_keys.max(axis=0).astype(np.int64) - lat_keys.min(axis=0)).max())   # expansion
+    del lat_keys
+    lat_M = ss.lattice_modulus(lat_K, lat_n, 0.01)
+    lat_z = np.random.default_rng(4242).integers(1, lat_M, size=st.d)
+    lat_ok, lat_vals = st.lattice(lat_z, lat_M)
+    t = time.perf_counter()
+    for _ in range(5):
+        lat_ok, lat_vals = st.lattice(lat_z, lat_M)
+    lat_ms = (time.perf_counter() - t) / 5 * 1e3
+    lattice = {"keys": st.n_total, "problems": st.n_prob, "M": lat_M, "sigma": 0.01, "ms": lat_ms,
+               "keys_per_s": st.n_total / (lat_ms / 1e3), "reconstructing": int(lat_ok.sum())}
+    del lat_vals
+    log(f"lattice: {st.n_total} keys, M {lat_M}: {lat_ms:.2f} ms, {int(lat_ok.sum())}/{st.n_prob} sets reconstructed")
     solve_ms = {}
     sols = {}
     iters = {}
@@ -580,6 +597,7 @@ def main():
                      "measured_copy_GB/s": copy_gbs, "measured_read_GB/s": read_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
         "proxy_error": proxy,
+        "lattice": lattice,
         "direct_solve": direct,
         "adr": adr_out,
         "cpu_baseline": cpu,

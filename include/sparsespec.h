@@ -127,6 +127,32 @@ ss_status ss_stamp_lookup_batch(const ss_stamp* st, int64_t nq, const int32_t* p
  * coefficient has a slot.  Synchronises `stream`. */
 ss_status ss_stamp_forcing(const ss_stamp* st, const double* f_hat, void* f, void* stream);
 
+/* ---------------------------------------------------------------- rank-1 lattices
+ * Random rank-1 lattices Lambda(z, M) on the stamping sets (Sec. 8, Definition of a
+ * reconstructing rank-1 lattice, Lemma RandomRank1Lattice).  The lattice gives frequency k
+ * the index k . z mod M; it reconstructs a set when distinct frequencies get distinct indices.
+ *
+ * ss_lattice_modulus -- the Lemma's modulus: *M (host) = the smallest prime greater than
+ *   max(expansion, n^2 / sigma), where expansion is K of the Lemma (side of the smallest cube
+ *   holding the set) and n the set's size; a z drawn uniformly from {1..M-1}^d then
+ *   reconstructs the set with probability at least 1 - sigma.  The threshold is formed in
+ *   double precision.  sigma outside (0, 1] or negative sizes -> SS_EINVAL; a modulus above
+ *   2^40 -> SS_ERANGE.  Host only, no device work.
+ */
+ss_status ss_lattice_modulus(int64_t expansion, int64_t n, double sigma, int64_t* M);
+
+/* ss_stamp_lattice -- lattice indices of every key of st and, per problem, whether the
+ * lattice reconstructs that problem's stamping set.
+ *   z: d generating-vector entries (host, borrowed for the call), each in [1, M-1].
+ *   M: the lattice size, 2 <= M <= 2^40 (need not be prime).
+ *   values: device, int64 [n_total] in canonical order, receives k . z mod M in [0, M);
+ *     nullable (only the check).
+ *   reconstructing: host, int32 [n_prob]: 1 if the indices of the problem's keys are distinct.
+ * Argument errors -> SS_EINVAL (nothing written).  Synchronises `stream`.
+ */
+ss_status ss_stamp_lattice(const ss_stamp* st, const int64_t* z, int64_t M, void* values,
+                           int32_t* reconstructing, void* stream);
+
 void ss_free_stamp(ss_stamp* st);
 
 /* ---------------------------------------------------------------- operator

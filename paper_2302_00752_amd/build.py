@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsparsespec.so")
-SOURCES = ["abi.hip", "alloc.hip", "stamp.hip", "op.hip", "solve.hip", "batch.hip", "proxy.hip", "direct.hip", "adr.hip"]
+SOURCES = ["abi.hip", "alloc.hip", "stamp.hip", "op.hip", "solve.hip", "batch.hip", "proxy.hip", "direct.hip", "adr.hip", "lattice.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

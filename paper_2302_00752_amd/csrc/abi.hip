@@ -138,6 +138,18 @@ ss_status ss_stamp_forcing(const ss_stamp* st, const double* f_hat, void* f, voi
   });
 }
 
+ss_status ss_lattice_modulus(int64_t expansion, int64_t n, double sigma, int64_t* M) {
+  return guarded([&]() -> ss_status { return lattice_modulus_impl(expansion, n, sigma, M); });
+}
+
+ss_status ss_stamp_lattice(const ss_stamp* st, const int64_t* z, int64_t M, void* values, int32_t* reconstructing,
+                           void* stream) {
+  return guarded([&]() -> ss_status {
+    if (!st || !st->impl) return fail(SS_EINVAL, "null stamp");
+    return stamp_lattice_impl(st->impl, z, M, static_cast<int64_t*>(values), reconstructing, as_stream(stream));
+  });
+}
+
 void ss_free_stamp(ss_stamp* st) {
   if (!st) return;
   free_stamp_impl(st->impl);

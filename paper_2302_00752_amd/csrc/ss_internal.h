@@ -273,6 +273,9 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
                             int64_t* slot_out, hipStream_t stream, const int32_t* probs = nullptr);
 
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream);
+ss_status lattice_modulus_impl(int64_t K, int64_t n, double sigma, int64_t* M);
+ss_status stamp_lattice_impl(const StampImpl* st, const int64_t* z, int64_t M, int64_t* values,
+                             int32_t* reconstructing, hipStream_t s);
 // proxy error of level-N solutions u (canonical order of the level-N stamp) from the stamp and
 // operator built at level N + 1 (proxy.hip); err: host [n_prob]
 struct AdrImpl;

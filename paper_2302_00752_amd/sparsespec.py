@@ -30,7 +30,7 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
             "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
             "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes", "ss_build_adr", "ss_adr_apply",
-            "ss_adr_solve", "ss_free_adr"]
+            "ss_adr_solve", "ss_free_adr", "ss_lattice_modulus", "ss_stamp_lattice"]
 
 
 class SolveInfo(C.Structure):
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_stamp_lookup": [P, i32, i64, pi16, pi64],
         "ss_stamp_lookup_batch": [P, i64, pi32, pi16, pi64],
         "ss_stamp_forcing": [P, pd, P, P],
+        "ss_lattice_modulus": [i64, i64, dbl, pi64],
+        "ss_stamp_lattice": [P, pi64, i64, P, pi32, P],
         "ss_build_op": [P, pi32, pi16, pd, u32, P, C.POINTER(P)],
         "ss_op_info": [P, pi64, pi64, pi64, pi64],
         "ss_op_csr": [P, pi64, pi32, pi32, pi32],
@@ -234,6 +236,22 @@ class Stamp:
         _check(_lib.ss_stamp_forcing(self._h, _ptr(vals, C.c_double), C.c_void_p(f.data_ptr()),
                                      C.c_void_p(_stream(stream))))
         return f
+
+    def lattice(self, z, M, values=True, stream=None):
+        """Rank-1 lattice Lambda(z, M) on every problem's set (Sec. 8, Lemma
+        RandomRank1Lattice): (reconstructing, values) with reconstructing a bool array per
+        problem and values the int64 tensor of k . z mod M per key in canonical order (None
+        when ``values`` is false)."""
+        import torch
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.int64))
+        if z.shape != (self.d,):
+            raise SparseSpecError(SS_EINVAL, "z needs one entry per dimension")
+        ok = np.zeros(self.n_prob, dtype=np.int32)
+        vals = torch.empty(self.n_total, dtype=torch.int64, device="cuda") if values else None
+        _check(_lib.ss_stamp_lattice(self._h, _ptr(z, C.c_int64), int(M),
+                                     C.c_void_p(vals.data_ptr() if values else 0), _ptr(ok, C.c_int32),
+                                     C.c_void_p(_stream(stream))))
+        return ok.astype(bool), vals
 
     def close(self):
         if self._h:
@@ -517,3 +535,10 @@ def solve_batch(problems, tol: float, precision="fp64", max_iter: int = 1000, fl
     if st not in (SS_OK, SS_ENOCONV, SS_EBREAKDOWN) or not h.value:
         _check(st)
     return BatchSolution(h, b.n_prob), [i.as_dict() for i in info]
+
+
+def lattice_modulus(expansion: int, n: int, sigma: float) -> int:
+    """The smallest prime greater than max(expansion, n^2 / sigma) (Lemma RandomRank1Lattice)."""
+    M = C.c_int64(0)
+    _check(_lib.ss_lattice_modulus(int(expansion), int(n), float(sigma), C.byref(M)))
+    return M.value
