@@ -31,7 +31,7 @@ constexpr int kLatChunk = 128;                     // coordinates summed between
 // 2^15 * 2^40 in size.
 __global__ void k_lattice_values(int64_t total, int d, const int16_t* __restrict__ keys,
                                  const int64_t* __restrict__ z, int64_t M, const int32_t* __restrict__ pid,
-                                 int64_t* __restrict__ values, uint64_t* __restrict__ words) {
+                                 int vbits, int64_t* __restrict__ values, uint64_t* __restrict__ words) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int16_t* k = keys + r * d;
@@ -43,15 +43,15 @@ __global__ void k_lattice_values(int64_t total, int d, const int16_t* __restrict
   }
   if (acc < 0) acc += M;
   if (values) values[r] = acc;
-  words[r] = ((uint64_t)pid[r] << kLatBits) | (uint64_t)acc;
+  words[r] = ((uint64_t)pid[r] << vbits) | (uint64_t)acc;
 }
 
 // equal neighbours in the sorted words: the problem in the word's high bits is not separated
-__global__ void k_lattice_dups(int64_t total, const uint64_t* __restrict__ sorted, int32_t* __restrict__ bad) {
+__global__ void k_lattice_dups(int64_t total, const uint64_t* __restrict__ sorted, int vbits, int32_t* __restrict__ bad) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < 1 || r >= total) return;
   const uint64_t w = sorted[r];
-  if (w == sorted[r - 1]) bad[w >> kLatBits] = 1;
+  if (w == sorted[r - 1]) bad[w >> vbits] = 1;
 }
 
 inline unsigned lat_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
@@ -136,17 +136,20 @@ ss_status stamp_lattice_impl(const StampImpl* st, const int64_t* z, int64_t M, i
   SS_HIP(h2d(dz, z, (size_t)st->d * 8, s));
   SS_HIP(hipMemsetAsync(bad, 0, (size_t)np * 4, s));
   if (n > 0) {
-    k_lattice_values<<<lat_grid(n), kBlock, 0, s>>>(n, st->d, st->d_keys, dz, M, st->d_pid, values, w);
+    // sort words: the problem above the vbits bits an index below M needs, as few bits as the sort can take
+    int vbits = 1;
+    while ((int64_t(1) << vbits) < M) ++vbits;
+    k_lattice_values<<<lat_grid(n), kBlock, 0, s>>>(n, st->d, st->d_keys, dz, M, st->d_pid, vbits, values, w);
     SS_HIP(hipGetLastError());
-    int end_bit = kLatBits;
-    while ((int64_t(1) << (end_bit - kLatBits)) < np) ++end_bit;
+    int end_bit = vbits;
+    while ((int64_t(1) << (end_bit - vbits)) < np) ++end_bit;
     size_t tmp_bytes = 0;
     SS_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, w, w2, n, 0, end_bit, s));
     void* tmp = nullptr;
     SS_TRY(dalloc((char**)&tmp, tmp_bytes));
     blocks.push_back(tmp);
     SS_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, w, w2, n, 0, end_bit, s));
-    k_lattice_dups<<<lat_grid(n), kBlock, 0, s>>>(n, w2, bad);
+    k_lattice_dups<<<lat_grid(n), kBlock, 0, s>>>(n, w2, vbits, bad);
     SS_HIP(hipGetLastError());
   }
   std::vector<int32_t> hb(np);
