@@ -28,7 +28,9 @@ constexpr int kLatChunk = 128;                     // coordinates summed between
 
 // index k . z mod M of every key, one thread per key.  Between reductions the sum stays below
 // 2^63: the carried value is below M <= 2^40 and each of the at most 128 terms is below
-// 2^15 * 2^40 in size.
+// 2^15 * 2^40 in size.  For even d each key starts 4-byte aligned and is read two coordinates
+// per load.
+template <bool EVEN>
 __global__ void k_lattice_values(int64_t total, int d, const int16_t* __restrict__ keys,
                                  const int64_t* __restrict__ z, int64_t M, const int32_t* __restrict__ pid,
                                  int vbits, int64_t* __restrict__ values, uint64_t* __restrict__ words) {
@@ -38,7 +40,15 @@ __global__ void k_lattice_values(int64_t total, int d, const int16_t* __restrict
   int64_t acc = 0;
   for (int i0 = 0; i0 < d; i0 += kLatChunk) {
     const int i1 = min(d, i0 + kLatChunk);
-    for (int i = i0; i < i1; ++i) acc += (int64_t)k[i] * z[i];
+    if (EVEN) {   // i0 and i1 are even
+      const uint32_t* k2 = reinterpret_cast<const uint32_t*>(k);
+      for (int i = i0; i < i1; i += 2) {
+        const uint32_t v = k2[i >> 1];
+        acc += (int64_t)(int16_t)(v & 0xffff) * z[i] + (int64_t)(int16_t)(v >> 16) * z[i + 1];
+      }
+    } else {
+      for (int i = i0; i < i1; ++i) acc += (int64_t)k[i] * z[i];
+    }
     acc %= M;
   }
   if (acc < 0) acc += M;
@@ -139,7 +149,10 @@ ss_status stamp_lattice_impl(const StampImpl* st, const int64_t* z, int64_t M, i
     // sort words: the problem above the vbits bits an index below M needs, as few bits as the sort can take
     int vbits = 1;
     while ((int64_t(1) << vbits) < M) ++vbits;
-    k_lattice_values<<<lat_grid(n), kBlock, 0, s>>>(n, st->d, st->d_keys, dz, M, st->d_pid, vbits, values, w);
+    if (st->d % 2 == 0)
+      k_lattice_values<true><<<lat_grid(n), kBlock, 0, s>>>(n, st->d, st->d_keys, dz, M, st->d_pid, vbits, values, w);
+    else
+      k_lattice_values<false><<<lat_grid(n), kBlock, 0, s>>>(n, st->d, st->d_keys, dz, M, st->d_pid, vbits, values, w);
     SS_HIP(hipGetLastError());
     int end_bit = vbits;
     while ((int64_t(1) << (end_bit - vbits)) < np) ++end_bit;
