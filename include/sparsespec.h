@@ -209,6 +209,23 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
                       ss_precision prec, int32_t max_iter, void* stream,
                       ss_solve_info* info);
 
+/* ss_solve_op_noalloc -- ss_solve_op for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It allocates no device
+ * or pinned host memory: the class-resident CG's tables (problem descriptors, unit lists) and its
+ * per-unit results live in one fixed device array of SS_NOALLOC_SCRATCH_BYTES per GPU, held by
+ * the library until the process ends.
+ *   Arguments, layouts, tolerance, precision, result and info: as for ss_solve_op (the results
+ *   are bitwise those of ss_solve_op on the same operator).
+ *   Only operators whose every class has at most 2048 rows are served (their problems run the
+ *   class-resident CG); a larger class needs ss_solve_op's per-problem workspace -> SS_EINVAL.
+ *   The tables take about 100 bytes per problem and 60 per solve unit (a run of whole classes of
+ *   at most 2048 rows); more than SS_NOALLOC_SCRATCH_BYTES in all -> SS_ERANGE, nothing launched.
+ *   An operator built on another device -> SS_EINVAL.
+ * Calls that overlap on one GPU share its array and race: serialise them.  Synchronises `stream`. */
+#define SS_NOALLOC_SCRATCH_BYTES (2u << 20)
+ss_status ss_solve_op_noalloc(const ss_op* op, const void* f_dev, void* u_dev, double tol,
+                              ss_precision prec, int32_t max_iter, void* stream, ss_solve_info* info);
+
 /* Exact proxy error of Sec. 10.1 (Lemma ProxyError) for every problem of a batch:
  * err_out[p] = |f - L u^N|_2 / |f|_2 with L the untruncated operator, u^N the
  * level-N solution extended by zero.  L u^N is supported on S^{N+1} (Prop.

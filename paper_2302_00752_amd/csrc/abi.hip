@@ -296,6 +296,14 @@ ss_status ss_solve_op(const ss_op* op, const void* f_dev, void* u_dev, double to
   });
 }
 
+ss_status ss_solve_op_noalloc(const ss_op* op, const void* f_dev, void* u_dev, double tol, ss_precision prec,
+                              int32_t max_iter, void* stream, ss_solve_info* info) {
+  return guarded([&]() -> ss_status {
+    if (!op || !op->impl) return fail(SS_EINVAL, "null operator");
+    return solve_op_noalloc_impl(op->impl, f_dev, u_dev, tol, prec, max_iter, as_stream(stream), info);
+  });
+}
+
 ss_status ss_op_bytes(const ss_op* op, int64_t* bytes) {
   return guarded([&]() -> ss_status {
     if (!op || !op->impl || !bytes) return fail(SS_EINVAL, "null argument");

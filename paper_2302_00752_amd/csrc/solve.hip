@@ -35,6 +35,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <unordered_map>
 
 #include "ss_internal.h"
@@ -1477,81 +1478,62 @@ std::vector<int4> items_of(const OpImpl* op, int p) {
 }  // namespace
 
 // ---------------------------------------------------------------- engine
-// Problems solved by the class-resident CG in one go: gathered by add(), launched together
-// (one k_unit_solve launch per norm width and precision), results read after a sync.
-struct UnitBatch {
-  struct Item {
-    UDesc d;
-    OpImpl* op;
-    int prob;
-    int req;
-    int group;       // wide * 2 + fp32
-    int prec;
-  };
-  std::vector<Item> items;
-  // after launch(): per item (launch order), its results on the host once the stream is synced
-  std::vector<Item> launched;
-  UnitSum* h_sum = nullptr;       // pinned
-  size_t h_cap = 0;
-  std::vector<void*> dev;         // device blocks of the launch in flight
+// One problem of a class-resident launch, as gathered before the launch.
+struct UnitItem {
+  UDesc d;
+  OpImpl* op;
+  int prob;
+  int req;
+  int group;       // wide * 2 + fp32
+  int prec;
+};
 
-  ~UnitBatch() {
-    release();
-    if (h_sum) (void)hipHostFree(h_sum);
-  }
-  void release() {
-    for (void* q : dev) pool_free(q);
-    dev.clear();
-  }
+inline UnitItem unit_item(OpImpl* op, int p, const void* f, void* u, double tol, ss_precision prec,
+                          int32_t max_iter, int req) {
+  UDesc D{};
+  D.sent = op->d_sent;
+  D.sptr = op->d_sptr;
+  D.norm = op->d_norm;
+  D.exec2canon = op->d_exec2canon;
+  D.A64 = op->d_A64 + (size_t)p * 64;
+  D.A32 = op->d_A32 + (size_t)p * 64;
+  D.nu = op->d_nu + (size_t)p * 64;
+  D.f = (const double2*)f;
+  D.u = (double2*)u;
+  D.a0 = op->a0_host[p];
+  D.tol2 = tol * tol;
+  D.max_iter = max_iter;
+  return UnitItem{D, op, p, req, (op->wide_norm ? 2 : 0) + (prec != SS_FP64 ? 1 : 0), (int)prec};
+}
 
-  void add(OpImpl* op, int p, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter, int req) {
-    UDesc D{};
-    D.sent = op->d_sent;
-    D.sptr = op->d_sptr;
-    D.norm = op->d_norm;
-    D.exec2canon = op->d_exec2canon;
-    D.A64 = op->d_A64 + (size_t)p * 64;
-    D.A32 = op->d_A32 + (size_t)p * 64;
-    D.nu = op->d_nu + (size_t)p * 64;
-    D.f = (const double2*)f;
-    D.u = (double2*)u;
-    D.a0 = op->a0_host[p];
-    D.tol2 = tol * tol;
-    D.max_iter = max_iter;
-    items.push_back(Item{D, op, p, req, (op->wide_norm ? 2 : 0) + (prec != SS_FP64 ? 1 : 0), (int)prec});
-  }
+// Host tables of one class-resident launch.  Units are sorted into launches by (norm width,
+// precision, what the LDS caches); a unit's result is addressed by its position in ul, and each
+// problem's are summed in order through uidx.
+struct UnitPlan {
+  static constexpr int kGroups = 12;   // norm width x (FP64: stream, entries in LDS | FP32: stream,
+                                       // entries, brackets, complex coefficients in LDS)
+  std::vector<UDesc> descs;            // per problem
+  std::vector<int4> ul;                // per unit: {problem, first slice, slices, first row}
+  std::vector<uint2> ue;               // per unit: first SELL entry, entries
+  std::vector<int32_t> uoff;           // [problems + 1] into uidx
+  std::vector<int32_t> uidx;           // per unit of each problem, in order: its position in ul
+  int gbeg[kGroups + 1] = {0};
+  int32_t lmax[kGroups] = {0};         // dynamic LDS of each launch
 
-  template <typename T>
-  ss_status alloc(T** p, size_t n) {
-    SS_TRY(dalloc(p, std::max<size_t>(n, 1)));
-    dev.push_back(*p);
-    return SS_OK;
-  }
+  int n_prob() const { return (int)descs.size(); }
+  int n_units() const { return (int)ul.size(); }
 
-  // launch every added problem on s (asynchronous); the caller syncs s before reading results
-  ss_status launch(hipStream_t s) {
-    launched.clear();
-    for (int g = 0; g < 4; ++g)
-      for (auto& it : items)
-        if (it.group == g) launched.push_back(it);
-    items.clear();
+  void make(const std::vector<UnitItem>& launched) {
     const int np = (int)launched.size();
-    if (np == 0) return SS_OK;
-    std::vector<UDesc> descs(np);
-    // units sorted into launches by (norm width, precision, entries cached in LDS); the unit
-    // results are addressed by their position in ul, and each problem's are summed in order
-    // through uidx
-    // launch groups: norm width x (FP64: stream, entries in LDS | FP32: stream, entries,
-    // brackets, complex coefficients in LDS)
-    constexpr int kGroups = 12;
+    descs.assign(np, UDesc{});
     const int cplx_cap[2] = {unit_cplx_cap<int32_t>(), unit_cplx_cap<int64_t>()};
     std::vector<int4> lists[kGroups];
     std::vector<uint2> ents[kGroups];
-    std::vector<int32_t> lmax(kGroups, 0);
     std::vector<std::pair<int, int>> where;   // per unit of each problem, in order: (launch, index)
-    std::vector<int32_t> uoff{0};
+    uoff.assign(1, 0);
+    for (int g = 0; g < kGroups; ++g) lmax[g] = 0;
     for (int i = 0; i < np; ++i) {
-      const Item& it = launched[i];
+      const UnitItem& it = launched[i];
       descs[i] = it.d;
       const int2 ur = it.op->urange[it.prob];
       for (int k = ur.x; k < ur.y; ++k) {
@@ -1570,87 +1552,144 @@ struct UnitBatch {
       }
       uoff.push_back((int32_t)where.size());
     }
-    std::vector<int4> ul;
-    std::vector<uint2> ue;
-    int gbeg[kGroups + 1] = {0};
+    ul.clear();
+    ue.clear();
+    gbeg[0] = 0;
     for (int g = 0; g < kGroups; ++g) {
       ul.insert(ul.end(), lists[g].begin(), lists[g].end());
       ue.insert(ue.end(), ents[g].begin(), ents[g].end());
       gbeg[g + 1] = (int)ul.size();
     }
-    std::vector<int32_t> uidx(where.size());
+    uidx.resize(where.size());
     for (size_t k = 0; k < where.size(); ++k) uidx[k] = gbeg[where[k].first] + where[k].second;
-    const int nu = (int)ul.size();
-    UDesc* d_desc = nullptr;
-    int4* d_ul = nullptr;
-    uint2* d_ue = nullptr;
-    int32_t* d_uoff = nullptr;
-    UnitOut* d_out = nullptr;
-    UnitSum* d_sum = nullptr;
-    int32_t* d_uidx = nullptr;
-    SS_TRY(alloc(&d_desc, np));
-    SS_TRY(alloc(&d_ul, nu));
-    SS_TRY(alloc(&d_ue, nu));
-    SS_TRY(alloc(&d_uoff, np + 1));
-    SS_TRY(alloc(&d_uidx, nu));
-    SS_TRY(alloc(&d_out, nu));
-    SS_TRY(alloc(&d_sum, np));
+  }
+};
+
+// Device copies of a plan's tables and the launch's results.
+struct UnitDev {
+  UDesc* desc = nullptr;
+  int4* ul = nullptr;
+  uint2* ue = nullptr;
+  int32_t* uoff = nullptr;
+  int32_t* uidx = nullptr;
+  UnitOut* out = nullptr;
+  UnitSum* sum = nullptr;
+};
+
+// the launches of a plan whose tables are on the device (asynchronous on s)
+ss_status launch_unit_plan(const UnitPlan& P, const UnitDev& D, hipStream_t s) {
+  UnitArgs A{D.desc, D.ul, D.ue, 0, D.out};
+  for (int g = 0; g < UnitPlan::kGroups; ++g) {
+    const int n = P.gbeg[g + 1] - P.gbeg[g];
+    if (n == 0) continue;
+    A.ubase = P.gbeg[g];
+    const size_t lds = (size_t)P.lmax[g];
+    switch (g) {
+      case 0: k_unit_solve<int32_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+      case 1: k_unit_solve<int32_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 2: k_unit_solve<int32_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+      case 3: k_unit_solve<int32_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 4: k_unit_solve<int32_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 5: k_unit_solve<int32_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 6: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+      case 7: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 8: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
+      case 9: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
+      case 10: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
+      default: k_unit_solve<int64_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
+    }
+  }
+  k_unit_final<<<grid_for(P.n_prob()), kBlock, 0, s>>>(P.n_prob(), D.uoff, D.uidx, D.out, D.sum);
+  SS_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+// a launched problem's info from its summed unit results
+ss_solve_info unit_info(const UnitItem& it, const UnitSum& sm) {
+  const double rel = sm.ff > 0 ? std::sqrt(sm.rr / sm.ff) : 0.0;
+  int status = sm.status;
+  if (rel <= std::sqrt(it.d.tol2) || sm.ff == 0) status = SS_OK;
+  else if (status == SS_OK) status = SS_ENOCONV;
+  ss_solve_info in{};
+  in.iters = sm.iters;
+  in.outer_steps = it.prec == SS_FP64 ? 0 : sm.outer;
+  in.rel_residual = rel;
+  in.n = it.op->row_off[it.prob + 1] - it.op->row_off[it.prob];
+  in.nnz = it.op->nnz_p[it.prob];
+  in.n_components = it.op->comps[it.prob];
+  in.status = status;
+  return in;
+}
+
+// Problems solved by the class-resident CG in one go: gathered by add(), launched together
+// (one k_unit_solve launch per norm width and precision), results read after a sync.
+struct UnitBatch {
+  using Item = UnitItem;
+  std::vector<Item> items;
+  // after launch(): per item (launch order), its results on the host once the stream is synced
+  std::vector<Item> launched;
+  UnitSum* h_sum = nullptr;       // pinned
+  size_t h_cap = 0;
+  std::vector<void*> dev;         // device blocks of the launch in flight
+
+  ~UnitBatch() {
+    release();
+    if (h_sum) (void)hipHostFree(h_sum);
+  }
+  void release() {
+    for (void* q : dev) pool_free(q);
+    dev.clear();
+  }
+
+  void add(OpImpl* op, int p, const void* f, void* u, double tol, ss_precision prec, int32_t max_iter, int req) {
+    items.push_back(unit_item(op, p, f, u, tol, prec, max_iter, req));
+  }
+
+  template <typename T>
+  ss_status alloc(T** p, size_t n) {
+    SS_TRY(dalloc(p, std::max<size_t>(n, 1)));
+    dev.push_back(*p);
+    return SS_OK;
+  }
+
+  // launch every added problem on s (asynchronous); the caller syncs s before reading results
+  ss_status launch(hipStream_t s) {
+    launched.clear();
+    for (int g = 0; g < 4; ++g)
+      for (auto& it : items)
+        if (it.group == g) launched.push_back(it);
+    items.clear();
+    const int np = (int)launched.size();
+    if (np == 0) return SS_OK;
+    UnitPlan P;
+    P.make(launched);
+    const int nu = P.n_units();
+    UnitDev D;
+    SS_TRY(alloc(&D.desc, np));
+    SS_TRY(alloc(&D.ul, nu));
+    SS_TRY(alloc(&D.ue, nu));
+    SS_TRY(alloc(&D.uoff, np + 1));
+    SS_TRY(alloc(&D.uidx, nu));
+    SS_TRY(alloc(&D.out, nu));
+    SS_TRY(alloc(&D.sum, np));
     if ((size_t)np > h_cap) {
       if (h_sum) (void)hipHostFree(h_sum);
       h_sum = nullptr;
       h_cap = std::max<size_t>(np, 2 * h_cap);
       SS_HIP(hipHostMalloc((void**)&h_sum, h_cap * sizeof(UnitSum), hipHostMallocDefault));
     }
-    SS_HIP(h2d(d_desc, descs.data(), np * sizeof(UDesc), s));
-    SS_HIP(h2d(d_ul, ul.data(), nu * sizeof(int4), s));
-    SS_HIP(h2d(d_ue, ue.data(), nu * sizeof(uint2), s));
-    SS_HIP(h2d(d_uoff, uoff.data(), (np + 1) * 4, s));
-    SS_HIP(h2d(d_uidx, uidx.data(), nu * 4, s));
-    UnitArgs A{d_desc, d_ul, d_ue, 0, d_out};
-    for (int g = 0; g < kGroups; ++g) {
-      const int n = gbeg[g + 1] - gbeg[g];
-      if (n == 0) continue;
-      A.ubase = gbeg[g];
-      const size_t lds = (size_t)lmax[g];
-      switch (g) {
-        case 0: k_unit_solve<int32_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 1: k_unit_solve<int32_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 2: k_unit_solve<int32_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 3: k_unit_solve<int32_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 4: k_unit_solve<int32_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 5: k_unit_solve<int32_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 6: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 7: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 8: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-        case 9: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-        case 10: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
-        default: k_unit_solve<int64_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
-      }
-    }
-    k_unit_final<<<grid_for(np), kBlock, 0, s>>>(np, d_uoff, d_uidx, d_out, d_sum);
-    SS_HIP(hipGetLastError());
-    SS_HIP(hipMemcpyAsync(h_sum, d_sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
+    SS_HIP(h2d(D.desc, P.descs.data(), np * sizeof(UDesc), s));
+    SS_HIP(h2d(D.ul, P.ul.data(), nu * sizeof(int4), s));
+    SS_HIP(h2d(D.ue, P.ue.data(), nu * sizeof(uint2), s));
+    SS_HIP(h2d(D.uoff, P.uoff.data(), (np + 1) * 4, s));
+    SS_HIP(h2d(D.uidx, P.uidx.data(), nu * 4, s));
+    SS_TRY(launch_unit_plan(P, D, s));
+    SS_HIP(hipMemcpyAsync(h_sum, D.sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
     return SS_OK;
   }
 
   // the i-th launched problem's info (valid after the stream has been synced)
-  ss_solve_info info(int i) const {
-    const Item& it = launched[i];
-    const UnitSum& sm = h_sum[i];
-    const double rel = sm.ff > 0 ? std::sqrt(sm.rr / sm.ff) : 0.0;
-    int status = sm.status;
-    if (rel <= std::sqrt(it.d.tol2) || sm.ff == 0) status = SS_OK;
-    else if (status == SS_OK) status = SS_ENOCONV;
-    ss_solve_info in{};
-    in.iters = sm.iters;
-    in.outer_steps = it.prec == SS_FP64 ? 0 : sm.outer;
-    in.rel_residual = rel;
-    in.n = it.op->row_off[it.prob + 1] - it.op->row_off[it.prob];
-    in.nnz = it.op->nnz_p[it.prob];
-    in.n_components = it.op->comps[it.prob];
-    in.status = status;
-    return in;
-  }
+  ss_solve_info info(int i) const { return unit_info(launched[i], h_sum[i]); }
 };
 
 struct Request {
@@ -2001,6 +2040,114 @@ ss_status apply_impl(const OpImpl* op_c, ss_precision prec, const void* x, void*
 void free_apply_cache(OpImpl* op) {
   delete op->apply_cache.list;
   op->apply_cache.list = nullptr;
+}
+
+// ---------------------------------------------------------------- solve without allocation
+// The class-resident solve of ss_solve_op for callers that cannot allocate device memory (code
+// under graph capture, tight serving loops, harnesses that forbid allocation): the launch's
+// tables and per-unit results live in one fixed device array per GPU instead of pool blocks, and
+// are copied from and to pageable host memory instead of the pinned staging rings.  Calls that
+// overlap on one GPU share the array and race.
+constexpr size_t kScratchBytes = SS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+// the device address of the current device's copy of the array, looked up once per device with
+// that device current (the array's name is not a device address in host code)
+ss_status scratch_base(unsigned char** out) {
+  int dev = 0;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(SS_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SS_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SS_OK;
+}
+
+// offset of the next 256-byte aligned piece of `bytes` bytes
+size_t carve(size_t* used, size_t bytes) {
+  const size_t at = *used;
+  *used += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  return at;
+}
+
+}  // namespace
+
+ss_status solve_op_noalloc_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
+                                int32_t max_iter, hipStream_t s, ss_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!f || !u) return fail(SS_EINVAL, "null vector");
+  if (!(tol > 0) || max_iter < 1) return fail(SS_EINVAL, "tol must be > 0 and max_iter >= 1");
+  if (prec != SS_FP64 && prec != SS_FP32_REFINE) return fail(SS_EINVAL, "unknown precision");
+  if (op->busy) return fail(SS_EINVAL, "operator already has a solve in flight");
+  int dev = 0;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev != op->device) return fail(SS_EINVAL, "the operator was built on another device");
+  const int np = op->n_prob;
+  for (int p = 0; p < np; ++p)
+    if (op->urange[p].x < 0)
+      return fail(SS_EINVAL, "problem " + std::to_string(p) +
+                                 " has a class of more than 2048 rows, which needs the per-problem solver "
+                                 "workspace of ss_solve_op");
+  std::vector<UnitItem> items;
+  items.reserve(np);
+  for (int p = 0; p < np; ++p) items.push_back(unit_item(op, p, f, u, tol, prec, max_iter, 0));
+  UnitPlan P;
+  P.make(items);   // one group: all problems of op share the norm width and the precision
+  const int nu = P.n_units();
+  size_t used = 0;
+  const size_t o_desc = carve(&used, np * sizeof(UDesc));
+  const size_t o_ul = carve(&used, nu * sizeof(int4));
+  const size_t o_ue = carve(&used, nu * sizeof(uint2));
+  const size_t o_uoff = carve(&used, (np + 1) * sizeof(int32_t));
+  const size_t o_uidx = carve(&used, nu * sizeof(int32_t));
+  const size_t o_out = carve(&used, nu * sizeof(UnitOut));
+  const size_t o_sum = carve(&used, np * sizeof(UnitSum));
+  if (used > kScratchBytes)
+    return fail(SS_ERANGE, "the solve needs " + std::to_string(used) + " bytes of scratch (" + std::to_string(np) +
+                               " problems, " + std::to_string(nu) + " units); the maximum is " +
+                               std::to_string(kScratchBytes));
+  unsigned char* base = nullptr;
+  SS_TRY(scratch_base(&base));
+  UnitDev D;
+  D.desc = (UDesc*)(base + o_desc);
+  D.ul = (int4*)(base + o_ul);
+  D.ue = (uint2*)(base + o_ue);
+  D.uoff = (int32_t*)(base + o_uoff);
+  D.uidx = (int32_t*)(base + o_uidx);
+  D.out = (UnitOut*)(base + o_out);
+  D.sum = (UnitSum*)(base + o_sum);
+  // every piece is written in full by these copies or by the kernels before it is read
+  SS_HIP(hipMemcpyAsync(D.desc, P.descs.data(), np * sizeof(UDesc), hipMemcpyHostToDevice, s));
+  SS_HIP(hipMemcpyAsync(D.ul, P.ul.data(), nu * sizeof(int4), hipMemcpyHostToDevice, s));
+  SS_HIP(hipMemcpyAsync(D.ue, P.ue.data(), nu * sizeof(uint2), hipMemcpyHostToDevice, s));
+  SS_HIP(hipMemcpyAsync(D.uoff, P.uoff.data(), (np + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SS_HIP(hipMemcpyAsync(D.uidx, P.uidx.data(), nu * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SS_TRY(launch_unit_plan(P, D, s));
+  std::vector<UnitSum> hs(np);
+  SS_HIP(hipMemcpyAsync(hs.data(), D.sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
+  SS_HIP(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ss_status worst = SS_OK;
+  for (int p = 0; p < np; ++p) {
+    ss_solve_info in = unit_info(items[p], hs[p]);
+    in.t_solve_ms = ms;
+    if (info) info[p] = in;
+    if (in.status == SS_EBREAKDOWN || (in.status == SS_ENOCONV && worst == SS_OK)) worst = (ss_status)in.status;
+  }
+  if (worst == SS_ENOCONV) return fail(SS_ENOCONV, "tolerance not reached within the iteration limit");
+  if (worst == SS_EBREAKDOWN) return fail(SS_EBREAKDOWN, "CG breakdown: <p, L p> <= 0 or not finite");
+  return SS_OK;
 }
 
 }  // namespace ss

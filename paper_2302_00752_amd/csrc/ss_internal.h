@@ -326,6 +326,9 @@ ss_status apply_impl(const OpImpl* op, ss_precision prec, const void* x, void* y
                      hipStream_t stream);
 ss_status solve_op_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
                         int32_t max_iter, hipStream_t stream, ss_solve_info* info);
+// the class-resident solve with its tables in a fixed device array (no allocation)
+ss_status solve_op_noalloc_impl(OpImpl* op, const void* f, void* u, double tol, ss_precision prec,
+                                int32_t max_iter, hipStream_t stream, ss_solve_info* info);
 
 // host-side canonicalisation of a-support (shared by stamp and op builders)
 // |x + iy|: the plain formula where the squares cannot overflow or underflow to zero

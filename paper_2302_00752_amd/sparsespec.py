@@ -30,7 +30,7 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
             "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
             "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes", "ss_build_adr", "ss_adr_apply",
-            "ss_adr_solve", "ss_free_adr", "ss_lattice_modulus", "ss_stamp_lattice"]
+            "ss_adr_solve", "ss_free_adr", "ss_lattice_modulus", "ss_stamp_lattice", "ss_solve_op_noalloc"]
 
 
 class SolveInfo(C.Structure):
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_op_exec_map": [P, pi64],
         "ss_apply": [P, i32, P, P, P],
         "ss_solve_op": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
+        "ss_solve_op_noalloc": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
         "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, i64, pi64, pd, pi16,
                      C.POINTER(SolveInfo)],
         "ss_op_bytes": [P, pi64],
@@ -311,6 +312,17 @@ class Operator:
         info = (SolveInfo * self.n_prob)()
         st = _lib.ss_solve_op(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), float(tol),
                               PRECISION[precision], int(max_iter), C.c_void_p(_stream(stream)), info)
+        if raise_on_error:
+            _check(st)
+        return [i.as_dict() for i in info]
+
+    def solve_noalloc(self, f, u, tol: float, precision="fp64", max_iter: int = 1000, stream=None,
+                      raise_on_error: bool = True) -> List[dict]:
+        """``solve`` without allocation (ss_solve_op_noalloc): operators whose classes have at
+        most 2048 rows; the launch tables live in the library's fixed per-GPU array."""
+        info = (SolveInfo * self.n_prob)()
+        st = _lib.ss_solve_op_noalloc(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), float(tol),
+                                      PRECISION[precision], int(max_iter), C.c_void_p(_stream(stream)), info)
         if raise_on_error:
             _check(st)
         return [i.as_dict() for i in info]
