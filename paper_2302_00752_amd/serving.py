@@ -35,6 +35,9 @@ class Finished:
     info: dict
     result: object = None
     prob: int = 0           # problem of the unit's handle that answered this request (grouped builds)
+    admit_tick: int = 0     # ticks run before the request's unit was admitted
+    done_tick: int = 0      # ticks run when it finished
+    offered: float = 0.0    # when its built unit became ready for admission
 
     @property
     def latency(self) -> float:
@@ -52,6 +55,8 @@ class _Unit:
     per_problem: bool
     admitted: float = 0.0
     left: int = 0
+    offered: float = 0.0
+    admit_tick: int = 0
 
 
 class Scheduler:
@@ -75,13 +80,17 @@ class Scheduler:
         self.finished: List[Finished] = []
         self.retired: List[object] = []
         self.max_active = 0
+        self.ticks = 0              # engine steps run so far
+        self.refusals = 0           # admission attempts the engine refused (budget or slots)
+        self.joined_running = 0     # units admitted while a unit admitted at an earlier tick was active
 
     def offer(self, rid: int, arrival: float, handle, n_prob: int = 1):
-        self.ready.append(_Unit(rid, handle, [[rid, arrival, n_prob]], n_prob, False))
+        self.ready.append(_Unit(rid, handle, [[rid, arrival, n_prob]], n_prob, False, offered=self.clock()))
 
     def offer_group(self, tag: int, handle, reqs):
         """``reqs``: [(rid, arrival)] answered by problems 0, 1, ... of ``handle``."""
-        self.ready.append(_Unit(tag, handle, [[rid, arr, 1] for rid, arr in reqs], len(reqs), True))
+        self.ready.append(_Unit(tag, handle, [[rid, arr, 1] for rid, arr in reqs], len(reqs), True,
+                                offered=self.clock()))
 
     def admit(self) -> int:
         """Admit ready units in arrival order until the engine refuses one."""
@@ -89,9 +98,13 @@ class Scheduler:
         while self.ready:
             u = self.ready[0]
             if not self.engine.submit(u.handle, u.tag):
+                self.refusals += 1
                 break
             self.ready.popleft()
+            if any(a.admit_tick < self.ticks for a in self.active.values()):
+                self.joined_running += 1
             u.admitted = self.clock()
+            u.admit_tick = self.ticks
             u.left = u.n_prob
             self.active[u.tag] = u
             n += 1
@@ -103,6 +116,7 @@ class Scheduler:
         if not self.active:
             return 0
         self.engine.step(self.iters)
+        self.ticks += 1
         done = 0
         for tag, prob, info in self.engine.poll():
             u = self.active[tag]
@@ -110,7 +124,8 @@ class Scheduler:
             req[2] -= 1
             if req[2] == 0:
                 self.finished.append(Finished(req[0], req[1], u.admitted, self.clock(), info, u.handle,
-                                              prob if u.per_problem else 0))
+                                              prob if u.per_problem else 0, u.admit_tick, self.ticks,
+                                              u.offered))
                 done += 1
             u.left -= 1
             if u.left == 0:
@@ -175,7 +190,13 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     has arrived together with every later one already arrived (at most ``max_group``) and
     builds each precision's share as one batch, dimensions padded to the largest.  Returns
     a summary dict and the list of ``Finished`` records (with ``result`` = host solution
-    when ``keep_results``)."""
+    when ``keep_results``).
+
+    At most two builder threads are allowed: a run with four stopped making progress on the
+    GPU host and its cause has not been found, so larger counts are refused rather than run."""
+    if not 1 <= build_threads <= 2:
+        raise ValueError("serve() runs one or two builder threads (a four-thread run stopped making "
+                         "progress and its cause is not known)")
     import torch
 
     from . import sparsespec as ss
@@ -246,6 +267,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     group_sizes = []
     ticks = 0
     results = {}
+    peak_bytes = 0
 
     def take(b: Built):
         sched.offer_group(b.tag, b, [(rid, arrivals[rid]) for rid in b.rids])
@@ -262,8 +284,11 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
                 moved += 1
             except queue.Empty:
                 break
-        for _ in range(sched.admit()):
+        n_adm = sched.admit()
+        for _ in range(n_adm):
             in_ready.release()          # bounded: built requests not yet admitted
+        if n_adm:
+            peak_bytes = max(peak_bytes, engine.usage()[1])
         if sched.ready and not sched.active:
             raise RuntimeError("a request does not fit the engine's HBM budget even alone")
         if sched.active:
@@ -291,6 +316,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     for r in recs:
         r.result = results.get(r.rid)
     lat = np.array([r.latency for r in recs]) * 1e3
+    queued = np.array([r.admitted - r.offered for r in recs]) * 1e3     # built, waiting for admission
     first = min(arrivals)
     summary = {
         "requests": len(recs),
@@ -305,6 +331,12 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
         "status_ok": int(sum(1 for r in recs if r.info["status"] == 0)),
         "fp32_refine": int(sum(1 for i in range(len(requests)) if requests[i].precision != "fp64")),
         "hbm_budget_bytes": int(hbm_budget_bytes),
+        "peak_bytes_admitted": int(peak_bytes),
+        "refused_admissions": int(sched.refusals),
+        "joined_running": int(sched.joined_running),
+        "queue_ms_p50": float(np.percentile(queued, 50)),
+        "queue_ms_p99": float(np.percentile(queued, 99)),
+        "build_threads": int(build_threads),
     }
     engine.close()
     recs.sort(key=lambda r: r.rid)

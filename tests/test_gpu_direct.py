@@ -200,6 +200,11 @@ def test_direct_class_near_the_row_limit(ss):
     op.solve(fd, ud, 1e-13, "fp64", 20000)
     torch.cuda.synchronize()
     assert rel(u, ud.cpu().numpy()) <= 1e-9
+    # and against the oracle (its textbook CG above 6000 rows, to 1e-15)
+    afo, aho = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, _ = ost.stamp(p.f_freqs, afo, p.level)
+    assert len(keys) == 7919
+    assert rel(u, og.solve(keys, afo, aho, f)) <= ERR64
 
 
 @pytest.mark.parametrize("case", [(1, None), (2, 2), (2, None), (4, 1)])
@@ -257,3 +262,7 @@ def test_direct_classes_beyond_lds(ss):
     op.solve(fd, ud, 1e-13, "fp64", 5000)
     torch.cuda.synchronize()
     assert rel(u, ud.cpu().numpy()) <= 1e-9
+    # and against the oracle (its textbook CG for classes this size, to 1e-15)
+    afo, aho = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, _ = ost.stamp(p.f_freqs, afo, p.level)
+    assert rel(u, og.solve(keys, afo, aho, f)) <= ERR64

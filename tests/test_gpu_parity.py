@@ -32,6 +32,15 @@ def ss():
 FLAGS = {3: 1}          # the multiscale product coefficient fails the l1 certificate but is positive
 TOL64, TOL32 = 1e-11, 1e-10
 ERR64, ERR32 = 1e-10, 1e-9
+# The stop test bounds the relative residual; the relative error it allows grows with the spread of
+# the operator's spectrum (4 pi^2 |k|^2 a over S^N).  The d = 3 multiscale problem (|k|^2 from 1 to
+# 2.6e6, a from 0.125 to 3.375) needs a residual 10 x smaller than the others to meet the error
+# targets for any right-hand side (a manufactured one weights its high frequencies).
+TOLS = {3: (1e-12, 1e-11)}
+
+
+def tols(config):
+    return TOLS.get(config, (TOL64, TOL32))
 
 
 @functools.lru_cache(maxsize=None)
@@ -190,16 +199,48 @@ def test_solve_matches_oracle(ss, config, precision):
     assert np.all(u[~np.any(oc["keys"] != 0, axis=1)] == 0)       # u_0 = 0
 
 
-@pytest.mark.parametrize("config", [2, 4])
+@pytest.mark.parametrize("config", [1, 2, 3, 4])
 def test_manufactured_solution(ss, config):
     oc = oracle_case(config)
     st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
     u_star = workloads.manufactured_solution(op.n_total, 77 + config, density=0.2)
     u_star[~np.any(oc["keys"] != 0, axis=1)] = 0
     f = oc["M"] @ u_star                    # L_N u* by the (pinned) oracle operator
-    for precision, tol, err in (("fp64", TOL64, ERR64), ("fp32_refine", TOL32, ERR32)):
+    t64, t32 = tols(config)
+    for precision, tol, err in (("fp64", t64, ERR64), ("fp32_refine", t32, ERR32)):
         u, info = gpu_solve(ss, op, f, tol, precision)
         assert rel(u, u_star) <= err, (precision, rel(u, u_star))
+
+
+def test_config1_at_its_stated_settings(ss):
+    # d = 2, level 2: FP64 CG to a relative residual of 1e-12, against the oracle's dense solve
+    # and against a manufactured solution
+    oc = oracle_case(1)
+    st, op = build(ss, [oc["p"]])
+    u, info = gpu_solve(ss, op, oc["f"], 1e-12, "fp64")
+    assert info[0]["status"] == ss.SS_OK and info[0]["rel_residual"] <= 1e-12
+    assert rel(u, oc["u"]) <= 1e-11, rel(u, oc["u"])
+    u_star = workloads.manufactured_solution(op.n_total, 101, density=0.3)
+    u_star[~np.any(oc["keys"] != 0, axis=1)] = 0
+    um, info = gpu_solve(ss, op, oc["M"] @ u_star, 1e-12, "fp64")
+    assert info[0]["rel_residual"] <= 1e-12 and rel(um, u_star) <= 1e-11, rel(um, u_star)
+
+
+# the relative residual the benchmark stops both solvers at (bench.py --tol)
+BENCH_TOL = 1e-10
+
+
+@pytest.mark.parametrize("config", [2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_solve_at_the_benchmark_tolerance(ss, config, precision):
+    # the rates are quoted for solves stopped at BENCH_TOL: the error against the oracle must
+    # meet the target there (1e-10 FP64, 1e-9 FP32 + FP64 refinement), on two instances
+    for inst in (0, 1):
+        oc = oracle_case(config, inst)
+        st, op = build(ss, [oc["p"]], FLAGS.get(config, 0))
+        u, info = gpu_solve(ss, op, oc["f"], BENCH_TOL, precision)
+        assert info[0]["status"] == ss.SS_OK and info[0]["rel_residual"] <= BENCH_TOL
+        assert rel(u, oc["u"]) <= (ERR64 if precision == "fp64" else ERR32), (inst, rel(u, oc["u"]))
 
 
 def test_batch_equals_alone_bitwise(ss):

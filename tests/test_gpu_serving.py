@@ -41,29 +41,79 @@ def solve_alone(ss, p, tol):
     return u.cpu().numpy(), keys, info[0]
 
 
+def oracle_solution(p, dense_limit=500):
+    """The oracle's u for a request (classes above ``dense_limit`` rows by its textbook CG)."""
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    keys, _ = ost.stamp(p.f_freqs, af, p.level)
+    pos = og.slot_index(keys)
+    f = np.zeros(len(keys), dtype=np.complex128)
+    for k, v in zip(p.f_freqs, p.f_hat):
+        f[pos[tuple(int(x) for x in k)]] = v
+    return og.solve(keys, af, ah, f, dense_limit=dense_limit)
+
+
+def check_served(ss, reqs, recs):
+    """Every served result is bitwise its solve alone and within the target of the oracle."""
+    assert sorted(r.rid for r in recs) == list(range(len(reqs)))
+    for r in recs:
+        p = reqs[r.rid]
+        tol = 1e-10 if p.precision == "fp64" else 1e-9
+        assert r.info["status"] == 0 and r.info["rel_residual"] <= tol
+        u, keys, info = solve_alone(ss, p, tol)
+        assert np.array_equal(r.result, u), (r.rid, p.d, p.precision)
+        assert r.info["iters"] == info["iters"]
+        uo = oracle_solution(p)
+        err = np.linalg.norm(r.result - uo) / np.linalg.norm(uo)
+        print(f"request {r.rid}: d={p.d} |S|={len(u)} {p.precision} rel_err={err:.2e}", flush=True)
+        assert err <= (1e-9 if p.precision == "fp32_refine" else 1e-10), (r.rid, err)
+
+
 def test_served_equals_alone_bitwise_and_oracle(ss):
     from paper_2302_00752_amd.serving import serve
     reqs = small_stream(10)
     assert len({r.d for r in reqs}) > 3 and {r.precision for r in reqs} == {"fp64", "fp32_refine"}
     summary, recs = serve(reqs, hbm_budget_bytes=1 << 30, iters_per_tick=3, keep_results=True, realtime=True)
     assert summary["requests"] == len(reqs) and summary["status_ok"] == len(reqs)
-    for r in recs:
-        p = reqs[r.rid]
-        tol = 1e-10 if p.precision == "fp64" else 1e-9
-        u, keys, info = solve_alone(ss, p, tol)
-        assert np.array_equal(r.result, u), (r.rid, p.d, p.precision)
-        assert r.info["iters"] == info["iters"]
-    for r in recs[:3]:
-        p = reqs[r.rid]
-        af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
-        keys, _ = ost.stamp(p.f_freqs, af, p.level)
-        pos = og.slot_index(keys)
-        f = np.zeros(len(keys), dtype=np.complex128)
-        for k, v in zip(p.f_freqs, p.f_hat):
-            f[pos[tuple(int(x) for x in k)]] = v
-        uo = og.solve(keys, af, ah, f)
-        err = np.linalg.norm(r.result - uo) / np.linalg.norm(uo)
-        assert err <= (1e-9 if p.precision == "fp32_refine" else 1e-10), (r.rid, err)
+    check_served(ss, reqs, recs)
+
+
+def bench_law_requests():
+    """Twelve requests of the benchmark's serving stream (its size law: 1e3 - 1e5 keys, d = 2..50,
+    mixed precision): the two largest in d <= 4 (one merged class of 5e4 - 1e5 rows, solved over
+    many ticks), the two largest of the others and eight at size quantiles, arriving 1 ms apart in
+    that order."""
+    stream = workloads.cfg5_stream(1024, rate_per_s=1000.0, instance=0)
+    size = np.array([workloads.generic_stamp_size(len(p.f_freqs), len(p.a_freqs), p.level) for p in stream])
+    dims = np.array([p.d for p in stream])
+    by_size = [int(i) for i in np.argsort(size, kind="stable")]
+    low = [i for i in by_size if dims[i] <= 4][-2:]
+    top = [i for i in by_size if i not in low][-2:]
+    rest = [i for i in by_size if i not in low and i not in top]
+    quant = [rest[int(q * (len(rest) - 1))] for q in np.linspace(0.02, 0.9, 8)]
+    picked = low + top + quant
+    reqs = []
+    for k, i in enumerate(picked):
+        p = stream[i]
+        p.arrival_s = 0.001 * k
+        reqs.append(p)
+    return reqs
+
+
+def test_served_benchmark_law_requests(ss):
+    # requests of the benchmark's own size law, every result against the oracle; requests that
+    # arrive while the low-dimensional ones are mid-solve join the running batch
+    from paper_2302_00752_amd.serving import serve
+    reqs = bench_law_requests()
+    assert max(workloads.generic_stamp_size(len(p.f_freqs), len(p.a_freqs), p.level) for p in reqs) >= 99000
+    assert {r.precision for r in reqs} == {"fp64", "fp32_refine"}
+    summary, recs = serve(reqs, hbm_budget_bytes=4 << 30, iters_per_tick=1, keep_results=True, realtime=True)
+    print(summary, flush=True)
+    assert summary["requests"] == len(reqs) and summary["status_ok"] == len(reqs)
+    assert summary["max_active"] >= 2
+    # a request admitted after another had started and before that one finished
+    assert summary["joined_running"] >= 1
+    assert any(a.admit_tick < b.admit_tick < a.done_tick for a in recs for b in recs)
+    check_served(ss, reqs, recs)
 
 
 def test_engine_mixes_unit_and_iterative_problems(ss):

@@ -24,6 +24,18 @@ from paper_2302_00752_amd import workloads
 from tests import _phys
 
 
+def lemma_stamp_decay_rate(af, ah):
+    """A / (1 - 2A) of Lemma StampDecay for a coefficient with one cosine mode (|a - a_0|_inf = the
+    sum of |a_w| over w != 0, attained; a_min = a_0 minus it); requires 3 |a - a_0|_inf < a_min."""
+    zero = ~np.any(np.asarray(af) != 0, axis=1)
+    a0 = float(np.real(np.asarray(ah)[zero][0]))
+    dev = float(np.abs(np.asarray(ah)[~zero]).sum())
+    amin = a0 - dev
+    assert 3 * dev < amin
+    A = dev / amin
+    return A / (1 - 2 * A)
+
+
 def _setup(p):
     af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
     keys, lev = ost.stamp(p.f_freqs, af, p.level)
@@ -108,7 +120,11 @@ def test_lowsparsity_proxy_decays_geometrically_and_lives_on_the_new_level(d):
         assert e == pytest.approx(np.linalg.norm(Lu_top) / np.linalg.norm(p.f_hat), rel=1e-9)
         errs.append(e)
     ratios = np.array(errs[1:]) / np.array(errs[:-1])
-    assert np.all(ratios < 0.5)
+    # Lemma StampDecay: with A = |a - a_0|_inf / a_min and 3 |a - a_0|_inf < a_min, the truncation
+    # error bound shrinks by A / (1 - 2A) per level; for one cosine mode |a - a_0|_inf is the sum of
+    # |a_w| over w != 0 and a_min = a_0 minus that sum
+    ratio = lemma_stamp_decay_rate(af, ah)
+    assert 0 < ratio < 1 and np.all(ratios <= ratio), (ratios, ratio)
 
 
 def test_highsparsity_workload_and_its_proxy_decay():

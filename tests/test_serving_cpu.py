@@ -107,3 +107,35 @@ def test_refused_request_stays_queued():
     for _ in range(3):
         s.tick()
     assert s.admit() == 1 and not s.ready
+
+
+def test_refusals_and_joins_are_counted():
+    eng = FakeEngine(budget=50)
+    s = Scheduler(eng, clock=Clock())
+    s.offer(0, 0.0, {"bytes": 30, "steps": 3, "n_prob": 1})
+    assert s.admit() == 1 and s.refusals == 0 and s.joined_running == 0
+    s.tick()                                                   # 0 is now mid-solve
+    s.offer(1, 1.0, {"bytes": 30, "steps": 1, "n_prob": 1})   # does not fit beside 0
+    s.offer(2, 1.0, {"bytes": 10, "steps": 1, "n_prob": 1})
+    assert s.admit() == 0 and s.refusals == 1                 # head of the queue refused, order kept
+    s.tick()
+    s.tick()                                                  # 0 retires
+    assert s.admit() == 2 and s.joined_running == 0           # nothing was running any more
+    s.offer(3, 2.0, {"bytes": 5, "steps": 3, "n_prob": 1})
+    s.admit()
+    s.tick()
+    s.offer(4, 3.0, {"bytes": 5, "steps": 1, "n_prob": 1})
+    s.admit()
+    assert s.joined_running == 1                              # 4 joined 3, admitted a tick earlier
+    while not s.idle():
+        s.admit()
+        s.tick()
+    fin = {r.rid: r for r in s.finished}
+    assert sorted(fin) == [0, 1, 2, 3, 4]
+    assert fin[4].admit_tick > fin[3].admit_tick and fin[4].admit_tick < fin[3].done_tick
+
+
+def test_serve_refuses_more_than_two_builders():
+    from paper_2302_00752_amd.serving import serve
+    with pytest.raises(ValueError):
+        serve([], build_threads=4)
