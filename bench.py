@@ -37,6 +37,7 @@ def log(*a):
 
 
 CONFIG_FLAGS = {3: 1}   # the multiscale product coefficient fails the l1 certificate but is positive
+ORACLE_SAMPLES = 2      # problems per configuration whose GPU solutions are checked against the oracle
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_mv_fp64_cfg2_b512_traffic.md")
@@ -64,9 +65,27 @@ def measured_traffic(batch: int):
 
 
 def matvec_bytes(nnz: int, n: int, complex_bytes: int) -> int:
-    """Algorithmic bytes of one y = L x: packed entries, slice offsets, |k|^2,
-    x read once, y written once (gathers assumed cache-resident)."""
-    return 4 * nnz + 4 * (n + 1) + 4 * n + 2 * complex_bytes * n
+    """Algorithmic bytes of one y = L x: the packed 4-byte entries, one 4-byte slice offset per
+    64 rows, |k|^2 (4 bytes) of every row once, x read once, y written once (gathers assumed
+    cache-resident)."""
+    return 4 * nnz + 4 * (n // 64 + 1) + 4 * n + 2 * complex_bytes * n
+
+
+def cpu_description():
+    """(logical CPUs this process may run on, the CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return n, model
 
 
 def main():
@@ -77,9 +96,12 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--matvec-reps", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=2, help="problems the CPU oracle solves (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="problems the C sparse PCG solves on the host (0 = skip the CPU leg)")
     ap.add_argument("--serve", type=int, default=1024, help="requests in the serving stream (0 = skip)")
-    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0,
+                    help="engine HBM budget (0: --serve-budget-units x the largest unit of the warm-up)")
+    ap.add_argument("--serve-budget-units", type=float, default=1.0)
     ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
@@ -184,8 +206,10 @@ def main():
     log(f"step {ms_step:.1f} ms (stamp {1e3*t_stamp:.1f}, op {1e3*t_op:.1f}); solve fp32+refine "
         f"{solve_ms['fp32_refine']:.1f} ms, fp64 {solve_ms['fp64']:.1f} ms; iters {iters}")
 
-    # --- solve-only FP64 vs FP32 + refinement per configuration (batched, operator prebuilt)
+    # --- solve-only FP64 vs FP32 + refinement per configuration (batched, operator prebuilt), and
+    # the whole path of the same batch
     per_config = {}
+    samples = {}
     if args.configs:
         for c in [int(x) for x in args.configs.split(",")]:
             bc = B if c == 2 else args.config_batch
@@ -211,9 +235,29 @@ def main():
                 row[prec] = {"tol": tol, "ms": ms, "solves_per_s": bc / (ms / 1e3),
                              "iters": float(np.mean([i["iters"] for i in inf])),
                              "max_rel_residual": float(max(i["rel_residual"] for i in inf))}
+                # the sampled problems' solutions, checked against the oracle in the CPU leg
+                uh = u.cpu().numpy()
+                samples.setdefault(c, {"problems": ps[:ORACLE_SAMPLES], "u": {}})
+                samples[c]["u"][prec] = [uh[stc.offsets[i]:stc.offsets[i + 1]].copy() for i in range(ORACLE_SAMPLES)]
+            # the whole path (stamp, operator, forcing, solve) of the same batch from host data
+            for prec in ("fp64", "fp32_refine"):
+                ss.solve_batch(bb, args.tol, prec, 1000, CONFIG_FLAGS.get(c, 0), parts=args.parts)[0].close()
+                reps = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    res_c, inf = ss.solve_batch(bb, args.tol, prec, 1000, CONFIG_FLAGS.get(c, 0), parts=args.parts)
+                    torch.cuda.synchronize()
+                    reps.append(time.perf_counter() - t)
+                    res_c.close()
+                ms = 1e3 * float(np.median(reps))
+                row[prec]["whole_path_ms"] = ms
+                row[prec]["whole_path_solves_per_s"] = bc / (ms / 1e3)
             per_config[f"cfg{c}"] = row
-            log(f"cfg{c}: B={bc} fp64 {row['fp64']['solves_per_s']:.0f}/s ({row['fp64']['iters']:.1f} it), "
-                f"fp32+refine {row['fp32_refine']['solves_per_s']:.0f}/s ({row['fp32_refine']['iters']:.1f} it)")
+            log(f"cfg{c}: B={bc} solve-only fp64 {row['fp64']['solves_per_s']:.0f}/s ({row['fp64']['iters']:.1f} it), "
+                f"fp32+refine {row['fp32_refine']['solves_per_s']:.0f}/s ({row['fp32_refine']['iters']:.1f} it); "
+                f"whole path fp64 {row['fp64']['whole_path_solves_per_s']:.0f}/s, "
+                f"fp32+refine {row['fp32_refine']['whole_path_solves_per_s']:.0f}/s")
             if c != 2:
                 del opc, stc
 
@@ -260,39 +304,76 @@ def main():
     log(f"matvec fp64 {mv['fp64']['ms']*1e3:.1f} us {mv['fp64']['gbs']:.0f} GB/s; "
         f"fp32 {mv['fp32_refine']['ms']*1e3:.1f} us {mv['fp32_refine']['gbs']:.0f} GB/s; copy {copy_gbs:.0f} GB/s, read {read_gbs:.0f} GB/s")
 
-    # --- CPU oracle on a bounded sample; its solutions check the GPU error
+    # --- CPU leg: the oracle on bounded samples.  (i) the sparse FP64 Jacobi PCG in C (stamp, index
+    # and solve phases) on one thread and on every host thread; (ii) the dense per-class route of the
+    # paper (brute-force stamp, dict neighbour map, dense LU per class).  The dense route's solutions
+    # also check the GPU's sampled solutions of every configuration.
     cpu = None
     err = {}
     if args.cpu_sample > 0:
+        from oracle import cpcg
         from oracle import galerkin as og
         from oracle import stamp as ost
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count() or 1
-        keys_all, _ = st.keys()
-        t = time.perf_counter()
-        errs = {"fp32_refine": [], "fp64": []}
-        for i in range(args.cpu_sample):
-            p = probs[i]
+        n_cpus, cpu_model = cpu_description()
+        threads = min(n_cpus, int(os.environ.get("OMP_NUM_THREADS", n_cpus)))
+        c_sample = probs[:args.cpu_sample]
+        legs = {}
+        for th in (1, threads):
+            t = time.perf_counter()
+            st_c, inf_c, used, _ = cpcg.solve_batch(c_sample, args.tol, th, matvec_reps=5)
+            wall = time.perf_counter() - t
+            assert st_c == 0, st_c
+            nb = len(c_sample)
+            mv_ms = float(np.mean([i["matvec_ms"] for i in inf_c]))
+            legs[th] = {"solves_per_s": nb / wall, "threads": used, "wall_s": wall,
+                        "phase_ms_per_problem": {k: float(np.mean([i[k + "_ms"] for i in inf_c]))
+                                                 for k in ("stamp", "index", "solve")},
+                        "iters": float(np.mean([i["iters"] for i in inf_c])),
+                        "max_rel_residual": float(max(i["rel_residual"] for i in inf_c)),
+                        "matvec_us": 1e3 * mv_ms,
+                        "matvec_GB/s_per_thread": matvec_bytes(inf_c[0]["nnz"], inf_c[0]["n"], 16) / (mv_ms / 1e3) / 1e9}
+            log(f"cpu sparse PCG (C) on {used} thread(s): {nb / wall:.1f} solves/s; per problem "
+                f"{legs[th]['phase_ms_per_problem']}")
+        # the C solver's error against the dense oracle, on the first sampled problems
+        _, _, _, u_c = cpcg.solve_batch(c_sample[:ORACLE_SAMPLES], args.tol, 1, want_u=True)
+
+        def oracle_u(p):
             af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
             keys, _ = ost.stamp(p.f_freqs, af, p.level)
             pos = og.slot_index(keys)
             fo = np.zeros(len(keys), dtype=np.complex128)
             for k, v in zip(p.f_freqs, p.f_hat):
                 fo[pos[tuple(int(x) for x in k)]] = v
-            uo = og.solve(keys, af, ah, fo)
-            sl = slice(st.offsets[i], st.offsets[i + 1])
-            assert np.array_equal(keys_all[sl].astype(np.int64), keys)
-            for prec in errs:
-                errs[prec].append(float(np.linalg.norm(sols[prec][sl] - uo) / np.linalg.norm(uo)))
-        t_cpu = time.perf_counter() - t
-        cpu = {"value": args.cpu_sample / t_cpu, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"{args.cpu_sample} d=10 level-3 problems (|S^N|=31220): brute-force stamp, "
-                         f"dict neighbour map, dense per-class LU solve, FP64"}
-        err = {k: max(v) for k, v in errs.items()}
-        log(f"cpu oracle {cpu['value']:.3f} solves/s on {cores} threads; max rel err {err}")
+            return og.solve(keys, af, ah, fo)
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+        t = time.perf_counter()
+        u_cfg2 = [oracle_u(p) for p in probs[:ORACLE_SAMPLES]]
+        t_dense = time.perf_counter() - t
+        c_err = max(rel(u_c[i], u_cfg2[i]) for i in range(ORACLE_SAMPLES))
+        # every configuration's sampled GPU solutions against the oracle, per precision
+        for c, smp in samples.items():
+            uo = u_cfg2 if c == 2 else [oracle_u(p) for p in smp["problems"]]
+            per_config[f"cfg{c}"]["rel_l2_err_vs_oracle"] = {
+                prec: max(rel(smp["u"][prec][i], uo[i]) for i in range(ORACLE_SAMPLES)) for prec in smp["u"]}
+        for prec in ("fp32_refine", "fp64"):
+            err[prec] = max(rel(sols[prec][st.offsets[i]:st.offsets[i + 1]], u_cfg2[i]) for i in range(ORACLE_SAMPLES))
+        all_c = legs[threads]
+        cpu = {"value": all_c["solves_per_s"], "unit": "solves/s", "cores": int(all_c["threads"]), "kind": "oracle",
+               "sample": f"{len(c_sample)} d=10 level-3 problems (|S^N|=31220) from host data: stamp, neighbour "
+                         f"index and FP64 Jacobi PCG to rel. residual {args.tol:g}, sparse C solver with OpenMP "
+                         f"over problems",
+               "host": {"logical_cpus": n_cpus, "model": cpu_model},
+               "one_thread": legs[1], "all_threads": all_c,
+               "rel_l2_err_vs_dense_oracle": c_err,
+               "dense_oracle": {"solves_per_s": ORACLE_SAMPLES / t_dense, "threads": 1,
+                                "sample": f"{ORACLE_SAMPLES} of the same problems: brute-force stamp (Python sets), "
+                                          f"dict neighbour map (Python), dense LU per class (LAPACK)"}}
+        log(f"cpu: C PCG {cpu['value']:.1f} solves/s on {cpu['cores']} threads ({cpu_model}, {n_cpus} cpus), "
+            f"1 thread {legs[1]['solves_per_s']:.1f}/s, err vs dense {c_err:.1e}; dense oracle "
+            f"{ORACLE_SAMPLES / t_dense:.2f} solves/s; GPU err {err}")
 
     # --- exact proxy error (Sec. 10.1) of level-N solutions, from the level-(N+1) build
     proxy = None
@@ -548,19 +629,65 @@ def main():
     serving = None
     if args.serve > 0:
         from paper_2302_00752_amd import serving as srv
-        budget = int(args.serve_budget_gib * (1 << 30))
+        # saturated rate with an unlimited budget; its largest unit sizes the gating budget
         warm = workloads.cfg5_stream(min(128, args.serve), rate_per_s=1e9, instance=1)
-        sat, _ = srv.serve(warm, hbm_budget_bytes=budget, realtime=False)
+        sat, _ = srv.serve(warm, hbm_budget_bytes=0, realtime=False)
+        budget = int(args.serve_budget_gib * (1 << 30)) if args.serve_budget_gib > 0 else \
+            int(args.serve_budget_units * sat["max_unit_bytes"])
         rate = 0.8 * sat["solves_per_s"]
         stream_reqs = workloads.cfg5_stream(args.serve, rate_per_s=rate, instance=0)
         summ, recs = srv.serve(stream_reqs, hbm_budget_bytes=budget, realtime=True)
         sizes = [r.info["n"] for r in recs]
+        # single-instance latency: requests of the same stream arriving 25 ms apart, served alone
+        alone = workloads.cfg5_stream(32, rate_per_s=1000.0, instance=0)
+        for i, r in enumerate(alone):
+            r.arrival_s = 0.025 * i
+        s1, _ = srv.serve(alone, hbm_budget_bytes=0, realtime=True)
         serving = dict(summ, arrival_rate_per_s=rate, saturated_solves_per_s=sat["solves_per_s"],
+                       budget_rule=(f"{args.serve_budget_gib} GiB" if args.serve_budget_gib > 0 else
+                                    f"{args.serve_budget_units} x the largest unit of the saturated warm-up "
+                                    f"({sat['max_unit_bytes']} B)"),
+                       single_instance={"requests": s1["requests"], "p50_ms": s1["p50_ms"], "p99_ms": s1["p99_ms"],
+                                        "max_active": s1["max_active"]},
                        stamp_sizes={"min": int(min(sizes)), "median": int(np.median(sizes)), "max": int(max(sizes))},
                        dims={"min": int(min(r.d for r in stream_reqs)), "max": int(max(r.d for r in stream_reqs))})
         log(f"serving: {summ['requests']} req at {rate:.0f}/s -> {summ['solves_per_s']:.0f} solves/s, "
             f"p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms, max active {summ['max_active']}, "
-            f"ok {summ['status_ok']}")
+            f"budget {budget / 2**20:.0f} MiB (refused {summ['refused_admissions']}, queue p99 "
+            f"{summ['queue_ms_p99']:.2f} ms, peak {summ['peak_bytes_admitted'] / 2**20:.0f} MiB), "
+            f"ok {summ['status_ok']}; alone p50 {s1['p50_ms']:.2f} ms")
+
+    # --- single-instance latency of the d = 10 problem: whole path from host data and solve only
+    single = {}
+    lat_w, lat_s = {"fp64": [], "fp32_refine": []}, {"fp64": [], "fp32_refine": []}
+    for i in range(20):
+        p1 = [probs[i]]
+        for prec in ("fp64", "fp32_refine"):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r1, _ = ss.solve_batch(p1, args.tol, prec, 1000, 0, parts=1)
+            torch.cuda.synchronize()
+            lat_w[prec].append(1e3 * (time.perf_counter() - t))
+            r1.close()
+    st1 = ss.Stamp.build(probs[:1])
+    op1 = ss.Operator.build(st1, probs[:1])
+    f1 = st1.forcing_vector(probs[:1], dev)
+    u1 = torch.zeros_like(f1)
+    for prec in ("fp64", "fp32_refine"):
+        for i in range(21):
+            u1.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            op1.solve(f1, u1, args.tol, prec, 1000)
+            torch.cuda.synchronize()
+            if i:
+                lat_s[prec].append(1e3 * (time.perf_counter() - t))
+        single[prec] = {"whole_path_ms_p50": float(np.median(lat_w[prec])),
+                        "whole_path_ms_p99": float(np.percentile(lat_w[prec], 99)),
+                        "solve_only_ms_p50": float(np.median(lat_s[prec]))}
+    op1.close()
+    st1.close()
+    log(f"single instance (d=10): {single}")
 
     value = B / (ms_step / 1e3)
     traffic = measured_traffic(B)
@@ -596,6 +723,7 @@ def main():
                      "bytes_per_launch": mv["fp64"]["bytes"], "traffic": traffic,
                      "measured_copy_GB/s": copy_gbs, "measured_read_GB/s": read_gbs, "frac_of_copy": mv["fp64"]["gbs"] / copy_gbs},
         "serving": serving,
+        "single_instance_cfg2": single,
         "proxy_error": proxy,
         "lattice": lattice,
         "direct_solve": direct,

@@ -330,8 +330,9 @@ ss_status ss_op_bytes(const ss_op* op, int64_t* bytes);
  * is bitwise the same alone and in any mix.
  *
  * ss_engine_create: hbm_budget_bytes (0 = unlimited) bounds the device bytes
- *   of admitted operators plus their solver workspaces; max_slots (0 =
- *   unlimited) bounds the admitted requests.  stream: the engine's stream.
+ *   of admitted operators plus their solver workspaces (a request larger than
+ *   the whole budget is admitted only when the engine holds no other); max_slots
+ *   (0 = unlimited) bounds the admitted requests.  stream: the engine's stream.
  * ss_engine_submit: admits every problem of op as one request.  f_dev, u_dev:
  *   device complex128 vectors of op's n_total entries in canonical order
  *   (u_dev: initial guess in, solution out); op, f_dev and u_dev must stay
@@ -388,6 +389,9 @@ void ss_free_batch(ss_batch* b);
  * ss_solve -- Alg. 1 steps 3-5 for one problem from host data.
  *   a: n_a frequencies/coefficients (exact zeros dropped, -w completed);
  *   f: n_f frequencies/coefficients (host);
+ *   tol, prec, max_iter, flags: as for ss_solve_op and ss_build_op.
+ *   x0 (host, nullable): initial guess, |S^N| complex128 in canonical order (query the size
+ *   first); NULL starts from 0.
  *   u_cap: complex entries available in u_hat_out.  u_hat_out == NULL is a
  *   size query: *n_out = |S^N| and SS_OK.  u_cap < |S^N| -> SS_EINVAL.
  *   keys_out (nullable): [|S^N| x d] canonical keys.
@@ -395,8 +399,8 @@ void ss_free_batch(ss_batch* b);
 ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double* a_hat,
                    int32_t n_f, const int16_t* f_freqs, const double* f_hat, int32_t level,
                    double tol, ss_precision prec, int32_t max_iter, uint32_t flags,
-                   int64_t u_cap, int64_t* n_out, double* u_hat_out, int16_t* keys_out,
-                   ss_solve_info* info);
+                   const double* x0, int64_t u_cap, int64_t* n_out, double* u_hat_out,
+                   int16_t* keys_out, ss_solve_info* info);
 
 const char* ss_last_error(void);
 const char* ss_version(void);

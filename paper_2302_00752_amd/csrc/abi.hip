@@ -408,7 +408,7 @@ void ss_free_batch(ss_batch* b) {
 
 ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double* a_hat, int32_t n_f,
                    const int16_t* f_freqs, const double* f_hat, int32_t level, double tol, ss_precision prec,
-                   int32_t max_iter, uint32_t flags, int64_t u_cap, int64_t* n_out, double* u_hat_out,
+                   int32_t max_iter, uint32_t flags, const double* x0, int64_t u_cap, int64_t* n_out, double* u_hat_out,
                    int16_t* keys_out, ss_solve_info* info) {
   return guarded([&]() -> ss_status {
     if (d < 1 || d > 1024) return fail(SS_EINVAL, "d must be in [1, 1024]");
@@ -464,7 +464,8 @@ ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double*
     SS_HIP(pool_alloc((void**)&fd.p, n * 16));
     SS_HIP(pool_alloc((void**)&ud.p, n * 16));
     SS_HIP(hipMemcpy(fd.p, fdense.data(), n * 16, hipMemcpyHostToDevice));
-    SS_HIP(hipMemset(ud.p, 0, n * 16));
+    if (x0) SS_HIP(hipMemcpy(ud.p, x0, n * 16, hipMemcpyHostToDevice));   // warm start
+    else SS_HIP(hipMemset(ud.p, 0, n * 16));
     const double t_build = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     ss_solve_info inf{};
     const ss_status rs = solve_op_impl(op->impl, fd.p, ud.p, tol, prec, max_iter, nullptr, &inf);

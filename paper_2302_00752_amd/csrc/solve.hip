@@ -1750,7 +1750,10 @@ struct EngineImpl {
         op_device_bytes(op) + (any_engine ? (int64_t)std::max(op->ws.bytes, workspace_bytes(op)) : 0);
     int active = 0;
     for (auto& r : reqs) active += r.op != nullptr;
-    if (budget > 0 && bytes_in_use + bytes > budget) return fail(SS_ENOMEM, "HBM budget of the engine exceeded");
+    // a request larger than the whole budget could never be admitted beside others: it is admitted
+    // when the engine holds nothing else
+    if (budget > 0 && bytes_in_use + bytes > budget && active > 0)
+      return fail(SS_ENOMEM, "HBM budget of the engine exceeded");
     if (max_slots > 0 && active >= max_slots) return fail(SS_ENOMEM, "no free engine slot");
     WS w{};
     if (any_engine) SS_TRY(workspace(op, &w));

@@ -268,6 +268,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     ticks = 0
     results = {}
     peak_bytes = 0
+    max_unit = 0                        # largest footprint of a unit admitted on its own
 
     def take(b: Built):
         sched.offer_group(b.tag, b, [(rid, arrivals[rid]) for rid in b.rids])
@@ -284,13 +285,17 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
                 moved += 1
             except queue.Empty:
                 break
+        before_bytes = engine.usage()[1] if sched.ready else 0
         n_adm = sched.admit()
         for _ in range(n_adm):
             in_ready.release()          # bounded: built requests not yet admitted
         if n_adm:
-            peak_bytes = max(peak_bytes, engine.usage()[1])
+            used = engine.usage()[1]
+            peak_bytes = max(peak_bytes, used)
+            if n_adm == 1:
+                max_unit = max(max_unit, used - before_bytes)
         if sched.ready and not sched.active:
-            raise RuntimeError("a request does not fit the engine's HBM budget even alone")
+            raise RuntimeError("the engine refused a request while it held no other")
         if sched.active:
             before = len(sched.finished)
             sched.tick()
@@ -332,6 +337,7 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
         "fp32_refine": int(sum(1 for i in range(len(requests)) if requests[i].precision != "fp64")),
         "hbm_budget_bytes": int(hbm_budget_bytes),
         "peak_bytes_admitted": int(peak_bytes),
+        "max_unit_bytes": int(max_unit),
         "refused_admissions": int(sched.refusals),
         "joined_running": int(sched.joined_running),
         "queue_ms_p50": float(np.percentile(queued, 50)),

@@ -81,7 +81,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_apply": [P, i32, P, P, P],
         "ss_solve_op": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
         "ss_solve_op_noalloc": [P, P, P, dbl, i32, i32, P, C.POINTER(SolveInfo)],
-        "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, i64, pi64, pd, pi16,
+        "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, pd, i64, pi64, pd, pi16,
                      C.POINTER(SolveInfo)],
         "ss_op_bytes": [P, pi64],
         "ss_engine_create": [i64, i32, P, C.POINTER(P)],
@@ -477,8 +477,9 @@ def proxy_error(stamp_next: Stamp, op_next: Operator, u, problems, stream=None) 
 
 
 def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64", max_iter=2000, flags=0,
-          want_keys=True):
-    """One-shot solve from host data; returns ``(u_hat, keys, info)`` in canonical order."""
+          want_keys=True, x0=None):
+    """One-shot solve from host data; returns ``(u_hat, keys, info)`` in canonical order.
+    ``x0``: optional initial guess (complex, |S^N| entries in canonical order)."""
     af = _i16(np.asarray(a_freqs).reshape(-1, d))
     ff = _i16(np.asarray(f_freqs).reshape(-1, d))
     ah = _c128(a_hat)
@@ -487,12 +488,18 @@ def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64",
     info = SolveInfo()
     _check(_lib.ss_solve(d, len(af), _ptr(af, C.c_int16), _ptr(ah, C.c_double), len(ff), _ptr(ff, C.c_int16),
                          _ptr(fh, C.c_double), int(level), float(tol), PRECISION[precision], int(max_iter),
-                         int(flags), 0, C.byref(n), None, None, C.byref(info)))
+                         int(flags), None, 0, C.byref(n), None, None, C.byref(info)))
     u = np.zeros(n.value, dtype=np.complex128)
+    x0v = None
+    if x0 is not None:
+        x0v = _c128(x0)
+        if len(x0v) != 2 * n.value:
+            raise SparseSpecError(SS_EINVAL, "x0 needs |S^N| entries")
     keys = np.zeros((n.value, d), dtype=np.int16) if want_keys else None
     _check(_lib.ss_solve(d, len(af), _ptr(af, C.c_int16), _ptr(ah, C.c_double), len(ff), _ptr(ff, C.c_int16),
                          _ptr(fh, C.c_double), int(level), float(tol), PRECISION[precision], int(max_iter),
-                         int(flags), n.value, C.byref(n), _ptr(u.view(np.float64), C.c_double),
+                         int(flags), _ptr(x0v, C.c_double) if x0v is not None else None, n.value, C.byref(n),
+                         _ptr(u.view(np.float64), C.c_double),
                          _ptr(keys, C.c_int16) if want_keys else None, C.byref(info)))
     return u, keys, info.as_dict()
 

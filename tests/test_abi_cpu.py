@@ -70,7 +70,7 @@ def _solve(ss, d, af, ah, ff, fh, level=1):
     fh = np.ascontiguousarray(np.asarray(fh, dtype=np.complex128)).view(np.float64)
     n = C.c_int64()
     st = ss._lib.ss_solve(d, len(af), ss._ptr(af, C.c_int16), ss._ptr(ah, C.c_double), len(ff),
-                          ss._ptr(ff, C.c_int16), ss._ptr(fh, C.c_double), level, 1e-10, 0, 100, 0, 0,
+                          ss._ptr(ff, C.c_int16), ss._ptr(fh, C.c_double), level, 1e-10, 0, 100, 0, None, 0,
                           C.byref(n), None, None, None)
     return st, ss._lib.ss_last_error().decode()
 

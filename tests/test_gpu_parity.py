@@ -289,6 +289,11 @@ def test_one_shot_solve(ss):
     u, keys, info = ss.solve(p.d, p.a_freqs, p.a_hat, p.f_freqs, p.f_hat, p.level, tol=TOL64)
     assert np.array_equal(keys.astype(np.int64), oc["keys"])
     assert rel(u, oc["u"]) <= ERR64 and info["status"] == 0 and info["n"] == len(keys)
+    # a warm start from the oracle's solution needs at most one iteration
+    u2, _, info2 = ss.solve(p.d, p.a_freqs, p.a_hat, p.f_freqs, p.f_hat, p.level, tol=TOL64, x0=oc["u"])
+    assert info2["iters"] <= 1 and rel(u2, oc["u"]) <= ERR64
+    with pytest.raises(ss.SparseSpecError):
+        ss.solve(p.d, p.a_freqs, p.a_hat, p.f_freqs, p.f_hat, p.level, tol=TOL64, x0=oc["u"][:-1])
 
 
 # ---------------------------------------------------------------- edge cases

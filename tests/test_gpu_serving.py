@@ -182,6 +182,18 @@ def test_engine_budget_refuses_and_recovers(ss):
         pass
     assert [t for t, _, _ in eng.poll()] == [1]
     eng.close()
+    # a request larger than the whole budget: refused beside another, admitted alone
+    small = ss.Engine(min(b0, b1) - 1, 0)
+    assert small.submit(built[0][0], built[0][1], built[0][2], 1e-10, "fp64", 2000, 0)
+    assert not small.submit(built[1][0], built[1][1], built[1][2], 1e-10, "fp64", 2000, 1)
+    while small.step(8):
+        pass
+    assert [t for t, _, _ in small.poll()] == [0]
+    assert small.submit(built[1][0], built[1][1], built[1][2], 1e-10, "fp64", 2000, 1)
+    while small.step(8):
+        pass
+    assert [t for t, _, i in small.poll() if i["status"] == 0] == [1]
+    small.close()
 
 
 def test_engine_rejects_double_submit(ss):
