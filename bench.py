@@ -107,7 +107,9 @@ def main():
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
     ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
     ap.add_argument("--adr", type=int, default=256,
-                    help="3-D advection-diffusion-reaction problems per batch (0 = skip)")
+                    help="3-D advection-diffusion-reaction problems at level 1 (0 = skip the ADR runs)")
+    ap.add_argument("--adr-n2", type=int, default=192,
+                    help="ADR problems at level 2 (the matvec's working set above 1 GiB)")
     ap.add_argument("--direct", type=int, default=16,
                     help="d=10 problems for the dense direct (Cholesky) solve comparison (0 = skip)")
     args = ap.parse_args()
@@ -579,7 +581,7 @@ def main():
     adr_out = None
     if args.adr > 0:
         adr_out = {}
-        for N, Ba in ((1, args.adr), (2, max(1, args.adr // 4))):
+        for N, Ba in ((1, args.adr), (2, args.adr_n2)):
             ap_ = [workloads.adr3d(N, i) for i in range(Ba)]
             dps = [q.diffusion_on_union() for q in ap_]
             torch.cuda.synchronize()
@@ -610,6 +612,8 @@ def main():
             e_ev.record()
             torch.cuda.synchronize()
             mv_ms = s_ev.elapsed_time(e_ev) / 10
+            # algorithmic bytes: per stored pair (k, l) its 4-byte column and 16-byte coefficient, per
+            # row x once and y once
             mv_bytes = opa.nnz * 20 + opa.n_total * (16 + 16)
             med = float(np.median(ts))
             adr_out[f"N={N}"] = {"batch": Ba, "rows": int(opa.n_total), "nnz": int(opa.nnz),
@@ -617,7 +621,11 @@ def main():
                                  "solves_per_s": Ba / (med / 1e3),
                                  "iters_median": float(np.median([i["iters"] for i in inf])),
                                  "max_rel_residual": float(max(i["rel_residual"] for i in inf)),
-                                 "matvec_us": 1e3 * mv_ms, "matvec_GB/s": mv_bytes / (mv_ms / 1e3) / 1e9}
+                                 "matvec_us": 1e3 * mv_ms, "matvec_bytes": int(mv_bytes),
+                                 "matvec_GB/s": mv_bytes / (mv_ms / 1e3) / 1e9,
+                                 "roofline": {"bound": "hbm", "kernel": "k_adr_mv", "achieved": mv_bytes / (mv_ms / 1e3) / 1e9,
+                                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                              "frac": mv_bytes / (mv_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
             log(f"adr N={N} B={Ba}: rows {opa.n_total}, build {t_build:.1f} ms, solve {med:.1f} ms "
                 f"({Ba / (med / 1e3):.0f} solves/s, {np.median([i['iters'] for i in inf]):.0f} iters), matvec "
                 f"{1e3 * mv_ms:.0f} us = {mv_bytes / (mv_ms / 1e3) / 1e9:.0f} GB/s")

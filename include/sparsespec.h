@@ -32,7 +32,7 @@
  *     lexicographic order of their signed coordinates, coordinate 0 most
  *     significant ("canonical order").  A batch numbers problem after
  *     problem.
- *   - Limits: 1 <= d <= 1024; |supp a| (after closing under negation) <= 63;
+ *   - Limits: 1 <= d <= 1024; |supp a| (after closing under negation) <= 127;
  *     every key coordinate must fit int16 (else SS_ERANGE); at most 16383
  *     problems per batch and 4194303 keys per problem.
  */

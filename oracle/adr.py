@@ -17,9 +17,11 @@ L_{k,l} = 4 pi^2 (k.l) a_{k-l} + 2 pi i (l . b_{k-l}) + c_{k-l} for k, l in S.
                 the smallest set holding the operator's N-fold action on F).
 * ``matrix``    L on a key set, entry by entry from the definition above, exact integer dot
                 products.
-* ``solve``     L u = f on the key set, one dense solve per connected class (the relation is
-                still the union-support shift, so classes still decouple).  The reaction
-                term's c_0 > 0 keeps the zero frequency an ordinary unknown.
+* ``solve``     L u = f on the key set, one direct solve per connected class (the relation is
+                still the union-support shift, so classes still decouple): a dense LU up to
+                ``dense_limit`` rows, a sparse LU (SuperLU) of the same block above (the paper's
+                3-D data at level 2 form one class of about 4e4 rows).  The reaction term's
+                c_0 > 0 keeps the zero frequency an ordinary unknown.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ from typing import Dict, Tuple
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from oracle import galerkin as og
 from oracle import stamp as ost
@@ -88,8 +91,9 @@ def matrix(keys, a_freqs, a_hat, b_freqs, b_hat, c_freqs, c_hat):
     return sp.csr_matrix((np.array(vals, dtype=np.complex128), (rows, cols)), shape=(n, n))
 
 
-def solve(keys, a_freqs, a_hat, b_freqs, b_hat, c_freqs, c_hat, f, M=None):
-    """u with L u = f on the key set: one dense LU solve per connected class."""
+def solve(keys, a_freqs, a_hat, b_freqs, b_hat, c_freqs, c_hat, f, M=None, dense_limit: int = 6000):
+    """u with L u = f on the key set: one LU solve per connected class (dense up to
+    ``dense_limit`` rows, sparse above)."""
     keys = np.asarray(keys, dtype=np.int64)
     d = keys.shape[1]
     if M is None:
@@ -102,5 +106,9 @@ def solve(keys, a_freqs, a_hat, b_freqs, b_hat, c_freqs, c_hat, f, M=None):
     u = np.zeros(len(keys), dtype=np.complex128)
     for c in np.unique(label):
         rows = np.nonzero(label == c)[0]
-        u[rows] = np.linalg.solve(M[rows][:, rows].toarray(), f[rows])
+        block = M[rows][:, rows]
+        if len(rows) <= dense_limit:
+            u[rows] = np.linalg.solve(block.toarray(), f[rows])
+        else:
+            u[rows] = spla.spsolve(sp.csc_matrix(block), f[rows])
     return u

@@ -45,7 +45,7 @@ __global__ void k_adr_coef(int64_t n_exec, int d, const int32_t* __restrict__ pi
                            const NormT* __restrict__ norm, const double2* __restrict__ A64,
                            const int64_t* __restrict__ nu, const double2* __restrict__ Bt,
                            const double2* __restrict__ Ct, const int32_t* __restrict__ zero_j,
-                           double2* __restrict__ E, double2* __restrict__ D) {
+                           double2* __restrict__ E, uint32_t* __restrict__ col, double2* __restrict__ D) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_exec) return;
   const int64_t sl = e / kSlice;
@@ -54,13 +54,16 @@ __global__ void k_adr_coef(int64_t n_exec, int d, const int32_t* __restrict__ pi
   const uint32_t width = (sptr[sl + 1] - base) / kSlice;
   if (exec2canon[e] < 0) {
     D[e] = make_double2(1.0, 0.0);
-    for (uint32_t q = 0; q < width; ++q) E[base + q * kSlice + lane] = make_double2(0.0, 0.0);
+    for (uint32_t q = 0; q < width; ++q) {
+      E[base + q * kSlice + lane] = make_double2(0.0, 0.0);
+      col[base + q * kSlice + lane] = (uint32_t)e;
+    }
     return;
   }
   const int p = pid[e];
   const NormT nk = norm[e];
-  const double2* Bp = Bt + (int64_t)p * 64 * d;
-  const double2* Cp = Ct + (int64_t)p * 64;
+  const double2* Bp = Bt + (int64_t)p * kTab * d;
+  const double2* Cp = Ct + (int64_t)p * kTab;
   const int zj = zero_j[p];
   double2 diag = make_double2(0.0, 0.0);
   for (uint32_t q = 0; q < width; ++q) {
@@ -78,62 +81,81 @@ __global__ void k_adr_coef(int64_t n_exec, int d, const int32_t* __restrict__ pi
         si += lt * b[t].y;
       }
       const double tp = 2.0 * M_PI;
-      const NormT I = nk + norm[ge] - (NormT)nu[(int64_t)p * 64 + j];
-      const double2 a = A64[(int64_t)p * 64 + j];
+      const NormT I = nk + norm[ge] - (NormT)nu[(int64_t)p * kTab + j];
+      const double2 a = A64[(int64_t)p * kTab + j];
       v = make_double2((double)I * a.x + (Cp[j].x - tp * si), (double)I * a.y + (Cp[j].y + tp * sr));
       if ((int)j == zj) diag = v;
     }
     E[base + q * kSlice + lane] = v;
+    // a padding entry keeps coefficient 0 and points at its own row
+    col[base + q * kSlice + lane] = j != (uint32_t)kNullJ ? (uint32_t)(eoff[p] + (int64_t)(ent & kColMask)) : (uint32_t)e;
   }
   D[e] = diag;
 }
 
-// y = L x over every problem (execution order), the stored coefficients streamed with
-// nontemporal loads; padding rows get 0
-typedef double adr_d2v __attribute__((ext_vector_type(2)));
-__global__ void k_adr_mv(int64_t n_exec, const int32_t* __restrict__ pid, const int64_t* __restrict__ eoff,
-                         const int64_t* __restrict__ exec2canon, const uint32_t* __restrict__ sent,
-                         const uint32_t* __restrict__ sptr, const double2* __restrict__ E,
-                         const uint8_t* __restrict__ done, const double2* __restrict__ x,
-                         double2* __restrict__ y) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_exec) return;
-  const int p = pid[e];
-  if (done && done[p]) return;
-  if (exec2canon[e] < 0) {
-    y[e] = make_double2(0.0, 0.0);
-    return;
+// problem of every SELL slice (problems start on slice boundaries)
+__global__ void k_adr_spid(int64_t n_slices, int n_prob, const int64_t* __restrict__ eoff, int32_t* __restrict__ spid) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n_slices) return;
+  const int64_t e = sl * kSlice;
+  int lo = 0, hi = n_prob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (eoff[mid] <= e) lo = mid;
+    else hi = mid - 1;
   }
-  const int64_t sl = e / kSlice;
-  const int lane = (int)(e % kSlice);
-  const uint32_t base = sptr[sl];
-  const uint32_t width = (sptr[sl + 1] - base) / kSlice;
-  const double2* xp = x + eoff[p];
+  spid[sl] = lo;
+}
+
+// y = L x over every problem: one wavefront per SELL slice (64 rows, one per lane), the global
+// column and the whole complex coefficient of every stored entry streamed with nontemporal loads,
+// eight entries of a lane in flight while a row has that many left; padding entries have
+// coefficient 0 and padding rows only such entries, so they get 0.  A slice of a finished problem
+// is skipped.  Blocks are numbered XCD by XCD, so each XCD walks a contiguous eighth of the slices
+// (a problem or two at a time) and its L2 keeps those problems' x for the gathers.
+typedef double adr_d2v __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(kAdrBlock) void k_adr_mv(int64_t n_slices, const int32_t* __restrict__ spid,
+                                                      const uint32_t* __restrict__ sptr,
+                                                      const uint32_t* __restrict__ col, const double2* __restrict__ E,
+                                                      const uint8_t* __restrict__ done, const double2* __restrict__ x,
+                                                      double2* __restrict__ y) {
+  const int64_t nb = (n_slices * kSlice + kAdrBlock - 1) / kAdrBlock;
+  const int64_t sl = __builtin_amdgcn_readfirstlane((int)((xcd_block(nb) * kAdrBlock + threadIdx.x) >> 6));
+  if (sl >= n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int p = __builtin_amdgcn_readfirstlane(spid[sl]);
+  if (done && done[p]) return;
+  const uint32_t base = __builtin_amdgcn_readfirstlane(sptr[sl]);
+  const uint32_t width = (__builtin_amdgcn_readfirstlane(sptr[sl + 1]) - base) / kSlice;
+  const uint32_t* cl = col + base + lane;
+  const adr_d2v* El = reinterpret_cast<const adr_d2v*>(E + base + lane);
   double ar = 0, ai = 0;
-  // eight entries in flight: their words, then their coefficients and x values, then the sums
   constexpr int kU = 8;
-  for (uint32_t q0 = 0; q0 < width; q0 += kU) {
-    uint32_t ent[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      ent[u] = q0 + u < width ? __builtin_nontemporal_load(sent + base + (q0 + u) * kSlice + lane)
-                              : (uint32_t)kNullJ << kColBits;
-    adr_d2v c[kU];
+  uint32_t q0 = 0;
+  for (; q0 + kU <= width; q0 += kU) {
+    uint32_t c[kU];
+    adr_d2v v[kU];
     double2 xv[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const bool live = (ent[u] >> kColBits) != (uint32_t)kNullJ;
-      c[u] = live ? __builtin_nontemporal_load(reinterpret_cast<const adr_d2v*>(E + base + (q0 + u) * kSlice + lane))
-                  : adr_d2v{0.0, 0.0};
-      xv[u] = live ? xp[ent[u] & kColMask] : make_double2(0.0, 0.0);
-    }
+    for (int u = 0; u < kU; ++u) c[u] = __builtin_nontemporal_load(cl + (q0 + u) * kSlice);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = __builtin_nontemporal_load(El + (q0 + u) * kSlice);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) xv[u] = x[c[u]];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      ar += c[u].x * xv[u].x - c[u].y * xv[u].y;
-      ai += c[u].x * xv[u].y + c[u].y * xv[u].x;
+      ar += v[u].x * xv[u].x - v[u].y * xv[u].y;
+      ai += v[u].x * xv[u].y + v[u].y * xv[u].x;
     }
   }
-  y[e] = make_double2(ar, ai);
+  for (; q0 < width; ++q0) {
+    const uint32_t c = __builtin_nontemporal_load(cl + q0 * kSlice);
+    const adr_d2v v = __builtin_nontemporal_load(El + q0 * kSlice);
+    const double2 xv = x[c];
+    ar += v.x * xv.x - v.y * xv.y;
+    ai += v.x * xv.y + v.y * xv.x;
+  }
+  __builtin_nontemporal_store(adr_d2v{ar, ai}, reinterpret_cast<adr_d2v*>(y + sl * kSlice + lane));
 }
 
 // per-problem BiCGSTAB scalars
@@ -363,8 +385,10 @@ struct AdrImpl {
   const OpImpl* op = nullptr;
   int device = 0;
   double2* E = nullptr;        // [n_sell] whole coefficient of every stored entry
+  uint32_t* col = nullptr;     // [n_sell] global execution column of every stored entry
   double2* D = nullptr;        // [n_exec] diagonal
   int32_t* pid = nullptr;      // [n_exec]
+  int32_t* spid = nullptr;     // [n_slices]
 };
 
 ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n_b, const int16_t* b_freqs,
@@ -375,7 +399,7 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
   if (op->total != st->total || op->n_prob != st->n_prob) return fail(SS_EINVAL, "the operator was not built on this stamp");
   const int np = op->n_prob, d = op->d;
   // per problem: table index of every b and c frequency in the operator's (union) table
-  std::vector<double2> Bt((size_t)np * 64 * d, make_double2(0, 0)), Ct((size_t)np * 64, make_double2(0, 0));
+  std::vector<double2> Bt((size_t)np * kTab * d, make_double2(0, 0)), Ct((size_t)np * kTab, make_double2(0, 0));
   std::vector<int32_t> zj(np);
   int64_t bpos = 0, cpos = 0;
   for (int p = 0; p < np; ++p) {
@@ -395,7 +419,7 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
       for (int t = 0; t < d; ++t) {
         const double re = b_hat[2 * (bpos * d + t)], im = b_hat[2 * (bpos * d + t) + 1];
         if (!std::isfinite(re) || !std::isfinite(im)) return fail(SS_EINVAL, "b_hat is not finite");
-        double2& dst = Bt[((size_t)p * 64 + j) * d + t];
+        double2& dst = Bt[((size_t)p * kTab + j) * d + t];
         dst.x += re;
         dst.y += im;
       }
@@ -406,11 +430,11 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
       if (j < 0) return fail(SS_EINVAL, "a frequency of c is not in the operator's support (build on the union)");
       const double re = c_hat[2 * cpos], im = c_hat[2 * cpos + 1];
       if (!std::isfinite(re) || !std::isfinite(im)) return fail(SS_EINVAL, "c_hat is not finite");
-      Ct[(size_t)p * 64 + j].x += re;
-      Ct[(size_t)p * 64 + j].y += im;
+      Ct[(size_t)p * kTab + j].x += re;
+      Ct[(size_t)p * kTab + j].y += im;
       if (j == zj[p]) c0 = true;
     }
-    if (!c0 || !(Ct[(size_t)p * 64 + zj[p]].x > 0.0) || Ct[(size_t)p * 64 + zj[p]].y != 0.0)
+    if (!c0 || !(Ct[(size_t)p * kTab + zj[p]].x > 0.0) || Ct[(size_t)p * kTab + zj[p]].y != 0.0)
       return fail(SS_EINVAL, "c_0 must be real and positive (the zero frequency is then an ordinary unknown)");
   }
   std::unique_ptr<AdrImpl, void (*)(AdrImpl*)> A(new AdrImpl(), adr_free_impl);   // frees on every error path
@@ -435,20 +459,24 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
   SS_HIP(h2d(dB, Bt.data(), Bt.size() * sizeof(double2), s));
   SS_HIP(h2d(dC, Ct.data(), Ct.size() * sizeof(double2), s));
   SS_HIP(h2d(dz, zj.data(), (size_t)np * sizeof(int32_t), s));
+  if (op->n_exec >= (int64_t(1) << 32)) return fail(SS_ERANGE, "too many rows for 32-bit global columns");
   SS_TRY(dalloc(&A->E, (size_t)std::max<int64_t>(op->n_sell, 1)));
+  SS_TRY(dalloc(&A->col, (size_t)std::max<int64_t>(op->n_sell, 1)));
   SS_TRY(dalloc(&A->D, (size_t)op->n_exec));
   SS_TRY(dalloc(&A->pid, (size_t)op->n_exec));
+  SS_TRY(dalloc(&A->spid, (size_t)std::max<int64_t>(op->n_slices, 1)));
   const OpDev od = op->dev();
   const int64_t ne = op->n_exec;
   k_adr_pid<<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, np, op->d_eoff, A->pid);
+  k_adr_spid<<<adr_grid(op->n_slices), kAdrBlock, 0, s>>>(op->n_slices, np, op->d_eoff, A->spid);
   if (op->wide_norm)
     k_adr_coef<int64_t><<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, d, A->pid, op->d_eoff, op->d_exec2canon, st->d_keys,
                                                            od.sent, od.sptr, (const int64_t*)od.norm, od.A64, od.nu,
-                                                           dB, dC, dz, A->E, A->D);
+                                                           dB, dC, dz, A->E, A->col, A->D);
   else
     k_adr_coef<int32_t><<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, d, A->pid, op->d_eoff, op->d_exec2canon, st->d_keys,
                                                            od.sent, od.sptr, (const int32_t*)od.norm, od.A64, od.nu,
-                                                           dB, dC, dz, A->E, A->D);
+                                                           dB, dC, dz, A->E, A->col, A->D);
   SS_HIP(hipGetLastError());
   SS_HIP(hipStreamSynchronize(s));
   *out = A.release();
@@ -458,8 +486,10 @@ ss_status adr_build_impl(const StampImpl* st, const OpImpl* op, const int32_t* n
 void adr_free_impl(AdrImpl* A) {
   if (!A) return;
   dfree(A->E);
+  dfree(A->col);
   dfree(A->D);
   dfree(A->pid);
+  dfree(A->spid);
   delete A;
 }
 
@@ -467,9 +497,8 @@ namespace {
 ss_status adr_mv(const AdrImpl* A, const uint8_t* done, const double2* x, double2* y, hipStream_t s) {
   const OpImpl* op = A->op;
   const OpDev od = op->dev();
-  const int64_t ne = op->n_exec;
-  k_adr_mv<<<adr_grid(ne), kAdrBlock, 0, s>>>(ne, A->pid, op->d_eoff, op->d_exec2canon, od.sent, od.sptr, A->E, done,
-                                              x, y);
+  const int64_t ns = op->n_slices;
+  k_adr_mv<<<xcd_grid(ceil_div(ns * kSlice, kAdrBlock)), kAdrBlock, 0, s>>>(ns, A->spid, od.sptr, A->col, A->E, done, x, y);
   SS_HIP(hipGetLastError());
   return SS_OK;
 }

@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kDnBlock) void k_dn_assemble(int nc, const DClass* 
   const int lane = (int)(e % kSlice);
   const uint32_t base = sptr[sl];
   const uint32_t width = (sptr[sl + 1] - base) / kSlice;
-  const double2* At = A64 + (int64_t)C.prob * 64;
-  const int64_t* nut = nu + (int64_t)C.prob * 64;
+  const double2* At = A64 + (int64_t)C.prob * kTab;
+  const int64_t* nut = nu + (int64_t)C.prob * kTab;
   for (uint32_t q = 0; q < width; ++q) {
     const uint32_t ent = sent[base + q * kSlice + lane];
     const uint32_t j = ent >> kColBits;

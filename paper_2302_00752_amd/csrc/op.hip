@@ -34,7 +34,7 @@ struct NbrArgs {
   int64_t total;
   int32_t d;
   int32_t smax;
-  int32_t rows_per_wave;          // floor(64 / smax)
+  int32_t rows_per_wave;          // floor(64 / smax), at least 1
   const int16_t* keys;
   const uint64_t* hash;
   const int32_t* pid;
@@ -46,25 +46,28 @@ struct NbrArgs {
   const int64_t* toff;
   const uint64_t* tmask;
   const uint64_t* table;
-  uint32_t* buf;       // [smax x total] compact row entries (entry q of row r at q * total + r): local canonical column | j << 26
+  uint32_t* buf;       // [smax x total] compact row entries (entry q of row r at q * total + r): local canonical column | j << kColBits
   int64_t* rowlen;     // [total]
 };
 
-// One lane per (row, a-table index): look up k - w_j; a ballot over the row's
-// lanes compacts the hits to the front of the row's buffer in j order.
+// One lane per (row, a-table index): look up k - w_j; a ballot over the row's lanes compacts the
+// hits to the front of the row's buffer in j order.  A table of more than 64 entries takes one wave
+// per row, its lanes covering j = 0..63, then 64..127.
 __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t n_blocks = ceil_div(ceil_div(a.total, a.rows_per_wave), kBlock / 64);
   const int64_t wave = (xcd_block(n_blocks) * kBlock + threadIdx.x) >> 6;
-  const int rl = lane / a.smax, j = lane % a.smax;
+  const int width = a.smax < 64 ? a.smax : 64;   // lanes per row
+  const int rl = lane / width, jl = lane % width;
   const int64_t r = wave * a.rows_per_wave + rl;
   const bool live = rl < a.rows_per_wave && r < a.total;
-  int64_t col = -1;
-  int p = 0;
-  if (live) {
-    p = a.pid[r];
-    const int j0 = a.aoff[p];
-    if (j < a.aoff[p + 1] - j0) {
+  const int p = live ? a.pid[r] : 0;
+  const int j0 = live ? a.aoff[p] : 0, s = live ? a.aoff[p + 1] - j0 : 0;
+  int found = 0;   // entries of this row found in earlier chunks
+  for (int jb = 0; jb < a.smax; jb += 64) {
+    const int j = jb + jl;
+    int64_t col = -1;
+    if (live && j < s) {
       if (j == a.azero[p]) {
         col = r;
       } else {
@@ -88,17 +91,15 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
         }
       }
     }
-  }
-  const uint64_t hits = __ballot(col >= 0);
-  const int sh = rl * a.smax;
-  const uint64_t seg = a.smax >= 64 ? hits : (hits >> sh) & ((1ull << a.smax) - 1);
-  if (live) {
-    if (col >= 0) {
-      const int q = __popcll(seg & ((1ull << j) - 1));
+    const uint64_t hits = __ballot(col >= 0);
+    const uint64_t seg = width >= 64 ? hits : (hits >> (rl * width)) & ((1ull << width) - 1);
+    if (live && col >= 0) {
+      const int q = found + __popcll(seg & ((1ull << jl) - 1));
       a.buf[q * a.total + r] = (uint32_t)(col - a.rowoff[p]) | ((uint32_t)j << kColBits);
     }
-    if (j == 0) a.rowlen[r] = __popcll(seg);
+    found += __popcll(seg);
   }
+  if (live && jl == 0) a.rowlen[r] = found;
 }
 
 constexpr int kNbrGroup = 8;   // lookup-table words per probe group (64 bytes)
@@ -135,7 +136,7 @@ __device__ __forceinline__ bool key_is_shift(const int16_t* __restrict__ cp, con
 // that entry and, when l = k - w_j is present, the mirror entry (l, s-1-j) = k into l's row.
 // Entries go to a dense j-major table (entry j of row r at j * n + r; absent = all ones); the
 // lower half of it is cleared beforehand, the upper half and the diagonal are written here.  An
-// entry is `local column | j << 26` (u32), or the local column alone (u16) when every problem has
+// entry is `local column | j << kColBits` (u32), or the local column alone (u16) when every problem has
 // fewer than 65535 keys (j is then the table row the entry sits in).
 template <typename E>
 __device__ inline E dense_entry(int64_t col, int j) {
@@ -164,7 +165,6 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   const int64_t ro = a.rowoff[p];
   const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
   const uint64_t* table = a.table + base;   // lookup table: one word per slot
-  const int16_t* wsrc = UNI ? wtab : a.akeys + (int64_t)j0 * d;
   E* D = reinterpret_cast<E*>(a.buf);
   constexpr E kNone = (E)~(E)0;
   const int64_t T = a.total;
@@ -172,8 +172,9 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   for (int j = z + 1; j < s; ++j) {
     int64_t m = -1;
     {
-      const int16_t* w = wsrc + j * d;
-      const uint64_t h = hr - (UNI ? htab[j] : a.ahash[j0 + j]);
+      // (the LDS tables hold the upper half, entries z + 1 .. s - 1)
+      const int16_t* w = UNI ? wtab + (j - z - 1) * d : a.akeys + (int64_t)(j0 + j) * d;
+      const uint64_t h = hr - (UNI ? htab[j - z - 1] : a.ahash[j0 + j]);
       const uint64_t pos = fmix64(h) & mask;
       const uint64_t g0 = pos & ~(uint64_t)(G - 1);   // regions are multiples of 64 slots: aligned
       uint64_t sv[G];
@@ -271,8 +272,9 @@ __global__ void k_csr_from_dense(int64_t total, const E* __restrict__ D, const i
 
 template <int DMAX, bool EVEN, typename E>
 __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
-  __shared__ int16_t s_w[kBlock / 64][kMaxA * DMAX];
-  __shared__ uint64_t s_h[kBlock / 64][kMaxA];
+  // the upper half of a mirrored table: at most (kMaxA - 1) / 2 entries
+  __shared__ int16_t s_w[kBlock / 64][(kMaxA / 2) * DMAX];
+  __shared__ uint64_t s_h[kBlock / 64][kMaxA / 2];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t r = xcd_block(ceil_div(a.total, kBlock)) * kBlock + threadIdx.x;
   const bool live = r < a.total;
@@ -280,9 +282,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
   const int pu = __builtin_amdgcn_readfirstlane(p);
   const bool uni = pu >= 0 && __all(!live || p == pu);
   if (uni) {
-    const int j0 = a.aoff[pu], s = a.aoff[pu + 1] - j0;
-    for (int i = lane; i < s * a.d; i += 64) s_w[wv][i] = a.akeys[(int64_t)j0 * a.d + i];
-    for (int i = lane; i < s; i += 64) s_h[wv][i] = a.ahash[j0 + i];
+    const int j1 = a.aoff[pu] + a.azero[pu] + 1, nh = a.aoff[pu + 1] - j1;
+    for (int i = lane; i < nh * a.d; i += 64) s_w[wv][i] = a.akeys[(int64_t)j1 * a.d + i];
+    for (int i = lane; i < nh; i += 64) s_h[wv][i] = a.ahash[j1 + i];
   }
   __syncthreads();
   if (!live) return;
@@ -360,7 +362,7 @@ __global__ void k_class_min(int64_t n_cls, int64_t total, const int64_t* __restr
   for (int64_t q = q0 + lane; q < q1; q += 64) comp[order[q]] = (int32_t)(m - base);
 }
 
-// sort key (problem, class, 63 - row length) packed with `lb` bits per local index; the rows
+// sort key (problem, class, kMaxA - row length) packed with `lb` bits per local index; the rows
 // come in canonical order and the radix sort is stable, so the canonical slot breaks ties
 __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ pid,
                             const int64_t* __restrict__ rowoff, const int64_t* __restrict__ label,
@@ -370,7 +372,7 @@ __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ p
   if (r >= total) return;
   const int p = pid[r];
   const uint64_t cls = (uint64_t)(label[r] - rowoff[p]);
-  key[r] = ((((uint64_t)p << lb) | cls) << 6) | (uint64_t)(63 - rowlen[r]);
+  key[r] = ((((uint64_t)p << lb) | cls) << kJBits) | (uint64_t)(kMaxA - rowlen[r]);
   val[r] = (uint32_t)r;
 }
 
@@ -515,9 +517,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   thread_local std::vector<double2> A64;
   thread_local std::vector<float2> A32;
   thread_local std::vector<int64_t> nu;
-  A64.assign((size_t)n_prob * 64, make_double2(0, 0));
-  A32.assign((size_t)n_prob * 64, make_float2(0, 0));
-  nu.assign((size_t)n_prob * 64, 0);
+  A64.assign((size_t)n_prob * kTab, make_double2(0, 0));
+  A32.assign((size_t)n_prob * kTab, make_float2(0, 0));
+  nu.assign((size_t)n_prob * kTab, 0);
   std::vector<double> a0(n_prob);
   int smax = 1;
   int64_t pos = 0;
@@ -533,11 +535,11 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     double l1 = 0;
     for (int j = 0; j < s; ++j) {
       const double2 c = at.coef[j];
-      A64[(size_t)p * 64 + j] = make_double2(two_pi2 * c.x, two_pi2 * c.y);
-      A32[(size_t)p * 64 + j] = make_float2((float)(two_pi2 * c.x), (float)(two_pi2 * c.y));
+      A64[(size_t)p * kTab + j] = make_double2(two_pi2 * c.x, two_pi2 * c.y);
+      A32[(size_t)p * kTab + j] = make_float2((float)(two_pi2 * c.x), (float)(two_pi2 * c.y));
       int64_t nn = 0;
       for (int t = 0; t < d; ++t) nn += (int64_t)at.key(j)[t] * at.key(j)[t];
-      nu[(size_t)p * 64 + j] = nn;
+      nu[(size_t)p * kTab + j] = nn;
       if (j != at.zero) l1 += cabs2d(c.x, c.y);
     }
     a0[p] = at.coef[at.zero].x;
@@ -580,7 +582,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(nbr);
   SS_TRY(dalloc(&rowlen, total + 1));
   track(rowlen);
-  const int rpw = 64 / smax;
+  const int rpw = smax <= 64 ? 64 / smax : 1;
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
              st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen};
   if (dense) {
@@ -674,7 +676,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   while ((int64_t(1) << lb) < max_rows) ++lb;
   int pb = 0;
   while ((1 << pb) < n_prob) ++pb;
-  const int key_bits = pb + lb + 6;   // <= 14 + 22 + 6
+  const int key_bits = pb + lb + kJBits;   // <= 14 + 22 + 7
   k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, label, rowlen, ek, ev);
   {
     size_t tb = 0;

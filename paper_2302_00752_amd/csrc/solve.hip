@@ -55,7 +55,7 @@ constexpr int kMaxOuter = 30;
 enum { MV_PLAIN = 0, MV_DOT = 1, MV_RESID = 2 };
 
 // LDS of the matvec: a-table (64 x 16 B), |w_j|^2 (64 x 8 B), 4 partials, then the window
-constexpr int kLdsFixed = 64 * 16 + 64 * 8 + kSolveWaves * 8;
+constexpr int kLdsFixed = kTab * 16 + kTab * 8 + kSolveWaves * 8;
 
 // dynamic LDS bytes of a matvec over windows of up to `win` rows
 inline size_t mv_lds_bytes(int64_t win, bool fp64, bool wide) {
@@ -67,7 +67,7 @@ struct Desc {
   const uint32_t* sent;        // operator SELL entries
   const uint32_t* sptr;        // operator slice offsets (operator-global slice index)
   const void* norm;            // |k|^2 of the problem's first execution row
-  const double2* A64;          // the problem's 64-entry tables
+  const double2* A64;          // the problem's kTab-entry tables
   const float2* A32;
   const int64_t* nu;
   const int64_t* exec2canon;   // problem's execution rows -> operator-global canonical slot (-1 pad)
@@ -199,8 +199,8 @@ template <> __device__ inline const float2* a_table<float2>(const Desc& D) { ret
 template <typename NormT, typename V, int MODE>
 __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) {
   V* As = (V*)lds;
-  NormT* nus = (NormT*)(lds + 64 * sizeof(double2));
-  double* red = (double*)(lds + 64 * sizeof(double2) + 64 * sizeof(int64_t));
+  NormT* nus = (NormT*)(lds + kTab * sizeof(double2));
+  double* red = (double*)(lds + kTab * sizeof(double2) + kTab * sizeof(int64_t));
   const int nsl = wk.z & 0xffff, wlen = wk.z >> 16, w0 = wk.w;
   V* xw = (V*)(lds + kLdsFixed);
   NormT* nw = (NormT*)(lds + kLdsFixed + (size_t)wlen * sizeof(V));
@@ -218,7 +218,7 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) 
     y = (V*)(sizeof(V) == 16 ? (void*)D.q64 : (void*)D.q32);
   }
   const NormT* normv = (const NormT*)D.norm;
-  if (tid < 64) {
+  if (tid < kTab) {
     As[tid] = a_table<V>(D)[tid];
     nus[tid] = (NormT)D.nu[tid];
   }
@@ -690,7 +690,7 @@ struct UDesc {
   const uint32_t* sptr;
   const void* norm;              // operator execution order (op-global rows)
   const int64_t* exec2canon;     // operator execution row -> operator canonical slot
-  const double2* A64;            // the problem's 64-entry tables
+  const double2* A64;            // the problem's kTab-entry tables
   const float2* A32;
   const int64_t* nu;
   const double2* f;              // request: operator canonical f
@@ -948,9 +948,9 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   __shared__ NormT s_norm[kWinRows];
   __shared__ uint32_t s_sptr[kWinRows / kSlice + 1];
   extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF, CM_CPLX: brackets or coefficients, columns, j
-  __shared__ double2 s_A64[64];
-  __shared__ float2 s_A32[64];
-  __shared__ NormT s_nu[64];
+  __shared__ double2 s_A64[kTab];
+  __shared__ float2 s_A32[kTab];
+  __shared__ NormT s_nu[kTab];
   __shared__ double s_red[2][2 * kUnitWaves];   // reductions alternate between the two
   int rsel = 0;
   auto red_next = [&]() -> double* { rsel ^= 1; return s_red[rsel]; };
@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
   float2 tA32 = make_float2(0.f, 0.f);
   NormT tnu = 0;
   uint32_t tsp = 0;
-  if (tid < 64) {
+  if (tid < kTab) {
     tA64 = A.A64[tid];
     tA32 = A.A32[tid];
     tnu = (NormT)A.nu[tid];
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
 #pragma unroll
   for (int k = 0; k < kUnitSlots; ++k)
     if (wave + k * kUnitWaves < ns) s_norm[tid + k * kUnitThreads] = nk[k];
-  if (tid < 64) {
+  if (tid < kTab) {
     s_A64[tid] = tA64;
     s_A32[tid] = tA32;
     s_nu[tid] = tnu;
@@ -1449,9 +1449,9 @@ Desc make_desc(const OpImpl* op, const WS& w, int p) {
   D.sent = op->d_sent;
   D.sptr = op->d_sptr;
   D.norm = (const char*)op->d_norm + e0 * (op->wide_norm ? 8 : 4);
-  D.A64 = op->d_A64 + (size_t)p * 64;
-  D.A32 = op->d_A32 + (size_t)p * 64;
-  D.nu = op->d_nu + (size_t)p * 64;
+  D.A64 = op->d_A64 + (size_t)p * kTab;
+  D.A32 = op->d_A32 + (size_t)p * kTab;
+  D.nu = op->d_nu + (size_t)p * kTab;
   D.exec2canon = op->d_exec2canon + e0;
   D.x64 = w.x64 + e0;
   D.r64 = w.r64 + e0;
@@ -1495,9 +1495,9 @@ inline UnitItem unit_item(OpImpl* op, int p, const void* f, void* u, double tol,
   D.sptr = op->d_sptr;
   D.norm = op->d_norm;
   D.exec2canon = op->d_exec2canon;
-  D.A64 = op->d_A64 + (size_t)p * 64;
-  D.A32 = op->d_A32 + (size_t)p * 64;
-  D.nu = op->d_nu + (size_t)p * 64;
+  D.A64 = op->d_A64 + (size_t)p * kTab;
+  D.A32 = op->d_A32 + (size_t)p * kTab;
+  D.nu = op->d_nu + (size_t)p * kTab;
   D.f = (const double2*)f;
   D.u = (double2*)u;
   D.a0 = op->a0_host[p];
@@ -1931,7 +1931,7 @@ struct EngineImpl {
 int64_t op_device_bytes(const OpImpl* op) {
   const int64_t nb = op->wide_norm ? 8 : 4;
   return (op->total + 1) * 8 + op->nnz * 4 + op->total * 4 + op->n_exec * 8 + op->total * 8 + op->n_sell * 4 +
-         (op->n_slices + 1) * 4 + op->n_exec * nb + (int64_t)op->n_prob * 64 * (16 + 8 + 8) +
+         (op->n_slices + 1) * 4 + op->n_exec * nb + (int64_t)op->n_prob * kTab * (16 + 8 + 8) +
          (int64_t)op->work.size() * 16 + (int64_t)op->units.size() * 16;
 }
 

@@ -31,9 +31,12 @@ ss_status fail(ss_status st, const std::string& msg);
   } while (0)
 
 // ------------------------------------------------------------------ limits
-constexpr int kMaxA = 63;             // a-table entries per problem (index 63 = null entry)
-constexpr int kNullJ = 63;
-constexpr int kColBits = 26;          // execution-layout column bits in a packed entry
+constexpr int kJBits = 7;             // bits of an a-table index
+constexpr int kTab = 1 << kJBits;     // per-problem stride of the a-tables (coefficients, |w|^2)
+constexpr int kMaxA = kTab - 1;       // a-table entries per problem (index kTab - 1 = null entry)
+constexpr int kNullJ = kTab - 1;
+constexpr uint32_t kJMask = kTab - 1;
+constexpr int kColBits = 32 - kJBits; // execution-layout column bits in a packed entry
 constexpr uint32_t kColMask = (1u << kColBits) - 1;
 constexpr int kSlice = 64;            // SELL slice height = wavefront size
 constexpr int kBlock = 256;           // threads per block (4 wavefronts)
@@ -49,7 +52,7 @@ constexpr int kMaxProblems = (1 << 14) - 1;
 // hash-slot encoding
 // Build hash table: one word per slot.  MAIN: a key of an earlier level, its index (bits 0-30)
 // and fingerprint = hash >> 33 (bits 31-61); CAND: a candidate of the level being built,
-// (frontier key << 6) | a-table index in bits 0-61.  0 = empty.
+// (frontier key << kJBits) | a-table index in bits 0-61.  0 = empty.
 constexpr uint64_t kTagMain = 1ull << 62;
 constexpr uint64_t kTagCand = 2ull << 62;
 constexpr uint64_t kTagMask = 3ull << 62;
@@ -172,7 +175,7 @@ struct PState {
 
 // Plain-old-data view of an operator passed to kernels by value.
 struct OpDev {
-  const uint32_t* sent;      // SELL entries: local exec column | j << 26
+  const uint32_t* sent;      // SELL entries: local exec column | j << kColBits
   const uint32_t* sptr;      // [n_slices+1] entry offset of each slice
   const void* norm;          // [n_exec] |k|^2 per exec row (int32 or int64)
   const int64_t* eoff;       // [n_prob+1] first exec row of each problem
@@ -218,7 +221,7 @@ struct OpImpl {
   int4* d_units = nullptr;
   // canonical CSR (kept for export and tests)
   int64_t* d_crow = nullptr;           // [total+1]
-  uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << 26
+  uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << kColBits
   int32_t* d_comp = nullptr;           // [total] local label
   // execution layout
   int64_t* d_exec2canon = nullptr;     // [n_exec] global canonical or -1

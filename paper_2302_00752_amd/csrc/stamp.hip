@@ -76,7 +76,7 @@ __global__ void k_insert_main(int64_t n, const uint64_t* __restrict__ hash, cons
 struct ExpandArgs {
   int64_t n_cand;         // frontier size * smax1: an upper bound of the listed candidates
   const uint32_t* n_act;  // the listed candidates (device)
-  const uint64_t* cand;   // [n_cand] listed candidates, (frontier key << 6) | a-table index
+  const uint64_t* cand;   // [n_cand] listed candidates, (frontier key << kJBits) | a-table index
   int32_t d;
   const int16_t* keys;    // unsorted keys
   const uint64_t* hash;
@@ -99,8 +99,8 @@ __global__ void k_expand(ExpandArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)*a.n_act) return;
   const uint64_t c = a.cand[t];
-  const int64_t i = (int64_t)(c >> 6);
-  const int j = (int)(c & 63);
+  const int64_t i = (int64_t)(c >> kJBits);
+  const int j = (int)(c & kJMask);
   const int p = a.pid[i];
   const int wo = a.woff[p];
   const int d = a.d;
@@ -128,8 +128,8 @@ __global__ void k_expand(ExpandArgs a) {
         return;
       }
     } else {
-      const int64_t i2 = (int64_t)((v & kIdxMask) >> 6);
-      const int j2 = (int)(v & 63);
+      const int64_t i2 = (int64_t)((v & kIdxMask) >> kJBits);
+      const int j2 = (int)(v & kJMask);
       const uint64_t h2 = a.hash[i2] + a.whash[wo + j2];     // same problem: same region
       if (h2 == h && key_eq_shift2(a.keys + i2 * d, a.wkeys + (int64_t)(wo + j2) * d, k, w, d)) {
         // equal key among this level's candidates: the smallest candidate keeps the slot
@@ -156,7 +156,7 @@ __global__ void k_winners(int64_t n_cand, const uint32_t* __restrict__ n_act, co
   uint32_t f = 0;
   if (t < (int64_t)*n_act && cpos[t] != kNoSlot) {
     const uint64_t c = cand[t];
-    f = table[(uint64_t)toff[pid[c >> 6]] + cpos[t]] == (kTagCand | c) ? 1u : 0u;
+    f = table[(uint64_t)toff[pid[c >> kJBits]] + cpos[t]] == (kTagCand | c) ? 1u : 0u;
   }
   flag[t] = f;
 }
@@ -167,8 +167,8 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)*a.n_act || !flag[t]) return;
   const uint64_t c = a.cand[t];
-  const int64_t i = (int64_t)(c >> 6);
-  const int j = (int)(c & 63);
+  const int64_t i = (int64_t)(c >> kJBits);
+  const int j = (int)(c & kJMask);
   const int p = a.pid[i];
   const int wo = a.woff[p];
   const int d = a.d;
@@ -236,7 +236,7 @@ __global__ void k_cand_fill(int64_t n_front, int64_t f0, const int32_t* __restri
   const int64_t i = f0 + t;
   const uint32_t c0 = coff[t], n = coff[t + 1] - c0;
   const uint32_t lo = full[pid[i]] ? 0u : (uint32_t)last[i];
-  for (uint32_t q = 0; q < n; ++q) cand[c0 + q] = ((uint64_t)i << 6) | (uint64_t)(lo + q);
+  for (uint32_t q = 0; q < n; ++q) cand[c0 + q] = ((uint64_t)i << kJBits) | (uint64_t)(lo + q);
 }
 
 // one packed field of a radix pass: coordinate t (or -1 = problem id), minus `lo`, at bit `shift`
@@ -615,7 +615,7 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
     out->coef.push_back(cv);
   }
   if (out->zero < 0) return fail(SS_EINVAL, "0 must be in supp(a) (a_0 > 0 for a positive coefficient)");
-  if (out->size() > kMaxA) return fail(SS_ERANGE, "|supp(a)| after closing under negation exceeds 63");
+  if (out->size() > kMaxA) return fail(SS_ERANGE, "|supp(a)| after closing under negation exceeds 127");
   return SS_OK;
 }
 

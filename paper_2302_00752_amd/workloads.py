@@ -326,13 +326,12 @@ def _trig(rng, d, n_sin, n_cos, draw, coef, forbid=()):
     return fr, co, c
 
 
-def adr3d(level: int, instance: int = 0, n_b: int = 3, n_c: int = 3) -> AdrProblem:
-    """The exactly sparse 3-D ADR problem of Sec. 10.5: a = a_0 + 2 sine + 2 cosine modes, each b_j
-    and c (c with c_0) n_b resp. n_c sine + cosine modes each, f = 2 sine + 3 cosine modes; every
-    frequency uniform in [-49, 50]^3; a and f coefficients U[-1, 1], b and c coefficients U[0, 1];
-    a_0 = 4 ceil(|c_a|_2), c_0 = 4 ceil(|c_c|_2).  The paper takes 5 + 5 modes for b_j and c; the
-    union support then exceeds the 63 entries of the operator's table, so fewer are drawn by
-    default (3 + 3: 57 entries)."""
+def adr3d(level: int, instance: int = 0, n_b: int = 5, n_c: int = 5) -> AdrProblem:
+    """The exactly sparse 3-D ADR problem of Sec. 10.5 (Eq. ADRTerms): a = a_0 + 2 sine + 2 cosine
+    modes, each b_j and c (c with c_0) n_b resp. n_c sine + cosine modes each (the paper: 5 + 5,
+    the default), f = 2 sine + 3 cosine modes; every frequency uniform in [-49, 50]^3; a and f
+    coefficients U[-1, 1], b and c coefficients U[0, 1]; a_0 = 4 ceil(|c_a|_2), c_0 = 4 ceil(|c_c|_2).
+    With the paper's counts the operator has 45 terms and the union support 89 entries."""
     d = 3
     rng = np.random.Generator(np.random.PCG64(9000 + instance))
     draw = lambda: rng.integers(-49, 51, size=d)

@@ -59,7 +59,7 @@ def test_stamp_argument_errors(ss):
     assert _build(ss, 2, [[0, 0]], [[1, 1], [1, 1]])[0] == ss.SS_EINVAL          # duplicate f
     assert _build(ss, 2, [[0, 0]], [[1, 1]], level=-1)[0] == ss.SS_EINVAL        # level
     assert _build(ss, 2, [[0, 0], [-32768, 0]], [[1, 1]])[0] == ss.SS_ERANGE     # -w not in int16
-    many = [[0, 0]] + [[i, 1] for i in range(1, 40)]                             # 79 after closure
+    many = [[0, 0]] + [[i, 1] for i in range(1, 65)]                             # 129 after closure
     assert _build(ss, 2, many, [[1, 1]])[0] == ss.SS_ERANGE
 
 

@@ -85,8 +85,12 @@ def test_adr_stamp_and_apply(ss, case):
 
 @pytest.mark.parametrize("case", ["adr3d-1", "adr3d-2", "pins-1", "pins-2"])
 def test_adr_solve_matches_oracle(ss, case):
+    # adr3d: the paper's data size (45 operator terms, an 89-entry union support; at level 2 one
+    # class of about 4e4 rows, which the oracle solves by a sparse LU)
     kind, lv = case.split("-")
     p = workloads.adr3d(int(lv)) if kind == "adr3d" else _from_pins(1, int(lv))
+    if kind == "adr3d":
+        assert len(p.union()) == 89
     keys, M = oracle_of(p)
     st, op, A, dps = build(ss, [p])
     f = f_vector(ss, st, dps)

@@ -440,3 +440,55 @@ def test_empty_inputs_rejected(ss):
                                       z16.ctypes.data_as(C.POINTER(C.c_int16)),
                                       z32.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(h))
     assert st == ss.SS_EINVAL and not h.value
+
+
+def _wide_problem(d, n_modes, seed, level=1, lo=-6, hi=6):
+    # a with n_modes cosine pairs (2 n_modes + 1 table entries), l1 certificate kept
+    rng = np.random.default_rng(seed)
+    seen, modes = set(), []
+    while len(modes) < n_modes:
+        w = np.zeros(d, dtype=np.int64)
+        nz = rng.choice(d, size=min(d, 3), replace=False)
+        w[nz] = rng.integers(lo, hi + 1, size=len(nz))
+        t = tuple(int(v) for v in w)
+        if not any(t) or t in seen or tuple(-v for v in t) in seen:
+            continue
+        seen.add(t)
+        modes.append(w)
+    modes = np.array(modes)
+    amp = 0.4 / n_modes * (rng.uniform(0.5, 1.0, n_modes) * np.exp(2j * np.pi * rng.random(n_modes)))
+    af = np.concatenate([np.zeros((1, d), np.int64), modes, -modes])
+    ah = np.concatenate([[1.0], amp, np.conj(amp)])
+    fw = rng.integers(-9, 10, size=(2, d))
+    ff = np.concatenate([fw, -fw])
+    fh = np.array([1.0 + 0.5j, -0.3j, 1.0 - 0.5j, 0.3j])
+    return P(d, af, ah, ff, fh, level)
+
+
+@pytest.mark.parametrize("d", [2, 70])
+def test_wide_a_table(ss, d):
+    # 101 a-table entries (beyond 64: the neighbour map of d <= 64 looks up the upper half with the
+    # table in LDS, above 64 one wave covers a row's entries in two passes): stamp, neighbour map
+    # and solve against the oracle
+    p = _wide_problem(d, 50, seed=d)
+    af, ah = ost.canonical_a(p.a_freqs, p.a_hat)
+    assert len(af) == 101
+    keys, lev = ost.stamp(p.f_freqs, af, p.level)
+    st, op = build(ss, [p])
+    gk, gl = st.keys()
+    assert np.array_equal(gk.astype(np.int64), keys) and np.array_equal(gl.astype(np.int64), lev)
+    rp, cols, js, comp = op.csr()
+    orp, ocols, ojs = og.neighbours(keys, af)
+    assert np.array_equal(rp, orp) and np.array_equal(cols, ocols) and np.array_equal(js, ojs)
+    f = f_vector(ss, st, [p])
+    u_ref = og.solve(keys, af, ah, f)
+    for precision, tol, err in (("fp64", TOL64, ERR64), ("fp32_refine", TOL32, ERR32)):
+        u, info = gpu_solve(ss, op, f, tol, precision)
+        assert info[0]["status"] == ss.SS_OK and rel(u, u_ref) <= err, (precision, rel(u, u_ref))
+
+
+def test_a_table_limit(ss):
+    p = _wide_problem(3, 64, seed=5)        # 129 entries after closing under negation
+    with pytest.raises(ss.SparseSpecError) as e:
+        ss.Stamp.build([p])
+    assert e.value.status == ss.SS_ERANGE

@@ -123,3 +123,20 @@ def test_manufactured_solution_recovered(seed):
     M = adr.matrix(keys, af, ah, bf, bh, cf, ch)
     u = adr.solve(keys, af, ah, bf, bh, cf, ch, M @ u_star, M=M)
     assert np.linalg.norm(u - u_star) <= 1e-10 * np.linalg.norm(u_star)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_sparse_class_solve_equals_dense(seed):
+    # classes above the dense limit are solved by a sparse LU of the same block: forced on every
+    # class here (dense_limit 0), the result equals the dense LU's and a manufactured solution
+    af, ah, bf, bh, cf, ch, F = _problem(seed, d=3)
+    W = adr.support(af, bf, cf, 3)
+    keys, _ = ost.stamp(F, W, 2)
+    rng = np.random.default_rng(190 + seed)
+    u_star = rng.standard_normal(len(keys)) + 1j * rng.standard_normal(len(keys))
+    M = adr.matrix(keys, af, ah, bf, bh, cf, ch)
+    f = M @ u_star
+    u_dense = adr.solve(keys, af, ah, bf, bh, cf, ch, f, M=M)
+    u_sparse = adr.solve(keys, af, ah, bf, bh, cf, ch, f, M=M, dense_limit=0)
+    assert np.linalg.norm(u_sparse - u_dense) <= 1e-12 * np.linalg.norm(u_dense)
+    assert np.linalg.norm(u_sparse - u_star) <= 1e-10 * np.linalg.norm(u_star)
