@@ -187,6 +187,37 @@ def main():
     lattice = {"keys": st.n_total, "problems": st.n_prob, "M": lat_M, "sigma": 0.01, "ms": lat_ms,
                "keys_per_s": st.n_total / (lat_ms / 1e3), "reconstructing": int(lat_ok.sum())}
     del lat_vals
+
+    # the lattice as the neighbour index: operator builds whose lookups match lattice values (the
+    # default) against builds that compare keys (SS_EXACT_LOOKUP), at d = 10, 100 and 1024
+    def op_build_ms(stamp, problems, flags, reps=3):
+        ss.Operator.build(stamp, problems, flags).close()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            o = ss.Operator.build(stamp, problems, flags)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t))
+            o.close()
+        return float(np.median(ts))
+
+    lat_lookup = {}
+    for name, mk in (("d=10 (512 level-3 problems)", lambda: None),
+                     ("d=100 (256 level-2 problems)", lambda: ss.Batch([workloads.make(4, i) for i in range(256)])),
+                     ("d=1024 (64 high-sparsity level-2 problems)",
+                      lambda: ss.Batch([workloads.highsparsity(1024, 2, i) for i in range(64)]))):
+        bl = mk()
+        stl = st if bl is None else ss.Stamp.build(bl)
+        bl = batch if bl is None else bl
+        row = {"keys": int(stl.n_total), "key_compare_ms": op_build_ms(stl, bl, ss.SS_EXACT_LOOKUP),
+               "lattice_ms": op_build_ms(stl, bl, 0)}
+        lat_lookup[name] = row
+        log(f"operator build, {name}: keys compared {row['key_compare_ms']:.2f} ms, lattice values "
+            f"{row['lattice_ms']:.2f} ms")
+        if stl is not st:
+            stl.close()
+    lattice["neighbour_index_op_build"] = lat_lookup
     log(f"lattice: {st.n_total} keys, M {lat_M}: {lat_ms:.2f} ms, {int(lat_ok.sum())}/{st.n_prob} sets reconstructed")
     solve_ms = {}
     sols = {}

@@ -60,6 +60,7 @@ typedef enum { SS_FP64 = 0, SS_FP32_REFINE = 1 } ss_precision;
 
 /* ss_build_op flags */
 #define SS_SKIP_L1_CHECK 1u   /* accept a whose l1 certificate fails (e.g. product coefficients) */
+#define SS_EXACT_LOOKUP 2u    /* neighbour lookups compare keys, not rank-1 lattice values (see ss_build_op) */
 
 typedef struct ss_stamp ss_stamp;  /* device-resident stamping sets of a batch of problems       */
 typedef struct ss_op ss_op;        /* device-resident operator(s) L_N built on an ss_stamp        */
@@ -169,6 +170,17 @@ void ss_free_stamp(ss_stamp* st);
  */
 ss_status ss_build_op(const ss_stamp* st, const int32_t* n_a, const int16_t* a_freqs,
                       const double* a_hat, uint32_t flags, void* stream, ss_op** out);
+/* Neighbour lookups.  By default the map finds l = k - w_j in S^N by the rank-1 lattice value
+ * lat(k) = k . z mod M (Sec. 8, Definition of a reconstructing rank-1 lattice; M = 2^61 - 1 prime,
+ * z drawn once from [1, M - 1]^d by a fixed seeded generator): the map is linear, so
+ * lat(k - w_j) = lat(k) - lat(w_j) mod M comes from two stored values, and a hash-table slot whose
+ * 31-bit fingerprint matches is accepted when its key's stored lattice value equals it -- no key
+ * (2d bytes) is read.  The result is exact whenever the lattice separates S^N from the looked-up
+ * differences (the reconstructing property of Lemma RandomRank1Lattice on that set); a false
+ * match needs a distinct key with the same fingerprint and the same lattice value, probability at
+ * most 1/M per compared pair over z, below |S^N|^2 s / M (about 1e-8 at |S| = 3e4, s = 21) per
+ * problem even ignoring the fingerprint.  SS_EXACT_LOOKUP confirms every match by comparing the
+ * keys instead (deterministic, slower for large d). */
 
 /* sizes: n_total keys, n_exec rows of the execution layout (>= n_total), nnz,
  * number of independent classes summed over problems (all nullable). */

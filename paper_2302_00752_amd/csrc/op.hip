@@ -48,11 +48,14 @@ struct NbrArgs {
   const uint64_t* table;
   uint32_t* buf;       // [smax x total] compact row entries (entry q of row r at q * total + r): local canonical column | j << kColBits
   int64_t* rowlen;     // [total]
+  const uint64_t* lat;   // [total] lattice value of every key (lattice lookups)
+  const uint64_t* alat;  // [sum s] lattice value of every a-table entry
 };
 
 // One lane per (row, a-table index): look up k - w_j; a ballot over the row's lanes compacts the
 // hits to the front of the row's buffer in j order.  A table of more than 64 entries takes one wave
 // per row, its lanes covering j = 0..63, then 64..127.
+template <bool LAT>
 __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t n_blocks = ceil_div(ceil_div(a.total, a.rows_per_wave), kBlock / 64);
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
         const int16_t* k = a.keys + r * d;
         const int16_t* w = a.akeys + (int64_t)(j0 + j) * d;
         const uint64_t h = a.hash[r] - a.ahash[j0 + j];
+        const uint64_t lt = LAT ? lat_sub(a.lat[r], a.alat[j0 + j]) : 0;
         const uint64_t base = (uint64_t)a.toff[p], mask = a.tmask[p];
         uint64_t pos = slot_first(h, base, mask);
         while (true) {
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(NbrArgs a) {
           if (v == 0) break;
           if (lslot_fp_eq(v, h)) {
             const int64_t m = lslot_idx(v);
-            if (key_eq_shift(a.keys + m * d, k, w, -1, d)) {
+            if (LAT ? a.lat[m] == lt : key_eq_shift(a.keys + m * d, k, w, -1, d)) {
               col = m;
               break;
             }
@@ -144,13 +148,14 @@ __device__ inline E dense_entry(int64_t col, int j) {
   return (E)((uint32_t)col | ((uint32_t)j << kColBits));
 }
 
-template <int DMAX, bool EVEN, bool UNI, int G, typename E>
+template <int DMAX, bool EVEN, bool UNI, int G, typename E, bool LAT>
 __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, const int16_t* wtab,
                                         const uint64_t* htab) {
   const int d = a.d;
   int kr[DMAX];
   const int16_t* kp = a.keys + r * d;
-  if (EVEN) {
+  if (LAT) {   // candidates are matched by lattice value: the row's key is not needed
+  } else if (EVEN) {
 #pragma unroll
     for (int t2 = 0; t2 < DMAX / 2; ++t2) {
       const uint32_t v = 2 * t2 < d ? reinterpret_cast<const uint32_t*>(kp)[t2] : 0u;
@@ -164,6 +169,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   const int j0 = a.aoff[p], s = a.aoff[p + 1] - j0, z = a.azero[p];
   const int64_t ro = a.rowoff[p];
   const uint64_t hr = a.hash[r], base = (uint64_t)a.toff[p], mask = a.tmask[p];
+  const uint64_t lr = LAT ? a.lat[r] : 0;
   const uint64_t* table = a.table + base;   // lookup table: one word per slot
   E* D = reinterpret_cast<E*>(a.buf);
   constexpr E kNone = (E)~(E)0;
@@ -175,6 +181,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
       // (the LDS tables hold the upper half, entries z + 1 .. s - 1)
       const int16_t* w = UNI ? wtab + (j - z - 1) * d : a.akeys + (int64_t)(j0 + j) * d;
       const uint64_t h = hr - (UNI ? htab[j - z - 1] : a.ahash[j0 + j]);
+      const uint64_t lt = LAT ? lat_sub(lr, a.alat[j0 + j]) : 0;
       const uint64_t pos = fmix64(h) & mask;
       const uint64_t g0 = pos & ~(uint64_t)(G - 1);   // regions are multiples of 64 slots: aligned
       uint64_t sv[G];
@@ -200,7 +207,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
       uint64_t next = g0 + G;    // where a probe sequence that left the group resumes
       if (cand >= 0) {
         const int64_t c = lslot_idx(cv);
-        if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
+        if (LAT ? a.lat[c] == lt : key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
           m = c;
           stop = true;
         } else {
@@ -215,7 +222,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
           if (v == 0) break;
           if (lslot_fp_eq(v, h)) {
             const int64_t c = lslot_idx(v);
-            if (key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
+            if (LAT ? a.lat[c] == lt : key_is_shift<DMAX, EVEN>(a.keys + c * d, kr, w, d)) {
               m = c;
               break;
             }
@@ -270,7 +277,7 @@ __global__ void k_csr_from_dense(int64_t total, const E* __restrict__ D, const i
   }
 }
 
-template <int DMAX, bool EVEN, typename E>
+template <int DMAX, bool EVEN, typename E, bool LAT>
 __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
   // the upper half of a mirrored table: at most (kMaxA - 1) / 2 entries
   __shared__ int16_t s_w[kBlock / 64][(kMaxA / 2) * DMAX];
@@ -283,16 +290,17 @@ __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
   const bool uni = pu >= 0 && __all(!live || p == pu);
   if (uni) {
     const int j1 = a.aoff[pu] + a.azero[pu] + 1, nh = a.aoff[pu + 1] - j1;
-    for (int i = lane; i < nh * a.d; i += 64) s_w[wv][i] = a.akeys[(int64_t)j1 * a.d + i];
+    if (!LAT)   // (lattice matches need no key)
+      for (int i = lane; i < nh * a.d; i += 64) s_w[wv][i] = a.akeys[(int64_t)j1 * a.d + i];
     for (int i = lane; i < nh; i += 64) s_h[wv][i] = a.ahash[j1 + i];
   }
   __syncthreads();
   if (!live) return;
   constexpr int G = kNbrGroup;
   if (uni)
-    nbr_row<DMAX, EVEN, true, G, E>(a, r, p, s_w[wv], s_h[wv]);
+    nbr_row<DMAX, EVEN, true, G, E, LAT>(a, r, p, s_w[wv], s_h[wv]);
   else
-    nbr_row<DMAX, EVEN, false, G, E>(a, r, p, nullptr, nullptr);
+    nbr_row<DMAX, EVEN, false, G, E, LAT>(a, r, p, nullptr, nullptr);
 }
 
 __global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
@@ -568,7 +576,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   for (int p = 0; p < n_prob; ++p) max_rows = std::max(max_rows, st->row_off[p + 1] - st->row_off[p]);
   const bool narrow = max_rows < 65535;   // 16-bit dense entries (0xffff = absent)
   // the mirrored half needs w_{s-1-j} = -w_j with w_z = 0 at z = (s-1)/2 in every a-table
-  bool dense = d <= 64;
+  // lattice matches read no key, so the row-per-lane kernel then serves any d
+  const bool lat = (flags & SS_EXACT_LOOKUP) == 0;
+  bool dense = d <= 64 || lat;
   for (int p = 0; dense && p < n_prob; ++p) {
     const int s = st->a_off[p + 1] - st->a_off[p];
     const int16_t* ak = st->a_keys.data() + (int64_t)st->a_off[p] * d;
@@ -584,7 +594,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(rowlen);
   const int rpw = smax <= 64 ? 64 / smax : 1;
   NbrArgs na{total, d, smax, rpw, st->d_keys, st->d_hash, st->d_pid, st->d_rowoff, st->d_akeys, st->d_ahash,
-             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen};
+             st->d_aoff, st->d_azero, st->d_toff, st->d_tmask, st->d_ltable, nbr, rowlen, st->d_lat, st->d_alat};
   if (dense) {
     int zmax = 0;
     for (int p = 0; p < n_prob; ++p) zmax = std::max(zmax, st->a_zero[p]);
@@ -593,20 +603,25 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     const bool even = d % 2 == 0;
     auto launch = [&](auto entry) {
       using E = decltype(entry);
-      if (d <= 8)
-        even ? k_neighbors_row<8, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<8, false, E><<<g, kBlock, 0, stream>>>(na);
+      if (lat)
+        k_neighbors_row<8, true, E, true><<<g, kBlock, 0, stream>>>(na);   // no key is read: any d
+      else if (d <= 8)
+        even ? k_neighbors_row<8, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<8, false, E, false><<<g, kBlock, 0, stream>>>(na);
       else if (d <= 16)
-        even ? k_neighbors_row<16, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false, E><<<g, kBlock, 0, stream>>>(na);
+        even ? k_neighbors_row<16, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<16, false, E, false><<<g, kBlock, 0, stream>>>(na);
       else if (d <= 32)
-        even ? k_neighbors_row<32, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false, E><<<g, kBlock, 0, stream>>>(na);
+        even ? k_neighbors_row<32, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false, E, false><<<g, kBlock, 0, stream>>>(na);
       else
-        even ? k_neighbors_row<64, true, E><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false, E><<<g, kBlock, 0, stream>>>(na);
+        even ? k_neighbors_row<64, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false, E, false><<<g, kBlock, 0, stream>>>(na);
       k_row_count<E><<<g, kBlock, 0, stream>>>(total, reinterpret_cast<const E*>(nbr), st->d_pid, st->d_aoff, rowlen);
     };
     if (narrow) launch(uint16_t{});
     else launch(uint32_t{});
   } else {
-    k_neighbors<<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
+    if (lat)
+      k_neighbors<true><<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
+    else
+      k_neighbors<false><<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
   }
   SS_TRY(dalloc(&op->d_crow, total + 1));
   {

@@ -103,6 +103,25 @@ __host__ __device__ inline uint64_t slot_next(uint64_t pos, uint64_t base, uint6
   return base + ((pos - base + 1) & mask);
 }
 
+// Rank-1 lattice values (Sec. 8, Definition of a reconstructing rank-1 lattice): k . z mod M with
+// the prime M = 2^61 - 1 and z drawn uniformly from [1, M - 1]^d.  The map is linear,
+// lat(k - w) = lat(k) - lat(w) mod M, so the value of a neighbour k - w_j follows from two stored
+// values without reading a key; two distinct keys share a value with probability 1 / M over z
+// (Lemma RandomRank1Lattice's argument).
+constexpr uint64_t kLatM = (uint64_t(1) << 61) - 1;
+__host__ __device__ inline uint64_t lat_fold(uint64_t r) {   // r < 2^63 -> r mod M
+  r = (r & kLatM) + (r >> 61);
+  return r >= kLatM ? r - kLatM : r;
+}
+__host__ __device__ inline uint64_t lat_mulmod(uint64_t a, uint64_t b) {   // a, b < M
+  const unsigned __int128 p = (unsigned __int128)a * b;                    // < 2^122
+  const uint64_t hi = (uint64_t)(p >> 64), lo = (uint64_t)p;               // 2^64 = 8 mod M
+  return lat_fold((hi << 3) + (lo & kLatM) + (lo >> 61));
+}
+__host__ __device__ inline uint64_t lat_add(uint64_t a, uint64_t b) { return lat_fold(a + b); }
+__host__ __device__ inline uint64_t lat_sub(uint64_t a, uint64_t b) { return lat_fold(a + (kLatM - b)); }
+__host__ __device__ inline uint64_t lat_of_coord(int v) { return v >= 0 ? (uint64_t)v : kLatM - (uint64_t)(-v); }
+
 inline uint64_t splitmix64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ULL;
   x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -145,6 +164,9 @@ struct StampImpl {
   int64_t n_f = 0;                     // forcing frequencies given to the build (all problems)
   uint32_t* d_fslot = nullptr;         // [n_f] canonical slot of each, in the order given
   uint64_t* d_coef = nullptr;          // [d] hash multipliers
+  uint64_t* d_latz = nullptr;          // [d] rank-1 lattice generating vector (entries in [1, M - 1])
+  uint64_t* d_lat = nullptr;           // [total] lattice value k . z mod M of every key
+  uint64_t* d_alat = nullptr;          // [sum s] lattice value of every a-table entry
   uint64_t* d_table = nullptr;         // build only: one word per slot (MAIN / CAND words)
   uint64_t* d_ltable = nullptr;        // lookups: one word per slot, the same positions:
                                        // (hash >> 32) << 32 | (canonical index + 1), 0 = empty

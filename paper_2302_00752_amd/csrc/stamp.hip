@@ -44,6 +44,20 @@ std::vector<uint64_t> hash_coefs(int d) {
   return z;
 }
 
+// the lattice generating vector: entries drawn from [1, M - 1] by a fixed seeded generator
+std::vector<uint64_t> lattice_z(int d) {
+  std::vector<uint64_t> z(d);
+  for (int t = 0; t < d; ++t) z[t] = 1 + splitmix64(0x1a77ce00ULL + (uint64_t)t * 104729u) % (kLatM - 1);
+  return z;
+}
+
+__host__ __device__ inline uint64_t lat_of_key(const int16_t* k, const uint64_t* z, int d) {
+  uint64_t acc = 0;
+  for (int t = 0; t < d; ++t)
+    if (k[t] != 0) acc = lat_add(acc, lat_mulmod(lat_of_coord(k[t]), z[t]));
+  return acc;
+}
+
 __device__ inline uint64_t atomic_load_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -163,7 +177,7 @@ __global__ void k_winners(int64_t n_cand, const uint32_t* __restrict__ n_act, co
 
 __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                          int64_t base, int16_t* keys_out, uint64_t* hash_out, int32_t* pid_out,
-                         int64_t* root, uint8_t* last_out) {
+                         int64_t* root, uint8_t* last_out, uint64_t* wide_src) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)*a.n_act || !flag[t]) return;
   const uint64_t c = a.cand[t];
@@ -176,7 +190,9 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   const int16_t* k = a.keys + i * d;
   const int16_t* w = a.wkeys + (int64_t)(wo + j) * d;
   int16_t* o = keys_out + m * d;
-  if ((d & 1) == 0) {   // rows are 4-byte aligned: two coordinates per load and store
+  if (wide_src) {       // long rows: k_append_keys_wide copies them, a wavefront per row
+    wide_src[m - base] = c;
+  } else if ((d & 1) == 0) {   // rows are 4-byte aligned: two coordinates per load and store
     const uint32_t* k32 = reinterpret_cast<const uint32_t*>(k);
     const uint32_t* w32 = reinterpret_cast<const uint32_t*>(w);
     uint32_t* o32 = reinterpret_cast<uint32_t*>(o);
@@ -196,6 +212,26 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
   root[m] = root[i];
   const uint64_t s = (uint64_t)a.toff[p] + a.cpos[t];
   a.table[s] = main_word(h, (uint64_t)m);
+}
+
+// The new key rows of a level for large d: row base + m = parent key + w_j (source word
+// wide_src[m] = parent << kJBits | j), one wavefront per row with its lanes over the coordinates,
+// so every load and store of a row is contiguous across the lanes.
+__global__ __launch_bounds__(kBlock) void k_append_keys_wide(int64_t n_new, int64_t base, int d,
+                                                             const uint64_t* __restrict__ wide_src,
+                                                             const int32_t* __restrict__ pid,
+                                                             const int32_t* __restrict__ woff,
+                                                             const int16_t* __restrict__ wkeys, int16_t* keys) {
+  const int64_t m = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (m >= n_new) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t c = wide_src[m];
+  const int64_t i = (int64_t)(c >> kJBits);
+  const int j = (int)(c & kJMask);
+  const int16_t* k = keys + i * d;
+  const int16_t* w = wkeys + (int64_t)(woff[pid[i]] + j) * d;
+  int16_t* o = keys + (base + m) * d;
+  for (int u = lane; u < d; u += 64) o[u] = (int16_t)((int)k[u] + (int)w[u]);
 }
 
 // new keys per problem of the level just built (candidates are grouped by problem)
@@ -263,6 +299,25 @@ __global__ void k_digits(int64_t n, int d, const int16_t* __restrict__ keys, con
   out[r] = v;
 }
 
+// Every least-significant-first word of every row at once, a thread per (row, pass): a pass packs
+// consecutive coordinates, so the threads of a row read it contiguously; out[q * n + r].
+__global__ void k_digits_all(int64_t n, int n_pass, int d, const int16_t* __restrict__ keys,
+                             const int32_t* __restrict__ pid, const Field* __restrict__ fields,
+                             const int2* __restrict__ prange, uint64_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * n_pass) return;
+  const int64_t r = g / n_pass;
+  const int q = (int)(g % n_pass);
+  const int16_t* k = keys + r * d;
+  uint64_t v = 0;
+  for (int f = prange[q].x; f < prange[q].y; ++f) {
+    const Field F = fields[f];
+    const int val = F.t >= 0 ? (int)k[F.t] : pid[r];
+    v |= (uint64_t)(uint32_t)(val - F.lo) << F.shift;
+  }
+  out[(int64_t)q * n + r] = v;
+}
+
 // flag = 1 if two neighbours of the sorted words are equal
 __global__ void k_adjacent_ties(int64_t n, const uint64_t* __restrict__ w, int32_t* flag) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,6 +335,61 @@ __global__ void k_iota_u32(int64_t n, uint32_t* p) {
   if (i < n) p[i] = (uint32_t)i;
 }
 
+// 64-bit sums over a wavefront (two 32-bit shuffles per step)
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return (uint64_t)hi << 32 | lo;
+}
+
+// k_permute_rows for large d: one wavefront per sorted row, its lanes over the coordinates (the
+// source row and the output row are read and written contiguously); hash, |k|^2 and lattice value
+// summed over the lanes.
+__global__ __launch_bounds__(kBlock) void k_permute_rows_wide(
+    int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
+    const uint64_t* __restrict__ words, int pid_shift, int pid_bits, const int64_t* __restrict__ lstart, int n_lev,
+    const uint64_t* __restrict__ z, const uint64_t* __restrict__ lz, int16_t* __restrict__ keys, uint64_t* hash,
+    uint64_t* lat, int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv, unsigned long long* max_norm) {
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  int64_t nn = 0;
+  if (r < n) {
+    const int64_t s = perm[r];
+    const int16_t* src = ukeys + s * d;
+    int16_t* dst = keys + r * d;
+    uint64_t h = 0, lv_ = 0;
+    for (int t = lane; t < d; t += 64) {
+      const int v = src[t];
+      dst[t] = (int16_t)v;
+      h += (uint64_t)(int64_t)v * z[t];
+      nn += (int64_t)v * v;
+      if (v) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord(v), lz[t]));
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+      h += shfl_xor_u64(h, m);
+      nn += (int64_t)shfl_xor_u64((uint64_t)nn, m);
+      lv_ = lat_add(lv_, shfl_xor_u64(lv_, m));
+    }
+    if (lane == 0) {
+      int lvl = 0;
+      for (int q = 1; q < n_lev; ++q) lvl = lstart[q] <= s ? q : lvl;
+      hash[r] = h;
+      lat[r] = lv_;
+      pid[r] = pid_bits > 0 ? (int32_t)((words[r] >> pid_shift) & ((uint64_t(1) << pid_bits) - 1)) : 0;
+      lev[r] = (uint8_t)lvl;
+      norm[r] = nn;
+      inv[s] = (uint32_t)r;
+    }
+  }
+  __shared__ int64_t wmax[kBlock / 64];
+  if (lane == 0) wmax[threadIdx.x >> 6] = nn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t m = wmax[0];
+    for (int q = 1; q < kBlock / 64; ++q) m = wmax[q] > m ? wmax[q] : m;
+    atomicMax(max_norm, (unsigned long long)m);
+  }
+}
+
 // sorted key rows: one thread per (row, coordinate), so reads of a source row and the
 // writes of the output are contiguous across neighbouring threads
 // Sorted row r from unsorted row perm[r]: the key (copied in 32-bit words when d is even); the
@@ -290,15 +400,16 @@ __global__ void k_iota_u32(int64_t n, uint32_t* p) {
 __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
                                const uint64_t* __restrict__ words, int pid_shift, int pid_bits,
                                const int64_t* __restrict__ lstart, int n_lev, const uint64_t* __restrict__ z,
-                               int16_t* __restrict__ keys, uint64_t* hash, int32_t* pid, uint8_t* lev, int64_t* norm,
-                               uint32_t* inv, unsigned long long* max_norm) {
+                               const uint64_t* __restrict__ lz, int16_t* __restrict__ keys, uint64_t* hash,
+                               uint64_t* lat, int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv,
+                               unsigned long long* max_norm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = 0;
   if (r < n) {
     const int64_t s = perm[r];
     const int16_t* src = ukeys + s * d;
     int16_t* dst = keys + r * d;
-    uint64_t h = 0;
+    uint64_t h = 0, lv_ = 0;
     if ((d & 1) == 0) {
       const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
       uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
@@ -308,6 +419,8 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
         const int64_t lo = (int16_t)(w & 0xffffu), hi = (int16_t)(w >> 16);
         h += (uint64_t)lo * z[t] + (uint64_t)hi * z[t + 1];
         nn += lo * lo + hi * hi;
+        if (lo) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)lo), lz[t]));
+        if (hi) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)hi), lz[t + 1]));
       }
     } else {
       for (int t = 0; t < d; ++t) {
@@ -315,8 +428,10 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
         dst[t] = (int16_t)v;
         h += (uint64_t)v * z[t];
         nn += v * v;
+        if (v) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)v), lz[t]));
       }
     }
+    lat[r] = lv_;
     int lv = 0;
     for (int q = 1; q < n_lev; ++q) lv = lstart[q] <= s ? q : lv;
     hash[r] = h;
@@ -492,6 +607,10 @@ struct Scratch {
   }
 };
 
+// Rows of at least this many coordinates are copied a wavefront per row (contiguous loads and
+// stores across the lanes) rather than a thread per row.
+constexpr int kWideD = 32;
+
 // Slots per key when a region is sized: a load factor of at most 1/4 keeps linear-probe
 // sequences short (a lookup costs a cache line per probe; the lanes of a wave wait for the
 // longest sequence among them).  A region is grown when it would pass a load of 1/2.
@@ -636,8 +755,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 
   // ---- host: canonical a-tables, validation
   const std::vector<uint64_t> z = hash_coefs(d);
+  const std::vector<uint64_t> lz = lattice_z(d);
   std::vector<int16_t> wkeys;
-  std::vector<uint64_t> ahash, whash;
+  std::vector<uint64_t> ahash, whash, alat;
   std::vector<int64_t> anorm;
   std::vector<int32_t> woff(n_prob + 1, 0), f_off(n_prob + 1, 0), s_of(n_prob);
   int max_level = 0, smax1 = 1;
@@ -668,6 +788,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       }
       ahash.push_back(h);
       anorm.push_back(nn);
+      alat.push_back(lat_of_key(kj, lz.data(), d));
       if (j != at.zero) {
         wkeys.insert(wkeys.end(), kj, kj + d);
         whash.push_back(h);
@@ -714,6 +835,10 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&st->d_aoff, n_prob + 1));
   SS_TRY(dalloc(&st->d_azero, n_prob));
   SS_TRY(dalloc(&st->d_coef, d));
+  SS_TRY(dalloc(&st->d_latz, d));
+  SS_TRY(dalloc(&st->d_alat, alat.size()));
+  SS_HIP(h2d(st->d_latz, lz.data(), d * 8, stream));
+  SS_HIP(h2d(st->d_alat, alat.data(), alat.size() * 8, stream));
   SS_HIP(h2d(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, stream));
   SS_HIP(h2d(st->d_ahash, ahash.data(), ahash.size() * 8, stream));
   SS_HIP(h2d(st->d_anorm, anorm.data(), anorm.size() * 8, stream));
@@ -734,12 +859,14 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   int64_t* uroot = nullptr;
   uint32_t *cpos = nullptr, *flag = nullptr, *idx = nullptr, *ccnt = nullptr, *coff = nullptr;
   uint64_t* cand = nullptr;
+  uint64_t* wsrc = nullptr;              // large d: source words of a level's new rows
+  const bool wide = d >= kWideD;
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev);
   sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot);
   sc.hold(ulast); sc.hold(d_full);
-  sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp); sc.hold(ccnt); sc.hold(coff); sc.hold(cand);
+  sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp); sc.hold(ccnt); sc.hold(coff); sc.hold(cand); sc.hold(wsrc);
   sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
   SS_TRY(dalloc(&wk, wkeys.size()));
   SS_TRY(dalloc(&wh, whash.size()));
@@ -830,11 +957,13 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       sc.retire(flag);
       sc.retire(idx);
       sc.retire(cand);
+      sc.retire(wsrc);
       ccap = n_cand;
       SS_TRY(dalloc(&cpos, ccap));
       SS_TRY(dalloc(&flag, ccap));
       SS_TRY(dalloc(&idx, ccap));
       SS_TRY(dalloc(&cand, ccap));
+      if (wide) SS_TRY(dalloc(&wsrc, ccap));
     }
     if (n_front + 1 > fcap) {
       sc.retire(ccnt);
@@ -903,7 +1032,14 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_expand<<<cg, kBlock, 0, stream>>>(ea);
       SS_TRY(count_level());
     }
-    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, ulast);
+    k_append<<<cg, kBlock, 0, stream>>>(ea, flag, idx, total, ukeys, uhash, upid, uroot, ulast, wide ? wsrc : nullptr);
+    if (wide) {
+      int64_t n_new = 0;
+      for (int p = 0; p < n_prob; ++p) n_new += added[p];
+      if (n_new > 0)
+        k_append_keys_wide<<<(unsigned)ceil_div(n_new * 64, kBlock), kBlock, 0, stream>>>(n_new, total, d, wsrc, upid,
+                                                                                           wo, wk, ukeys);
+    }
     f0 = total;
     lstart.push_back(total);
     for (int p = 0; p < n_prob; ++p) {
@@ -1016,9 +1152,29 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   }
   uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
   sc.hold(wq);
-  if (passes.size() > 1 && !done) SS_TRY(dalloc(&wq, total));
+  // long rows: every pass's words formed in one read of the keys (the per-pass form would read a
+  // row's cache lines once per pass), when they fit 2 GiB
+  const int np_ = (int)passes.size();
+  const bool all_words = !done && np_ > 1 && wide && (int64_t)np_ * total * 8 <= (int64_t(1) << 31);
+  if (all_words) {
+    std::vector<int2> pr(np_);
+    for (int q = 0; q < np_; ++q) pr[q] = make_int2(passes[q].first, passes[q].second);
+    int2* d_pr = nullptr;
+    sc.hold(d_pr);
+    SS_TRY(dalloc(&d_pr, np_));
+    SS_HIP(h2d(d_pr, pr.data(), np_ * sizeof(int2), stream));
+    SS_TRY(dalloc(&wq, (size_t)np_ * total));
+    k_digits_all<<<(unsigned)ceil_div((int64_t)np_ * total, kBlock), kBlock, 0, stream>>>(total, np_, d, ukeys, upid,
+                                                                                           d_fields, d_pr, wq);
+  } else if (passes.size() > 1 && !done) {
+    SS_TRY(dalloc(&wq, total));
+  }
   for (size_t q = 0; q < passes.size() && !done; ++q) {
-    if (q == 0) {
+    const uint64_t* kin = k64;
+    if (all_words) {
+      if (q == 0) kin = wq;
+      else k_gather_u64<<<grid_for(total), kBlock, 0, stream>>>(total, perm, wq + q * total, k64);
+    } else if (q == 0) {
       k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, passes[q].first,
                                                        passes[q].second, k64);
     } else {
@@ -1027,13 +1183,14 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_gather_u64<<<grid_for(total), kBlock, 0, stream>>>(total, perm, wq, k64);
     }
     size_t tb = tmp_bytes;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, pass_bits[q], stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, k64b, perm, perm2, total, 0, pass_bits[q], stream));
     std::swap(perm, perm2);
   }
 
   // ---- final arrays in canonical order; re-point the hash table at them
   SS_TRY(dalloc(&st->d_keys, (size_t)total * d));
   SS_TRY(dalloc(&st->d_hash, total));
+  SS_TRY(dalloc(&st->d_lat, total));
   SS_TRY(dalloc(&st->d_pid, total));
   SS_TRY(dalloc(&st->d_lev, total));
   SS_TRY(dalloc(&st->d_norm, total));
@@ -1049,9 +1206,15 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   sc.hold(d_lstart);
   SS_TRY(dalloc(&d_lstart, lstart.size()));
   SS_HIP(h2d(d_lstart, lstart.data(), lstart.size() * sizeof(int64_t), stream));
-  k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart,
-                                                         (int)lstart.size(), st->d_coef, st->d_keys, st->d_hash,
-                                                         st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  if (wide)
+    k_permute_rows_wide<<<(unsigned)ceil_div(total * 64, kBlock), kBlock, 0, stream>>>(
+        total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart, (int)lstart.size(), st->d_coef, st->d_latz,
+        st->d_keys, st->d_hash, st->d_lat, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
+  else
+    k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart,
+                                                           (int)lstart.size(), st->d_coef, st->d_latz, st->d_keys,
+                                                           st->d_hash, st->d_lat, st->d_pid, st->d_lev, st->d_norm,
+                                                           inv, d_maxn);
   k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   // the forcing frequencies are the first nF unsorted keys, in the order given
   st->n_f = nF;
@@ -1103,6 +1266,9 @@ void free_stamp_impl(StampImpl* st) {
   dfree(st->d_root);
   dfree(st->d_rowoff);
   dfree(st->d_coef);
+  dfree(st->d_latz);
+  dfree(st->d_lat);
+  dfree(st->d_alat);
   dfree(st->d_table);
   dfree(st->d_ltable);
   dfree(st->d_toff);

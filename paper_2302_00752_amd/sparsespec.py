@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libsparsespec.so")
 SS_OK, SS_EINVAL, SS_ENOMEM, SS_ERANGE, SS_ENOTPD, SS_ENOCONV, SS_EBREAKDOWN, SS_EDEVICE = range(8)
 SS_FP64, SS_FP32_REFINE = 0, 1
 SS_SKIP_L1_CHECK = 1
+SS_EXACT_LOOKUP = 2
 STATUS_NAMES = {0: "SS_OK", 1: "SS_EINVAL", 2: "SS_ENOMEM", 3: "SS_ERANGE", 4: "SS_ENOTPD",
                 5: "SS_ENOCONV", 6: "SS_EBREAKDOWN", 7: "SS_EDEVICE"}
 PRECISION = {"fp64": SS_FP64, "fp32_refine": SS_FP32_REFINE, SS_FP64: SS_FP64, SS_FP32_REFINE: SS_FP32_REFINE}
