@@ -215,23 +215,39 @@ __global__ void k_append(ExpandArgs a, const uint32_t* __restrict__ flag, const 
 }
 
 // The new key rows of a level for large d: row base + m = parent key + w_j (source word
-// wide_src[m] = parent << kJBits | j), one wavefront per row with its lanes over the coordinates,
-// so every load and store of a row is contiguous across the lanes.
+// wide_src[m] = parent << kJBits | j).  Each wavefront walks rows (grid-stride), its lanes over
+// the row's coordinates, two per 32-bit word when d is even, so every load and store of a row is
+// contiguous across the lanes.
+constexpr unsigned kWideGrid = 2048;   // blocks of the grid-stride wide-row kernels (8 per CU)
+
 __global__ __launch_bounds__(kBlock) void k_append_keys_wide(int64_t n_new, int64_t base, int d,
                                                              const uint64_t* __restrict__ wide_src,
                                                              const int32_t* __restrict__ pid,
                                                              const int32_t* __restrict__ woff,
                                                              const int16_t* __restrict__ wkeys, int16_t* keys) {
-  const int64_t m = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (m >= n_new) return;
   const int lane = threadIdx.x & 63;
-  const uint64_t c = wide_src[m];
-  const int64_t i = (int64_t)(c >> kJBits);
-  const int j = (int)(c & kJMask);
-  const int16_t* k = keys + i * d;
-  const int16_t* w = wkeys + (int64_t)(woff[pid[i]] + j) * d;
-  int16_t* o = keys + (base + m) * d;
-  for (int u = lane; u < d; u += 64) o[u] = (int16_t)((int)k[u] + (int)w[u]);
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t m = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < n_new; m += waves) {
+    const uint64_t c = wide_src[m];
+    const int64_t i = (int64_t)(c >> kJBits);
+    const int j = (int)(c & kJMask);
+    const int16_t* k = keys + i * d;
+    const int16_t* w = wkeys + (int64_t)(woff[pid[i]] + j) * d;
+    int16_t* o = keys + (base + m) * d;
+    if ((d & 1) == 0) {
+      const uint32_t* k32 = reinterpret_cast<const uint32_t*>(k);
+      const uint32_t* w32 = reinterpret_cast<const uint32_t*>(w);
+      uint32_t* o32 = reinterpret_cast<uint32_t*>(o);
+      for (int u = lane; u < d / 2; u += 64) {
+        const uint32_t x = k32[u], y = w32[u];
+        const uint32_t lo = (uint32_t)(uint16_t)((int16_t)(x & 0xffffu) + (int16_t)(y & 0xffffu));
+        const uint32_t hi = (uint32_t)(uint16_t)((int16_t)(x >> 16) + (int16_t)(y >> 16));
+        o32[u] = lo | (hi << 16);
+      }
+    } else {
+      for (int u = lane; u < d; u += 64) o[u] = (int16_t)((int)k[u] + (int)w[u]);
+    }
+  }
 }
 
 // new keys per problem of the level just built (candidates are grouped by problem)
@@ -341,18 +357,19 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
   return (uint64_t)hi << 32 | lo;
 }
 
-// k_permute_rows for large d: one wavefront per sorted row, its lanes over the coordinates (the
-// source row and the output row are read and written contiguously); hash, |k|^2 and lattice value
-// summed over the lanes.
+// k_permute_rows for large d: each wavefront walks sorted rows (grid-stride), its lanes over the
+// coordinates (the source row and the output row are read and written contiguously); hash, |k|^2
+// and lattice value summed over the lanes; one atomic per block for the largest |k|^2.
 __global__ __launch_bounds__(kBlock) void k_permute_rows_wide(
     int64_t n, int d, const uint32_t* __restrict__ perm, const int16_t* __restrict__ ukeys,
     const uint64_t* __restrict__ words, int pid_shift, int pid_bits, const int64_t* __restrict__ lstart, int n_lev,
     const uint64_t* __restrict__ z, const uint64_t* __restrict__ lz, int16_t* __restrict__ keys, uint64_t* hash,
     uint64_t* lat, int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv, unsigned long long* max_norm) {
-  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  int64_t nn = 0;
-  if (r < n) {
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  int64_t nmax = 0;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += waves) {
+    int64_t nn = 0;
     const int64_t s = perm[r];
     const int16_t* src = ukeys + s * d;
     int16_t* dst = keys + r * d;
@@ -379,9 +396,10 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows_wide(
       norm[r] = nn;
       inv[s] = (uint32_t)r;
     }
+    nmax = nn > nmax ? nn : nmax;
   }
   __shared__ int64_t wmax[kBlock / 64];
-  if (lane == 0) wmax[threadIdx.x >> 6] = nn;
+  if (lane == 0) wmax[threadIdx.x >> 6] = nmax;
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t m = wmax[0];
@@ -390,8 +408,6 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows_wide(
   }
 }
 
-// sorted key rows: one thread per (row, coordinate), so reads of a source row and the
-// writes of the output are contiguous across neighbouring threads
 // Sorted row r from unsorted row perm[r]: the key (copied in 32-bit words when d is even); the
 // problem id from the top bits of the row's sorted word; the level from where the unsorted row
 // lies (levels were appended in order: level n holds rows [lstart[n], lstart[n+1])); hash and
@@ -1037,8 +1053,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       int64_t n_new = 0;
       for (int p = 0; p < n_prob; ++p) n_new += added[p];
       if (n_new > 0)
-        k_append_keys_wide<<<(unsigned)ceil_div(n_new * 64, kBlock), kBlock, 0, stream>>>(n_new, total, d, wsrc, upid,
-                                                                                           wo, wk, ukeys);
+        k_append_keys_wide<<<(unsigned)std::min<int64_t>(kWideGrid, ceil_div(n_new * 64, kBlock)), kBlock, 0,
+                             stream>>>(n_new, total, d, wsrc, upid, wo, wk, ukeys);
     }
     f0 = total;
     lstart.push_back(total);
@@ -1130,15 +1146,38 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(pool_alloc((void**)&tmp, tmp_bytes));
   }
   bool done = false;
+  uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
+  sc.hold(wq);
+  // long rows: every pass's words (and the most-significant word) formed in one read of the keys
+  // (the per-pass form would read a row's cache lines once per pass), when they fit 2 GiB
+  const int np_ = (int)passes.size();
+  const int nw_ = np_ + (top_bits > 0 ? 1 : 0);
+  const bool all_words = np_ > 1 && wide && (int64_t)nw_ * total * 8 <= (int64_t(1) << 31);
+  if (all_words) {
+    std::vector<int2> pr(nw_);
+    for (int q = 0; q < np_; ++q) pr[q] = make_int2(passes[q].first, passes[q].second);
+    if (top_bits > 0) pr[np_] = make_int2(nf, (int)fields.size());
+    int2* d_pr = nullptr;
+    sc.hold(d_pr);
+    SS_TRY(dalloc(&d_pr, nw_));
+    SS_HIP(h2d(d_pr, pr.data(), nw_ * sizeof(int2), stream));
+    SS_TRY(dalloc(&wq, (size_t)nw_ * total));
+    k_digits_all<<<(unsigned)ceil_div((int64_t)nw_ * total, kBlock), kBlock, 0, stream>>>(total, nw_, d, ukeys, upid,
+                                                                                           d_fields, d_pr, wq);
+  }
   if (top_bits > 0) {
     int32_t* d_tie = nullptr;
     sc.hold(d_tie);
     SS_TRY(dalloc(&d_tie, 1));
     SS_HIP(hipMemsetAsync(d_tie, 0, 4, stream));
-    k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, nf,
-                                                     (int)fields.size(), k64);
+    const uint64_t* kin = k64;
+    if (all_words)
+      kin = wq + (int64_t)np_ * total;
+    else
+      k_digits<<<grid_for(total), kBlock, 0, stream>>>(total, d, ukeys, upid, nullptr, d_fields, nf,
+                                                       (int)fields.size(), k64);
     size_t tb = tmp_bytes;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64, k64b, perm, perm2, total, 0, top_bits, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, k64b, perm, perm2, total, 0, top_bits, stream));
     k_adjacent_ties<<<grid_for(total), kBlock, 0, stream>>>(total, k64b, d_tie);
     int32_t tie = 1;
     SS_HIP(hipMemcpyAsync(&tie, d_tie, 4, hipMemcpyDeviceToHost, stream));
@@ -1150,25 +1189,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
     }
   }
-  uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
-  sc.hold(wq);
-  // long rows: every pass's words formed in one read of the keys (the per-pass form would read a
-  // row's cache lines once per pass), when they fit 2 GiB
-  const int np_ = (int)passes.size();
-  const bool all_words = !done && np_ > 1 && wide && (int64_t)np_ * total * 8 <= (int64_t(1) << 31);
-  if (all_words) {
-    std::vector<int2> pr(np_);
-    for (int q = 0; q < np_; ++q) pr[q] = make_int2(passes[q].first, passes[q].second);
-    int2* d_pr = nullptr;
-    sc.hold(d_pr);
-    SS_TRY(dalloc(&d_pr, np_));
-    SS_HIP(h2d(d_pr, pr.data(), np_ * sizeof(int2), stream));
-    SS_TRY(dalloc(&wq, (size_t)np_ * total));
-    k_digits_all<<<(unsigned)ceil_div((int64_t)np_ * total, kBlock), kBlock, 0, stream>>>(total, np_, d, ukeys, upid,
-                                                                                           d_fields, d_pr, wq);
-  } else if (passes.size() > 1 && !done) {
-    SS_TRY(dalloc(&wq, total));
-  }
+  if (!all_words && passes.size() > 1 && !done) SS_TRY(dalloc(&wq, total));
   for (size_t q = 0; q < passes.size() && !done; ++q) {
     const uint64_t* kin = k64;
     if (all_words) {
@@ -1207,7 +1228,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&d_lstart, lstart.size()));
   SS_HIP(h2d(d_lstart, lstart.data(), lstart.size() * sizeof(int64_t), stream));
   if (wide)
-    k_permute_rows_wide<<<(unsigned)ceil_div(total * 64, kBlock), kBlock, 0, stream>>>(
+    k_permute_rows_wide<<<(unsigned)std::min<int64_t>(kWideGrid, ceil_div(total * 64, kBlock)), kBlock, 0, stream>>>(
         total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart, (int)lstart.size(), st->d_coef, st->d_latz,
         st->d_keys, st->d_hash, st->d_lat, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   else
