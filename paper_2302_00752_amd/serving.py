@@ -184,7 +184,7 @@ def _padded(p, d: int):
 def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 0, iters_per_tick: int = 4,
           build_threads: int = 2, ready_depth: int = 16, tol64: float = 1e-10, tol32: float = 1e-9,
           max_iter: int = 2000, keep_results: bool = False, realtime: bool = True, flags_for=None,
-          max_group: int = 8):
+          max_group: int = 64):
     """Serve ``requests`` (objects with ``d, a_freqs, a_hat, f_freqs, f_hat, level,
     precision, arrival_s``) on the current GPU.  A builder takes the next request once it
     has arrived together with every later one already arrived (at most ``max_group``) and
