@@ -184,14 +184,35 @@ ss_status ss_op_csr(const ss_op* op, int64_t* row_ptr, int32_t* cols, int32_t* j
   return guarded([&]() -> ss_status {
     if (!op || !op->impl) return fail(SS_EINVAL, "null operator");
     const OpImpl* o = op->impl;
-    if (row_ptr) SS_HIP(hipMemcpy(row_ptr, o->d_crow, (o->total + 1) * 8, hipMemcpyDeviceToHost));
-    if (cols || js) {
-      std::vector<uint32_t> ent(o->nnz);
-      if (o->nnz) SS_HIP(hipMemcpy(ent.data(), o->d_cent, o->nnz * 4, hipMemcpyDeviceToHost));
-      for (int64_t e = 0; e < o->nnz; ++e) {
-        if (cols) cols[e] = (int32_t)(ent[e] & kColMask);
-        if (js) js[e] = (int32_t)(ent[e] >> kColBits);
+    if (row_ptr || cols || js) {
+      // the canonical CSR is read back from the SELL-64 layout: canonical row r is execution row
+      // e = canon2exec[r] (lane e % 64 of slice e / 64); its entries, in j order, are followed by
+      // null entries up to the slice width, and columns are mapped back to canonical rows
+      std::vector<uint32_t> sptr(o->n_slices + 1), sent(std::max<int64_t>(o->n_sell, 1));
+      std::vector<int64_t> c2e(o->total), e2c(o->n_exec);
+      SS_HIP(hipMemcpy(sptr.data(), o->d_sptr, sptr.size() * 4, hipMemcpyDeviceToHost));
+      if (o->n_sell) SS_HIP(hipMemcpy(sent.data(), o->d_sent, o->n_sell * 4, hipMemcpyDeviceToHost));
+      SS_HIP(hipMemcpy(c2e.data(), o->d_canon2exec, o->total * 8, hipMemcpyDeviceToHost));
+      SS_HIP(hipMemcpy(e2c.data(), o->d_exec2canon, o->n_exec * 8, hipMemcpyDeviceToHost));
+      int64_t pos = 0;
+      for (int p = 0; p < o->n_prob; ++p) {
+        const int64_t ro = o->row_off[p], eo = o->eoff[p];
+        for (int64_t r = ro; r < o->row_off[p + 1]; ++r) {
+          if (row_ptr) row_ptr[r] = pos;
+          const int64_t e = c2e[r], sl = e / kSlice, lane = e % kSlice;
+          const uint32_t base = sptr[sl], w = (sptr[sl + 1] - base) / kSlice;
+          for (uint32_t q = 0; q < w; ++q) {
+            const uint32_t v = sent[base + q * kSlice + lane];
+            if ((v >> kColBits) == (uint32_t)kNullJ) break;
+            if (pos >= o->nnz) return fail(SS_EDEVICE, "operator layout holds more entries than its count");
+            if (cols) cols[pos] = (int32_t)(e2c[eo + (v & kColMask)] - ro);
+            if (js) js[pos] = (int32_t)(v >> kColBits);
+            ++pos;
+          }
+        }
       }
+      if (pos != o->nnz) return fail(SS_EDEVICE, "operator layout holds fewer entries than its count");
+      if (row_ptr) row_ptr[o->total] = pos;
     }
     if (component) SS_HIP(hipMemcpy(component, o->d_comp, o->total * 4, hipMemcpyDeviceToHost));
     return SS_OK;

@@ -236,44 +236,54 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
   }
 }
 
-// present entries of each row of the dense table, in j order: the row lengths, then the CSR
-// (the table is read kDenseChunk entries per row at a time, every load of a chunk in flight)
+// The neighbour table as the later kernels read it, row r's slots u at u * total + r (reads of a
+// slot are coalesced over consecutive rows):
+//   kDense16  slot u = a-table index j, local canonical column or 0xffff (absent);
+//   kDense32  slot u = j, `column | j << kColBits` or all ones (absent);
+//   kCompact  slots u < rowlen[r], present entries in j order, `column | j << kColBits`.
+enum NbrKind { kDense16 = 0, kDense32 = 1, kCompact = 2 };
+
+// row r's entries are read kDenseChunk slots at a time, every load of a chunk in flight
 constexpr int kDenseChunk = 8;
 
-template <typename E>
-__global__ void k_row_count(int64_t total, const E* __restrict__ D, const int32_t* __restrict__ pid,
-                            const int32_t* __restrict__ aoff, int64_t* rowlen) {
-  constexpr E kNone = (E)~(E)0;
-  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
-  if (r >= total) return;
-  const int p = pid[r], s = aoff[p + 1] - aoff[p];
-  int64_t c = 0;
-  for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
-    E v[kDenseChunk];
-#pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kNone;
-#pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) c += v[u] != kNone;
+template <int K>
+struct NbrView {
+  static constexpr int kKind = K;
+  const void* D;
+  int64_t total;
+  const int32_t* aoff;
+  const int64_t* rowlen;
+  __device__ int slots(int p, int64_t r) const {
+    return K == kCompact ? (int)rowlen[r] : aoff[p + 1] - aoff[p];
   }
-  rowlen[r] = c;
-}
+  // slot u of row r: true and (column, j) when an entry is present
+  __device__ bool load(int64_t r, int u, uint32_t& v) const {
+    if (K == kDense16) {
+      const uint16_t x = reinterpret_cast<const uint16_t*>(D)[(int64_t)u * total + r];
+      v = (uint32_t)x | ((uint32_t)u << kColBits);
+      return x != 0xffffu;
+    }
+    v = reinterpret_cast<const uint32_t*>(D)[(int64_t)u * total + r];
+    return K == kCompact || v != 0xffffffffu;
+  }
+};
 
-template <typename E>
-__global__ void k_csr_from_dense(int64_t total, const E* __restrict__ D, const int32_t* __restrict__ pid,
-                                 const int32_t* __restrict__ aoff, const int64_t* __restrict__ crow,
-                                 uint32_t* __restrict__ cent) {
-  constexpr E kNone = (E)~(E)0;
-  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
-  if (r >= total) return;
-  const int p = pid[r], s = aoff[p + 1] - aoff[p];
-  int64_t q = crow[r];
-  for (int j0 = 0; j0 < s; j0 += kDenseChunk) {
-    E v[kDenseChunk];
-#pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) v[u] = j0 + u < s ? D[(int64_t)(j0 + u) * total + r] : kNone;
-#pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u)
-      if (v[u] != kNone) cent[q++] = sizeof(E) == 2 ? (uint32_t)v[u] | ((uint32_t)(j0 + u) << kColBits) : (uint32_t)v[u];
+// entries per problem: one block per problem sums the row lengths of its rows (rows of a
+// problem are contiguous), in a fixed order
+__global__ __launch_bounds__(kBlock) void k_problem_nnz(const int64_t* __restrict__ rowoff,
+                                                        const int64_t* __restrict__ rowlen, int64_t* __restrict__ nnz_p) {
+  const int p = blockIdx.x;
+  const int64_t r0 = rowoff[p], r1 = rowoff[p + 1];
+  int64_t c = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) c += rowlen[r];
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  __shared__ int64_t part[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int q = 0; q < kBlock / 64; ++q) t += part[q];
+    nnz_p[p] = t;
   }
 }
 
@@ -303,39 +313,36 @@ __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
     nbr_row<DMAX, EVEN, false, G, E, LAT>(a, r, p, nullptr, nullptr);
 }
 
-__global__ void k_csr_copy(int64_t total, int32_t smax, const uint32_t* __restrict__ buf,
-                           const int64_t* __restrict__ crow, uint32_t* __restrict__ cent) {
+// one pass of min-label propagation over the neighbour relation (thread per canonical row); with
+// COUNT the pass also writes every row's entry count
+template <int K, bool COUNT>
+__global__ void k_cc_prop(NbrView<K> v, const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
+                          int64_t* label, int32_t* changed, int64_t* __restrict__ rowlen) {
+  const int64_t total = v.total;
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
-  const int64_t c0 = crow[r], n = crow[r + 1] - c0;
-  for (int64_t q = 0; q < n; ++q) cent[c0 + q] = buf[q * total + r];
-}
-
-__global__ void k_nnz_per_problem(int n_prob, const int64_t* __restrict__ rowoff, const int64_t* __restrict__ crow,
-                                  int64_t* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n_prob) out[p] = crow[rowoff[p + 1]] - crow[rowoff[p]];
-}
-
-__global__ void k_cc_prop(int64_t total, const int64_t* __restrict__ crow, const uint32_t* __restrict__ cent,
-                          const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff, int64_t* label,
-                          int32_t* changed) {
-  const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
-  if (r >= total) return;
-  const int64_t base = rowoff[pid[r]];
+  const int p = pid[r];
+  const int64_t base = rowoff[p];
   const int64_t own = label[r];
   int64_t l = own;
-  const int64_t e1 = crow[r + 1];
-  for (int64_t e0 = crow[r]; e0 < e1; e0 += kDenseChunk) {   // entries, then labels, a chunk at a time
+  const int n = v.slots(p, r);
+  int cnt = 0;
+  for (int u0 = 0; u0 < n; u0 += kDenseChunk) {   // entries, then labels, a chunk at a time
     uint32_t c[kDenseChunk];
+    bool ok[kDenseChunk];
     int64_t lc[kDenseChunk];
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) c[u] = e0 + u < e1 ? cent[e0 + u] & kColMask : 0u;
+    for (int u = 0; u < kDenseChunk; ++u) {
+      ok[u] = u0 + u < n && v.load(r, u0 + u, c[u]);
+      c[u] &= kColMask;
+      cnt += ok[u] ? 1 : 0;
+    }
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) lc[u] = e0 + u < e1 ? label[base + c[u]] : own;
+    for (int u = 0; u < kDenseChunk; ++u) lc[u] = ok[u] ? label[base + c[u]] : own;
 #pragma unroll
     for (int u = 0; u < kDenseChunk; ++u) l = lc[u] < l ? lc[u] : l;
   }
+  if (COUNT) rowlen[r] = cnt;
   if (l < own) {
     label[r] = l;
     *changed = 1;
@@ -343,7 +350,7 @@ __global__ void k_cc_prop(int64_t total, const int64_t* __restrict__ crow, const
 }
 
 __global__ void k_cc_jump(int64_t total, int64_t* label) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = xcd_tid();
   if (r >= total) return;
   label[r] = label[label[r]];
 }
@@ -353,7 +360,7 @@ __global__ void k_cc_jump(int64_t total, int64_t* label) {
 __global__ void k_class_min(int64_t n_cls, int64_t total, const int64_t* __restrict__ cq,
                             const uint32_t* __restrict__ order, const int32_t* __restrict__ pid,
                             const int64_t* __restrict__ rowoff, int32_t* __restrict__ comp) {
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t k = xcd_tid() >> 6;
   const int lane = threadIdx.x & 63;
   if (k >= n_cls) return;
   const int64_t q0 = cq[k], q1 = k + 1 < n_cls ? cq[k + 1] : total;
@@ -394,7 +401,7 @@ __global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, co
                            const uint32_t* __restrict__ cidx, const int64_t* __restrict__ cq0,
                            const int64_t* __restrict__ ce0, int64_t* __restrict__ canon2exec,
                            int64_t* __restrict__ exec2canon) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = xcd_tid();
   if (q >= total) return;
   const int64_t r = order[q];
   const int64_t k = (int64_t)cidx[q] + cflag[q] - 1;
@@ -406,7 +413,7 @@ __global__ void k_exec_map(int64_t total, const uint32_t* __restrict__ order, co
 // width (in entries) of each 64-row slice: one wavefront per slice, one lane per row
 __global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec2canon,
                               const int64_t* __restrict__ rowlen, uint32_t* __restrict__ width) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = xcd_tid();
   const int64_t sl = g >> 6;
   if (sl >= n_slices) return;
   const int64_t r = exec2canon[g];
@@ -422,7 +429,7 @@ __global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec
 // or a class change
 __global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ order, const int64_t* __restrict__ label,
                                     const int32_t* __restrict__ pid, uint32_t* __restrict__ flag) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = xcd_tid();
   if (q >= n) return;
   const int64_t r = order[q];
   uint32_t f = 1;
@@ -439,51 +446,50 @@ __global__ void k_compact_starts(int64_t n, const uint32_t* __restrict__ flag, c
   if (e < n && flag[e]) out[idx[e]] = e;
 }
 
-template <typename NormT>
-__global__ void k_sell_fill(int64_t n_exec, int n_prob, const int64_t* __restrict__ exec2canon,
-                            const int64_t* __restrict__ canon2exec, const int64_t* __restrict__ crow,
-                            const uint32_t* __restrict__ cent, const int64_t* __restrict__ rowoff,
-                            const int64_t* __restrict__ eoff, const int64_t* __restrict__ norm,
-                            const uint32_t* __restrict__ sptr, uint32_t* __restrict__ sent,
-                            NormT* __restrict__ norm_exec) {
-  const int64_t e = xcd_block(ceil_div(n_exec, kBlock)) * kBlock + threadIdx.x;
-  if (e >= n_exec) return;
+// SELL-64 entries from the neighbour table, a thread per canonical row (its slots read coalesced
+// with the neighbouring rows'): the row's entries go, in j order, to its execution row
+// e = canon2exec[r] (lane e % 64 of slice e / 64, entry q at sptr + q * 64 + lane) with their
+// columns mapped to local execution rows, and null entries pad it to the slice width.  Threads
+// t < n_exec also pad the execution rows that hold no canonical row.
+template <int K, typename NormT>
+__global__ void k_sell_fill(NbrView<K> v, int64_t n_exec, const int64_t* __restrict__ exec2canon,
+                            const int64_t* __restrict__ canon2exec, const int32_t* __restrict__ pid,
+                            const int64_t* __restrict__ rowoff, const int64_t* __restrict__ eoff,
+                            const int64_t* __restrict__ norm, const uint32_t* __restrict__ sptr,
+                            uint32_t* __restrict__ sent, NormT* __restrict__ norm_exec, int64_t n_threads) {
+  const int64_t t = xcd_block(ceil_div(n_threads, kBlock)) * kBlock + threadIdx.x;
+  if (t >= n_threads) return;
+  const uint32_t null_ent = (uint32_t)kNullJ << kColBits;
+  if (t < n_exec && exec2canon[t] < 0) {   // a padding row
+    const int64_t sl = t / kSlice;
+    const int lane = (int)(t % kSlice);
+    const uint32_t base = sptr[sl], w = (sptr[sl + 1] - base) / kSlice;
+    for (uint32_t q = 0; q < w; ++q) sent[base + q * kSlice + lane] = null_ent;
+    norm_exec[t] = 0;
+  }
+  const int64_t r = t;
+  if (r >= v.total) return;
+  const int p = pid[r];
+  const int64_t e = canon2exec[r];
   const int64_t sl = e / kSlice;
   const int lane = (int)(e % kSlice);
-  const uint32_t base = sptr[sl];
-  const uint32_t w = (sptr[sl + 1] - base) / kSlice;
-  const int64_t r = exec2canon[e];
-  const uint32_t null_ent = (uint32_t)kNullJ << kColBits;
-  if (r < 0) {
-    for (uint32_t q = 0; q < w; ++q) sent[base + q * kSlice + lane] = null_ent;
-    norm_exec[e] = 0;
-    return;
-  }
-  // the problem of this slice (slices never straddle problems): a binary search over the
-  // execution offsets on values that are the same in every lane of the wavefront
-  int lo = 0, hi = n_prob;
-  const int64_t e0 = sl * kSlice;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (eoff[mid] <= e0) lo = mid;
-    else hi = mid;
-  }
-  const int p = lo;
-  const int64_t c0 = crow[r], len = crow[r + 1] - c0;
+  const uint32_t base = sptr[sl], w = (sptr[sl + 1] - base) / kSlice;
   const int64_t ro = rowoff[p], eo = eoff[p];
-  // a chunk of the row's entries, then their execution columns, each round of loads in flight
-  for (uint32_t q0 = 0; q0 < w; q0 += kDenseChunk) {
+  const int n = v.slots(p, r);
+  uint32_t q = 0;
+  for (int u0 = 0; u0 < n; u0 += kDenseChunk) {
     uint32_t ent[kDenseChunk];
+    bool ok[kDenseChunk];
     int64_t col[kDenseChunk];
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) ent[u] = (int64_t)(q0 + u) < len ? cent[c0 + q0 + u] : null_ent;
+    for (int u = 0; u < kDenseChunk; ++u) ok[u] = u0 + u < n && v.load(r, u0 + u, ent[u]);
+#pragma unroll
+    for (int u = 0; u < kDenseChunk; ++u) col[u] = ok[u] ? canon2exec[ro + (ent[u] & kColMask)] - eo : 0;
 #pragma unroll
     for (int u = 0; u < kDenseChunk; ++u)
-      col[u] = (int64_t)(q0 + u) < len ? canon2exec[ro + (ent[u] & kColMask)] - eo : 0;
-#pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u)
-      if (q0 + u < w) sent[base + (q0 + u) * kSlice + lane] = (int64_t)(q0 + u) < len ? (uint32_t)col[u] | (ent[u] & ~kColMask) : null_ent;
+      if (ok[u]) sent[base + (q++) * kSlice + lane] = (uint32_t)col[u] | (ent[u] & ~kColMask);
   }
+  for (; q < w; ++q) sent[base + q * kSlice + lane] = null_ent;
   norm_exec[e] = (NormT)norm[r];
 }
 
@@ -613,7 +619,6 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
         even ? k_neighbors_row<32, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<32, false, E, false><<<g, kBlock, 0, stream>>>(na);
       else
         even ? k_neighbors_row<64, true, E, false><<<g, kBlock, 0, stream>>>(na) : k_neighbors_row<64, false, E, false><<<g, kBlock, 0, stream>>>(na);
-      k_row_count<E><<<g, kBlock, 0, stream>>>(total, reinterpret_cast<const E*>(nbr), st->d_pid, st->d_aoff, rowlen);
     };
     if (narrow) launch(uint16_t{});
     else launch(uint32_t{});
@@ -623,34 +628,13 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     else
       k_neighbors<false><<<xcd_grid(ceil_div(ceil_div(total, rpw), kBlock / 64)), kBlock, 0, stream>>>(na);
   }
-  SS_TRY(dalloc(&op->d_crow, total + 1));
-  {
-    size_t tb = 0;
-    SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, rowlen, op->d_crow, total + 1, stream));
-    void* t = nullptr;
-    SS_HIP(pool_alloc((void**)&t, tb));
-    track(t);
-    SS_HIP(hipMemsetAsync(rowlen + total, 0, 8, stream));
-    SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, rowlen, op->d_crow, total + 1, stream));
-  }
-  int64_t* d_nnzp = nullptr;
-  SS_TRY(dalloc(&d_nnzp, n_prob));
-  track(d_nnzp);
-  k_nnz_per_problem<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, st->d_rowoff, op->d_crow, d_nnzp);
-  op->nnz_p.resize(n_prob);
-  SS_HIP(hipMemcpyAsync(op->nnz_p.data(), d_nnzp, n_prob * 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipMemcpyAsync(&op->nnz, op->d_crow + total, 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
-  SS_TRY(dalloc(&op->d_cent, op->nnz));
-  if (dense && narrow)
-    k_csr_from_dense<uint16_t><<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(
-        total, reinterpret_cast<const uint16_t*>(nbr), st->d_pid, st->d_aoff, op->d_crow, op->d_cent);
-  else if (dense)
-    k_csr_from_dense<uint32_t><<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, nbr, st->d_pid,
-                                                                                         st->d_aoff, op->d_crow,
-                                                                                         op->d_cent);
-  else
-    k_csr_copy<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, smax, nbr, op->d_crow, op->d_cent);
+  const int kind = dense ? (narrow ? kDense16 : kDense32) : kCompact;
+  // the neighbour table in the view of `kind`, passed to f
+  auto with_view = [&](auto f) {
+    if (kind == kDense16) f(NbrView<kDense16>{nbr, total, st->d_aoff, rowlen});
+    else if (kind == kDense32) f(NbrView<kDense32>{nbr, total, st->d_aoff, rowlen});
+    else f(NbrView<kCompact>{nbr, total, st->d_aoff, rowlen});
+  };
 
   // ---- connected classes: labels start at each key's root forcing key (so classes that no
   // coincidence merged are final at once); min-propagation with pointer jumping settles merges.
@@ -666,13 +650,24 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   for (int it = 0; it < 100000; ++it) {
     int32_t h = 0;
     SS_HIP(hipMemsetAsync(changed, 0, 4, stream));
-    k_cc_prop<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, op->d_crow, op->d_cent, st->d_pid,
-                                                                          st->d_rowoff, label, changed);
-    k_cc_jump<<<grid_for(total), kBlock, 0, stream>>>(total, label);
+    with_view([&](auto v) {
+      constexpr int K = decltype(v)::kKind;
+      const unsigned g = xcd_grid(ceil_div(total, kBlock));
+      if (K != kCompact && it == 0)   // the first pass also counts the entries of every row
+        k_cc_prop<K, true><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, label, changed, rowlen);
+      else
+        k_cc_prop<K, false><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, label, changed, rowlen);
+    });
+    k_cc_jump<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, label);
     SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
     SS_HIP(hipStreamSynchronize(stream));
     if (!h) break;
   }
+  // entries per problem (read back with the slice offsets below)
+  int64_t* d_nnzp = nullptr;
+  SS_TRY(dalloc(&d_nnzp, n_prob));
+  track(d_nnzp);
+  k_problem_nnz<<<n_prob, kBlock, 0, stream>>>(st->d_rowoff, rowlen, d_nnzp);
 
   // ---- execution order: (problem, class, -row length, canonical slot); a class whose
   // padding to a slice boundary costs at most 1/8 of its rows is padded, so the slices of
@@ -707,7 +702,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(cflag);
   SS_TRY(dalloc(&cidx, total + 1));
   track(cidx);
-  k_class_start_flags<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, label, st->d_pid, cflag);
+  k_class_start_flags<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, ev2, label, st->d_pid, cflag);
   SS_HIP(hipMemsetAsync(cflag + total, 0, 4, stream));
   std::vector<int64_t> cq;   // sorted position of every class start
   {
@@ -726,7 +721,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     k_compact_starts<<<grid_for(total), kBlock, 0, stream>>>(total, cflag, cidx, d_cq);
     SS_TRY(dalloc(&op->d_comp, total));
     if (n_cls)
-      k_class_min<<<(unsigned)ceil_div((int64_t)n_cls * 64, kBlock), kBlock, 0, stream>>>(
+      k_class_min<<<xcd_grid(ceil_div((int64_t)n_cls * 64, kBlock)), kBlock, 0, stream>>>(
           n_cls, total, d_cq, ev2, st->d_pid, st->d_rowoff, op->d_comp);
     cq.resize(n_cls);
     if (n_cls) SS_HIP(hipMemcpyAsync(cq.data(), d_cq, n_cls * 8, hipMemcpyDeviceToHost, stream));
@@ -783,7 +778,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
   SS_TRY(dalloc(&op->d_canon2exec, total));
   k_fill_i64<<<grid_for(op->n_exec), kBlock, 0, stream>>>(op->n_exec, op->d_exec2canon, -1);
-  k_exec_map<<<grid_for(total), kBlock, 0, stream>>>(total, ev2, cflag, cidx, d_cq0, d_ce0, op->d_canon2exec,
+  k_exec_map<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, ev2, cflag, cidx, d_cq0, d_ce0, op->d_canon2exec,
                                                       op->d_exec2canon);
 
   // ---- SELL-64 slices
@@ -791,7 +786,7 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&width, op->n_slices + 1));
   track(width);
   SS_TRY(dalloc(&op->d_sptr, op->n_slices + 1));
-  k_slice_width<<<grid_for(op->n_slices * kSlice), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen,
+  k_slice_width<<<xcd_grid(ceil_div(op->n_slices * kSlice, kBlock)), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen,
                                                                         width);
   SS_HIP(hipMemsetAsync(width + op->n_slices, 0, 4, stream));
   {
@@ -805,27 +800,36 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   thread_local std::vector<uint32_t> sptr_h;   // slice entry offsets, for sizing solve units
   sptr_h.resize(op->n_slices + 1);
   SS_HIP(hipMemcpyAsync(sptr_h.data(), op->d_sptr, (op->n_slices + 1) * 4, hipMemcpyDeviceToHost, stream));
+  op->nnz_p.resize(n_prob);
+  SS_HIP(hipMemcpyAsync(op->nnz_p.data(), d_nnzp, n_prob * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
+  op->nnz = 0;
+  for (int p = 0; p < n_prob; ++p) op->nnz += op->nnz_p[p];
   const uint32_t n_sell = sptr_h[op->n_slices];
   op->n_sell = n_sell;
   int64_t ncomp_total = 0;
   for (int p = 0; p < n_prob; ++p) ncomp_total += op->comps[p];
   op->n_components = ncomp_total;
   SS_TRY(dalloc(&op->d_sent, std::max<int64_t>(n_sell, 1)));
+  const int64_t n_fill = std::max(total, op->n_exec);   // canonical rows, and padding execution rows
   if (op->wide_norm) {
     int64_t* ne = nullptr;
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
-    k_sell_fill<int64_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
-        op->n_exec, n_prob, op->d_exec2canon, op->d_canon2exec, op->d_crow, op->d_cent, st->d_rowoff, op->d_eoff,
-        st->d_norm, op->d_sptr, op->d_sent, ne);
+    with_view([&](auto v) {
+      k_sell_fill<<<xcd_grid(ceil_div(n_fill, kBlock)), kBlock, 0, stream>>>(
+          v, op->n_exec, op->d_exec2canon, op->d_canon2exec, st->d_pid, st->d_rowoff, op->d_eoff, st->d_norm,
+          op->d_sptr, op->d_sent, ne, n_fill);
+    });
   } else {
     int32_t* ne = nullptr;
     SS_TRY(dalloc(&ne, op->n_exec));
     op->d_norm = ne;
-    k_sell_fill<int32_t><<<xcd_grid(ceil_div(op->n_exec, kBlock)), kBlock, 0, stream>>>(
-        op->n_exec, n_prob, op->d_exec2canon, op->d_canon2exec, op->d_crow, op->d_cent, st->d_rowoff, op->d_eoff,
-        st->d_norm, op->d_sptr, op->d_sent, ne);
+    with_view([&](auto v) {
+      k_sell_fill<<<xcd_grid(ceil_div(n_fill, kBlock)), kBlock, 0, stream>>>(
+          v, op->n_exec, op->d_exec2canon, op->d_canon2exec, st->d_pid, st->d_rowoff, op->d_eoff, st->d_norm,
+          op->d_sptr, op->d_sent, ne, n_fill);
+    });
   }
 
   // ---- work items: runs of slices of one problem whose rows' classes fit an LDS window
@@ -936,8 +940,6 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
 
 void free_op_impl(OpImpl* op) {
   if (!op) return;
-  dfree(op->d_crow);
-  dfree(op->d_cent);
   dfree(op->d_comp);
   dfree(op->d_exec2canon);
   dfree(op->d_canon2exec);

@@ -1930,7 +1930,7 @@ struct EngineImpl {
 
 int64_t op_device_bytes(const OpImpl* op) {
   const int64_t nb = op->wide_norm ? 8 : 4;
-  return (op->total + 1) * 8 + op->nnz * 4 + op->total * 4 + op->n_exec * 8 + op->total * 8 + op->n_sell * 4 +
+  return op->total * 4 + op->n_exec * 8 + op->total * 8 + op->n_sell * 4 +
          (op->n_slices + 1) * 4 + op->n_exec * nb + (int64_t)op->n_prob * kTab * (16 + 8 + 8) +
          (int64_t)op->work.size() * 16 + (int64_t)op->units.size() * 16;
 }

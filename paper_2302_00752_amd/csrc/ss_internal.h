@@ -241,10 +241,7 @@ struct OpImpl {
   std::vector<int32_t> unit_entries;   // SELL entries of each unit
   std::vector<uint32_t> unit_ebase;    // first SELL entry of each unit
   int4* d_units = nullptr;
-  // canonical CSR (kept for export and tests)
-  int64_t* d_crow = nullptr;           // [total+1]
-  uint32_t* d_cent = nullptr;          // [nnz] local canonical column | j << kColBits
-  int32_t* d_comp = nullptr;           // [total] local label
+  int32_t* d_comp = nullptr;           // [total] local class label
   // execution layout
   int64_t* d_exec2canon = nullptr;     // [n_exec] global canonical or -1
   int64_t* d_canon2exec = nullptr;     // [total]
@@ -412,5 +409,10 @@ __device__ inline int64_t xcd_block(int64_t nblocks) {
   const int64_t per = (nblocks + 7) / 8;
   return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
+// The global thread index under that numbering, for a grid of xcd_grid(n) blocks (a multiple of 8,
+// so the numbering is a bijection on the launched blocks); kernels check the index against their
+// size as with plain numbering.  Work items of one problem lie together in most arrays, so
+// consecutive blocks on one XCD keep a problem's gathers and scatters in that XCD's L2.
+__device__ inline int64_t xcd_tid() { return xcd_block(gridDim.x) * blockDim.x + threadIdx.x; }
 
 }  // namespace ss

@@ -419,7 +419,7 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
                                const uint64_t* __restrict__ lz, int16_t* __restrict__ keys, uint64_t* hash,
                                uint64_t* lat, int32_t* pid, uint8_t* lev, int64_t* norm, uint32_t* inv,
                                unsigned long long* max_norm) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t r = xcd_tid();
   int64_t nn = 0;
   if (r < n) {
     const int64_t s = perm[r];
@@ -472,23 +472,24 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
 
 __global__ void k_root_out(int64_t n, const uint32_t* __restrict__ perm, const int64_t* __restrict__ uroot,
                            const uint32_t* __restrict__ inv, int64_t* __restrict__ root) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t r = xcd_tid();
   if (r < n) root[r] = inv[uroot[perm[r]]];
 }
 
-// the lookup table from the build table: same slots, one word each; with inv the build table
-// still holds unsorted indices, which are mapped to canonical ones on the way
-__global__ void k_lookup_table(uint64_t n_slots, const uint64_t* __restrict__ table, const uint32_t* __restrict__ inv,
-                               uint64_t* __restrict__ lt) {
+// the lookup table from the build table, in place: same slots, one word each; with inv the build
+// table still holds unsorted indices, which are mapped to canonical ones on the way.  Every slot
+// is rewritten by its own thread only, and empty slots (most of them) are not written at all.
+__global__ void k_lookup_table(uint64_t n_slots, uint64_t* table, const uint32_t* __restrict__ inv) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_slots) return;
   const uint64_t v = table[s];
+  if (v == 0) return;
   uint64_t out = 0;
   if ((v & kTagMask) == kTagMain) {
     const uint64_t m = v & kMainIdxMask;
     out = lslot_from_fp((v >> 31) & 0x7fffffffull, inv ? (uint64_t)inv[m] : m);
   }
-  lt[s] = out;
+  table[s] = out;
 }
 
 
@@ -1232,11 +1233,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
         total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart, (int)lstart.size(), st->d_coef, st->d_latz,
         st->d_keys, st->d_hash, st->d_lat, st->d_pid, st->d_lev, st->d_norm, inv, d_maxn);
   else
-    k_permute_rows<<<grid_for(total), kBlock, 0, stream>>>(total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart,
+    k_permute_rows<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, d, perm, ukeys, k64b, pid_shift, pid_bits, d_lstart,
                                                            (int)lstart.size(), st->d_coef, st->d_latz, st->d_keys,
                                                            st->d_hash, st->d_lat, st->d_pid, st->d_lev, st->d_norm,
                                                            inv, d_maxn);
-  k_root_out<<<grid_for(total), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
+  k_root_out<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, perm, uroot, inv, st->d_root);
   // the forcing frequencies are the first nF unsorted keys, in the order given
   st->n_f = nF;
   SS_TRY(dalloc(&st->d_fslot, nF));
@@ -1251,10 +1252,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       shrink |= tight[p] < cap[p];
     }
     if (shrink) SS_TRY(layout_table(st, tight, total, st->d_hash, st->d_pid, stream));
-    // the lookup table (the build table goes once the stream has drained, below)
-    SS_TRY(dalloc(&st->d_ltable, st->n_slots));
+    // the lookup table takes over the build table's slots
     k_lookup_table<<<(unsigned)ceil_div((int64_t)st->n_slots, kBlock), kBlock, 0, stream>>>(
-        st->n_slots, st->d_table, shrink ? nullptr : inv, st->d_ltable);
+        st->n_slots, st->d_table, shrink ? nullptr : inv);
+    st->d_ltable = st->d_table;
+    st->d_table = nullptr;
   }
   k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, n_prob, st->d_pid, st->d_rowoff);
   unsigned long long maxn = 0;
@@ -1262,7 +1264,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 1) * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
-  dfree(st->d_table);
   st->max_norm = (int64_t)maxn;
   for (int p = 0; p < n_prob; ++p)
     if (st->row_off[p + 1] - st->row_off[p] > kMaxRowsPerProblem)
