@@ -182,7 +182,7 @@ __device__ __forceinline__ void nbr_row(const NbrArgs& a, int64_t r, int p, cons
       const int16_t* w = UNI ? wtab + (j - z - 1) * d : a.akeys + (int64_t)(j0 + j) * d;
       const uint64_t h = hr - (UNI ? htab[j - z - 1] : a.ahash[j0 + j]);
       const uint64_t lt = LAT ? lat_sub(lr, a.alat[j0 + j]) : 0;
-      const uint64_t pos = fmix64(h) & mask;
+      const uint64_t pos = h >> slot_shift(mask);
       const uint64_t g0 = pos & ~(uint64_t)(G - 1);   // regions are multiples of 64 slots: aligned
       uint64_t sv[G];
 #pragma unroll

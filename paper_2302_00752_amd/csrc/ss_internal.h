@@ -62,15 +62,6 @@ __host__ __device__ inline uint64_t main_word(uint64_t h, uint64_t idx) { return
 __host__ __device__ inline bool main_fp_eq(uint64_t v, uint64_t h) { return ((v >> 31) & 0x7fffffffull) == (h >> 33); }
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
-__host__ __device__ inline uint64_t fmix64(uint64_t k) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdULL;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ULL;
-  k ^= k >> 33;
-  return k;
-}
-
 // a == b + sign * w over d int16 coordinates, in int arithmetic (no wrap-around).  No early
 // exit: every load is independent, so a wavefront keeps all of them in flight at once.
 __device__ inline bool key_eq_shift(const int16_t* __restrict__ a, const int16_t* __restrict__ b,
@@ -89,9 +80,13 @@ __device__ inline bool key_eq_shift2(const int16_t* __restrict__ b1, const int16
   return acc == 0;
 }
 
-// linear probing inside one problem's power-of-two table region [base, base + mask + 1)
+// Linear probing inside one problem's power-of-two table region [base, base + mask + 1) (at least
+// 64 slots).  The first probe slot is the top log2(region) bits of the key's hash, a sum of
+// coordinate x random odd coefficient products mod 2^64 (multiply-shift hashing: its high bits
+// are evenly spread, and h(k - w) = h(k) - h(w) gives a neighbour's slot with one subtraction).
+__host__ __device__ inline int slot_shift(uint64_t mask) { return __builtin_clzll(mask); }
 __host__ __device__ inline uint64_t slot_first(uint64_t h, uint64_t base, uint64_t mask) {
-  return base + (fmix64(h) & mask);
+  return base + (h >> slot_shift(mask));
 }
 // a lookup-table word: the key's fingerprint (hash >> 33, as in the build table) in the high half and
 // its canonical index + 1 in the low half
