@@ -377,17 +377,19 @@ __global__ void k_class_min(int64_t n_cls, int64_t total, const int64_t* __restr
   for (int64_t q = q0 + lane; q < q1; q += 64) comp[order[q]] = (int32_t)(m - base);
 }
 
-// sort key (problem, class, kMaxA - row length) packed with `lb` bits per local index; the rows
-// come in canonical order and the radix sort is stable, so the canonical slot breaks ties
+// sort key (problem, class, kMaxA - row length) packed with `lb` bits per local index (32-bit keys
+// when the fields fit, which halves the key traffic of every sort pass); the rows come in
+// canonical order and the radix sort is stable, so the canonical slot breaks ties
+template <typename K>
 __global__ void k_exec_keys(int64_t total, int lb, const int32_t* __restrict__ pid,
                             const int64_t* __restrict__ rowoff, const int64_t* __restrict__ label,
-                            const int64_t* __restrict__ rowlen, uint64_t* __restrict__ key,
+                            const int64_t* __restrict__ rowlen, K* __restrict__ key,
                             uint32_t* __restrict__ val) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   const int p = pid[r];
   const uint64_t cls = (uint64_t)(label[r] - rowoff[p]);
-  key[r] = ((((uint64_t)p << lb) | cls) << kJBits) | (uint64_t)(kMaxA - rowlen[r]);
+  key[r] = (K)(((((uint64_t)p << lb) | cls) << kJBits) | (uint64_t)(kMaxA - rowlen[r]));
   val[r] = (uint32_t)r;
 }
 
@@ -687,15 +689,18 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   int pb = 0;
   while ((1 << pb) < n_prob) ++pb;
   const int key_bits = pb + lb + kJBits;   // <= 14 + 22 + 7
-  k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, label, rowlen, ek, ev);
-  {
+  auto exec_sort = [&](auto* k1, auto* k2) -> ss_status {
+    k_exec_keys<<<grid_for(total), kBlock, 0, stream>>>(total, lb, st->d_pid, st->d_rowoff, label, rowlen, k1, ev);
     size_t tb = 0;
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k1, k2, ev, ev2, total, 0, key_bits, stream));
     void* t = nullptr;
     SS_HIP(pool_alloc((void**)&t, tb));
     track(t);
-    SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, ek, ek2, ev, ev2, total, 0, key_bits, stream));
-  }
+    SS_HIP(hipcub::DeviceRadixSort::SortPairs(t, tb, k1, k2, ev, ev2, total, 0, key_bits, stream));
+    return SS_OK;
+  };
+  if (key_bits <= 32) SS_TRY(exec_sort(reinterpret_cast<uint32_t*>(ek), reinterpret_cast<uint32_t*>(ek2)));
+  else SS_TRY(exec_sort(ek, ek2));
   // class starts in sorted order
   uint32_t *cflag = nullptr, *cidx = nullptr;
   SS_TRY(dalloc(&cflag, total + 1));
