@@ -184,7 +184,7 @@ def _padded(p, d: int):
 def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 0, iters_per_tick: int = 4,
           build_threads: int = 2, ready_depth: int = 16, tol64: float = 1e-10, tol32: float = 1e-9,
           max_iter: int = 2000, keep_results: bool = False, realtime: bool = True, flags_for=None,
-          max_group: int = 64):
+          max_group: int = 64, stall_timeout_s: float = 120.0):
     """Serve ``requests`` (objects with ``d, a_freqs, a_hat, f_freqs, f_hat, level,
     precision, arrival_s``) on the current GPU.  A builder takes the next request once it
     has arrived together with every later one already arrived (at most ``max_group``) and
@@ -193,7 +193,9 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     when ``keep_results``).
 
     At most two builder threads are allowed: a run with four stopped making progress on the
-    GPU host and its cause has not been found, so larger counts are refused rather than run."""
+    GPU host and its cause has not been found, so larger counts are refused rather than run.
+    A run that makes no progress for ``stall_timeout_s`` seconds while no request is still to
+    arrive raises, naming what every builder was doing."""
     if not 1 <= build_threads <= 2:
         raise ValueError("serve() runs one or two builder threads (a four-thread run stopped making "
                          "progress and its cause is not known)")
@@ -203,7 +205,50 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
 
     dev = torch.device("cuda", torch.cuda.current_device())
     engine = ss.Engine(hbm_budget_bytes, max_slots)
-    sched = Scheduler(_EngineAdapter(engine, max_iter), iters_per_tick)
+    local = threading.local()
+
+    def build(probs, flags):
+        """Stamps, operator, f and u = 0 of one batch on this builder thread's own stream."""
+        stream = getattr(local, "stream", None)
+        if stream is None:
+            stream = local.stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(stream):
+            st = ss.Stamp.build(probs, stream=stream.cuda_stream)
+            op = ss.Operator.build(st, probs, flags, stream=stream.cuda_stream)
+            f = st.forcing_vector(probs, dev, stream=stream.cuda_stream)
+            u = torch.zeros_like(f)
+            stream.synchronize()
+        offsets = st.offsets.copy()
+        st.close()
+        return op, f, u, offsets
+
+    try:
+        summary, recs = serve_loop(requests, _EngineAdapter(engine, max_iter), engine.usage, build,
+                                   solution=lambda b, lo, hi: b.u[lo:hi].cpu().numpy(),
+                                   release=lambda b: b.op.close(), iters_per_tick=iters_per_tick,
+                                   build_threads=build_threads, ready_depth=ready_depth, tol64=tol64,
+                                   tol32=tol32, keep_results=keep_results, realtime=realtime,
+                                   flags_for=flags_for, max_group=max_group, stall_timeout_s=stall_timeout_s)
+    finally:
+        engine.close()
+    summary["hbm_budget_bytes"] = int(hbm_budget_bytes)
+    return summary, recs
+
+
+def serve_loop(requests: Sequence, adapter, usage, build, solution, release, iters_per_tick: int = 4,
+               build_threads: int = 2, ready_depth: int = 16, tol64: float = 1e-10, tol32: float = 1e-9,
+               keep_results: bool = False, realtime: bool = True, flags_for=None, max_group: int = 64,
+               stall_timeout_s: float = 120.0):
+    """The request loop of ``serve`` over any engine and builder.
+
+    ``adapter``: submit / step / poll as ``Scheduler`` expects them; ``usage() -> (slots,
+    bytes)`` of the engine; ``build(probs, flags) -> (op, f, u, offsets)`` runs on a builder
+    thread; ``solution(built, lo, hi)`` returns a host copy of u[lo:hi]; ``release(built)``
+    frees a retired build.  Every builder's work, from taking requests to queueing the build,
+    runs under one handler, so an error anywhere in it ends the run with that error; a run whose
+    builders have all ended with requests unbuilt, or that makes no progress for
+    ``stall_timeout_s`` seconds while no request is still to arrive, raises too."""
+    sched = Scheduler(adapter, iters_per_tick)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     built_q: "queue.Queue[Built]" = queue.Queue()
     t0 = time.perf_counter()
@@ -213,67 +258,68 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
     lock = threading.Lock()
     errors: List[BaseException] = []
     in_ready = threading.Semaphore(ready_depth)
+    phase = ["starting"] * build_threads   # what every builder is doing (stall reports)
 
-    def builder():
-        stream = torch.cuda.Stream(device=dev)
-        while True:
-            with lock:
-                if next_job[0] >= len(order):
-                    return
-                first = order[next_job[0]]
-                next_job[0] += 1
-            wait = arrivals[first] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            group = [first]
-            with lock:   # every request that has arrived meanwhile joins the build
-                now = time.perf_counter()
-                while next_job[0] < len(order) and len(group) < max_group and arrivals[order[next_job[0]]] <= now:
-                    group.append(order[next_job[0]])
+    def builder(w: int):
+        try:
+            while True:
+                with lock:
+                    if next_job[0] >= len(order):
+                        phase[w] = "done"
+                        return
+                    first = order[next_job[0]]
                     next_job[0] += 1
-            shares = collections.OrderedDict()
-            for i in group:
-                p = requests[i]
-                shares.setdefault((p.precision, flags_for(p) if flags_for else 0), []).append(i)
-            for (prec, flags), rids in shares.items():
-                in_ready.acquire()
-                try:
+                wait = arrivals[first] - time.perf_counter()
+                if wait > 0:
+                    phase[w] = f"waiting for request {first} to arrive"
+                    time.sleep(wait)
+                group = [first]
+                with lock:   # every request that has arrived meanwhile joins the build
+                    now = time.perf_counter()
+                    while next_job[0] < len(order) and len(group) < max_group and arrivals[order[next_job[0]]] <= now:
+                        group.append(order[next_job[0]])
+                        next_job[0] += 1
+                shares = collections.OrderedDict()
+                for i in group:
+                    p = requests[i]
+                    shares.setdefault((p.precision, flags_for(p) if flags_for else 0), []).append(i)
+                for (prec, flags), rids in shares.items():
+                    phase[w] = f"waiting for a ready slot ({len(rids)} requests built next)"
+                    in_ready.acquire()
+                    phase[w] = f"building {len(rids)} requests from request {rids[0]}"
                     tb = time.perf_counter()
                     dmax = max(requests[i].d for i in rids)
                     probs = [_padded(requests[i], dmax) for i in rids]
-                    with torch.cuda.stream(stream):
-                        st = ss.Stamp.build(probs, stream=stream.cuda_stream)
-                        op = ss.Operator.build(st, probs, flags, stream=stream.cuda_stream)
-                        f = st.forcing_vector(probs, dev, stream=stream.cuda_stream)
-                        u = torch.zeros_like(f)
-                        stream.synchronize()
-                    offsets = st.offsets.copy()
-                    st.close()
+                    op, f, u, offsets = build(probs, flags)
                     with lock:
                         tag = next_tag[0]
                         next_tag[0] += 1
                     tol = tol64 if prec == "fp64" else tol32
                     built_q.put(Built(tag, rids, op, f, u, offsets, tol, prec, 1e3 * (time.perf_counter() - tb)))
-                except BaseException as e:   # surfaced by the scheduler loop
-                    errors.append(e)
-                    in_ready.release()
-                    return
+        except BaseException as e:   # surfaced by the scheduler loop
+            phase[w] = f"failed: {e!r}"
+            errors.append(e)
+            in_ready.release()
 
-    threads = [threading.Thread(target=builder, daemon=True) for _ in range(build_threads)]
+    threads = [threading.Thread(target=builder, args=(w,), daemon=True) for w in range(build_threads)]
     for t in threads:
         t.start()
     n_done = 0
+    n_built = 0
     build_ms = []
     group_sizes = []
     ticks = 0
     results = {}
     peak_bytes = 0
     max_unit = 0                        # largest footprint of a unit admitted on its own
+    last_progress = time.perf_counter()
 
     def take(b: Built):
+        nonlocal n_built
         sched.offer_group(b.tag, b, [(rid, arrivals[rid]) for rid in b.rids])
         build_ms.append(b.build_ms)
         group_sizes.append(len(b.rids))
+        n_built += len(b.rids)
 
     while n_done < len(requests):
         if errors:
@@ -285,17 +331,18 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
                 moved += 1
             except queue.Empty:
                 break
-        before_bytes = engine.usage()[1] if sched.ready else 0
+        before_bytes = usage()[1] if sched.ready else 0
         n_adm = sched.admit()
         for _ in range(n_adm):
             in_ready.release()          # bounded: built requests not yet admitted
         if n_adm:
-            used = engine.usage()[1]
+            used = usage()[1]
             peak_bytes = max(peak_bytes, used)
             if n_adm == 1:
                 max_unit = max(max_unit, used - before_bytes)
         if sched.ready and not sched.active:
             raise RuntimeError("the engine refused a request while it held no other")
+        finished_before = n_done
         if sched.active:
             before = len(sched.finished)
             sched.tick()
@@ -303,17 +350,30 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
             for r in sched.finished[before:]:
                 b: Built = r.result
                 if keep_results:
-                    results[r.rid] = b.u[int(b.offsets[r.prob]):int(b.offsets[r.prob + 1])].cpu().numpy()
+                    results[r.rid] = solution(b, int(b.offsets[r.prob]), int(b.offsets[r.prob + 1]))
                 r.result = None
             for b in sched.retired:
-                b.op.close()            # frees the operator and its workspace
+                release(b)              # frees the operator and its workspace
             sched.retired.clear()
             n_done = len(sched.finished)
         elif not moved:
             try:
                 take(built_q.get(timeout=0.005))
+                moved += 1
             except queue.Empty:
                 pass
+        now = time.perf_counter()
+        if moved or n_adm or n_done > finished_before:
+            last_progress = now
+        elif not sched.active and built_q.empty() and not any(t.is_alive() for t in threads):
+            if errors:
+                raise errors[0]
+            raise RuntimeError(f"the builders ended with {len(requests) - n_built} requests unbuilt")
+        elif not sched.active and now - last_progress > stall_timeout_s and \
+                not any(ph.startswith("waiting for request") for ph in phase):
+            raise RuntimeError(f"serving made no progress for {now - last_progress:.0f} s with "
+                               f"{len(requests) - n_built} requests unbuilt, {len(sched.ready)} built units "
+                               f"waiting; builders: " + "; ".join(phase))
     for t in threads:
         t.join()
     t_end = time.perf_counter()
@@ -335,7 +395,6 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
         "requests_per_build_mean": float(np.mean(group_sizes)) if group_sizes else 0.0,
         "status_ok": int(sum(1 for r in recs if r.info["status"] == 0)),
         "fp32_refine": int(sum(1 for i in range(len(requests)) if requests[i].precision != "fp64")),
-        "hbm_budget_bytes": int(hbm_budget_bytes),
         "peak_bytes_admitted": int(peak_bytes),
         "max_unit_bytes": int(max_unit),
         "refused_admissions": int(sched.refusals),
@@ -344,6 +403,5 @@ def serve(requests: Sequence, hbm_budget_bytes: int = 2 << 30, max_slots: int = 
         "queue_ms_p99": float(np.percentile(queued, 99)),
         "build_threads": int(build_threads),
     }
-    engine.close()
     recs.sort(key=lambda r: r.rid)
     return summary, recs
