@@ -8,7 +8,9 @@
 // block is released and the allocation retried).  A block is released only
 // after the work that used it has completed (every release point in the
 // library follows a stream synchronisation), so handing it to another stream
-// needs no event.
+// needs no event.  The pool's lock guards its lists only: hipMalloc and
+// hipFree run without it, so a thread waiting in the driver (hipFree waits
+// for the device) never holds up another thread's cached allocations.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -42,11 +44,14 @@ size_t size_class(size_t bytes) {
   return (bytes + step - 1) / step * step;
 }
 
-void release_cached_locked(Pool& P) {
-  for (auto& kv : P.free_blocks)
-    for (void* b : kv.second) (void)hipFree(b);
+// every cached block, taken off the lists (the caller frees them without the lock)
+std::vector<void*> take_cached(Pool& P) {
+  std::lock_guard<std::mutex> g(P.mu);
+  std::vector<void*> out;
+  for (auto& kv : P.free_blocks) out.insert(out.end(), kv.second.begin(), kv.second.end());
   P.free_blocks.clear();
   P.cached_bytes = 0;
+  return out;
 }
 
 }  // namespace
@@ -58,24 +63,28 @@ hipError_t pool_alloc(void** out, size_t bytes) {
   if (e != hipSuccess) return e;
   const size_t cls = size_class(bytes);
   Pool& P = pool();
-  std::lock_guard<std::mutex> g(P.mu);
-  auto it = P.free_blocks.find({dev, cls});
-  if (it != P.free_blocks.end() && !it->second.empty()) {
-    *out = it->second.back();
-    it->second.pop_back();
-    P.cached_bytes -= cls;
-  } else {
-    e = hipMalloc(out, cls);
-    if (e == hipErrorOutOfMemory) {
-      (void)hipGetLastError();
-      release_cached_locked(P);
-      e = hipMalloc(out, cls);
-    }
-    if (e != hipSuccess) {
-      *out = nullptr;
-      return e;
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    auto it = P.free_blocks.find({dev, cls});
+    if (it != P.free_blocks.end() && !it->second.empty()) {
+      *out = it->second.back();
+      it->second.pop_back();
+      P.cached_bytes -= cls;
+      P.live[*out] = {dev, cls};
+      return hipSuccess;
     }
   }
+  e = hipMalloc(out, cls);
+  if (e == hipErrorOutOfMemory) {   // give the cached blocks back to the driver and try again
+    (void)hipGetLastError();
+    for (void* b : take_cached(P)) (void)hipFree(b);
+    e = hipMalloc(out, cls);
+  }
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return e;
+  }
+  std::lock_guard<std::mutex> g(P.mu);
   P.live[*out] = {dev, cls};
   return hipSuccess;
 }
