@@ -707,8 +707,19 @@ struct UnitArgs {
   const int4* ulist;
   const uint2* uent;             // per unit: first SELL entry (operator-global), entries
   int32_t ubase;                 // first unit of this launch within ulist
+  int32_t rows;                  // rows of the LDS window and norms: the launch's largest unit
   UnitOut* out;                  // per unit (ulist order)
 };
+
+// Dynamic LDS of a unit block: the window (complex128 per row), the rows' |k|^2, then the entry
+// cache of the cache mode (`ent_bytes`).  Sized by the launch's largest unit, so a block of small
+// units leaves room for more blocks on its CU.
+template <typename NormT>
+constexpr size_t unit_norm_off(int rows) { return (size_t)rows * 16; }
+template <typename NormT>
+constexpr size_t unit_ent_off(int rows) { return (unit_norm_off<NormT>(rows) + (size_t)rows * sizeof(NormT) + 15) & ~(size_t)15; }
+template <typename NormT>
+constexpr size_t unit_lds_bytes(int rows, size_t ent_bytes) { return unit_ent_off<NormT>(rows) + ent_bytes; }
 
 // 64-bit DPP move (the two halves moved alike); lanes of rows outside ROW_MASK get 0
 template <int CTRL, int ROW_MASK = 0xf>
@@ -931,8 +942,8 @@ __device__ inline void unit_mv_cplx(const uint32_t* sptr, const float2* cf, cons
 // complex FP32 coefficients in place of the brackets; the correction solves use the brackets or
 // coefficients and the columns, the FP64 residuals the columns and indices.
 enum { CM_STREAM = 0, CM_ENTRIES = 1, CM_COEF = 2, CM_CPLX = 3 };
-// entries whose caches fit the LDS beside the static arrays (int32 / int64 norms); CM_CPLX is
-// further capped at run time by the LDS the kernel leaves
+// entries each cache may hold (the set-up stages them through registers; int32 / int64 norms); a
+// unit's mode is then chosen at run time by the LDS its window, norms and cache take together
 constexpr int kCoefBytes = 7;    // FP32 bracket, 16-bit column, 8-bit a-table index
 constexpr int kCplxBytes = 11;   // complex FP32 coefficient, 16-bit column, 8-bit a-table index
 constexpr int kCoefEntries32 = 17152;
@@ -941,13 +952,17 @@ constexpr int kCplxEntries = 10944;
 static_assert(kUnitEntries <= kCoefEntries64 && kCoefEntries64 <= kCoefEntries32, "units must fit every cache");
 static_assert(kCplxEntries <= kCoefEntries64, "the group map covers every cache");
 
-template <typename NormT, bool FP64, int CM>
-__global__ __launch_bounds__(kUnitThreads) void k_unit_solve(UnitArgs Args) {
+// TWO: built for two blocks per CU (at most 64 VGPRs: eight wavefronts per SIMD), launched for
+// units whose LDS leaves room for a second block; otherwise one block per CU.  The solve is
+// latency-bound (barriers, dependent LDS gathers), so a second unit on the CU hides it.
+template <typename NormT, bool FP64, int CM, bool TWO>
+__global__ __launch_bounds__(kUnitThreads, TWO ? 8 : 4) void k_unit_solve(UnitArgs Args) {
   constexpr bool CACHED = CM == CM_ENTRIES;
-  __shared__ __align__(16) double2 s_win[kWinRows];   // search direction / iterate window
-  __shared__ NormT s_norm[kWinRows];
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  double2* s_win = reinterpret_cast<double2*>(s_dyn);                                   // search direction / iterate window
+  NormT* s_norm = reinterpret_cast<NormT*>(s_dyn + unit_norm_off<NormT>(Args.rows));     // |k|^2 of the rows
+  uint32_t* s_ent = reinterpret_cast<uint32_t*>(s_dyn + unit_ent_off<NormT>(Args.rows)); // CM_ENTRIES: entries; CM_COEF, CM_CPLX: brackets or coefficients, columns, j
   __shared__ uint32_t s_sptr[kWinRows / kSlice + 1];
-  extern __shared__ __align__(16) uint32_t s_ent[];    // CM_ENTRIES: entries; CM_COEF, CM_CPLX: brackets or coefficients, columns, j
   __shared__ double2 s_A64[kTab];
   __shared__ float2 s_A32[kTab];
   __shared__ NormT s_nu[kTab];
@@ -1306,23 +1321,59 @@ __global__ void k_unit_final(int n_prob, const int32_t* __restrict__ uoff, const
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
 
-// entries a CM_CPLX unit may hold: what the LDS leaves beside the kernel's static arrays, at
-// most kCplxEntries (0 if the device cannot be queried)
+// LDS a unit block may take beside the kernel's static arrays: all a block can have, and the share
+// that leaves room for a second block on the CU (0 if the device cannot be queried: units then
+// stream their entries)
+struct UnitLds {
+  int full = 0, half = 0;
+};
 template <typename NormT>
-int unit_cplx_cap() {
-  static const int cap = [] {
+UnitLds unit_lds() {
+  static const UnitLds v = [] {
+    UnitLds r;
     int dev = 0, lds = 0;
     hipFuncAttributes fa{};
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_unit_solve<NormT, false, CM_CPLX>)) != hipSuccess) {
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_unit_solve<NormT, false, CM_CPLX, false>)) != hipSuccess) {
       (void)hipGetLastError();   // not left for the launch checks that follow
-      return 0;
+      return r;
     }
-    const int fit = (lds - (int)fa.sharedSizeBytes) / kCplxBytes;
-    return std::max(0, std::min(fit, kCplxEntries));
+    r.full = std::max(0, lds - (int)fa.sharedSizeBytes);
+    r.half = std::max(0, lds / 2 - (int)fa.sharedSizeBytes);
+    return r;
   }();
-  return cap;
+  return v;
+}
+
+// The cache mode of a unit of `rows` rows and `ne` entries, its dynamic LDS and whether two such
+// blocks share a CU: the richest cache that lets two blocks share it, else the richest that fits
+// at all, else streaming (FP64: entries or streaming; FP32 + refinement: complex coefficients,
+// brackets, entries)
+template <typename NormT>
+int unit_mode(bool fp32, int rows, int ne, size_t* lds, bool* two) {
+  const UnitLds L = unit_lds<NormT>();
+  struct Cand {
+    int mode, bytes, cap;
+  };
+  const Cand c64[] = {{CM_ENTRIES, 4, kUnitEntries}};
+  const Cand c32[] = {{CM_CPLX, kCplxBytes, kCplxEntries},
+                      {CM_COEF, kCoefBytes, sizeof(NormT) == 8 ? kCoefEntries64 : kCoefEntries32},
+                      {CM_ENTRIES, 4, kUnitEntries}};
+  const Cand* cs = fp32 ? c32 : c64;
+  const int nc = fp32 ? 3 : 1;
+  for (int budget : {L.half, L.full})
+    for (int i = 0; i < nc; ++i) {
+      const size_t need = unit_lds_bytes<NormT>(rows, (size_t)ne * cs[i].bytes);
+      if (ne <= cs[i].cap && need <= (size_t)budget) {
+        *lds = need;
+        *two = budget == L.half;
+        return cs[i].mode;
+      }
+    }
+  *lds = unit_lds_bytes<NormT>(rows, 0);
+  *two = *lds <= (size_t)L.half;
+  return CM_STREAM;
 }
 
 }  // namespace
@@ -1510,7 +1561,7 @@ inline UnitItem unit_item(OpImpl* op, int p, const void* f, void* u, double tol,
 // precision, what the LDS caches); a unit's result is addressed by its position in ul, and each
 // problem's are summed in order through uidx.
 struct UnitPlan {
-  static constexpr int kGroups = 12;   // norm width x (FP64: stream, entries in LDS | FP32: stream,
+  static constexpr int kGroups = 24;   // blocks per CU (1, 2) x norm width x (FP64: stream, entries in LDS | FP32: stream,
                                        // entries, brackets, complex coefficients in LDS)
   std::vector<UDesc> descs;            // per problem
   std::vector<int4> ul;                // per unit: {problem, first slice, slices, first row}
@@ -1519,6 +1570,7 @@ struct UnitPlan {
   std::vector<int32_t> uidx;           // per unit of each problem, in order: its position in ul
   int gbeg[kGroups + 1] = {0};
   int32_t lmax[kGroups] = {0};         // dynamic LDS of each launch
+  int32_t rmax[kGroups] = {0};         // rows of the largest unit of each launch
 
   int n_prob() const { return (int)descs.size(); }
   int n_units() const { return (int)ul.size(); }
@@ -1526,12 +1578,11 @@ struct UnitPlan {
   void make(const std::vector<UnitItem>& launched) {
     const int np = (int)launched.size();
     descs.assign(np, UDesc{});
-    const int cplx_cap[2] = {unit_cplx_cap<int32_t>(), unit_cplx_cap<int64_t>()};
     std::vector<int4> lists[kGroups];
     std::vector<uint2> ents[kGroups];
     std::vector<std::pair<int, int>> where;   // per unit of each problem, in order: (launch, index)
     uoff.assign(1, 0);
-    for (int g = 0; g < kGroups; ++g) lmax[g] = 0;
+    for (int g = 0; g < kGroups; ++g) lmax[g] = rmax[g] = 0;
     for (int i = 0; i < np; ++i) {
       const UnitItem& it = launched[i];
       descs[i] = it.d;
@@ -1540,15 +1591,18 @@ struct UnitPlan {
         const int4 un = it.op->units[k];
         const int32_t ne = it.op->unit_entries[k];
         const bool wide = it.group >= 2, fp32 = it.group & 1;
-        int mode = ne <= kUnitEntries ? CM_ENTRIES : CM_STREAM;
-        if (fp32 && ne <= cplx_cap[wide]) mode = CM_CPLX;
-        else if (fp32 && ne <= (wide ? kCoefEntries64 : kCoefEntries32)) mode = CM_COEF;
-        const int g = (wide ? 6 : 0) + (fp32 ? 2 : 0) + mode;
+        const int rows = un.z * kSlice;
+        size_t lds = 0;
+        bool two = false;
+        const int mode = wide ? unit_mode<int64_t>(fp32, rows, ne, &lds, &two)
+                              : unit_mode<int32_t>(fp32, rows, ne, &lds, &two);
+        const int g = (two ? 12 : 0) + (wide ? 6 : 0) + (fp32 ? 2 : 0) + mode;
         where.emplace_back(g, (int)lists[g].size());
         lists[g].push_back(make_int4(i, un.y, un.z, un.w));
         ents[g].push_back(make_uint2(it.op->unit_ebase[k], (uint32_t)ne));
         const int bytes = mode == CM_CPLX ? kCplxBytes : mode == CM_COEF ? kCoefBytes : 4;
         if (mode != CM_STREAM) lmax[g] = std::max(lmax[g], ne * bytes);
+        rmax[g] = std::max(rmax[g], rows);
       }
       uoff.push_back((int32_t)where.size());
     }
@@ -1576,28 +1630,38 @@ struct UnitDev {
   UnitSum* sum = nullptr;
 };
 
+// one launch of unit group g (mod 12: norm width, precision, cache mode)
+template <bool TWO>
+void launch_unit_group(int g, unsigned n, size_t lds, hipStream_t s, const UnitArgs& A) {
+  switch (g) {
+    case 0: k_unit_solve<int32_t, true, CM_STREAM, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 1: k_unit_solve<int32_t, true, CM_ENTRIES, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 2: k_unit_solve<int32_t, false, CM_STREAM, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 3: k_unit_solve<int32_t, false, CM_ENTRIES, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 4: k_unit_solve<int32_t, false, CM_COEF, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 5: k_unit_solve<int32_t, false, CM_CPLX, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 6: k_unit_solve<int64_t, true, CM_STREAM, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 7: k_unit_solve<int64_t, true, CM_ENTRIES, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 8: k_unit_solve<int64_t, false, CM_STREAM, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 9: k_unit_solve<int64_t, false, CM_ENTRIES, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    case 10: k_unit_solve<int64_t, false, CM_COEF, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+    default: k_unit_solve<int64_t, false, CM_CPLX, TWO><<<n, kUnitThreads, lds, s>>>(A); break;
+  }
+}
+
 // the launches of a plan whose tables are on the device (asynchronous on s)
 ss_status launch_unit_plan(const UnitPlan& P, const UnitDev& D, hipStream_t s) {
-  UnitArgs A{D.desc, D.ul, D.ue, 0, D.out};
+  UnitArgs A{D.desc, D.ul, D.ue, 0, 0, D.out};
   for (int g = 0; g < UnitPlan::kGroups; ++g) {
     const int n = P.gbeg[g + 1] - P.gbeg[g];
     if (n == 0) continue;
     A.ubase = P.gbeg[g];
-    const size_t lds = (size_t)P.lmax[g];
-    switch (g) {
-      case 0: k_unit_solve<int32_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-      case 1: k_unit_solve<int32_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 2: k_unit_solve<int32_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-      case 3: k_unit_solve<int32_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 4: k_unit_solve<int32_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 5: k_unit_solve<int32_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 6: k_unit_solve<int64_t, true, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-      case 7: k_unit_solve<int64_t, true, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 8: k_unit_solve<int64_t, false, CM_STREAM><<<n, kUnitThreads, 0, s>>>(A); break;
-      case 9: k_unit_solve<int64_t, false, CM_ENTRIES><<<n, kUnitThreads, lds, s>>>(A); break;
-      case 10: k_unit_solve<int64_t, false, CM_COEF><<<n, kUnitThreads, lds, s>>>(A); break;
-      default: k_unit_solve<int64_t, false, CM_CPLX><<<n, kUnitThreads, lds, s>>>(A); break;
-    }
+    A.rows = P.rmax[g];
+    const int gl = g % 12;
+    const size_t lds = gl >= 6 ? unit_lds_bytes<int64_t>(P.rmax[g], (size_t)P.lmax[g])
+                               : unit_lds_bytes<int32_t>(P.rmax[g], (size_t)P.lmax[g]);
+    if (g >= 12) launch_unit_group<true>(gl, (unsigned)n, lds, s, A);
+    else launch_unit_group<false>(gl, (unsigned)n, lds, s, A);
   }
   k_unit_final<<<grid_for(P.n_prob()), kBlock, 0, s>>>(P.n_prob(), D.uoff, D.uidx, D.out, D.sum);
   SS_HIP(hipGetLastError());
