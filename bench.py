@@ -101,10 +101,12 @@ def main():
     ap.add_argument("--serve", type=int, default=1024, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0,
                     help="engine HBM budget (0: --serve-budget-units x the largest unit of the warm-up)")
-    ap.add_argument("--serve-budget-units", type=float, default=1.0)
+    ap.add_argument("--serve-budget-units", type=float, default=0.75)
     ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_refine"),
+                    help="precision of the timed whole-path step (both are reported per configuration)")
     ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
     ap.add_argument("--adr", type=int, default=256,
                     help="3-D advection-diffusion-reaction problems at level 1 (0 = skip the ADR runs)")
@@ -134,7 +136,7 @@ def main():
 
     batch = ss.Batch(probs)     # host inputs packed once, as a caller holding flat arrays would
 
-    def run_step(precision="fp32_refine"):
+    def run_step(precision=args.precision):
         # the whole path from the packed host inputs to device-resident solutions, the batch split
         # into parts built and solved concurrently
         res, infos = ss.solve_batch(batch, args.tol, precision, 1000, 0, parts=args.parts)
@@ -742,12 +744,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+c128",
+        "dtype": "c128" if args.precision == "fp64" else "c64+c128",
         "data": "synthetic",
         "config": {"workload": "d=10 torus, 10 a-modes in [-16,16]^10 (1/|w|^2 decay, a>=0.5), 20 f-freqs, "
-                               "stamp level 3 (|S|=31220); FP32+refine PCG to rel. residual "
+                               f"stamp level 3 (|S|=31220); {'FP64' if args.precision == 'fp64' else 'FP32+refine'} PCG to rel. residual "
                                f"{args.tol:g}, whole path incl. stamp/index build",
-                   "global_batch": B, "precision": "fp32_refine", "parallelism": "single-gpu",
+                   "global_batch": B, "precision": args.precision, "parallelism": "single-gpu",
                    "concurrent_parts": args.parts},
         "solve_only_per_config": per_config,
         "fp64_solve_only_solves_per_s": B / (solve_ms["fp64"] / 1e3),
