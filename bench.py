@@ -105,6 +105,10 @@ def main():
     ap.add_argument("--configs", default="2,3,4", help="configurations for the solve-only comparison ('' = skip)")
     ap.add_argument("--config-batch", type=int, default=256)
     ap.add_argument("--parts", type=int, default=4, help="concurrent parts of the step's batch")
+    ap.add_argument("--single", type=int, default=20,
+                    help="single-problem whole-path runs per precision for the single-instance latency (0 = skip)")
+    ap.add_argument("--lattice-builds", type=int, default=1,
+                    help="time operator builds with lattice lookups against key comparison (0 = skip)")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_refine"),
                     help="precision of the timed whole-path step (both are reported per configuration)")
     ap.add_argument("--proxy", type=int, default=1, help="exact proxy-error measurements (0 = skip)")
@@ -205,10 +209,11 @@ def main():
         return float(np.median(ts))
 
     lat_lookup = {}
-    for name, mk in (("d=10 (512 level-3 problems)", lambda: None),
-                     ("d=100 (256 level-2 problems)", lambda: ss.Batch([workloads.make(4, i) for i in range(256)])),
-                     ("d=1024 (64 high-sparsity level-2 problems)",
-                      lambda: ss.Batch([workloads.highsparsity(1024, 2, i) for i in range(64)]))):
+    lat_cases = (("d=10 (512 level-3 problems)", lambda: None),
+                 ("d=100 (256 level-2 problems)", lambda: ss.Batch([workloads.make(4, i) for i in range(256)])),
+                 ("d=1024 (64 high-sparsity level-2 problems)",
+                  lambda: ss.Batch([workloads.highsparsity(1024, 2, i) for i in range(64)])))
+    for name, mk in lat_cases if args.lattice_builds else ():
         bl = mk()
         stl = st if bl is None else ss.Stamp.build(bl)
         bl = batch if bl is None else bl
@@ -701,7 +706,7 @@ def main():
     # --- single-instance latency of the d = 10 problem: whole path from host data and solve only
     single = {}
     lat_w, lat_s = {"fp64": [], "fp32_refine": []}, {"fp64": [], "fp32_refine": []}
-    for i in range(20):
+    for i in range(args.single):
         p1 = [probs[i]]
         for prec in ("fp64", "fp32_refine"):
             torch.cuda.synchronize()
@@ -710,25 +715,26 @@ def main():
             torch.cuda.synchronize()
             lat_w[prec].append(1e3 * (time.perf_counter() - t))
             r1.close()
-    st1 = ss.Stamp.build(probs[:1])
-    op1 = ss.Operator.build(st1, probs[:1])
-    f1 = st1.forcing_vector(probs[:1], dev)
-    u1 = torch.zeros_like(f1)
-    for prec in ("fp64", "fp32_refine"):
-        for i in range(21):
-            u1.zero_()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            op1.solve(f1, u1, args.tol, prec, 1000)
-            torch.cuda.synchronize()
-            if i:
-                lat_s[prec].append(1e3 * (time.perf_counter() - t))
-        single[prec] = {"whole_path_ms_p50": float(np.median(lat_w[prec])),
-                        "whole_path_ms_p99": float(np.percentile(lat_w[prec], 99)),
-                        "solve_only_ms_p50": float(np.median(lat_s[prec]))}
-    op1.close()
-    st1.close()
-    log(f"single instance (d=10): {single}")
+    if args.single > 0:
+        st1 = ss.Stamp.build(probs[:1])
+        op1 = ss.Operator.build(st1, probs[:1])
+        f1 = st1.forcing_vector(probs[:1], dev)
+        u1 = torch.zeros_like(f1)
+        for prec in ("fp64", "fp32_refine"):
+            for i in range(21):
+                u1.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                op1.solve(f1, u1, args.tol, prec, 1000)
+                torch.cuda.synchronize()
+                if i:
+                    lat_s[prec].append(1e3 * (time.perf_counter() - t))
+            single[prec] = {"whole_path_ms_p50": float(np.median(lat_w[prec])),
+                            "whole_path_ms_p99": float(np.percentile(lat_w[prec], 99)),
+                            "solve_only_ms_p50": float(np.median(lat_s[prec]))}
+        op1.close()
+        st1.close()
+        log(f"single instance (d=10): {single}")
 
     value = B / (ms_step / 1e3)
     traffic = measured_traffic(B)
