@@ -153,10 +153,9 @@ PinRing* pin_ring() {
   return holder.ring;
 }
 
-}  // namespace
-
-hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream) {
-  if (bytes == 0) return hipSuccess;
+// A slot of `bytes` in the calling thread's pinned ring for a copy queued on `stream`; pin_submit
+// queues the copy from it and records the chunk's event behind it.
+hipError_t pin_reserve(size_t bytes, hipStream_t stream, PinChunk** out, char** host) {
   PinRing& ring = *pin_ring();
   PinChunk* c = &ring.chunk[ring.cur];
   const size_t need = (bytes + 255) & ~size_t(255);
@@ -191,12 +190,57 @@ hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream) {
     }
     c->cap = cap;
   }
-  char* h = c->host + c->used;
-  std::memcpy(h, src, bytes);
+  *out = c;
+  *host = c->host + c->used;
+  return hipSuccess;
+}
+
+hipError_t pin_submit(PinChunk* c, void* dst, const char* h, size_t bytes, hipStream_t stream) {
   hipError_t e = hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipEventRecord(c->ev, stream);
-  if (e == hipSuccess) c->used += need;
+  if (e == hipSuccess) c->used += (bytes + 255) & ~size_t(255);
   return e;
+}
+
+}  // namespace
+
+hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  PinChunk* c = nullptr;
+  char* h = nullptr;
+  hipError_t e = pin_reserve(bytes, stream, &c, &h);
+  if (e != hipSuccess) return e;
+  std::memcpy(h, src, bytes);
+  return pin_submit(c, dst, h, bytes, stream);
+}
+
+ss_status Upload::commit(void** block, hipStream_t stream) {
+  *block = nullptr;
+  size_t total = 0;
+  std::vector<size_t> off(pieces.size());
+  for (size_t i = 0; i < pieces.size(); ++i) {
+    off[i] = total;
+    total += (pieces[i].bytes + 255) & ~size_t(255);
+  }
+  hipError_t e = pool_alloc(block, std::max<size_t>(total, 256));
+  if (e != hipSuccess) {
+    *block = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EDEVICE,
+                std::string("device allocation: ") + hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(*block);
+  for (size_t i = 0; i < pieces.size(); ++i) pieces[i].point(base + off[i]);
+  if (total == 0) return SS_OK;
+  PinChunk* c = nullptr;
+  char* h = nullptr;
+  e = pin_reserve(total, stream, &c, &h);
+  if (e == hipSuccess) {
+    for (size_t i = 0; i < pieces.size(); ++i)
+      if (pieces[i].bytes) std::memcpy(h + off[i], pieces[i].host, pieces[i].bytes);
+    e = pin_submit(c, base, h, total, stream);
+  }
+  if (e != hipSuccess) return fail(SS_EDEVICE, std::string("host-to-device copy: ") + hipGetErrorString(e));
+  return SS_OK;
 }
 
 }  // namespace ss

@@ -2,7 +2,12 @@
 // parts that run concurrently: each part is built and solved by its own host thread on its own
 // stream, so the host work and the short, latency-bound build launches of one part overlap the
 // kernels of the others.  A part is an ordinary batch (stamp build, operator build, forcing,
-// solve), and every problem's result is the one it gets alone.
+// solve), and every problem's result is the one it gets alone.  The part threads are kept
+// between calls (a new thread would pay its creation, the runtime's per-thread set-up and fresh
+// pages for its reused host staging at the start of every batch).
+#include <condition_variable>
+#include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -34,6 +39,64 @@ ss_status pipeline_streams(int device, int n, std::vector<hipStream_t>* out) {
 struct PartResult {
   ss_status status = SS_OK;
   std::string error;
+};
+
+// Worker threads that run queued jobs; they live as long as the process (never joined: a job
+// never waits on another job, so a caller waiting for its own jobs cannot deadlock).
+class PartPool {
+ public:
+  static PartPool& get() {
+    static PartPool* p = new PartPool();   // never destroyed: workers may be blocked at exit
+    return *p;
+  }
+  // run f(k) for k = 1 .. n - 1 on workers and f(0) on the caller; returns when all have ended
+  void run(int n, const std::function<void(int)>& f) {
+    struct Done {
+      std::mutex mu;
+      std::condition_variable cv;
+      int left = 0;
+    } done;
+    done.left = n - 1;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      while ((int)workers_ < n - 1 + busy_) {   // at least one idle worker per queued job
+        std::thread(&PartPool::loop, this).detach();
+        ++workers_;
+      }
+      for (int k = 1; k < n; ++k)
+        jobs_.push_back([&f, &done, k]() {
+          f(k);
+          std::lock_guard<std::mutex> g(done.mu);
+          if (--done.left == 0) done.cv.notify_all();
+        });
+      busy_ += n - 1;
+    }
+    cv_.notify_all();
+    f(0);
+    std::unique_lock<std::mutex> g(done.mu);
+    done.cv.wait(g, [&]() { return done.left == 0; });
+  }
+
+ private:
+  void loop() {
+    for (;;) {
+      std::function<void()> job;
+      {
+        std::unique_lock<std::mutex> g(mu_);
+        cv_.wait(g, [&]() { return !jobs_.empty(); });
+        job = std::move(jobs_.front());
+        jobs_.pop_front();
+      }
+      job();
+      std::lock_guard<std::mutex> g(mu_);
+      --busy_;
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::function<void()>> jobs_;
+  size_t workers_ = 0;
+  int busy_ = 0;   // jobs queued or running
 };
 
 }  // namespace
@@ -115,10 +178,7 @@ ss_status batch_solve_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     pool_free(f);
     if (e != SS_OK) failed(e);
   };
-  std::vector<std::thread> th;
-  for (int k = 1; k < n_parts; ++k) th.emplace_back(run, k);
-  run(0);
-  for (auto& t : th) t.join();
+  PartPool::get().run(n_parts, run);
   // a build or device error wins over a solve that merely did not converge
   int worst = -1;
   for (int k = 0; k < n_parts; ++k) {

@@ -314,16 +314,18 @@ __global__ __launch_bounds__(kBlock) void k_neighbors_row(NbrArgs a) {
 }
 
 // one pass of min-label propagation over the neighbour relation (thread per canonical row); with
-// COUNT the pass also writes every row's entry count
-template <int K, bool COUNT>
+// COUNT the pass also writes every row's entry count; FIRST the pass reads the initial labels from
+// `init` and writes every row's label (the later passes update `label` in place)
+template <int K, bool COUNT, bool FIRST>
 __global__ void k_cc_prop(NbrView<K> v, const int32_t* __restrict__ pid, const int64_t* __restrict__ rowoff,
-                          int64_t* label, int32_t* changed, int64_t* __restrict__ rowlen) {
+                          const int64_t* init, int64_t* label, int32_t* changed, int64_t* __restrict__ rowlen) {
   const int64_t total = v.total;
   const int64_t r = xcd_block(ceil_div(total, kBlock)) * kBlock + threadIdx.x;
   if (r >= total) return;
+  const int64_t* src = FIRST ? init : label;
   const int p = pid[r];
   const int64_t base = rowoff[p];
-  const int64_t own = label[r];
+  const int64_t own = src[r];
   int64_t l = own;
   const int n = v.slots(p, r);
   int cnt = 0;
@@ -338,15 +340,13 @@ __global__ void k_cc_prop(NbrView<K> v, const int32_t* __restrict__ pid, const i
       cnt += ok[u] ? 1 : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kDenseChunk; ++u) lc[u] = ok[u] ? label[base + c[u]] : own;
+    for (int u = 0; u < kDenseChunk; ++u) lc[u] = ok[u] ? src[base + c[u]] : own;
 #pragma unroll
     for (int u = 0; u < kDenseChunk; ++u) l = lc[u] < l ? lc[u] : l;
   }
   if (COUNT) rowlen[r] = cnt;
-  if (l < own) {
-    label[r] = l;
-    *changed = 1;
-  }
+  if (FIRST || l < own) label[r] = l;
+  if (l < own) *changed = 1;
 }
 
 __global__ void k_cc_jump(int64_t total, int64_t* label) {
@@ -425,10 +425,11 @@ __global__ void k_slice_width(int64_t n_slices, const int64_t* __restrict__ exec
     w = o > w ? o : w;
   }
   if ((g & 63) == 0) width[sl] = (uint32_t)(w * kSlice);
+  if (g == 0) width[n_slices] = 0;   // the scan's last element: the total
 }
 
 // 1 where a position of `order` (sorted rows) starts a new class: first row of a problem,
-// or a class change
+// or a class change; flag[n] = 0 (the scan's last element: the class count)
 __global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ order, const int64_t* __restrict__ label,
                                     const int32_t* __restrict__ pid, uint32_t* __restrict__ flag) {
   const int64_t q = xcd_tid();
@@ -440,6 +441,7 @@ __global__ void k_class_start_flags(int64_t n, const uint32_t* __restrict__ orde
     f = (pid[rp] != pid[r] || label[rp] != label[r]) ? 1u : 0u;
   }
   flag[q] = f;
+  if (q == 0) flag[n] = 0;
 }
 
 __global__ void k_compact_starts(int64_t n, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
@@ -648,17 +650,19 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   track(label);
   SS_TRY(dalloc(&changed, 1));
   track(changed);
-  SS_HIP(hipMemcpyAsync(label, st->d_root, total * 8, hipMemcpyDeviceToDevice, stream));
   for (int it = 0; it < 100000; ++it) {
     int32_t h = 0;
     SS_HIP(hipMemsetAsync(changed, 0, 4, stream));
     with_view([&](auto v) {
       constexpr int K = decltype(v)::kKind;
       const unsigned g = xcd_grid(ceil_div(total, kBlock));
-      if (K != kCompact && it == 0)   // the first pass also counts the entries of every row
-        k_cc_prop<K, true><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, label, changed, rowlen);
+      // the first pass starts from the roots and also counts the entries of every row
+      if (K != kCompact && it == 0)
+        k_cc_prop<K, true, true><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, st->d_root, label, changed, rowlen);
+      else if (it == 0)
+        k_cc_prop<K, false, true><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, st->d_root, label, changed, rowlen);
       else
-        k_cc_prop<K, false><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, label, changed, rowlen);
+        k_cc_prop<K, false, false><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, nullptr, label, changed, rowlen);
     });
     k_cc_jump<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, label);
     SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
@@ -708,7 +712,6 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&cidx, total + 1));
   track(cidx);
   k_class_start_flags<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, ev2, label, st->d_pid, cflag);
-  SS_HIP(hipMemsetAsync(cflag + total, 0, 4, stream));
   std::vector<int64_t> cq;   // sorted position of every class start
   {
     size_t tb = 0;
@@ -769,16 +772,14 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   op->n_slices = op->n_exec / kSlice;
   if (op->n_slices * (int64_t)kMaxA * kSlice >= (int64_t(1) << 32))
     return fail(SS_ERANGE, "batch too large for 32-bit SELL offsets (split it)");
-  SS_TRY(dalloc(&op->d_eoff, n_prob + 1));
-  SS_HIP(h2d(op->d_eoff, op->eoff.data(), (n_prob + 1) * 8, stream));
+  // problem offsets (kept) and the class starts of the execution map, one transfer
   int64_t *d_cq0 = nullptr, *d_ce0 = nullptr;
-  SS_TRY(dalloc(&d_cq0, std::max<int64_t>(n_cls, 1)));
-  track(d_cq0);
-  SS_TRY(dalloc(&d_ce0, std::max<int64_t>(n_cls, 1)));
-  track(d_ce0);
-  if (n_cls) {
-    SS_HIP(h2d(d_cq0, cq.data(), n_cls * 8, stream));
-    SS_HIP(h2d(d_ce0, ce0.data(), n_cls * 8, stream));
+  {
+    Upload up;
+    up.add(&op->d_eoff, op->eoff.data(), n_prob + 1);
+    up.add(&d_cq0, cq.data(), n_cls);
+    up.add(&d_ce0, ce0.data(), n_cls);
+    SS_TRY(up.commit(&op->d_upload[0], stream));
   }
   SS_TRY(dalloc(&op->d_exec2canon, op->n_exec));
   SS_TRY(dalloc(&op->d_canon2exec, total));
@@ -793,7 +794,6 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   SS_TRY(dalloc(&op->d_sptr, op->n_slices + 1));
   k_slice_width<<<xcd_grid(ceil_div(op->n_slices * kSlice, kBlock)), kBlock, 0, stream>>>(op->n_slices, op->d_exec2canon, rowlen,
                                                                         width);
-  SS_HIP(hipMemsetAsync(width + op->n_slices, 0, 4, stream));
   {
     size_t tb = 0;
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, width, op->d_sptr, op->n_slices + 1, stream));
@@ -922,22 +922,17 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     op->unit_entries[i] = (int32_t)(sptr_h[un.y + un.z] - sptr_h[un.y]);
     op->unit_ebase[i] = sptr_h[un.y];
   }
-  if (!op->units.empty()) {
-    SS_TRY(dalloc(&op->d_units, op->units.size()));
-    SS_HIP(h2d(op->d_units, op->units.data(), op->units.size() * sizeof(int4), stream));
+  {   // the operator's launch tables and coefficient tables, one transfer
+    Upload up;
+    if (!op->units.empty()) up.add(&op->d_units, op->units.data(), op->units.size());
+    up.add(&op->d_work, op->work.data(), op->work.size());
+    up.add(&op->d_wrange, op->wrange.data(), n_prob);
+    up.add(&op->d_A64, A64.data(), A64.size());
+    up.add(&op->d_A32, A32.data(), A32.size());
+    up.add(&op->d_nu, nu.data(), nu.size());
+    up.add(&op->d_a0, a0.data(), n_prob);
+    SS_TRY(up.commit(&op->d_upload[1], stream));
   }
-  SS_TRY(dalloc(&op->d_work, op->work.size()));
-  SS_TRY(dalloc(&op->d_wrange, n_prob));
-  SS_TRY(dalloc(&op->d_A64, A64.size()));
-  SS_TRY(dalloc(&op->d_A32, A32.size()));
-  SS_TRY(dalloc(&op->d_nu, nu.size()));
-  SS_TRY(dalloc(&op->d_a0, n_prob));
-  SS_HIP(h2d(op->d_work, op->work.data(), op->work.size() * sizeof(int4), stream));
-  SS_HIP(h2d(op->d_wrange, op->wrange.data(), n_prob * sizeof(int2), stream));
-  SS_HIP(h2d(op->d_A64, A64.data(), A64.size() * sizeof(double2), stream));
-  SS_HIP(h2d(op->d_A32, A32.data(), A32.size() * sizeof(float2), stream));
-  SS_HIP(h2d(op->d_nu, nu.data(), nu.size() * 8, stream));
-  SS_HIP(h2d(op->d_a0, a0.data(), n_prob * 8, stream));
   SS_HIP(hipStreamSynchronize(stream));
   *out = guard.release();
   return SS_OK;
@@ -952,14 +947,8 @@ void free_op_impl(OpImpl* op) {
   dfree(op->d_sptr);
   if (op->d_norm) pool_free(op->d_norm);
   op->d_norm = nullptr;
-  dfree(op->d_eoff);
-  dfree(op->d_work);
-  dfree(op->d_units);
-  dfree(op->d_wrange);
-  dfree(op->d_A64);
-  dfree(op->d_A32);
-  dfree(op->d_nu);
-  dfree(op->d_a0);
+  dfree(op->d_upload[0]);   // d_eoff is a view into it
+  dfree(op->d_upload[1]);   // d_units, d_work, d_wrange, d_A64, d_A32, d_nu and d_a0 are views into it
   if (op->ws.base) pool_free(op->ws.base);
   if (op->h_pinned) (void)hipHostFree(op->h_pinned);
   free_apply_cache(op);

@@ -1729,11 +1729,6 @@ struct UnitBatch {
     P.make(launched);
     const int nu = P.n_units();
     UnitDev D;
-    SS_TRY(alloc(&D.desc, np));
-    SS_TRY(alloc(&D.ul, nu));
-    SS_TRY(alloc(&D.ue, nu));
-    SS_TRY(alloc(&D.uoff, np + 1));
-    SS_TRY(alloc(&D.uidx, nu));
     SS_TRY(alloc(&D.out, nu));
     SS_TRY(alloc(&D.sum, np));
     if ((size_t)np > h_cap) {
@@ -1742,11 +1737,18 @@ struct UnitBatch {
       h_cap = std::max<size_t>(np, 2 * h_cap);
       SS_HIP(hipHostMalloc((void**)&h_sum, h_cap * sizeof(UnitSum), hipHostMallocDefault));
     }
-    SS_HIP(h2d(D.desc, P.descs.data(), np * sizeof(UDesc), s));
-    SS_HIP(h2d(D.ul, P.ul.data(), nu * sizeof(int4), s));
-    SS_HIP(h2d(D.ue, P.ue.data(), nu * sizeof(uint2), s));
-    SS_HIP(h2d(D.uoff, P.uoff.data(), (np + 1) * 4, s));
-    SS_HIP(h2d(D.uidx, P.uidx.data(), nu * 4, s));
+    {   // descriptors and unit lists, one transfer
+      Upload up;
+      up.add(&D.desc, P.descs.data(), np);
+      up.add(&D.ul, P.ul.data(), nu);
+      up.add(&D.ue, P.ue.data(), nu);
+      up.add(&D.uoff, P.uoff.data(), np + 1);
+      up.add(&D.uidx, P.uidx.data(), nu);
+      void* block = nullptr;
+      const ss_status e = up.commit(&block, s);
+      if (block) dev.push_back(block);
+      SS_TRY(e);
+    }
     SS_TRY(launch_unit_plan(P, D, s));
     SS_HIP(hipMemcpyAsync(h_sum, D.sum, np * sizeof(UnitSum), hipMemcpyDeviceToHost, s));
     return SS_OK;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -116,6 +117,24 @@ __host__ __device__ inline uint64_t lat_mulmod(uint64_t a, uint64_t b) {   // a,
 __host__ __device__ inline uint64_t lat_add(uint64_t a, uint64_t b) { return lat_fold(a + b); }
 __host__ __device__ inline uint64_t lat_sub(uint64_t a, uint64_t b) { return lat_fold(a + (kLatM - b)); }
 __host__ __device__ inline uint64_t lat_of_coord(int v) { return v >= 0 ? (uint64_t)v : kLatM - (uint64_t)(-v); }
+// k . z mod M of a key with int16 coordinates, accumulated without a 128-bit product per
+// coordinate: with z_t = zh_t 2^31 + zl_t (zl_t < 2^31, zh_t < 2^30) the sums lo = sum k_t zl_t
+// and hi = sum k_t zh_t are exact in int64 for d <= 1024, and since 2^61 = 1 mod M,
+// hi 2^31 = (hi >> 30) 2^61 + (hi mod 2^30) 2^31 = (hi >> 30) + (hi mod 2^30) 2^31 (mod M).
+// Partial sums over different coordinates add (lanes of a wavefront combine theirs).
+struct LatAcc {
+  int64_t lo = 0, hi = 0;
+  __host__ __device__ void add(int v, uint64_t z) {
+    lo += (int64_t)v * (int64_t)(int32_t)(z & 0x7fffffffu);
+    hi += (int64_t)v * (int64_t)(int32_t)(z >> 31);
+  }
+  __host__ __device__ uint64_t value() const {
+    int64_t t = (hi >> 30) + ((hi & ((int64_t(1) << 30) - 1)) << 31) + lo;   // |t| < 2^62
+    if (t < 0) t += (int64_t)kLatM;
+    if (t >= (int64_t)kLatM) t -= (int64_t)kLatM;
+    return (uint64_t)t;
+  }
+};
 
 inline uint64_t splitmix64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ULL;
@@ -162,11 +181,12 @@ struct StampImpl {
   uint64_t* d_latz = nullptr;          // [d] rank-1 lattice generating vector (entries in [1, M - 1])
   uint64_t* d_lat = nullptr;           // [total] lattice value k . z mod M of every key
   uint64_t* d_alat = nullptr;          // [sum s] lattice value of every a-table entry
+  void* d_upload = nullptr;            // one block holding d_akeys .. d_alat and d_coef, d_latz (views)
   uint64_t* d_table = nullptr;         // build only: one word per slot (MAIN / CAND words)
   uint64_t* d_ltable = nullptr;        // lookups: one word per slot, the same positions:
                                        // (hash >> 32) << 32 | (canonical index + 1), 0 = empty
   int64_t* d_toff = nullptr;           // [n_prob] first slot of each problem's region
-  uint64_t* d_tmask = nullptr;         // [n_prob] region size - 1
+  uint64_t* d_tmask = nullptr;         // [n_prob] region size - 1 (a view: d_toff + n_prob)
   uint64_t n_slots = 0;
   std::vector<uint64_t> tcap;
   int64_t max_norm = 0;
@@ -250,6 +270,7 @@ struct OpImpl {
   float2* d_A32 = nullptr;
   int64_t* d_nu = nullptr;
   double* d_a0 = nullptr;
+  void* d_upload[2] = {nullptr, nullptr};   // blocks holding d_eoff, then d_units .. d_a0 (views)
   // solver workspace (lazily allocated, reused)
   struct Work {
     size_t bytes = 0;
@@ -392,6 +413,26 @@ void dfree(T*& p) {
   pool_free((void*)p);
   p = nullptr;
 }
+
+// Small host arrays sent to the device in one transfer: every array gets a 256-byte aligned slice
+// of one pooled device block, and the arrays are staged side by side in the thread's pinned
+// buffer, so a build phase pays one copy (and one host call) instead of one per array.  The block
+// belongs to the caller (released with pool_free); the slices are views into it and are never
+// freed on their own.
+struct Upload {
+  struct Piece {
+    std::function<void(char*)> point;   // sets the caller's device pointer to its slice
+    const void* host;
+    size_t bytes;
+  };
+  std::vector<Piece> pieces;
+  template <typename T>
+  void add(T** dev, const T* host, size_t count) {
+    pieces.push_back(Piece{[dev](char* q) { *dev = reinterpret_cast<T*>(q); }, host, count * sizeof(T)});
+  }
+  // allocates the block into *block, points every slice into it and queues the copy on `stream`
+  ss_status commit(void** block, hipStream_t stream);
+};
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -373,19 +373,22 @@ __global__ __launch_bounds__(kBlock) void k_permute_rows_wide(
     const int64_t s = perm[r];
     const int16_t* src = ukeys + s * d;
     int16_t* dst = keys + r * d;
-    uint64_t h = 0, lv_ = 0;
+    uint64_t h = 0;
+    LatAcc la;
     for (int t = lane; t < d; t += 64) {
       const int v = src[t];
       dst[t] = (int16_t)v;
       h += (uint64_t)(int64_t)v * z[t];
       nn += (int64_t)v * v;
-      if (v) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord(v), lz[t]));
+      la.add(v, lz[t]);
     }
     for (int m = 32; m > 0; m >>= 1) {
       h += shfl_xor_u64(h, m);
       nn += (int64_t)shfl_xor_u64((uint64_t)nn, m);
-      lv_ = lat_add(lv_, shfl_xor_u64(lv_, m));
+      la.lo += (int64_t)shfl_xor_u64((uint64_t)la.lo, m);
+      la.hi += (int64_t)shfl_xor_u64((uint64_t)la.hi, m);
     }
+    const uint64_t lv_ = la.value();
     if (lane == 0) {
       int lvl = 0;
       for (int q = 1; q < n_lev; ++q) lvl = lstart[q] <= s ? q : lvl;
@@ -425,7 +428,8 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
     const int64_t s = perm[r];
     const int16_t* src = ukeys + s * d;
     int16_t* dst = keys + r * d;
-    uint64_t h = 0, lv_ = 0;
+    uint64_t h = 0;
+    LatAcc la;
     if ((d & 1) == 0) {
       const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
       uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
@@ -435,8 +439,8 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
         const int64_t lo = (int16_t)(w & 0xffffu), hi = (int16_t)(w >> 16);
         h += (uint64_t)lo * z[t] + (uint64_t)hi * z[t + 1];
         nn += lo * lo + hi * hi;
-        if (lo) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)lo), lz[t]));
-        if (hi) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)hi), lz[t + 1]));
+        la.add((int)lo, lz[t]);
+        la.add((int)hi, lz[t + 1]);
       }
     } else {
       for (int t = 0; t < d; ++t) {
@@ -444,10 +448,10 @@ __global__ void k_permute_rows(int64_t n, int d, const uint32_t* __restrict__ pe
         dst[t] = (int16_t)v;
         h += (uint64_t)v * z[t];
         nn += v * v;
-        if (v) lv_ = lat_add(lv_, lat_mulmod(lat_of_coord((int)v), lz[t]));
+        la.add((int)v, lz[t]);
       }
     }
-    lat[r] = lv_;
+    lat[r] = la.value();
     int lv = 0;
     for (int q = 1; q < n_lev; ++q) lv = lstart[q] <= s ? q : lv;
     hash[r] = h;
@@ -637,12 +641,11 @@ constexpr int kSlotsPerKey = 4;
 ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t n, const uint64_t* hash,
                        const int32_t* pid, hipStream_t stream) {
   const int np = st->n_prob;
-  std::vector<int64_t> off(np);
-  std::vector<uint64_t> mask(np);
+  std::vector<uint64_t> om(2 * (size_t)np);   // region offsets, then region masks
   uint64_t total = 0;
   for (int p = 0; p < np; ++p) {
-    off[p] = (int64_t)total;
-    mask[p] = cap[p] - 1;
+    om[p] = total;
+    om[np + p] = cap[p] - 1;
     total += cap[p];
   }
   if (total >= (uint64_t(1) << 40)) return fail(SS_ERANGE, "hash table too large");
@@ -651,11 +654,12 @@ ss_status layout_table(StampImpl* st, const std::vector<uint64_t>& cap, int64_t 
     dfree(st->d_table);
   }
   SS_TRY(dalloc(&st->d_table, total));
-  if (!st->d_toff) SS_TRY(dalloc(&st->d_toff, np));
-  if (!st->d_tmask) SS_TRY(dalloc(&st->d_tmask, np));
+  if (!st->d_toff) {   // offsets and masks in one block (d_tmask is a view into it)
+    SS_TRY(dalloc(&st->d_toff, 2 * (size_t)np));
+    st->d_tmask = reinterpret_cast<uint64_t*>(st->d_toff + np);
+  }
   SS_HIP(hipMemsetAsync(st->d_table, 0, total * 8, stream));
-  SS_HIP(h2d(st->d_toff, off.data(), np * 8, stream));
-  SS_HIP(h2d(st->d_tmask, mask.data(), np * 8, stream));
+  SS_HIP(h2d(st->d_toff, om.data(), om.size() * 8, stream));
   st->n_slots = total;
   st->tcap = cap;
   if (n > 0) k_insert_main<<<grid_for(n), kBlock, 0, stream>>>(n, hash, pid, st->d_toff, st->d_tmask, st->d_table);
@@ -845,23 +849,19 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       return fail(SS_ERANGE, "a stamped frequency coordinate leaves the int16 range");
   SS_HIP(hipGetDevice(&st->device));
 
-  // ---- device a-tables (kept by the stamp)
-  SS_TRY(dalloc(&st->d_akeys, st->a_keys.size()));
-  SS_TRY(dalloc(&st->d_ahash, ahash.size()));
-  SS_TRY(dalloc(&st->d_anorm, anorm.size()));
-  SS_TRY(dalloc(&st->d_aoff, n_prob + 1));
-  SS_TRY(dalloc(&st->d_azero, n_prob));
-  SS_TRY(dalloc(&st->d_coef, d));
-  SS_TRY(dalloc(&st->d_latz, d));
-  SS_TRY(dalloc(&st->d_alat, alat.size()));
-  SS_HIP(h2d(st->d_latz, lz.data(), d * 8, stream));
-  SS_HIP(h2d(st->d_alat, alat.data(), alat.size() * 8, stream));
-  SS_HIP(h2d(st->d_akeys, st->a_keys.data(), st->a_keys.size() * 2, stream));
-  SS_HIP(h2d(st->d_ahash, ahash.data(), ahash.size() * 8, stream));
-  SS_HIP(h2d(st->d_anorm, anorm.data(), anorm.size() * 8, stream));
-  SS_HIP(h2d(st->d_aoff, st->a_off.data(), (n_prob + 1) * 4, stream));
-  SS_HIP(h2d(st->d_azero, st->a_zero.data(), n_prob * 4, stream));
-  SS_HIP(h2d(st->d_coef, z.data(), d * 8, stream));
+  // ---- device a-tables (kept by the stamp), one transfer
+  {
+    Upload up;
+    up.add(&st->d_latz, lz.data(), d);
+    up.add(&st->d_alat, alat.data(), alat.size());
+    up.add(&st->d_akeys, st->a_keys.data(), st->a_keys.size());
+    up.add(&st->d_ahash, ahash.data(), ahash.size());
+    up.add(&st->d_anorm, anorm.data(), anorm.size());
+    up.add(&st->d_aoff, st->a_off.data(), n_prob + 1);
+    up.add(&st->d_azero, st->a_zero.data(), n_prob);
+    up.add(&st->d_coef, z.data(), d);
+    SS_TRY(up.commit(&st->d_upload, stream));
+  }
 
   // ---- build scratch
   Scratch sc(stream);
@@ -880,24 +880,25 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   const bool wide = d >= kWideD;
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
-  sc.hold(wk); sc.hold(wh); sc.hold(wo); sc.hold(plev);
+  void* d_in = nullptr;   // wk, wh, wo and plev are views into it
+  sc.hold(d_in);
   sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot);
   sc.hold(ulast); sc.hold(d_full);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp); sc.hold(ccnt); sc.hold(coff); sc.hold(cand); sc.hold(wsrc);
-  sc.hold(d_fstart); sc.hold(d_fcount); sc.hold(d_cnt);
-  SS_TRY(dalloc(&wk, wkeys.size()));
-  SS_TRY(dalloc(&wh, whash.size()));
-  SS_TRY(dalloc(&wo, n_prob + 1));
-  SS_TRY(dalloc(&plev, n_prob));
-  SS_TRY(dalloc(&d_fstart, n_prob));
-  SS_TRY(dalloc(&d_fcount, n_prob));
+  sc.hold(d_fstart); sc.hold(d_cnt);
+  {
+    Upload up;
+    up.add(&wk, wkeys.data(), wkeys.size());
+    up.add(&wh, whash.data(), whash.size());
+    up.add(&wo, woff.data(), n_prob + 1);
+    up.add(&plev, level, n_prob);
+    SS_TRY(up.commit(&d_in, stream));
+  }
+  SS_TRY(dalloc(&d_fstart, 2 * (size_t)n_prob));   // the level's frontier starts, then its counts
+  d_fcount = d_fstart + n_prob;
   SS_TRY(dalloc(&d_cnt, n_prob));
   SS_TRY(dalloc(&d_full, n_prob));
   SS_HIP(hipMemsetAsync(d_full, 0, n_prob, stream));
-  if (!wkeys.empty()) SS_HIP(h2d(wk, wkeys.data(), wkeys.size() * 2, stream));
-  if (!whash.empty()) SS_HIP(h2d(wh, whash.data(), whash.size() * 8, stream));
-  SS_HIP(h2d(wo, woff.data(), (n_prob + 1) * 4, stream));
-  SS_HIP(h2d(plev, level, n_prob * 4, stream));
 
   // ---- level 0: F
   // The rows of every level fit the App. A count of the whole build (a bound on |S^N| for any a):
@@ -934,7 +935,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   }
   SS_TRY(layout_table(st, cap, nF, uhash, upid, stream));
 
-  std::vector<int64_t> cnt(n_prob), fstart(n_prob), fcount(n_prob);
+  std::vector<int64_t> cnt(n_prob), front(2 * (size_t)n_prob);   // front: starts, then counts
+  int64_t* fstart = front.data();
+  int64_t* fcount = front.data() + n_prob;
   for (int p = 0; p < n_prob; ++p) {
     cnt[p] = n_f[p];
     fstart[p] = f_off[p];
@@ -992,8 +995,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     ExpandArgs ea{n_cand, coff + n_front, cand, d, ukeys, uhash, upid, wk, wh, wo, st->d_toff, st->d_tmask,
                   st->d_table, cpos};
     const unsigned cg = grid_for(n_cand);
-    SS_HIP(h2d(d_fstart, fstart.data(), n_prob * 8, stream));
-    SS_HIP(h2d(d_fcount, fcount.data(), n_prob * 8, stream));
+    SS_HIP(h2d(d_fstart, front.data(), front.size() * 8, stream));
     std::vector<int64_t> added(n_prob);
     auto scan_u32 = [&](const uint32_t* in, uint32_t* out, int64_t n_items) -> ss_status {
       size_t need_tmp = 0;
@@ -1217,9 +1219,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   SS_TRY(dalloc(&st->d_lev, total));
   SS_TRY(dalloc(&st->d_norm, total));
   SS_TRY(dalloc(&st->d_root, total));
-  SS_TRY(dalloc(&st->d_rowoff, n_prob + 1));
+  SS_TRY(dalloc(&st->d_rowoff, n_prob + 2));   // row offsets, then the largest |k|^2 (read back together)
   uint32_t* inv = perm2;
-  unsigned long long* d_maxn = (unsigned long long*)k64;
+  unsigned long long* d_maxn = reinterpret_cast<unsigned long long*>(st->d_rowoff + n_prob + 1);
   SS_HIP(hipMemsetAsync(d_maxn, 0, 8, stream));
   // the problem id sits at the top of the words the last sort ordered (k64b)
   const int pid_bits = bits_for((uint64_t)(n_prob - 1));
@@ -1259,12 +1261,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     st->d_table = nullptr;
   }
   k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, n_prob, st->d_pid, st->d_rowoff);
-  unsigned long long maxn = 0;
-  st->row_off.assign(n_prob + 1, 0);
-  SS_HIP(hipMemcpyAsync(&maxn, d_maxn, 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 1) * 8, hipMemcpyDeviceToHost, stream));
+  st->row_off.assign(n_prob + 2, 0);
+  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 2) * 8, hipMemcpyDeviceToHost, stream));
   SS_HIP(hipStreamSynchronize(stream));
-  st->max_norm = (int64_t)maxn;
+  st->max_norm = st->row_off[n_prob + 1];
+  st->row_off.pop_back();
   for (int p = 0; p < n_prob; ++p)
     if (st->row_off[p + 1] - st->row_off[p] > kMaxRowsPerProblem)
       return fail(SS_ERANGE, "a stamping set exceeds 4194303 keys");
@@ -1275,11 +1276,7 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
 void free_stamp_impl(StampImpl* st) {
   if (!st) return;
   dfree(st->d_fslot);
-  dfree(st->d_akeys);
-  dfree(st->d_ahash);
-  dfree(st->d_anorm);
-  dfree(st->d_aoff);
-  dfree(st->d_azero);
+  dfree(st->d_upload);   // the a-table arrays are views into it
   dfree(st->d_keys);
   dfree(st->d_lev);
   dfree(st->d_norm);
@@ -1287,14 +1284,10 @@ void free_stamp_impl(StampImpl* st) {
   dfree(st->d_pid);
   dfree(st->d_root);
   dfree(st->d_rowoff);
-  dfree(st->d_coef);
-  dfree(st->d_latz);
   dfree(st->d_lat);
-  dfree(st->d_alat);
   dfree(st->d_table);
   dfree(st->d_ltable);
-  dfree(st->d_toff);
-  dfree(st->d_tmask);
+  dfree(st->d_toff);   // d_tmask is a view into it
   delete st;
 }
 
