@@ -127,6 +127,40 @@ def test_solve_batch_parts_equal_alone(ss):
         ss.solve_batch([probs[0], bad], 1e-10, "fp64", 1000, 0, parts=2)
 
 
+def test_solve_batch_concurrent_callers(ss):
+    # two callers of the batch pipeline at once (its part threads are shared and kept between
+    # calls): every result equals the same call made alone, bit for bit, on every repetition
+    import threading
+    sets = [([workloads.make(2, i, level=2) for i in range(6)], 3, "fp64"),
+            ([workloads.make(4, i) for i in range(3)] , 4, "fp32_refine")]
+    alone = []
+    for probs, parts, prec in sets:
+        res, infos = ss.solve_batch(probs, 1e-10, prec, 1000, 0, parts=parts)
+        alone.append((res.solution().cpu().numpy(), [i["iters"] for i in infos]))
+        res.close()
+    out, errors = {}, []
+
+    def caller(k):
+        try:
+            probs, parts, prec = sets[k]
+            for rep in range(3):
+                res, infos = ss.solve_batch(probs, 1e-10, prec, 1000, 0, parts=parts)
+                out[(k, rep)] = (res.solution().cpu().numpy(), [i["iters"] for i in infos])
+                res.close()
+        except BaseException as e:   # surfaced below
+            errors.append(e)
+
+    th = [threading.Thread(target=caller, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=300)
+    assert not any(t.is_alive() for t in th) and not errors, errors
+    for (k, rep), (u, iters) in out.items():
+        assert np.array_equal(u, alone[k][0]) and iters == alone[k][1], (k, rep)
+    assert len(out) == 6
+
+
 def test_forcing_vector_matches_oracle_slots(ss):
     # f_hat placed at the slots the build recorded for F equals the oracle's f on S^N
     cases = [oracle_case(2, i, level=lv) for i, lv in ((0, 1), (1, 0), (2, 2))]
