@@ -254,8 +254,10 @@ __device__ void mv_body(const Desc& D, int4 wk, int w, double* part, char* lds) 
     const int64_t e = (sl - D.slice0) * kSlice + lane;
     const uint32_t base = D.sptr[sl];
     const uint32_t width = (D.sptr[sl + 1] - base) / kSlice;
+    // a window item's own rows lie inside its window (its classes and their padding rows), so the
+    // row's |k|^2 comes from the staged copy rather than a second read from HBM
     const V acc = wlen > 0
-                      ? sell_row<true, NormT, V>(D.sent, base, width, lane, normv[e], nw, xw, w0, As, nus)
+                      ? sell_row<true, NormT, V>(D.sent, base, width, lane, nw[e - w0], nw, xw, w0, As, nus)
                       : sell_row<false, NormT, V>(D.sent, base, width, lane, normv[e], normv, x, 0, As, nus);
     if (MODE == MV_PLAIN) {
       st_nt(y + e, acc);
