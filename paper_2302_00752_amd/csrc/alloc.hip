@@ -100,6 +100,116 @@ void pool_free(void* p) {
   P.live.erase(it);
 }
 
+// ---------------------------------------------------------------- pinned result buffers
+// Pinned host memory for the small device-to-host result buffers of a solve (per-problem sums and
+// states).  hipHostMalloc is slow and hipHostFree waits for the device -- in the batch pipeline
+// one part's free stalled behind the other parts' kernels for milliseconds -- so these buffers
+// are cached like device blocks: size classes, per-device free lists, never returned to the
+// driver (so a small class is allocated in slabs of several blocks).  A buffer is released only after the stream that filled it has been synchronised.
+
+namespace {
+
+constexpr size_t kPinnedSlab = 8;   // blocks per allocation of a small pinned class
+
+Pool& pinned_pool() {
+  static Pool* p = new Pool();   // never destroyed, like the device pool
+  return *p;
+}
+
+}  // namespace
+
+hipError_t pinned_alloc(void** out, size_t bytes) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t cls = size_class(bytes);
+  Pool& P = pinned_pool();
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    auto it = P.free_blocks.find({dev, cls});
+    if (it != P.free_blocks.end() && !it->second.empty()) {
+      *out = it->second.back();
+      it->second.pop_back();
+      P.cached_bytes -= cls;
+      P.live[*out] = {dev, cls};
+      return hipSuccess;
+    }
+  }
+  // a miss takes a slab of several blocks of the class (small classes): concurrent solves then
+  // find their buffers cached after the first one, instead of each paying an allocation that
+  // also disturbs the work in flight
+  const size_t n = cls <= (size_t(64) << 10) ? kPinnedSlab : 1;
+  char* slab = nullptr;
+  e = hipHostMalloc((void**)&slab, n * cls, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return e;
+  }
+  std::lock_guard<std::mutex> g(P.mu);
+  *out = slab;
+  P.live[*out] = {dev, cls};
+  for (size_t i = 1; i < n; ++i) {
+    P.free_blocks[{dev, cls}].push_back(slab + i * cls);
+    P.cached_bytes += cls;
+  }
+  return hipSuccess;
+}
+
+void pinned_free(void* p) {
+  if (!p) return;
+  Pool& P = pinned_pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  auto it = P.live.find(p);
+  if (it == P.live.end()) return;
+  P.free_blocks[it->second].push_back(p);
+  P.cached_bytes += it->second.second;
+  P.live.erase(it);
+}
+
+namespace {
+
+struct ReadbackBuf {   // the calling thread's pinned staging of device-to-host reads
+  char* p = nullptr;
+  size_t cap = 0;
+  ~ReadbackBuf() { pinned_free(p); }   // back to the cache: no device call here
+};
+thread_local ReadbackBuf t_readback;
+
+}  // namespace
+
+ss_status Readback::add(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return SS_OK;
+  size_t off = (used + 255) & ~size_t(255);
+  if (off + bytes > t_readback.cap) {
+    if (!parts.empty()) {   // the queued copies target the current buffer
+      SS_TRY(sync());
+      off = 0;
+    }
+    pinned_free(t_readback.p);
+    t_readback.p = nullptr;
+    const size_t cap = std::max({bytes, 2 * t_readback.cap, size_t(64) << 10});
+    t_readback.cap = 0;
+    const hipError_t e = pinned_alloc((void**)&t_readback.p, cap);
+    if (e != hipSuccess) return fail(SS_ENOMEM, std::string("pinned allocation: ") + hipGetErrorString(e));
+    t_readback.cap = cap;
+  }
+  const hipError_t e = hipMemcpyAsync(t_readback.p + off, src, bytes, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return fail(SS_EDEVICE, std::string("device-to-host copy: ") + hipGetErrorString(e));
+  parts.push_back(Part{dst, off, bytes});
+  used = off + bytes;
+  return SS_OK;
+}
+
+ss_status Readback::sync() {
+  const hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(SS_EDEVICE, std::string("stream synchronisation: ") + hipGetErrorString(e));
+  for (const Part& q : parts) std::memcpy(q.dst, t_readback.p + q.off, q.bytes);
+  parts.clear();
+  used = 0;
+  return SS_OK;
+}
+
 // ---------------------------------------------------------------- pinned staging of uploads
 // A copy from pageable host memory is staged by the runtime and holds the calling thread until
 // the stream has reached it, which drains the stream before the next launch is even issued.

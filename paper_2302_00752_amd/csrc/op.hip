@@ -665,8 +665,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
         k_cc_prop<K, false, false><<<g, kBlock, 0, stream>>>(v, st->d_pid, st->d_rowoff, nullptr, label, changed, rowlen);
     });
     k_cc_jump<<<xcd_grid(ceil_div(total, kBlock)), kBlock, 0, stream>>>(total, label);
-    SS_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
+    Readback rb(stream);
+    SS_TRY(rb.add(&h, changed, 4));
+    SS_TRY(rb.sync());
     if (!h) break;
   }
   // entries per problem (read back with the slice offsets below)
@@ -721,8 +722,9 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
     track(t);
     SS_HIP(hipcub::DeviceScan::ExclusiveSum(t, tb, cflag, cidx, total + 1, stream));
     uint32_t n_cls = 0;
-    SS_HIP(hipMemcpyAsync(&n_cls, cidx + total, 4, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
+    Readback rb(stream);
+    SS_TRY(rb.add(&n_cls, cidx + total, 4));
+    SS_TRY(rb.sync());
     int64_t* d_cq = nullptr;
     SS_TRY(dalloc(&d_cq, std::max<uint32_t>(n_cls, 1)));
     track(d_cq);
@@ -732,8 +734,8 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
       k_class_min<<<xcd_grid(ceil_div((int64_t)n_cls * 64, kBlock)), kBlock, 0, stream>>>(
           n_cls, total, d_cq, ev2, st->d_pid, st->d_rowoff, op->d_comp);
     cq.resize(n_cls);
-    if (n_cls) SS_HIP(hipMemcpyAsync(cq.data(), d_cq, n_cls * 8, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
+    SS_TRY(rb.add(cq.data(), d_cq, n_cls * 8));
+    SS_TRY(rb.sync());
   }
   op->comps.assign(n_prob, 0);
   for (int64_t q : cq) {
@@ -804,10 +806,13 @@ ss_status build_op_impl(const StampImpl* st, const int32_t* n_a, const int16_t* 
   }
   thread_local std::vector<uint32_t> sptr_h;   // slice entry offsets, for sizing solve units
   sptr_h.resize(op->n_slices + 1);
-  SS_HIP(hipMemcpyAsync(sptr_h.data(), op->d_sptr, (op->n_slices + 1) * 4, hipMemcpyDeviceToHost, stream));
   op->nnz_p.resize(n_prob);
-  SS_HIP(hipMemcpyAsync(op->nnz_p.data(), d_nnzp, n_prob * 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
+  {
+    Readback rb(stream);
+    SS_TRY(rb.add(sptr_h.data(), op->d_sptr, (op->n_slices + 1) * 4));
+    SS_TRY(rb.add(op->nnz_p.data(), d_nnzp, n_prob * 8));
+    SS_TRY(rb.sync());
+  }
   op->nnz = 0;
   for (int p = 0; p < n_prob; ++p) op->nnz += op->nnz_p[p];
   const uint32_t n_sell = sptr_h[op->n_slices];

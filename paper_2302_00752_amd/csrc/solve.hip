@@ -1694,13 +1694,13 @@ struct UnitBatch {
   std::vector<Item> items;
   // after launch(): per item (launch order), its results on the host once the stream is synced
   std::vector<Item> launched;
-  UnitSum* h_sum = nullptr;       // pinned
+  UnitSum* h_sum = nullptr;       // pinned (cached: pinned_alloc)
   size_t h_cap = 0;
   std::vector<void*> dev;         // device blocks of the launch in flight
 
-  ~UnitBatch() {
+  ~UnitBatch() {   // the owner has synchronised the stream of a launch in flight
     release();
-    if (h_sum) (void)hipHostFree(h_sum);
+    pinned_free(h_sum);
   }
   void release() {
     for (void* q : dev) pool_free(q);
@@ -1734,10 +1734,10 @@ struct UnitBatch {
     SS_TRY(alloc(&D.out, nu));
     SS_TRY(alloc(&D.sum, np));
     if ((size_t)np > h_cap) {
-      if (h_sum) (void)hipHostFree(h_sum);
+      pinned_free(h_sum);   // no copy into it is pending: the last launch's results were read
       h_sum = nullptr;
       h_cap = std::max<size_t>(np, 2 * h_cap);
-      SS_HIP(hipHostMalloc((void**)&h_sum, h_cap * sizeof(UnitSum), hipHostMallocDefault));
+      SS_HIP(pinned_alloc((void**)&h_sum, h_cap * sizeof(UnitSum)));
     }
     {   // descriptors and unit lists, one transfer
       Upload up;
@@ -1786,20 +1786,21 @@ struct EngineImpl {
     ss_solve_info info;
   };
   std::vector<Done> done;
-  PState* h_states = nullptr;             // pinned
+  PState* h_states = nullptr;             // pinned (cached: pinned_alloc)
   size_t h_cap = 0;
   UnitBatch units;                        // problems for the class-resident CG, launched next tick
   ~EngineImpl() {
-    if (!units.dev.empty()) (void)hipStreamSynchronize(s);   // a launch may still use its blocks
-    if (h_states) (void)hipHostFree(h_states);
+    // a launch may still use its blocks, or a copy still fill the pinned buffers (error paths)
+    if (!units.dev.empty() || h_states || units.h_sum) (void)hipStreamSynchronize(s);
+    pinned_free(h_states);
   }
 
   ss_status ensure_host(size_t n) {
     if (n <= h_cap) return SS_OK;
-    if (h_states) (void)hipHostFree(h_states);
+    pinned_free(h_states);   // called between ticks: no copy into it is pending
     h_states = nullptr;
     h_cap = std::max(n, 2 * h_cap);
-    SS_HIP(hipHostMalloc((void**)&h_states, h_cap * sizeof(PState), hipHostMallocDefault));
+    SS_HIP(pinned_alloc((void**)&h_states, h_cap * sizeof(PState)));
     return SS_OK;
   }
 

@@ -392,6 +392,10 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
 // device memory: a caching allocator (see alloc.hip)
 hipError_t pool_alloc(void** out, size_t bytes);
 void pool_free(void* p);
+// pinned host memory for small result buffers, cached (see alloc.hip); released only after the
+// stream that filled it has been synchronised
+hipError_t pinned_alloc(void** out, size_t bytes);
+void pinned_free(void* p);
 // Host-to-device copy of `bytes` from pageable host memory, queued on `stream` without holding the
 // calling thread: the bytes are first copied into a pinned buffer of the thread.
 hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t stream);
@@ -413,6 +417,26 @@ void dfree(T*& p) {
   pool_free((void*)p);
   p = nullptr;
 }
+
+// Device-to-host reads that end in a stream synchronisation, staged through the calling thread's
+// pinned buffer: a read into pageable memory is staged by the runtime, and in the batch pipeline
+// one part's read could wait for milliseconds behind another part's stream.  add() queues a copy
+// on `stream`; sync() synchronises the stream and moves every staged copy to its destination.
+// One Readback is in use per thread at a time.
+struct Readback {
+  hipStream_t stream;
+  explicit Readback(hipStream_t s) : stream(s) {}
+  ss_status add(void* dst, const void* src, size_t bytes);
+  ss_status sync();
+
+ private:
+  struct Part {
+    void* dst;
+    size_t off, bytes;
+  };
+  std::vector<Part> parts;
+  size_t used = 0;
+};
 
 // Small host arrays sent to the device in one transfer: every array gets a 256-byte aligned slice
 // of one pooled device block, and the arrays are staged side by side in the thread's pinned

@@ -603,6 +603,8 @@ struct Scratch {
   std::vector<void**> slots;
   std::vector<void*> retired;   // no longer used by the host, maybe still by queued work
   explicit Scratch(hipStream_t s) : stream(s) {}
+  // p's block (whatever p points to when the scratch ends) is freed then; p must outlive the
+  // scratch, so it is declared before it
   template <typename T>
   void hold(T*& p) {
     slots.push_back((void**)&p);
@@ -863,8 +865,8 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_TRY(up.commit(&st->d_upload, stream));
   }
 
-  // ---- build scratch
-  Scratch sc(stream);
+  // ---- build scratch: every pointer the scratch frees is declared before it, so each is still
+  // alive when the scratch's destructor reads it
   int16_t* wk = nullptr;
   uint64_t* wh = nullptr;
   int32_t *wo = nullptr, *plev = nullptr;
@@ -881,11 +883,21 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   int64_t *d_fstart = nullptr, *d_fcount = nullptr, *d_cnt = nullptr;
   void* tmp = nullptr;
   void* d_in = nullptr;   // wk, wh, wo and plev are views into it
+  Field* d_fields = nullptr;
+  uint32_t *perm = nullptr, *perm2 = nullptr;
+  uint64_t *k64 = nullptr, *k64b = nullptr;
+  uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
+  int2* d_pr = nullptr;
+  int32_t* d_tie = nullptr;
+  int64_t* d_lstart = nullptr;
+  Scratch sc(stream);
   sc.hold(d_in);
   sc.hold(ukeys); sc.hold(uhash); sc.hold(upid); sc.hold(uroot);
   sc.hold(ulast); sc.hold(d_full);
   sc.hold(cpos); sc.hold(flag); sc.hold(idx); sc.hold(tmp); sc.hold(ccnt); sc.hold(coff); sc.hold(cand); sc.hold(wsrc);
   sc.hold(d_fstart); sc.hold(d_cnt);
+  sc.hold(d_fields); sc.hold(perm); sc.hold(perm2); sc.hold(k64); sc.hold(k64b); sc.hold(wq);
+  sc.hold(d_pr); sc.hold(d_tie); sc.hold(d_lstart);
   {
     Upload up;
     up.add(&wk, wkeys.data(), wkeys.size());
@@ -1022,8 +1034,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
       SS_TRY(scan_u32(flag, idx, n_cand));
       k_level_counts<<<grid_for(n_prob), kBlock, 0, stream>>>(n_prob, f0, d_fstart, d_fcount, coff, idx, flag,
                                                               d_cnt);
-      SS_HIP(hipMemcpyAsync(added.data(), d_cnt, n_prob * 8, hipMemcpyDeviceToHost, stream));
-      SS_HIP(hipStreamSynchronize(stream));
+      Readback rb(stream);
+      SS_TRY(rb.add(added.data(), d_cnt, n_prob * 8));
+      SS_TRY(rb.sync());
       sc.release_retired();
       return SS_OK;
     };
@@ -1130,27 +1143,21 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     }
     top_bits = used;
   }
-  Field* d_fields = nullptr;
-  sc.hold(d_fields);
   SS_TRY(dalloc(&d_fields, std::max<size_t>(fields.size(), 1)));
   if (!fields.empty())
     SS_HIP(h2d(d_fields, fields.data(), fields.size() * sizeof(Field), stream));
 
-  uint32_t *perm = nullptr, *perm2 = nullptr;
-  uint64_t *k64 = nullptr, *k64b = nullptr;
-  sc.hold(perm); sc.hold(perm2); sc.hold(k64); sc.hold(k64b);
   SS_TRY(dalloc(&perm, total));
   SS_TRY(dalloc(&perm2, total));
   SS_TRY(dalloc(&k64, total));
   SS_TRY(dalloc(&k64b, total));
   k_iota_u32<<<grid_for(total), kBlock, 0, stream>>>(total, perm);
   if (!passes.empty()) {
+    sc.retire(tmp);   // the level scans' scratch: back to the pool once the stream has passed them
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k64, k64b, perm, perm2, total, 0, 64, stream));
     SS_HIP(pool_alloc((void**)&tmp, tmp_bytes));
   }
   bool done = false;
-  uint64_t* wq = nullptr;   // a later pass's words in unsorted order, gathered through the permutation
-  sc.hold(wq);
   // long rows: every pass's words (and the most-significant word) formed in one read of the keys
   // (the per-pass form would read a row's cache lines once per pass), when they fit 2 GiB
   const int np_ = (int)passes.size();
@@ -1160,8 +1167,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     std::vector<int2> pr(nw_);
     for (int q = 0; q < np_; ++q) pr[q] = make_int2(passes[q].first, passes[q].second);
     if (top_bits > 0) pr[np_] = make_int2(nf, (int)fields.size());
-    int2* d_pr = nullptr;
-    sc.hold(d_pr);
     SS_TRY(dalloc(&d_pr, nw_));
     SS_HIP(h2d(d_pr, pr.data(), nw_ * sizeof(int2), stream));
     SS_TRY(dalloc(&wq, (size_t)nw_ * total));
@@ -1169,8 +1174,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
                                                                                            d_fields, d_pr, wq);
   }
   if (top_bits > 0) {
-    int32_t* d_tie = nullptr;
-    sc.hold(d_tie);
     SS_TRY(dalloc(&d_tie, 1));
     SS_HIP(hipMemsetAsync(d_tie, 0, 4, stream));
     const uint64_t* kin = k64;
@@ -1183,8 +1186,9 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
     SS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, k64b, perm, perm2, total, 0, top_bits, stream));
     k_adjacent_ties<<<grid_for(total), kBlock, 0, stream>>>(total, k64b, d_tie);
     int32_t tie = 1;
-    SS_HIP(hipMemcpyAsync(&tie, d_tie, 4, hipMemcpyDeviceToHost, stream));
-    SS_HIP(hipStreamSynchronize(stream));
+    Readback rb(stream);
+    SS_TRY(rb.add(&tie, d_tie, 4));
+    SS_TRY(rb.sync());
     if (!tie) {
       std::swap(perm, perm2);
       done = true;
@@ -1226,8 +1230,6 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   // the problem id sits at the top of the words the last sort ordered (k64b)
   const int pid_bits = bits_for((uint64_t)(n_prob - 1));
   const int pid_shift = (done ? top_bits : (passes.empty() ? 0 : pass_bits.back())) - pid_bits;
-  int64_t* d_lstart = nullptr;
-  sc.hold(d_lstart);
   SS_TRY(dalloc(&d_lstart, lstart.size()));
   SS_HIP(h2d(d_lstart, lstart.data(), lstart.size() * sizeof(int64_t), stream));
   if (wide)
@@ -1262,8 +1264,11 @@ ss_status build_stamp_impl(int32_t n_prob, int32_t d, const int32_t* n_a, const 
   }
   k_rowoff<<<grid_for(total), kBlock, 0, stream>>>(total, n_prob, st->d_pid, st->d_rowoff);
   st->row_off.assign(n_prob + 2, 0);
-  SS_HIP(hipMemcpyAsync(st->row_off.data(), st->d_rowoff, (n_prob + 2) * 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
+  {
+    Readback rb(stream);
+    SS_TRY(rb.add(st->row_off.data(), st->d_rowoff, (n_prob + 2) * 8));
+    SS_TRY(rb.sync());
+  }
   st->max_norm = st->row_off[n_prob + 1];
   st->row_off.pop_back();
   for (int p = 0; p < n_prob; ++p)
@@ -1313,9 +1318,9 @@ ss_status stamp_lookup_impl(const StampImpl* st, int32_t prob, int64_t nq, const
   SS_HIP(h2d(dq, q, (size_t)nq * st->d * 2, stream));
   k_lookup<<<grid_for(nq), kBlock, 0, stream>>>(nq, st->d, dq, prob, dp, st->d_coef, st->d_keys, st->d_toff,
                                                  st->d_tmask, st->d_ltable, st->d_rowoff, dout);
-  SS_HIP(hipMemcpyAsync(slot_out, dout, nq * 8, hipMemcpyDeviceToHost, stream));
-  SS_HIP(hipStreamSynchronize(stream));
-  return SS_OK;
+  Readback rb(stream);
+  SS_TRY(rb.add(slot_out, dout, nq * 8));
+  return rb.sync();
 }
 
 ss_status stamp_forcing_impl(const StampImpl* st, const double* f_hat, void* f, hipStream_t stream) {
