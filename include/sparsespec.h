@@ -414,6 +414,19 @@ ss_status ss_solve(int32_t d, int32_t n_a, const int16_t* a_freqs, const double*
                    const double* x0, int64_t u_cap, int64_t* n_out, double* u_hat_out,
                    int16_t* keys_out, ss_solve_info* info);
 
+/* ---------------------------------------------------------------- device memory
+ * ss_memory_stats -- the library's caching allocator (not a passage of the paper: accounting for
+ *   callers that budget device memory, e.g. a serving loop).  Every device block the library uses
+ *   comes from it; a released block is kept for reuse and returned to the driver only when an
+ *   allocation would otherwise fail.
+ *   live_bytes: bytes in blocks currently held by stamps, operators, engines and calls in flight;
+ *   cached_bytes: bytes in released blocks kept for reuse;
+ *   driver_allocs: number of blocks taken from the driver since the process started.
+ *   All three are totals over every device, written to host memory the caller owns.  Needs no
+ *   device (all zero before the first allocation).  Null argument -> SS_EINVAL.
+ */
+ss_status ss_memory_stats(int64_t* live_bytes, int64_t* cached_bytes, int64_t* driver_allocs);
+
 const char* ss_last_error(void);
 const char* ss_version(void);
 

@@ -77,6 +77,14 @@ const char* ss_last_error(void) { return last_error_cstr(); }
 
 const char* ss_version(void) { return "sparsespec 0.1 (gfx950)"; }
 
+ss_status ss_memory_stats(int64_t* live_bytes, int64_t* cached_bytes, int64_t* driver_allocs) {
+  return guarded([&]() -> ss_status {
+    if (!live_bytes || !cached_bytes || !driver_allocs) return fail(SS_EINVAL, "null argument");
+    pool_stats(live_bytes, cached_bytes, driver_allocs);
+    return SS_OK;
+  });
+}
+
 ss_status ss_build_stamp_batch(int32_t n_prob, int32_t d, const int32_t* n_a, const int16_t* a_freqs,
                                const int32_t* n_f, const int16_t* f_freqs, const int32_t* level, void* stream,
                                ss_stamp** out) {

@@ -29,6 +29,8 @@ struct Pool {
   std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;   // (device, class) -> blocks
   std::unordered_map<void*, std::pair<int, size_t>> live;             // block -> (device, class)
   size_t cached_bytes = 0;
+  size_t live_bytes = 0;
+  uint64_t driver_allocs = 0;   // successful allocations from the driver
 };
 
 Pool& pool() {
@@ -70,6 +72,7 @@ hipError_t pool_alloc(void** out, size_t bytes) {
       *out = it->second.back();
       it->second.pop_back();
       P.cached_bytes -= cls;
+      P.live_bytes += cls;
       P.live[*out] = {dev, cls};
       return hipSuccess;
     }
@@ -86,6 +89,8 @@ hipError_t pool_alloc(void** out, size_t bytes) {
   }
   std::lock_guard<std::mutex> g(P.mu);
   P.live[*out] = {dev, cls};
+  P.live_bytes += cls;
+  P.driver_allocs += 1;
   return hipSuccess;
 }
 
@@ -97,7 +102,16 @@ void pool_free(void* p) {
   if (it == P.live.end()) return;
   P.free_blocks[it->second].push_back(p);
   P.cached_bytes += it->second.second;
+  P.live_bytes -= it->second.second;
   P.live.erase(it);
+}
+
+void pool_stats(int64_t* live_bytes, int64_t* cached_bytes, int64_t* driver_allocs) {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  *live_bytes = (int64_t)P.live_bytes;
+  *cached_bytes = (int64_t)P.cached_bytes;
+  *driver_allocs = (int64_t)P.driver_allocs;
 }
 
 // ---------------------------------------------------------------- pinned result buffers

@@ -392,6 +392,8 @@ ss_status canonical_a(int32_t d, int32_t n_a, const int16_t* freqs, const double
 // device memory: a caching allocator (see alloc.hip)
 hipError_t pool_alloc(void** out, size_t bytes);
 void pool_free(void* p);
+// bytes in blocks handed out, bytes cached, and allocations taken from the driver so far (all devices)
+void pool_stats(int64_t* live_bytes, int64_t* cached_bytes, int64_t* driver_allocs);
 // pinned host memory for small result buffers, cached (see alloc.hip); released only after the
 // stream that filled it has been synchronised
 hipError_t pinned_alloc(void** out, size_t bytes);

@@ -31,7 +31,8 @@ EXPORTED = ["ss_build_stamp_batch", "ss_build_stamp", "ss_stamp_size", "ss_stamp
             "ss_engine_create", "ss_engine_submit", "ss_engine_step", "ss_engine_poll", "ss_engine_usage",
             "ss_engine_free", "ss_solve_batch", "ss_batch_size", "ss_batch_solution", "ss_free_batch",
             "ss_proxy_error", "ss_solve_direct", "ss_op_class_sizes", "ss_build_adr", "ss_adr_apply",
-            "ss_adr_solve", "ss_free_adr", "ss_lattice_modulus", "ss_stamp_lattice", "ss_solve_op_noalloc"]
+            "ss_adr_solve", "ss_free_adr", "ss_lattice_modulus", "ss_stamp_lattice", "ss_solve_op_noalloc",
+            "ss_memory_stats"]
 
 
 class SolveInfo(C.Structure):
@@ -85,6 +86,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "ss_solve": [i32, i32, pi16, pd, i32, pi16, pd, i32, dbl, i32, i32, u32, pd, i64, pi64, pd, pi16,
                      C.POINTER(SolveInfo)],
         "ss_op_bytes": [P, pi64],
+        "ss_memory_stats": [pi64, pi64, pi64],
         "ss_engine_create": [i64, i32, P, C.POINTER(P)],
         "ss_engine_submit": [P, P, P, P, dbl, i32, i32, i64],
         "ss_engine_step": [P, i32, pi32],
@@ -507,6 +509,13 @@ def solve(d, a_freqs, a_hat, f_freqs, f_hat, level, tol=1e-12, precision="fp64",
 
 def version() -> str:
     return _lib.ss_version().decode()
+
+
+def memory_stats() -> dict:
+    """The library's device allocator: bytes held, bytes cached, driver allocations so far."""
+    live, cached, allocs = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(_lib.ss_memory_stats(C.byref(live), C.byref(cached), C.byref(allocs)))
+    return {"live_bytes": live.value, "cached_bytes": cached.value, "driver_allocs": allocs.value}
 
 
 class BatchSolution:

@@ -95,3 +95,10 @@ def test_solve_argument_errors(ss):
 def test_binding_rejects_out_of_range_keys(ss):
     with pytest.raises(ss.SparseSpecError):
         ss._i16(np.array([[40000, 0]]))
+
+
+def test_memory_stats_without_a_device(ss):
+    # the allocator's counters need no device: nothing allocated yet in a CPU-only process
+    m = ss.memory_stats()
+    assert m == {"live_bytes": 0, "cached_bytes": 0, "driver_allocs": 0}
+    assert ss._lib.ss_memory_stats(None, None, None) == ss.SS_EINVAL

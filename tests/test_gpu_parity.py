@@ -161,6 +161,34 @@ def test_solve_batch_concurrent_callers(ss):
     assert len(out) == 6
 
 
+def test_builds_and_solves_reuse_cached_blocks(ss):
+    # every block a stamp build, an operator build and a solve take returns to the allocator's
+    # cache: after two warm rounds, further rounds take nothing from the driver and hold nothing
+    probs = [workloads.make(2, i, level=2) for i in range(16)]
+
+    def one_round():
+        st = ss.Stamp.build(probs)
+        op = ss.Operator.build(st, probs, 0)
+        f = st.forcing_vector(probs)
+        u = torch.zeros_like(f)
+        op.solve(f, u, 1e-10, "fp64")
+        op.solve(f, u, 1e-10, "fp32_refine")
+        torch.cuda.synchronize()
+        op.close()
+        st.close()
+        res, _ = ss.solve_batch(probs, 1e-10, "fp64", 1000, 0, parts=1)
+        res.close()
+
+    for _ in range(2):
+        one_round()
+    before = ss.memory_stats()
+    for _ in range(5):
+        one_round()
+    after = ss.memory_stats()
+    assert after["driver_allocs"] == before["driver_allocs"], (before, after)
+    assert after["live_bytes"] == before["live_bytes"], (before, after)
+
+
 def test_forcing_vector_matches_oracle_slots(ss):
     # f_hat placed at the slots the build recorded for F equals the oracle's f on S^N
     cases = [oracle_case(2, i, level=lv) for i, lv in ((0, 1), (1, 0), (2, 2))]
