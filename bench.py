@@ -2,13 +2,17 @@
 
 One step = the whole path on one batch of ``--batch`` independent problems of
 the d = 10 workload (10 cosine modes of a in [-16,16]^10, 20 forcing
-frequencies, stamping level 3, |S^N| = 31 220 per problem): stamping sets,
-hash index and neighbour map, then the FP32 + FP64-refinement PCG solve to a
-relative residual of ``--tol`` (chosen so the error against the FP64 oracle is
-below 1e-9; checked on sampled problems).  Inputs are uploaded before the
-timed region.  Also reported: the plain FP64 PCG solve of the same batch, the
-matvec (ss_apply) bandwidth timed with HIP events against the HBM roofline,
-and the CPU oracle on a bounded sample.
+frequencies, stamping level 3, |S^N| = 31 220 per problem), from the problems'
+sparse coefficient lists in host memory (packed once, before the timed region;
+their upload is part of every step): stamping sets, hash index and neighbour
+map, forcing vector and the PCG solve to a relative residual of ``--tol``, in
+the precision ``--precision`` selects (FP64 by default, the faster of the two
+on this GPU; FP32 + FP64 refinement is the other).  Also reported: both
+precisions' whole-path and solve-only rates of every configuration with the
+error against the FP64 oracle on sampled problems, the matvec (ss_apply)
+bandwidth timed with HIP events against the HBM roofline, single-instance
+latency, continuous-batching serving, the proxy error, the dense direct solve,
+the ADR solve, the rank-1 lattice, and the CPU oracle on a bounded sample.
 
 Prints one JSON line.
 """
