@@ -68,6 +68,20 @@ def check_served(ss, reqs, recs):
         assert err <= (1e-9 if p.precision == "fp32_refine" else 1e-10), (r.rid, err)
 
 
+def test_serving_returns_every_block(ss):
+    # a serving run (builds of grouped requests, the engine's launches, retirement) gives every
+    # device block it took back to the allocator: the bytes held after a run equal those before
+    from paper_2302_00752_amd.serving import serve
+    reqs = small_stream(8, seed=3)
+    serve(reqs, hbm_budget_bytes=1 << 30, build_threads=1, realtime=False)
+    for _ in range(2):
+        before = ss.memory_stats()
+        summary, recs = serve(reqs, hbm_budget_bytes=1 << 30, build_threads=1, realtime=False)
+        after = ss.memory_stats()
+        assert summary["status_ok"] == len(reqs)
+        assert after["live_bytes"] == before["live_bytes"], (before, after)
+
+
 def test_served_equals_alone_bitwise_and_oracle(ss):
     from paper_2302_00752_amd.serving import serve
     reqs = small_stream(10)
